@@ -1,0 +1,234 @@
+"""Sequential FP64 CPU oracle for the parallel-in-time probabilistic ODE solver.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the HIP implementation: its arithmetic lives in
+``oracle.c`` (plain C, built with gcc), and this module only marshals numpy
+arrays through ctypes.
+
+Functions follow the paper (Bosch et al., JMLR 2024):
+  * ``iwp`` / ``precond_model``: IWP(q) transition and process noise in closed
+    form (Sec. 2.1) and the coordinate-change preconditioner (Sec. 2.4).
+  * ``taylor_mu0``: exact initial state mu0 (eq. mu0).
+  * ``field_f`` / ``field_jac``: the vector-field registry.
+  * ``tria``: the triangularisation operator (Sec. 3.1.2).
+  * ``kf_rts``: sequential square-root Kalman filter + RTS smoother, the plain
+    definition of what ParaRTS (Alg. 1) computes.
+  * ``ieks``: Alg. 2 with that smoother.
+  * ``filter_element`` / ``filter_combine`` / ``smoother_element`` /
+    ``smoother_combine``: the paper's square-root elements and operators.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+FIELDS = {
+    "logistic": 0,
+    "fhn": 1,
+    "lorenz": 2,
+    "lotka_volterra": 3,
+    "mol_heat_reaction": 4,
+    "affine": 5,
+    "rigid_body": 6,
+    "van_der_pol": 7,
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER(ctypes.c_double)
+        i, dl, l = ctypes.c_int, ctypes.c_double, ctypes.c_long
+        L.orc_tria.argtypes = [i, i, P, P]
+        L.orc_chol.argtypes = [i, P, P]
+        L.orc_chol.restype = i
+        L.orc_field_dim.argtypes = [i, i, i]
+        L.orc_field_dim.restype = i
+        L.orc_field_f.argtypes = [i, P, i, P, P]
+        L.orc_field_jac.argtypes = [i, P, i, P, P]
+        L.orc_taylor_mu0.argtypes = [i, P, i, P, i, P]
+        L.orc_iwp.argtypes = [i, dl, P, P]
+        L.orc_precond_diag.argtypes = [i, dl, P]
+        L.orc_precond_model.argtypes = [i, i, dl, P, P, P]
+        L.orc_kf_rts.argtypes = [i, i, l, P, P, P, P, P, P, P, P, P, P]
+        L.orc_kf_rts.restype = i
+        L.orc_ieks.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, P, P, P, ctypes.POINTER(ctypes.c_int)]
+        L.orc_ieks.restype = i
+        L.orc_filter_element.argtypes = [i, i, P, P, P, P, P, P, i, P, P, P, P, P]
+        L.orc_filter_combine.argtypes = [i] + [P] * 15
+        L.orc_smoother_element.argtypes = [i, P, P, P, P, i, P, P, P]
+        L.orc_smoother_combine.argtypes = [i] + [P] * 9
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _field_id(field):
+    return FIELDS[field] if isinstance(field, str) else int(field)
+
+
+def tria(M):
+    M = _f64(M)
+    n, m = M.shape
+    L = np.zeros((n, n))
+    lib().orc_tria(n, m, _p(M), _p(L))
+    return L
+
+
+def chol(A):
+    A = _f64(A)
+    L = np.zeros_like(A)
+    if lib().orc_chol(A.shape[0], _p(A), _p(L)) != 0:
+        raise np.linalg.LinAlgError("matrix is not positive definite")
+    return L
+
+
+def field_dim(field, d, nparams):
+    return lib().orc_field_dim(_field_id(field), d, nparams)
+
+
+def field_f(field, params, y):
+    y, p = _f64(y), _f64(params if len(params) else [0.0])
+    f = np.zeros_like(y)
+    lib().orc_field_f(_field_id(field), _p(p), y.size, _p(y), _p(f))
+    return f
+
+
+def field_jac(field, params, y):
+    y, p = _f64(y), _f64(params if len(params) else [0.0])
+    J = np.zeros((y.size, y.size))
+    lib().orc_field_jac(_field_id(field), _p(p), y.size, _p(y), _p(J))
+    return J
+
+
+def taylor_mu0(field, params, y0, q):
+    y0, p = _f64(y0), _f64(params if len(params) else [0.0])
+    mu0 = np.zeros(y0.size * (q + 1))
+    lib().orc_taylor_mu0(_field_id(field), _p(p), y0.size, _p(y0), q, _p(mu0))
+    return mu0
+
+
+def iwp(q, h):
+    Phi = np.zeros((q + 1, q + 1))
+    Q = np.zeros((q + 1, q + 1))
+    lib().orc_iwp(q, float(h), _p(Phi), _p(Q))
+    return Phi, Q
+
+
+def precond_diag(q, h):
+    T = np.zeros(q + 1)
+    lib().orc_precond_diag(q, float(h), _p(T))
+    return T
+
+
+def precond_model(d, q, h):
+    D = d * (q + 1)
+    PhiB, sQB, T = np.zeros((D, D)), np.zeros((D, D)), np.zeros(D)
+    lib().orc_precond_model(d, q, float(h), _p(PhiB), _p(sQB), _p(T))
+    return PhiB, sQB, T
+
+
+def kf_rts(mu0, S0, Phi, sqrtQ, H, dv):
+    """Sequential square-root KF + RTS.  H is [N, dobs, D], dv [N, dobs].
+    Returns (mf, sPf, ms, sPs), stacks over n = 0..N."""
+    mu0, S0, Phi, sqrtQ, H, dv = map(_f64, (mu0, S0, Phi, sqrtQ, H, dv))
+    N, dobs, D = H.shape
+    mf, ms = np.zeros((N + 1, D)), np.zeros((N + 1, D))
+    sPf, sPs = np.zeros((N + 1, D, D)), np.zeros((N + 1, D, D))
+    rc = lib().orc_kf_rts(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
+                          _p(ms), _p(sPs))
+    if rc != 0:
+        raise FloatingPointError("non-finite values in the sequential smoother")
+    return mf, sPf, ms, sPs
+
+
+def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
+         want_cov=True):
+    """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
+    sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas."""
+    y0 = _f64(y0).ravel()
+    params = _f64(params if len(params) else [0.0]).ravel()
+    dd = y0.size if d is None else d
+    fid = _field_id(field)
+    dim = lib().orc_field_dim(fid, dd, params.size)
+    if dim < 1:
+        raise ValueError("field/parameter mismatch")
+    D = dim * (q + 1)
+    mean = np.zeros((N + 1, D))
+    cov = np.zeros((N + 1, D, D)) if want_cov else None
+    hist = np.zeros(max(max_iter, fixed_iters, 1))
+    iters = ctypes.c_int(0)
+    init = _f64(init_traj) if init_traj is not None else None
+    rc = lib().orc_ieks(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter, float(tol),
+                        fixed_iters, _p(init) if init is not None else None, _p(mean),
+                        _p(cov) if cov is not None else None, _p(hist), ctypes.byref(iters))
+    if rc == -1:
+        raise ValueError("bad problem")
+    k = iters.value
+    return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy()}
+
+
+def filter_element(Phi, sqrtQ, H, dv, m_prev, sP_prev, first):
+    Phi, sqrtQ, H, dv, m_prev, sP_prev = map(_f64, (Phi, sqrtQ, H, dv, m_prev, sP_prev))
+    dobs, D = H.shape
+    A, sC, sJ = np.zeros((D, D)), np.zeros((D, D)), np.zeros((D, D))
+    b, eta = np.zeros(D), np.zeros(D)
+    lib().orc_filter_element(D, dobs, _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(m_prev), _p(sP_prev), int(first),
+                             _p(A), _p(b), _p(sC), _p(eta), _p(sJ))
+    return A, b, sC, eta, sJ
+
+
+def filter_combine(ai, aj):
+    ai = [_f64(x) for x in ai]
+    aj = [_f64(x) for x in aj]
+    D = ai[1].size
+    A, sC, sJ = np.zeros((D, D)), np.zeros((D, D)), np.zeros((D, D))
+    b, eta = np.zeros(D), np.zeros(D)
+    lib().orc_filter_combine(D, *[_p(x) for x in ai], *[_p(x) for x in aj], _p(A), _p(b), _p(sC), _p(eta), _p(sJ))
+    return A, b, sC, eta, sJ
+
+
+def smoother_element(Phi, sqrtQ, mf, sPf, last):
+    Phi, sqrtQ, mf, sPf = map(_f64, (Phi, sqrtQ, mf, sPf))
+    D = mf.size
+    E, sL, g = np.zeros((D, D)), np.zeros((D, D)), np.zeros(D)
+    lib().orc_smoother_element(D, _p(Phi), _p(sqrtQ), _p(mf), _p(sPf), int(last), _p(E), _p(g), _p(sL))
+    return E, g, sL
+
+
+def smoother_combine(bi, bj):
+    bi = [_f64(x) for x in bi]
+    bj = [_f64(x) for x in bj]
+    D = bi[1].size
+    E, sL, g = np.zeros((D, D)), np.zeros((D, D)), np.zeros(D)
+    lib().orc_smoother_combine(D, *[_p(x) for x in bi], *[_p(x) for x in bj], _p(E), _p(g), _p(sL))
+    return E, g, sL

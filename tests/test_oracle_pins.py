@@ -1,0 +1,480 @@
+"""Pins for the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine used as an independent route (scipy's matrix exponential, numpy's QR),
+exact rational arithmetic, dense joint-Gaussian conditioning, a closed-form
+ODE solution, finite differences, or an algebraic identity (associativity,
+Woodbury).  Each is chosen so that a plausible slip in the oracle (a dropped
+term, a wrong sign or index, a transposed operand) makes one of them fail.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+
+RNG = np.random.default_rng(20231001)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.1: IWP(q) transition and process noise (closed form vs Van Loan)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+@pytest.mark.parametrize("h", [0.5, 1.0, 1.7])
+def test_iwp_matches_van_loan(q, h):
+    """Phi(h), Q(h) of the IWP(q) SDE dY^(i) = Y^(i+1) dt, dY^(q) = dW, from the
+    Van Loan matrix exponential expm([[F, L L^T], [0, -F^T]] h)."""
+    S = q + 1
+    F = np.diag(np.ones(q), 1)
+    L = np.zeros((S, 1))
+    L[-1, 0] = 1.0
+    M = np.zeros((2 * S, 2 * S))
+    M[:S, :S] = F
+    M[:S, S:] = L @ L.T
+    M[S:, S:] = -F.T
+    E = scipy.linalg.expm(M * h)
+    Phi_vl = E[:S, :S]
+    Q_vl = E[:S, S:] @ Phi_vl.T
+    Phi, Q = oracle.iwp(q, h)
+    assert rel(Phi, Phi_vl) < 1e-12
+    assert rel(Q, Q_vl) < 1e-11
+    assert np.allclose(np.triu(Phi), Phi)  # reading of the garbled formula: upper triangular
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+@pytest.mark.parametrize("h", [1e-4, 0.01, 1.0])
+def test_preconditioned_prior_is_step_independent(q, h):
+    """Sec. 2.4 preconditioner: Phibar_ij = C(q-i, j-i), Qbar_ij = 1/(2q+1-i-j)
+    in exact rationals, and sqrtQbar equals the exact LDL^T factor times sqrt(D)."""
+    PhiB, sQB, T = oracle.precond_model(1, q, h)
+    S = q + 1
+    binom = np.array([[math.comb(q - i, j - i) if j >= i else 0 for j in range(S)] for i in range(S)], float)
+    assert np.abs(PhiB - binom).max() < 1e-12 * binom.max()
+    Qexact = [[Fraction(1, 2 * q + 1 - i - j) for j in range(S)] for i in range(S)]
+    # exact LDL^T over the rationals
+    Lr = [[Fraction(0)] * S for _ in range(S)]
+    Dr = [Fraction(0)] * S
+    for j in range(S):
+        Dr[j] = Qexact[j][j] - sum(Lr[j][k] ** 2 * Dr[k] for k in range(j))
+        Lr[j][j] = Fraction(1)
+        for i in range(j + 1, S):
+            Lr[i][j] = (Qexact[i][j] - sum(Lr[i][k] * Lr[j][k] * Dr[k] for k in range(j))) / Dr[j]
+    chol_exact = np.array([[float(Lr[i][j]) * math.sqrt(float(Dr[j])) for j in range(S)] for i in range(S)])
+    assert rel(sQB, chol_exact) < 1e-12
+    Tref = np.array([math.sqrt(h) * h ** (q - i) / math.factorial(q - i) for i in range(S)])
+    assert rel(T, Tref) < 1e-14
+
+
+def test_kronecker_state_ordering():
+    """State index k = i*(q+1) + j (the I_d (x) (q+1) ordering of Sec. 2.1)."""
+    PhiB, sQB, T = oracle.precond_model(3, 2, 0.1)
+    PB1, sQ1, T1 = oracle.precond_model(1, 2, 0.1)
+    assert np.allclose(PhiB, np.kron(np.eye(3), PB1))
+    assert np.allclose(sQB, np.kron(np.eye(3), sQ1))
+    assert np.allclose(T, np.tile(T1, 3))
+
+
+# ---------------------------------------------------------------------------
+# vector fields: Jacobians by central differences
+# ---------------------------------------------------------------------------
+FIELD_CASES = [
+    ("logistic", [], [0.3]),
+    ("fhn", [0.2, 0.2, 3.0], [-1.1, 0.7]),
+    ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.2, -0.4, 20.0]),
+    ("lotka_volterra", [0.7, 1.2, 0.9, 1.1], [1.3, 0.8]),
+    ("mol_heat_reaction", [0.01], list(0.5 + 0.1 * np.sin(2 * np.pi * np.arange(16) / 16))),
+    ("rigid_body", [], [1.0, 0.2, 0.9]),
+    ("van_der_pol", [1.0], [2.0, -0.3]),
+]
+
+
+@pytest.mark.parametrize("field,params,y", FIELD_CASES)
+def test_jacobian_central_differences(field, params, y):
+    y = np.array(y, float)
+    J = oracle.field_jac(field, params, y)
+    Jfd = np.zeros_like(J)
+    for k in range(y.size):
+        e = np.zeros_like(y)
+        e[k] = 1e-6 * max(1.0, abs(y[k]))
+        Jfd[:, k] = (oracle.field_f(field, params, y + e) - oracle.field_f(field, params, y - e)) / (2 * e[k])
+    assert np.abs(J - Jfd).max() <= 1e-7 * max(1.0, np.abs(J).max())
+
+
+def _ref_field(field, p):
+    """Independent statements of the vector fields, written for objects with
+    +, -, * (floats or numpy Polynomials); used by the Picard-iteration pin."""
+    if field == "logistic":
+        return lambda y: [y[0] * (1 - y[0])]
+    if field == "fhn":
+        a, b, c = p
+        return lambda y: [c * (y[0] - y[0] * y[0] * y[0] * (1.0 / 3.0) + y[1]), (y[0] - a + b * y[1]) * (-1.0 / c)]
+    if field == "lorenz":
+        s, r, be = p
+        return lambda y: [s * (y[1] - y[0]), y[0] * (r - y[2]) - y[1], y[0] * y[1] - be * y[2]]
+    if field == "lotka_volterra":
+        al, be, ga, de = p
+        return lambda y: [al * y[0] - be * y[0] * y[1], de * y[0] * y[1] - ga * y[1]]
+    if field == "rigid_body":
+        return lambda y: [-2.0 * y[1] * y[2], 1.25 * y[0] * y[2], -0.5 * y[0] * y[1]]
+    if field == "van_der_pol":
+        (mu,) = p
+        return lambda y: [y[1], mu * ((1 - y[0] * y[0]) * y[1] - y[0])]
+    if field == "mol_heat_reaction":
+        (nu,) = p
+
+        def f(y):
+            d = len(y)
+            k = nu * d * d
+            return [k * (y[i - 1] - 2.0 * y[i] + y[(i + 1) % d]) + y[i] * (1 - y[i]) for i in range(d)]
+
+        return f
+    raise KeyError(field)
+
+
+@pytest.mark.parametrize("field,params,y", FIELD_CASES)
+def test_field_values(field, params, y):
+    f_ref = _ref_field(field, params)
+    assert rel(oracle.field_f(field, params, y), np.array(f_ref(list(np.array(y, float))), float)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# eq. mu0: exact initial derivatives
+# ---------------------------------------------------------------------------
+def test_mu0_logistic_closed_form():
+    y = 0.01
+    y1 = y * (1 - y)
+    y2 = y1 * (1 - 2 * y)
+    y3 = y2 * (1 - 2 * y) - 2 * y1 ** 2
+    y4 = y3 * (1 - 2 * y) - 6 * y1 * y2
+    mu0 = oracle.taylor_mu0("logistic", [], [y], 4)
+    assert rel(mu0, [y, y1, y2, y3, y4]) < 1e-14
+
+
+def test_mu0_affine_closed_form():
+    d, q = 3, 4
+    L = RNG.normal(size=(d, d))
+    c = RNG.normal(size=d)
+    y0 = RNG.normal(size=d)
+    mu0 = oracle.taylor_mu0("affine", list(L.ravel()) + list(c), y0, q).reshape(d, q + 1)
+    expect = [y0]
+    v = L @ y0 + c
+    for k in range(1, q + 1):
+        expect.append(v)
+        v = L @ v
+    expect = np.array(expect).T
+    assert rel(mu0, expect) < 1e-13
+
+
+@pytest.mark.parametrize("field,params,y", FIELD_CASES)
+def test_mu0_picard(field, params, y):
+    """Taylor coefficients from Picard iteration y <- y0 + int_0^t f(y) in
+    truncated polynomial arithmetic (independent of the oracle's recursion)."""
+    from numpy.polynomial import Polynomial as Poly
+
+    q = 4
+    f = _ref_field(field, params)
+    y0 = np.array(y, float)
+    Y = [Poly([v]) for v in y0]
+    for _ in range(q + 1):
+        F = f(Y)
+        Y = [Poly([y0[i]]) + Poly(np.asarray(F[i].coef if isinstance(F[i], Poly) else [F[i]])[: q + 1]).integ()
+             for i in range(len(y0))]
+        Y = [Poly(p.coef[: q + 1]) for p in Y]
+    coef = np.zeros((len(y0), q + 1))
+    for i, p in enumerate(Y):
+        cc = p.coef[: q + 1]
+        coef[i, : cc.size] = cc
+    derivs = coef * np.array([math.factorial(k) for k in range(q + 1)])
+    mu0 = oracle.taylor_mu0(field, params, y0, q).reshape(len(y0), q + 1)
+    assert np.abs(mu0 - derivs).max() <= 1e-12 * max(1.0, np.abs(derivs).max())
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1.2: tria
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m", [(3, 6), (8, 16), (10, 10), (16, 16), (6, 3), (15, 30)])
+def test_tria(n, m):
+    M = RNG.normal(size=(n, m))
+    L = oracle.tria(M)
+    assert np.allclose(np.tril(L), L)
+    assert np.all(np.diag(L) >= 0)
+    assert rel(L @ L.T, M @ M.T) < 1e-13
+    if m >= n:  # full row rank: unique, equals R^T of numpy's QR of M^T with signs fixed
+        R = np.linalg.qr(M.T, mode="r")
+        Lq = R.T * np.sign(np.diag(R))
+        assert rel(L, Lq) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# ParaRTS target: sequential KF/RTS vs dense joint-Gaussian conditioning
+# ---------------------------------------------------------------------------
+def random_linear_model(D, dobs, N, rng, sigma0=True):
+    Phi = np.eye(D) + 0.3 * rng.normal(size=(D, D))
+    sQ = np.tril(rng.normal(size=(D, D))) * 0.5 + np.eye(D)
+    mu0 = rng.normal(size=D)
+    S0 = np.tril(rng.normal(size=(D, D))) * 0.3 if sigma0 else np.zeros((D, D))
+    H = rng.normal(size=(N, dobs, D))
+    dv = rng.normal(size=(N, dobs))
+    return mu0, S0, Phi, sQ, H, dv
+
+
+def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None):
+    """Joint Gaussian of Y_0..N (Y0 = mu0 + S0 w0, Y_n = Phi Y_{n-1} + sQ w_n),
+    conditioned on H_n Y_n = d_n for n = 1..upto (all when upto is None)."""
+    N, dobs, D = H.shape
+    upto = N if upto is None else upto
+    nw = (N + 1) * D
+    G = np.zeros(((N + 1) * D, nw))
+    m = np.zeros((N + 1) * D)
+    G[:D, :D] = S0
+    m[:D] = mu0
+    for n in range(1, N + 1):
+        G[n * D:(n + 1) * D] = Phi @ G[(n - 1) * D:n * D]
+        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += sQ
+        m[n * D:(n + 1) * D] = Phi @ m[(n - 1) * D:n * D]
+    Sig = G @ G.T
+    C = np.zeros((upto * dobs, (N + 1) * D))
+    for n in range(1, upto + 1):
+        C[(n - 1) * dobs:n * dobs, n * D:(n + 1) * D] = H[n - 1]
+    dd = dv[:upto].ravel()
+    S = C @ Sig @ C.T
+    K = np.linalg.solve(S, C @ Sig).T
+    mp = m + K @ (dd - C @ m)
+    Sp = Sig - K @ C @ Sig
+    return mp.reshape(N + 1, D), Sp
+
+
+@pytest.mark.parametrize("D,dobs,N", [(3, 1, 5), (4, 2, 6), (8, 2, 7)])
+def test_kf_rts_equals_dense_conditioning(D, dobs, N):
+    rng = np.random.default_rng(D * 100 + N)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng)
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv)
+    m_all, S_all = dense_conditioning(mu0, S0, Phi, sQ, H, dv)
+    for n in range(N + 1):
+        assert rel(ms[n], m_all[n]) < 1e-10
+        Pn = S_all[n * D:(n + 1) * D, n * D:(n + 1) * D]
+        assert np.abs(sPs[n] @ sPs[n].T - Pn).max() < 1e-10 * max(1.0, np.abs(Pn).max())
+    for n in range(1, N + 1):
+        m_n, S_n = dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=n)
+        assert rel(mf[n], m_n[n]) < 1e-10
+        Pn = S_n[n * D:(n + 1) * D, n * D:(n + 1) * D]
+        assert np.abs(sPf[n] @ sPf[n].T - Pn).max() < 1e-10 * max(1.0, np.abs(Pn).max())
+        # the Dirac observation holds exactly in the filtered marginal
+        assert np.abs(H[n - 1] @ mf[n] - dv[n - 1]).max() < 1e-9 * max(1.0, np.abs(mf[n]).max())
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1: paper-form elements and operators
+# ---------------------------------------------------------------------------
+def filter_elements(mu0, S0, Phi, sQ, H, dv):
+    N, dobs, D = H.shape
+    out = []
+    for n in range(1, N + 1):
+        if n == 1:
+            out.append(oracle.filter_element(Phi, sQ, H[0], dv[0], mu0, S0, True))
+        else:
+            out.append(oracle.filter_element(Phi, sQ, H[n - 1], dv[n - 1], np.zeros(D), np.zeros((D, D)), False))
+    return out
+
+
+@pytest.mark.parametrize("D,dobs,N", [(3, 1, 6), (8, 2, 9)])
+def test_filter_prefix_equals_sequential_filter(D, dobs, N):
+    """Alg. 1 forward part: the cumulative (x)_f of the elements gives the
+    filtering marginals m^f_n = b_{1:n}, sqrtP^f_n = sqrtC_{1:n}; A and J of
+    every prefix vanish."""
+    rng = np.random.default_rng(7 + D)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng)
+    mf, sPf, _, _ = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv)
+    els = filter_elements(mu0, S0, Phi, sQ, H, dv)
+    acc = els[0]
+    for n in range(1, N + 1):
+        if n > 1:
+            acc = oracle.filter_combine(acc, els[n - 1])
+        A, b, sC, eta, sJ = acc
+        assert rel(b, mf[n]) < 1e-10
+        assert np.abs(sC @ sC.T - sPf[n] @ sPf[n].T).max() < 1e-10 * max(1, np.abs(sPf[n]).max() ** 2)
+        assert np.abs(A).max() < 1e-12 and np.abs(eta).max() < 1e-12 and np.abs(sJ).max() < 1e-12
+
+
+@pytest.mark.parametrize("D,dobs,N", [(3, 1, 6), (8, 2, 9)])
+def test_smoother_suffix_equals_rts(D, dobs, N):
+    """Alg. 1 backward part: the reverse cumulative (x)_s of the smoothing
+    elements gives m^s_n = g_{n:N}, sqrtP^s_n = sqrtL_{n:N}."""
+    rng = np.random.default_rng(11 + D)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng)
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv)
+    els = [oracle.smoother_element(Phi, sQ, mf[n], sPf[n], n == N) for n in range(1, N + 1)]
+    acc = els[-1]
+    for n in range(N, 0, -1):
+        if n < N:
+            acc = oracle.smoother_combine(els[n - 1], acc)
+        E, g, sL = acc
+        assert rel(g, ms[n]) < 1e-10
+        assert np.abs(sL @ sL.T - sPs[n] @ sPs[n].T).max() < 1e-10 * max(1, np.abs(sPs[n]).max() ** 2)
+        assert np.abs(E).max() < 1e-12
+
+
+def random_fat_elements(D, dobs, k, rng):
+    """Non-trivial filtering elements: aggregates of a few consecutive raw
+    elements (so A, C, J are all full and no prefix structure is present)."""
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, 3 * k + 1, rng)
+    els = filter_elements(mu0, S0, Phi, sQ, H, dv)[1:]
+    out = []
+    for i in range(k):
+        a = els[3 * i]
+        for j in (1, 2):
+            a = oracle.filter_combine(a, els[3 * i + j])
+        out.append(a)
+    return out
+
+
+def _cmp_filter(x, y, tol):
+    A1, b1, sC1, e1, sJ1 = x
+    A2, b2, sC2, e2, sJ2 = y
+    assert rel(A1, A2) < tol
+    assert rel(b1, b2) < tol
+    assert rel(sC1 @ sC1.T, sC2 @ sC2.T) < tol
+    assert rel(e1, e2) < tol
+    assert rel(sJ1 @ sJ1.T, sJ2 @ sJ2.T) < tol
+
+
+@pytest.mark.parametrize("D,dobs", [(3, 1), (6, 2), (8, 2)])
+def test_filter_operator_associative(D, dobs):
+    a, b, c = random_fat_elements(D, dobs, 3, np.random.default_rng(D))
+    left = oracle.filter_combine(oracle.filter_combine(a, b), c)
+    right = oracle.filter_combine(a, oracle.filter_combine(b, c))
+    _cmp_filter(left, right, 1e-10)
+
+
+@pytest.mark.parametrize("D,dobs", [(3, 1), (8, 2)])
+def test_filter_operator_covariance_form(D, dobs):
+    """The square-root operator equals the covariance-form operator obtained
+    from it by the Woodbury identity:
+      A = A_j (I + C_i J_j)^{-1} A_i,  b = A_j (I + C_i J_j)^{-1}(b_i + C_i eta_j) + b_j,
+      C = A_j (I + C_i J_j)^{-1} C_i A_j^T + C_j,
+      eta = A_i^T (I + J_j C_i)^{-1}(eta_j - J_j b_i) + eta_i,
+      J = A_i^T (I + J_j C_i)^{-1} J_j A_i + J_i."""
+    ai, aj = random_fat_elements(D, dobs, 2, np.random.default_rng(3 * D))
+    Ai, bi, sCi, ei, sJi = ai
+    Aj, bj, sCj, ej, sJj = aj
+    Ci, Ji, Cj, Jj = sCi @ sCi.T, sJi @ sJi.T, sCj @ sCj.T, sJj @ sJj.T
+    I = np.eye(D)
+    M1 = np.linalg.inv(I + Ci @ Jj)
+    M2 = np.linalg.inv(I + Jj @ Ci)
+    ref = (Aj @ M1 @ Ai, Aj @ M1 @ (bi + Ci @ ej) + bj, Aj @ M1 @ Ci @ Aj.T + Cj,
+           Ai.T @ M2 @ (ej - Jj @ bi) + ei, Ai.T @ M2 @ Jj @ Ai + Ji)
+    A, b, sC, e, sJ = oracle.filter_combine(ai, aj)
+    assert rel(A, ref[0]) < 1e-10
+    assert rel(b, ref[1]) < 1e-10
+    assert rel(sC @ sC.T, ref[2]) < 1e-10
+    assert rel(e, ref[3]) < 1e-10
+    assert rel(sJ @ sJ.T, ref[4]) < 1e-10
+
+
+@pytest.mark.parametrize("D", [3, 8])
+def test_smoother_operator_associative(D):
+    rng = np.random.default_rng(100 + D)
+    els = []
+    for _ in range(3):
+        E = rng.normal(size=(D, D)) * 0.5
+        g = rng.normal(size=D)
+        sL = np.tril(rng.normal(size=(D, D)))
+        els.append((E, g, sL))
+    a, b, c = els
+    left = oracle.smoother_combine(oracle.smoother_combine(a, b), c)
+    right = oracle.smoother_combine(a, oracle.smoother_combine(b, c))
+    assert rel(left[0], right[0]) < 1e-12
+    assert rel(left[1], right[1]) < 1e-12
+    assert rel(left[2] @ left[2].T, right[2] @ right[2].T) < 1e-12
+    # and the marginal composition it encodes: L_ij = E_i L_j E_i^T + L_i
+    E, g, sL = oracle.smoother_combine(a, b)
+    assert rel(sL @ sL.T, a[0] @ b[2] @ b[2].T @ a[0].T + a[2] @ a[2].T) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2: IEKS
+# ---------------------------------------------------------------------------
+def test_affine_ode_converges_in_one_iteration():
+    """Sec. 3.1: for an affine vector field the linearisation is exact, so the
+    first smoothing pass is already the fixed point."""
+    d, q, N = 2, 2, 200
+    L = np.array([[-0.5, 1.0], [-1.0, -0.3]])
+    c = np.array([0.2, -0.1])
+    r = oracle.ieks("affine", list(L.ravel()) + list(c), [1.0, 0.0], 0.0, 5.0, q, N, fixed_iters=3, want_cov=False)
+    scale = np.abs(r["mean"]).max()
+    assert r["deltas"][1] <= 1e-12 * scale
+    assert r["deltas"][2] <= 1e-12 * scale
+    # and the solution is accurate: compare with the exact affine flow
+    t = np.linspace(0.0, 5.0, N + 1)
+    ystar = -np.linalg.solve(L, c)
+    exact = np.array([ystar + scipy.linalg.expm(L * tt) @ (np.array([1.0, 0.0]) - ystar) for tt in t])
+    assert np.abs(r["mean"][:, [0, q + 1]] - exact).max() < 1e-6
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_logistic_convergence_order(q):
+    """The MAP estimate converges polynomially to the true solution as h -> 0
+    (Sec. 3.2.2); on the logistic closed form 1/(1 + (1/y0 - 1) e^{-t}) the
+    observed rate is q + 1 at the grid points (above the order-q guarantee).
+    The range stays above the FP64 floor."""
+    Ns = {1: [1024, 2048, 4096], 2: [256, 512, 1024, 2048], 3: [256, 512, 1024]}[q]
+    errs = []
+    for N in Ns:
+        r = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, q, N, max_iter=40, tol=1e-13, want_cov=False)
+        assert r["status"] == 0
+        t = np.linspace(0.0, 10.0, N + 1)
+        y = 1.0 / (1.0 + (1.0 / 0.01 - 1.0) * np.exp(-t))
+        errs.append(np.abs(r["mean"][:, 0] - y).max())
+    slopes = -np.diff(np.log2(errs))
+    assert np.all(slopes > q + 0.5), slopes
+
+
+def test_fixed_point_satisfies_ode_at_grid_points():
+    """At convergence the Dirac constraints E1 mu_n = f(E0 mu_n) hold."""
+    r = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 1000, max_iter=20, tol=1e-10, want_cov=True)
+    assert r["status"] == 0 and r["iterations"] <= 20
+    m = r["mean"]
+    resid = m[1:, 1] - m[1:, 0] * (1 - m[1:, 0])
+    assert np.abs(resid).max() < 1e-8
+    # the posterior covariance of E1 - F_y E0 is zero at the grid points (noiseless data)
+    for n in (1, 500, 1000):
+        y = m[n, 0]
+        h = np.array([-(1 - 2 * y), 1.0, 0.0])
+        P = r["sqrtcov"][n] @ r["sqrtcov"][n].T
+        assert abs(h @ P @ h) <= 1e-10 * max(np.abs(P).max(), 1e-30) + 1e-30
+
+
+def test_ieks_iterate_equals_linear_smoother():
+    """One IEKS iteration = the linear smoother on the model linearised at the
+    constant trajectory mu0 (Alg. 2); built here independently from the
+    unpreconditioned closed forms and dense conditioning at tiny N."""
+    field, params, y0, q, N, t1 = "fhn", [0.2, 0.2, 3.0], np.array([-1.0, 1.0]), 2, 5, 0.5
+    d, S = 2, q + 1
+    D = d * S
+    h = t1 / N
+    Phi1, Q1 = oracle.iwp(q, h)
+    Phi, Q = np.kron(np.eye(d), Phi1), np.kron(np.eye(d), Q1)
+    mu0 = oracle.taylor_mu0(field, params, y0, q)
+    E0 = np.zeros((d, D))
+    E1 = np.zeros((d, D))
+    for i in range(d):
+        E0[i, i * S] = 1.0
+        E1[i, i * S + 1] = 1.0
+    y = E0 @ mu0
+    J = oracle.field_jac(field, params, y)
+    f = oracle.field_f(field, params, y)
+    Hn = E1 - J @ E0
+    dn = f - J @ y
+    H = np.repeat(Hn[None], N, axis=0)
+    dv = np.repeat(dn[None], N, axis=0)
+    m_all, _ = dense_conditioning(mu0, np.zeros((D, D)), Phi, np.linalg.cholesky(Q), H, dv)
+    r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=1, want_cov=False)
+    assert rel(r["mean"], m_all) < 1e-9
