@@ -478,3 +478,21 @@ def test_ieks_iterate_equals_linear_smoother():
     m_all, _ = dense_conditioning(mu0, np.zeros((D, D)), Phi, np.linalg.cholesky(Q), H, dv)
     r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=1, want_cov=False)
     assert rel(r["mean"], m_all) < 1e-9
+
+
+@pytest.mark.parametrize("D,dobs", [(3, 1), (8, 2)])
+def test_first_element_is_initial_state_combined_with_regular_element(D, dobs):
+    """Reading used by the GPU scan: the paper's first element a_1 = p(Y1 | Z1)
+    (built from m0 = mu0, P0 = Sigma0) equals the initial distribution, written
+    as the element (A=0, b=mu0, sqrtC=sqrtSigma0, eta=0, sqrtJ=0), combined by
+    (x)_f with the regular element of step 1 (built from m = 0, P = 0)."""
+    rng = np.random.default_rng(5 * D)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, 1, rng)
+    first = oracle.filter_element(Phi, sQ, H[0], dv[0], mu0, S0, True)
+    reg = oracle.filter_element(Phi, sQ, H[0], dv[0], np.zeros(D), np.zeros((D, D)), False)
+    Z = np.zeros((D, D))
+    state = (Z, mu0, S0, np.zeros(D), Z)
+    comb = oracle.filter_combine(state, reg)
+    assert np.abs(comb[0]).max() < 1e-12 and np.abs(comb[3]).max() < 1e-12 and np.abs(comb[4]).max() < 1e-12
+    assert rel(comb[1], first[1]) < 1e-10
+    assert rel(comb[2] @ comb[2].T, first[2] @ first[2].T) < 1e-10
