@@ -1,0 +1,219 @@
+"""Benchmark: ParaIEKS throughput on one MI355X.
+
+One step = one complete solve (prior and initial state, then for every IEKS
+iteration: linearisation, filtering elements, forward scan, smoothing
+elements, reverse scan, convergence test; finally the output in original
+coordinates) of the FitzHugh-Nagumo workload: d = 2, IWP(3) (D = 8),
+N = 2^18 steps on t in [0, 100], constant initial trajectory (Alg. 2), 20
+iterations.  value = N * iterations / seconds (time-steps x iterations per
+second), whole job, FP32 square-root path; the FP64 path is reported beside
+it.  Inputs live in HBM before timing starts (the solve's only host inputs
+are the problem's few scalars).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-steps×iterations/sec per IEKS solve (FP32-sqrt vs FP64); p50/p99 latency"
+UNIT = "time-steps*iterations/s"
+PEAK = {"f32": 157.3e12, "f64": 78.6e12}  # MI355X vector FP32 / FP64 peak, FLOP/s
+HBM_PEAK = 8.0e12
+
+
+def workload(N, iters):
+    return dict(field="fhn", params=[0.2, 0.2, 3.0], y0=[-1.0, 1.0], t0=0.0, t1=100.0, q=3, N=N, iters=iters)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("scan_kernels.hip", "rowalg.h", "fields.h"):
+        with open(os.path.join(ROOT, "paper_2310_01145_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload_tag))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"kernel_source_sha:\s*(\w+)", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != kernel_source_sha():
+        return None
+    return float(m_b.group(1))
+
+
+def run_gpu(pp, torch, wl, prec, steps, warmup, profile):
+    D = 2 * (wl["q"] + 1)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    mean = torch.empty((wl["N"] + 1, D), dtype=dt, device="cuda")
+    kw = dict(precision=prec, fixed_iters=wl["iters"], out=(mean, None))
+    args = (wl["field"], wl["params"], wl["y0"], wl["t0"], wl["t1"], wl["q"], wl["N"])
+    for _ in range(warmup):
+        pp.solve(*args, **kw)
+    torch.cuda.synchronize()
+    if profile:
+        pp.profile_enable(True)
+    lat, iters, statuses = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        r = pp.solve(*args, **kw)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+        iters.append(r["iterations"])
+        statuses.append(r["status"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = pp.profile_read() if profile else None
+    if profile:
+        pp.profile_enable(False)
+    return {
+        "value": wl["N"] * float(sum(iters)) / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+        "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+        "iterations_per_solve": iters,
+        "status": statuses,
+        "final_delta": r["final_delta"],
+        "profile": prof,
+    }
+
+
+def roofline(prof, wl, prec, b1=8):
+    from paper_2310_01145_amd import costmodel
+
+    d, q, N = 2, wl["q"], wl["N"]
+    esize = 4 if prec == "fp32" else 8
+    per = costmodel.per_step(d, q, esize, b1)
+    # dominant kernel by total time
+    name = max(prof, key=lambda k: prof[k][0])
+    total_ms, launches = prof[name]
+    avg_s = total_ms * 1e-3 / launches
+    steps_per_launch = N if name in per else None
+    out = {"kernel": name, "avg_launch_us": avg_s * 1e6, "launches": launches,
+           "share_of_kernel_time": total_ms / sum(v[0] for v in prof.values())}
+    if steps_per_launch is None:
+        out.update({"bound": "alu", "achieved": None, "peak": PEAK["f32" if esize == 4 else "f64"] / 1e12,
+                    "unit": "TFLOP/s", "frac": None, "traffic": None})
+        return out
+    flops, byts = per[name]
+    achieved = flops * steps_per_launch / avg_s
+    peak = PEAK["f32" if esize == 4 else "f64"]
+    out.update({
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": peak / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": stored_traffic(name, "fhn_n262144_%s" % prec),
+        "algorithmic_flops_per_launch": flops * steps_per_launch,
+        "algorithmic_bytes_per_launch": byts * steps_per_launch,
+        "achieved_GBps_algorithmic": byts * steps_per_launch / avg_s / 1e9,
+        "hbm_frac_algorithmic": byts * steps_per_launch / avg_s / HBM_PEAK,
+    })
+    return out
+
+
+def cpu_baseline(wl_full):
+    """The CPU oracle (sequential FP64 square-root EKF/RTS IEKS, one thread)
+    on a bounded sample of the same workload."""
+    import oracle
+
+    N, k = 1 << 17, 8
+    t = time.perf_counter()
+    r = oracle.ieks(wl_full["field"], wl_full["params"], wl_full["y0"], wl_full["t0"], wl_full["t1"], wl_full["q"],
+                    N, fixed_iters=k, want_cov=False)
+    el = time.perf_counter() - t
+    return {"value": N * r["iterations"] / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": "same FitzHugh-Nagumo problem at N=2^17 (h doubled), %d fixed iterations from the constant "
+                      "start, FP64, single thread, %.1f s" % (r["iterations"], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=1 << 18)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the path is a single-GPU solver and no "
+              "multi-GPU figure is produced.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2310_01145_amd as pp
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    pp.load_library()
+    wl = workload(args.N, args.iters)
+    print("bench: workload FHN N=%d iters=%d" % (wl["N"], wl["iters"]), file=sys.stderr, flush=True)
+    r32 = run_gpu(pp, torch, wl, "fp32", args.steps, args.warmup, not args.no_profile)
+    print("bench: fp32 done %.3f ms/solve" % r32["ms_per_step"], file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(pp, torch, wl, "fp64", args.steps, args.warmup, False)
+        print("bench: fp64 done %.3f ms/solve" % r64["ms_per_step"], file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FitzHugh-Nagumo a=b=0.2 c=3, y0=(-1,1), t in [0,100], IWP(3) D=8, N=%d, %d IEKS "
+                               "iterations per solve, constant initial trajectory" % (wl["N"], wl["iters"]),
+                   "N": wl["N"], "q": wl["q"], "d": 2, "iterations": wl["iters"], "precision": "fp32_sqrt"},
+        "latency_ms_p50": r32["latency_ms_p50"],
+        "latency_ms_p99": r32["latency_ms_p99"],
+        "iterations_per_solve": r32["iterations_per_solve"][0],
+        "solve_status": r32["status"][0],
+    }
+    if r64 is not None:
+        line["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                        "latency_ms_p50": r64["latency_ms_p50"], "latency_ms_p99": r64["latency_ms_p99"],
+                        "iterations_per_solve": r64["iterations_per_solve"][0], "solve_status": r64["status"][0]}
+    if r32["profile"]:
+        line["roofline"] = roofline(r32["profile"], wl, "fp32")
+        line["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in sorted(r32["profile"].items(),
+                                                                               key=lambda kv: -kv[1][0])}
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl)
+        cb["cores"] = 1
+        line["cpu_baseline"] = cb
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

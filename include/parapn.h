@@ -1,0 +1,162 @@
+/*
+ * parapn -- parallel-in-time probabilistic numerical ODE solver (ParaIEKS)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bosch, Corenflos, Yaghoobi, Tronarp, Hennig, Saerkkae,
+ * "Parallel-in-Time Probabilistic Numerical ODE Solvers", JMLR 25 (2024).
+ *
+ * Plain C ABI.  Pointers marked "device" are HIP device pointers (any memory
+ * the GPU can address, e.g. torch tensor storage); pointers marked "host" are
+ * ordinary host memory read during the call.  Matrices are dense row-major.
+ * The state ordering is the Kronecker order of Sec. 2.1: index
+ * k = i*(q+1) + j holds derivative j of ODE component i, D = d*(q+1).
+ * Square-root factors are lower-triangular ("left square roots", Sec. 3.1.2).
+ * Floating-point device buffers have the element type of the precision
+ * argument: double for PARAPN_FP64, float for PARAPN_FP32_SQRT.
+ *
+ * Every function returns a status code (PARAPN_OK = 0 on success).  A
+ * negative status leaves a message in parapn_last_error() (thread-local);
+ * output buffers are then unspecified.  No exception crosses the boundary.
+ * All GPU work is queued on the caller's stream (a hipStream_t passed as
+ * void*, NULL = the default stream).
+ */
+#ifndef PARAPN_H
+#define PARAPN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PARAPN_OK 0          /* done; for a solve: the stopping criterion was met   */
+#define PARAPN_MAXITER 1     /* solve hit max_iter; the returned result is valid     */
+#define PARAPN_EINVAL (-1)   /* bad argument (unknown field, d/q/N out of range, ..) */
+#define PARAPN_ENOMEM (-2)   /* device memory or the context budget is exhausted    */
+#define PARAPN_EDEVICE (-3)  /* HIP runtime error                                   */
+#define PARAPN_ENONFINITE (-4) /* NaN/Inf in the iterate; outputs hold the last one  */
+
+/* arithmetic of the path */
+#define PARAPN_FP64 0      /* every step in double                                  */
+#define PARAPN_FP32_SQRT 1 /* elements, scans and linearisation in float; the prior
+                            * constants, the output unscaling and the convergence
+                            * test in double (Sec. 2.4 preconditioned form)         */
+
+/* Vector-field registry.  f is autonomous in every entry.
+ * PARAPN_LOGISTIC        d=1  y' = y(1-y)                                     no params
+ * PARAPN_FHN             d=2  V' = c(V - V^3/3 + R), R' = -(V - a + bR)/c     params a,b,c
+ * PARAPN_LORENZ63        d=3  x' = s(y-x), y' = x(r-z)-y, z' = xy - b z      params s,r,b
+ * PARAPN_LOTKA_VOLTERRA  d=2  x' = al x - be x y, y' = de x y - ga y          params al,be,ga,de
+ * PARAPN_AFFINE          d    y' = L y + c                                    params L (d*d, row-major), c (d)
+ * PARAPN_RIGID_BODY      d=3  y' = (-2 y2 y3, 1.25 y1 y3, -0.5 y1 y2)         no params
+ * PARAPN_VAN_DER_POL     d=2  y' = (y2, mu((1-y1^2) y2 - y1))                 params mu
+ * The first three, the rigid body and Van der Pol follow the problems of the
+ * experiments section and the workload list; the affine field is the exactly
+ * solvable case of Sec. 3.1. */
+#define PARAPN_LOGISTIC 0
+#define PARAPN_FHN 1
+#define PARAPN_LORENZ63 2
+#define PARAPN_LOTKA_VOLTERRA 3
+#define PARAPN_AFFINE 5
+#define PARAPN_RIGID_BODY 6
+#define PARAPN_VAN_DER_POL 7
+
+/* limits of this build: 1 <= d <= 3, 1 <= q <= 4, D = d(q+1) <= 15 */
+#define PARAPN_MAX_D 15
+#define PARAPN_MAX_PARAMS 16
+
+typedef struct parapn_ctx parapn_ctx;
+
+/* One initial value problem (eq. ivp) on the uniform grid t_n = t0 + n h,
+ * h = (t1 - t0)/N, n = 0..N, solved with an IWP(q) prior (Sec. 2.1), exact
+ * Taylor initialisation mu0 and Sigma0 = 0 (eq. mu0), EK1 linearisation
+ * (Sec. 3.2.1) and the iterated smoother of Alg. 2. */
+typedef struct {
+    int32_t field;         /* PARAPN_* field id                                        */
+    int32_t d;             /* ODE dimension (must match the field; free for AFFINE)    */
+    const double *params;  /* host, n_params values (may be NULL when n_params == 0)   */
+    int32_t n_params;
+    const double *y0;      /* host, d values                                           */
+    double t0, t1;         /* time span, t1 > t0                                       */
+    int32_t q;             /* prior order, 1..4                                        */
+    int64_t N;             /* number of steps, >= 1                                    */
+    double tol;            /* stop when delta_k < tol (see parapn_solve)               */
+    int32_t max_iter;      /* iteration cap, >= 1                                      */
+    int32_t fixed_iters;   /* > 0: run exactly this many iterations, ignore tol        */
+    int32_t precision;     /* PARAPN_FP64 or PARAPN_FP32_SQRT                          */
+    const double *init_traj; /* host [N+1][D] starting trajectory in original
+                              * coordinates, or NULL for the constant mu0 of Alg. 2  */
+} parapn_problem;
+
+typedef struct {
+    int32_t iterations;     /* linearise+smooth passes run (including the last one)   */
+    int32_t converged;      /* 1 when the stopping test passed                        */
+    double final_delta;     /* delta of the last pass                                 */
+    double tol_used;        /* the threshold actually applied                         */
+    double *delta_history;  /* host, max_iter entries, may be NULL                    */
+} parapn_info;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * workspace the context may hold (0 = no bound).  The context caches the
+ * workspace between solves; it is not thread-safe (one context per thread). */
+int parapn_create(parapn_ctx **ctx, int device, size_t hbm_budget_bytes);
+void parapn_destroy(parapn_ctx *ctx);
+
+/* Device workspace a solve of this problem needs, in bytes. */
+int parapn_workspace_size(const parapn_problem *prob, size_t *bytes);
+
+/* ParaIEKS, Alg. 2.
+ * mean_out:    device [N+1][D], original coordinates; row 0 is mu0.
+ * sqrtcov_out: device [N+1][D][D] lower-triangular factors of Sigma_n in
+ *              original coordinates (row 0 is zero), or NULL.
+ * The user-facing solution is E0 mu_n and E0 Sigma_n E0^T (the entries k with
+ * k % (q+1) == 0).
+ * Convergence test: delta_k = max_n max_i |E0 (mu_n^(k) - mu_n^(k-1))|_i in
+ * original coordinates, accumulated in double; PARAPN_FP64 stops when
+ * delta_k < tol, PARAPN_FP32_SQRT when delta_k < max(tol, 2^-20 max_n |E0 mu_n|).
+ * Returns PARAPN_OK, PARAPN_MAXITER, or an error.  Synchronises the stream once
+ * per iteration (8-byte read of delta_k). */
+int parapn_solve(parapn_ctx *ctx, const parapn_problem *prob, void *mean_out, void *sqrtcov_out,
+                 parapn_info *info, void *stream);
+
+/* ParaRTS, Alg. 1, on a linear model (eq. affine-estimation) with constant
+ * transition:  Y0 ~ N(mu0, S0 S0^T),  Y_n = Phi Y_{n-1} + w_n, w_n ~ N(0, sqrtQ sqrtQ^T),
+ * and noiseless affine observations H_n Y_n = dvec_n, n = 1..N.
+ * Inputs (device): mu0 [D], sqrt_sigma0 [D][D], Phi [D][D], sqrtQ [D][D],
+ * H [N][dobs][D], dvec [N][dobs].  1 <= dobs < D <= PARAPN_MAX_D.
+ * Outputs (device): smoothed mean [N+1][D] and factors [N+1][D][D] (or NULL),
+ * filtered mean [N+1][D] and factors [N+1][D][D] (either may be NULL); row 0
+ * of the filtered outputs is (mu0, sqrt_sigma0), row 0 of the smoothed ones
+ * is conditioned on all data. */
+int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                   const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
+                   void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream);
+
+/* Batched square-root filtering operator (eq. sqrt-associative-filtering):
+ * out_k = a_k (x)_f c_k for k < count, a earlier than c.  Each element is the
+ * tuple (A [D][D], b [D], sqrtC [D][D], eta [D], sqrtJ [D][D]) stored
+ * contiguously as 3D^2 + 2D values in that order; arrays are [count][3D^2+2D]
+ * on the device.  sqrtC and sqrtJ need not be triangular; the outputs are
+ * lower-triangular with non-negative diagonal. */
+int parapn_filter_combine(parapn_ctx *ctx, int32_t D, int64_t count, int32_t precision, const void *a,
+                          const void *c, void *out, void *stream);
+
+/* Per-kernel timing for measurement tools (not needed to solve).  While
+ * enabled, every solver kernel launch is bracketed by two HIP events recorded
+ * on the launch stream; parapn_profile_read waits for them and returns, per
+ * kernel name, the summed elapsed milliseconds and the launch count.
+ * Enabling (or disabling) clears the counters.  Process-wide; not thread-safe.
+ * names receives up to max NUL-terminated names of name_len bytes each;
+ * *n_out is the number of distinct kernels seen (may exceed max). */
+int parapn_profile_enable(int on);
+int parapn_profile_read(int32_t max, char *names, int32_t name_len, double *total_ms, int64_t *launches,
+                        int32_t *n_out);
+
+const char *parapn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

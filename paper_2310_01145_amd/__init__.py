@@ -1,0 +1,271 @@
+"""parapn: parallel-in-time probabilistic numerical ODE solver (ParaIEKS) on MI355X.
+
+Thin Python binding over the C ABI of ``libparapn.so`` (include/parapn.h).
+It only marshals arguments: PyTorch provides device memory and the current
+HIP stream; every step of the solver runs in the library's HIP kernels.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparapn.so")
+
+OK, MAXITER, EINVAL, ENOMEM, EDEVICE, ENONFINITE = 0, 1, -1, -2, -3, -4
+FP64, FP32_SQRT = 0, 1
+
+FIELDS = {
+    "logistic": 0,
+    "fhn": 1,
+    "lorenz": 2,
+    "lotka_volterra": 3,
+    "affine": 5,
+    "rigid_body": 6,
+    "van_der_pol": 7,
+}
+FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
+PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
+EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_pararts",
+            "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_read", "parapn_last_error"]
+
+
+class ParapnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("parapn error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("field", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("params", ctypes.POINTER(ctypes.c_double)),
+        ("n_params", ctypes.c_int32),
+        ("y0", ctypes.POINTER(ctypes.c_double)),
+        ("t0", ctypes.c_double),
+        ("t1", ctypes.c_double),
+        ("q", ctypes.c_int32),
+        ("N", ctypes.c_int64),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("fixed_iters", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("init_traj", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("final_delta", ctypes.c_double),
+        ("tol_used", ctypes.c_double),
+        ("delta_history", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+_lib = None
+_ctx = {}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libparapn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libparapn.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2310_01145_amd.build)")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.parapn_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, sz]
+    L.parapn_create.restype = ctypes.c_int
+    L.parapn_destroy.argtypes = [vp]
+    L.parapn_destroy.restype = None
+    L.parapn_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz)]
+    L.parapn_workspace_size.restype = ctypes.c_int
+    L.parapn_solve.argtypes = [vp, ctypes.POINTER(Problem), vp, vp, ctypes.POINTER(Info), vp]
+    L.parapn_solve.restype = ctypes.c_int
+    L.parapn_pararts.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.parapn_pararts.restype = ctypes.c_int
+    L.parapn_filter_combine.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
+    L.parapn_filter_combine.restype = ctypes.c_int
+    L.parapn_profile_enable.argtypes = [ctypes.c_int]
+    L.parapn_profile_enable.restype = ctypes.c_int
+    L.parapn_profile_read.argtypes = [i32, ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+    L.parapn_profile_read.restype = ctypes.c_int
+    L.parapn_last_error.argtypes = []
+    L.parapn_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load_library().parapn_last_error().decode()
+
+
+def _check(rc, allow=(OK,)):
+    if rc not in allow:
+        raise ParapnError(rc, last_error())
+    return rc
+
+
+def context(device: int = 0, budget: int = 0):
+    key = (device, budget)
+    if key not in _ctx:
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.parapn_create(ctypes.byref(h), device, budget))
+        _ctx[key] = h
+    return _ctx[key]
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype(precision):
+    torch = _torch()
+    return torch.float64 if precision == FP64 else torch.float32
+
+
+def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
+                 init_traj=None, d=None):
+    """Build the ctypes Problem (keeps the host arrays alive on the object)."""
+    fid = FIELDS[field] if isinstance(field, str) else int(field)
+    y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
+    prm = np.ascontiguousarray(np.asarray(params if params is not None else [], dtype=np.float64).ravel())
+    pb = Problem()
+    pb.field = fid
+    pb.d = int(d if d is not None else y0.size)
+    pb.params = prm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if prm.size else None
+    pb.n_params = prm.size
+    pb.y0 = y0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    pb.t0, pb.t1 = float(t0), float(t1)
+    pb.q = int(q)
+    pb.N = int(N)
+    pb.tol = float(tol)
+    pb.max_iter = int(max_iter)
+    pb.fixed_iters = int(fixed_iters)
+    pb.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    keep = [y0, prm]
+    if init_traj is not None:
+        it = np.ascontiguousarray(np.asarray(init_traj, dtype=np.float64))
+        pb.init_traj = it.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep.append(it)
+    else:
+        pb.init_traj = None
+    pb._keep = keep
+    return pb
+
+
+def workspace_size(problem: Problem) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().parapn_workspace_size(ctypes.byref(problem), ctypes.byref(n)))
+    return n.value
+
+
+def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
+          init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None):
+    """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
+    (original coordinates, torch tensor on the device), ``sqrtcov``
+    [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
+    ``converged``, ``tol_used``."""
+    torch = _torch()
+    L = load_library()
+    pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
+                      fixed_iters=fixed_iters, init_traj=init_traj, d=d)
+    D = pb.d * (pb.q + 1)
+    dt = _dtype(pb.precision)
+    dev = torch.device("cuda", device)
+    if out is not None:
+        mean, cov = out
+    else:
+        mean = torch.empty((pb.N + 1, D), dtype=dt, device=dev)
+        cov = torch.empty((pb.N + 1, D, D), dtype=dt, device=dev) if want_cov else None
+    hist = np.zeros(max(pb.max_iter, pb.fixed_iters, 1))
+    info = Info()
+    info.delta_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = L.parapn_solve(context(device), ctypes.byref(pb), _dptr(mean), _dptr(cov), ctypes.byref(info),
+                        _stream_handle(stream))
+    _check(rc, allow=(OK, MAXITER, ENONFINITE))
+    k = info.iterations
+    return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy(),
+            "converged": bool(info.converged), "tol_used": info.tol_used, "final_delta": info.final_delta}
+
+
+def pararts(mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, *, precision="fp64", want_cov=True, want_filter=True,
+            device=0, stream=None):
+    """ParaRTS (Alg. 1) on a linear model with noiseless observations
+    H_n Y_n = dvec_n.  Inputs are torch tensors on the device with the dtype
+    of the precision; H is [N, dobs, D], dvec [N, dobs]."""
+    torch = _torch()
+    L = load_library()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    dt = _dtype(prec)
+    ins = [x.to(dtype=dt).contiguous() for x in (mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec)]
+    N, dobs, D = ins[4].shape
+    dev = ins[0].device
+    ms = torch.empty((N + 1, D), dtype=dt, device=dev)
+    sPs = torch.empty((N + 1, D, D), dtype=dt, device=dev) if want_cov else None
+    mf = torch.empty((N + 1, D), dtype=dt, device=dev) if want_filter else None
+    sPf = torch.empty((N + 1, D, D), dtype=dt, device=dev) if want_filter else None
+    _check(L.parapn_pararts(context(device), D, dobs, N, prec, *[_dptr(x) for x in ins], _dptr(ms), _dptr(sPs),
+                            _dptr(mf), _dptr(sPf), _stream_handle(stream)))
+    return {"mean": ms, "sqrtcov": sPs, "filt_mean": mf, "filt_sqrtcov": sPf}
+
+
+def filter_combine(a, c, *, precision="fp64", device=0, stream=None):
+    """Batched square-root filtering operator: rows of a and c are packed
+    elements (A, b, sqrtC, eta, sqrtJ) of 3D^2+2D values each."""
+    torch = _torch()
+    L = load_library()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    dt = _dtype(prec)
+    a = a.to(dtype=dt).contiguous()
+    c = c.to(dtype=dt).contiguous()
+    count, rec = a.shape
+    D = int(round((-2 + (4 + 12 * rec) ** 0.5) / 6))
+    assert 3 * D * D + 2 * D == rec, "bad record size"
+    out = torch.empty_like(a)
+    _check(L.parapn_filter_combine(context(device), D, count, prec, _dptr(a), _dptr(c), _dptr(out),
+                                   _stream_handle(stream)))
+    return out
+
+
+def profile_enable(on: bool = True):
+    """Start (or stop) per-kernel event timing; clears previous counters."""
+    _check(load_library().parapn_profile_enable(1 if on else 0))
+
+
+def profile_read(max_kernels: int = 64):
+    """{kernel name: (total ms, launches)} since profile_enable."""
+    L = load_library()
+    name_len = 64
+    names = ctypes.create_string_buffer(max_kernels * name_len)
+    tot = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int64 * max_kernels)()
+    n = ctypes.c_int32()
+    _check(L.parapn_profile_read(max_kernels, names, name_len, tot, cnt, ctypes.byref(n)))
+    out = {}
+    for k in range(min(n.value, max_kernels)):
+        nm = names.raw[k * name_len:(k + 1) * name_len].split(b"\0", 1)[0].decode()
+        out[nm] = (tot[k], cnt[k])
+    return out

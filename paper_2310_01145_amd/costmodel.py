@@ -1,0 +1,82 @@
+"""Algorithmic work per step for each kernel of one ParaIEKS iteration.
+
+Flops count a multiply-add as 2.  The counts follow the formulas each kernel
+evaluates (Householder tria of an nr x nc stack, dense products, triangular
+solves), not the instructions the lanes issue: work a kernel repeats for
+SIMD uniformity (e.g. updating already-finished rows in tria) is excluded.
+Bytes are the compulsory HBM traffic of the kernel's inputs and outputs.
+"""
+from __future__ import annotations
+
+
+def tria(nr, nc):
+    """Householder LQ of an nr x nc matrix: reflection k forms its vector
+    from row k (2(nc-k)) and updates the rows below it (4(nc-k) each)."""
+    f = 0
+    for k in range(min(nr, nc)):
+        f += 2 * (nc - k) + 4 * (nc - k) * (nr - k - 1)
+    return f
+
+
+def mm(n, k, m):
+    return 2 * n * k * m
+
+
+def trsolve(rows, n):
+    return rows * n * n
+
+
+def obs_setup(D, d):
+    return mm(d, D, D) + 4 * d * d  # H Phi and the linearised data
+
+
+def filter_element(D, d):
+    return (mm(d, D, D) + tria(d + D, D) + trsolve(D, d) + mm(D, d, D) + 2 * D * d + trsolve(D, d) + d * d
+            + 2 * D * d)
+
+
+def filter_combine(D):
+    return (mm(D, D, D) + tria(2 * D, 2 * D) + trsolve(D, D) + mm(D, D, D) + 4 * D * D + 2 * mm(D, D, D)
+            + 8 * D * D + mm(D, D, D) + tria(D, 2 * D) + 2 * D * D + mm(D, D, D) + tria(D, 2 * D))
+
+
+def state_apply(D):
+    return (mm(D, D, D) + tria(2 * D, 2 * D) + trsolve(D, D) + mm(D, D, D) + 2 * D * D + mm(D, D, D)
+            + 4 * D * D + mm(D, D, D) + tria(D, 2 * D))
+
+
+def kf_step(D, d):
+    return (mm(D, D, D) + 2 * D * D + tria(D, 2 * D) + mm(d, D, D) + tria(d + D, D) + 2 * d * D + trsolve(D, d)
+            + 2 * D * d)
+
+
+def smoother_element(D):
+    return mm(D, D, D) + 2 * D * D + tria(2 * D, 2 * D) + trsolve(D, D) + 2 * D * D
+
+
+def smoother_combine(D, with_cov=False):
+    return mm(D, D, D) + 2 * D * D + ((mm(D, D, D) + tria(D, 2 * D)) if with_cov else 0)
+
+
+def smoother_apply(D, with_cov=False):
+    return 2 * D * D + ((mm(D, D, D) + tria(D, 2 * D)) if with_cov else 0)
+
+
+def per_step(d, q, esize, b1=8):
+    """{kernel: (flops per step, bytes per step)} for a means-only iteration."""
+    D = d * (q + 1)
+    DP = D * (D + 1) // 2
+    FE, FS, SE, SA = 3 * D * D + 2 * D, D + D * D, D * D + D, 2 * D * D + D
+    s = esize
+    return {
+        "fwd_reduce1": (obs_setup(D, d) + filter_element(D, d) + filter_combine(D) * (b1 - 1) / b1,
+                        s * (d + FE / b1)),
+        "fwd_down1": (obs_setup(D, d) + kf_step(D, d), s * (d + FS / b1 + D + DP)),
+        "smoother_elements": (smoother_element(D), s * (D + DP + SE)),
+        "bwd_reduce1": (smoother_combine(D) * (b1 - 1) / b1, s * (SE + SA / b1)),
+        "bwd_down1": (smoother_apply(D), s * (SE + 2 * D + FS / b1)),
+    }
+
+
+def iteration_flops(d, q, b1=8):
+    return sum(v[0] for v in per_step(d, q, 4, b1).values())

@@ -1,0 +1,1535 @@
+// ParaRTS (Alg. 1) and the per-iteration work of ParaIEKS (Alg. 2) on gfx950.
+//
+// One group of R lanes (R = next power of two >= 2D) owns one element of the
+// scan; lane r holds row r of every D x D block (rowalg.h).  The associative
+// scans are hierarchical reduce-then-scan:
+//   step level   each group folds b1 consecutive elements, built on the fly,
+//                into one aggregate (the paper's operators);
+//   upper levels groups fold bu aggregates at a time until at most btop
+//                remain, which one group scans sequentially from the initial
+//                state; prefix states then flow back down;
+//   step level   each group walks its b1 steps again from its exclusive prefix
+//                state and writes the per-step marginals.
+// Every exclusive prefix of the filtering scan is a Gaussian state (A = 0,
+// eta = 0, J = 0: it does not depend on an earlier state), so prefix states
+// are stored as (mean, factor) only, and applying a state to the next element
+// is the filtering operator with those zeros substituted -- which is exactly a
+// Kalman predict + update step.  Suffixes of the smoothing scan always contain
+// the last element (E_N = 0), so suffix states are (mean, factor) as well.
+#include <hip/hip_runtime.h>
+
+#include "fields.h"
+#include "parapn_internal.h"
+#include "rowalg.h"
+
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace parapn {
+
+template <typename T_, int d_, int q_>
+struct Cfg {
+    using T = T_;
+    static constexpr int d = d_, q = q_, S = q_ + 1, D = d_ * (q_ + 1);
+    static constexpr int D2 = 2 * D;
+    static constexpr int DP = D * (D + 1) / 2;
+    static constexpr int R = pow2ceil(D2);  // lanes per group
+    static constexpr int LDM = D + 1;       // LDS row stride of D-wide blocks
+    static constexpr int LDB = D2 + 1;      // LDS row stride of 2D-wide blocks
+    // per-group LDS layout (in T units)
+    static constexpr int TR = 0;
+    static constexpr int BIG = TR + 2 * (D2 + 1);
+    static constexpr int M0 = BIG + D2 * LDB;
+    static constexpr int M1 = M0 + D * LDM;
+    static constexpr int M2 = M1 + D * LDM;
+    static constexpr int M3 = M2 + D * LDM;
+    static constexpr int M4 = M3 + D * LDM;
+    static constexpr int M5 = M4 + D * LDM;
+    static constexpr int V0 = M5 + D * LDM;
+    static constexpr int V1 = V0 + LDM;
+    static constexpr int V2 = V1 + LDM;
+    static constexpr int V3 = V2 + LDM;
+    static constexpr int V4 = V3 + LDM;
+    static constexpr int V5 = V4 + LDM;
+    static constexpr int HO = V5 + LDM;   // H   (d x LDM)
+    static constexpr int HPO = HO + d * LDM;  // H Phi (d x LDM)
+    static constexpr int DVO = HPO + d * LDM; // d (d)
+    static constexpr int SH = DVO + d + 1;
+    // block: groups per block chosen so that a block's LDS stays <= 64 KiB
+    static constexpr int GPB_MAX = 256 / R;
+    static constexpr int GPB_FIT = (65536 / (int)sizeof(T) - 2 * D * LDM) / SH;
+    static constexpr int GPB = GPB_FIT >= GPB_MAX ? GPB_MAX : (GPB_FIT >= 8 ? 8 : (GPB_FIT >= 4 ? 4 : (GPB_FIT >= 2 ? 2 : 1)));
+    static constexpr int NT = GPB * R;
+    // record sizes (T units)
+    static constexpr int FE = 3 * D * D + 2 * D;  // filter element / aggregate: A, b, sqrtC, eta, sqrtJ
+    static constexpr int FS = D + D * D;          // filter state: mean, factor
+    static constexpr int SE = D * D + D;          // smoothing element (E, g)
+    static constexpr int SA = 2 * D * D + D;      // smoothing aggregate: E, g, sqrtL
+    static constexpr int SS = D + D * D;          // smoother state: mean, factor
+    static_assert(R <= 64, "a group must fit in one wavefront");
+};
+
+// ---------------------------------------------------------------------------
+// record <-> row registers
+// ---------------------------------------------------------------------------
+template <class C>
+struct FRow {
+    using T = typename C::T;
+    T A[C::D];
+    T b;
+    T sC[C::D];
+    T eta;
+    T sJ[C::D];
+};
+
+template <class C>
+struct SRow {  // a (mean, factor) row: filter/smoother state
+    using T = typename C::T;
+    T m;
+    T P[C::D];
+};
+
+template <class C>
+struct ERow {  // smoothing element / aggregate row
+    using T = typename C::T;
+    T E[C::D];
+    T g;
+    T L[C::D];
+};
+
+template <class C>
+PARAPN_DEV void zero(FRow<C> &e)
+{
+#pragma unroll
+    for (int c = 0; c < C::D; ++c) e.A[c] = e.sC[c] = e.sJ[c] = 0;
+    e.b = e.eta = 0;
+}
+
+template <class C>
+PARAPN_DEV FRow<C> load_frow(const typename C::T *rec, int r)
+{
+    constexpr int D = C::D;
+    FRow<C> e;
+    zero(e);
+    if (r < D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            e.A[c] = rec[r * D + c];
+            e.sC[c] = rec[D * D + D + r * D + c];
+            e.sJ[c] = rec[2 * D * D + 2 * D + r * D + c];
+        }
+        e.b = rec[D * D + r];
+        e.eta = rec[2 * D * D + D + r];
+    }
+    return e;
+}
+
+template <class C>
+PARAPN_DEV void store_frow(typename C::T *rec, int r, const FRow<C> &e)
+{
+    constexpr int D = C::D;
+    if (r < D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            rec[r * D + c] = e.A[c];
+            rec[D * D + D + r * D + c] = e.sC[c];
+            rec[2 * D * D + 2 * D + r * D + c] = e.sJ[c];
+        }
+        rec[D * D + r] = e.b;
+        rec[2 * D * D + D + r] = e.eta;
+    }
+}
+
+template <class C>
+PARAPN_DEV SRow<C> load_state(const typename C::T *rec, int r)
+{
+    constexpr int D = C::D;
+    SRow<C> s;
+    s.m = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) s.P[c] = 0;
+    if (r < D) {
+        s.m = rec[r];
+#pragma unroll
+        for (int c = 0; c < D; ++c) s.P[c] = rec[D + r * D + c];
+    }
+    return s;
+}
+
+template <class C>
+PARAPN_DEV void store_state(typename C::T *rec, int r, const SRow<C> &s)
+{
+    constexpr int D = C::D;
+    if (r < D) {
+        rec[r] = s.m;
+#pragma unroll
+        for (int c = 0; c < D; ++c) rec[D + r * D + c] = s.P[c];
+    }
+}
+
+// packed lower-triangular rows: row r occupies [r(r+1)/2, r(r+1)/2 + r]
+template <class C>
+PARAPN_DEV void load_packed(typename C::T (&v)[C::D], const typename C::T *p, int r)
+{
+#pragma unroll
+    for (int c = 0; c < C::D; ++c) v[c] = 0;
+    if (r < C::D) {
+        const typename C::T *row = p + r * (r + 1) / 2;
+#pragma unroll
+        for (int c = 0; c < C::D; ++c)
+            if (c <= r) v[c] = row[c];
+    }
+}
+
+template <class C>
+PARAPN_DEV void store_packed(typename C::T *p, int r, const typename C::T (&v)[C::D])
+{
+    if (r < C::D) {
+        typename C::T *row = p + r * (r + 1) / 2;
+#pragma unroll
+        for (int c = 0; c < C::D; ++c)
+            if (c <= r) row[c] = v[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the observation of one step, placed in the group's LDS:
+//   H (d x D), H Phi (d x D), d (d)
+// ---------------------------------------------------------------------------
+template <class C>
+struct ObsDev {
+    using T = typename C::T;
+    int mode;
+    const T *traj;
+    int field;
+    T p[kMaxParams];
+    T T0, invT1, hq;
+    const T *H;
+    const T *dv;
+};
+
+template <class C>
+PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T *sh, const typename C::T *cphi)
+{
+    using T = typename C::T;
+    constexpr int d = C::d, D = C::D, S = C::S, LDM = C::LDM;
+    T hrow[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) hrow[c] = 0;
+    T dval = 0;
+    if (o.mode == 0) {
+        // EK1 at the trajectory (Sec. 3.2.1), preconditioned and row-scaled:
+        //   Hbar = E1 - (h/q) F_y E0,   dbar = (f(y) - F_y y) / T1,   y = T0 E0 traj_n
+        const T *tn = o.traj + n * D;
+        Dual<T, d> yd[d], fd[d];
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+            yd[i].v = o.T0 * tn[i * S];
+#pragma unroll
+            for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? T(1) : T(0);
+        }
+        field_eval<d>(o.field, o.p, yd, fd);
+#pragma unroll
+        for (int i = 0; i < d; ++i)
+            if (lane == i) {
+                T acc = fd[i].v;
+#pragma unroll
+                for (int j = 0; j < d; ++j) {
+                    acc -= fd[i].g[j] * yd[j].v;
+                    hrow[j * S] -= o.hq * fd[i].g[j];
+                }
+                hrow[i * S + 1] += T(1);
+                dval = acc * o.invT1;
+            }
+    } else if (lane < d) {
+        const T *hr = o.H + ((n - 1) * d + lane) * D;
+#pragma unroll
+        for (int c = 0; c < D; ++c) hrow[c] = hr[c];
+        dval = o.dv[(n - 1) * d + lane];
+    }
+    if (lane < d) {
+        T hp[D];
+        row_times<T, D, D>(hp, hrow, cphi, LDM);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            sh[C::HO + lane * LDM + c] = hrow[c];
+            sh[C::HPO + lane * LDM + c] = hp[c];
+        }
+        sh[C::DVO + lane] = dval;
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// square-root filtering element of a step n >= 1 with m_{n-1} = 0,
+// P_{n-1} = 0 (eq. sqrt-filtering-elements, sqrt R = 0):
+//   Psi = tria([[H sqrtQ], [sqrtQ]]),  K = Psi21 Psi11^{-1},
+//   A = (I - K H) Phi,  b = K d,  sqrtC = Psi22,
+//   sqrtJ = Phi^T H^T Psi11^{-T} (D x d, zero padded),  eta = sqrtJ Psi11^{-1} d.
+// The initial distribution is not folded in here: it enters the scan as the
+// exclusive prefix state of step 1.
+// ---------------------------------------------------------------------------
+template <class C>
+PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C::T *cphi, const typename C::T *csq)
+{
+    using T = typename C::T;
+    constexpr int d = C::d, D = C::D, LDM = C::LDM, LDB = C::LDB;
+    T w[D];
+    if (lane < d) {
+        T hrow[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) hrow[c] = sh[C::HO + lane * LDM + c];
+        row_times<T, D, D>(w, hrow, csq, LDM);
+    } else if (lane < d + D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[c] = csq[(lane - d) * LDM + c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[c] = 0;
+    }
+    tria_rows<T, d + D, D>(w, lane, sh + C::TR);
+    T *Psi = sh + C::BIG;
+    put_rows<T, d + D, D>(Psi, LDB, lane, w);
+    wave_sync();
+    FRow<C> e;
+    zero(e);
+    if (lane < D) {
+        const T *HP = sh + C::HPO;
+        const T *dv = sh + C::DVO;
+        T p21[d], K[d], hpc[d], x[d], dvv[d], u[d];
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+            p21[i] = Psi[(d + lane) * LDB + i];
+            hpc[i] = HP[i * LDM + lane];
+            dvv[i] = dv[i];
+        }
+        solve_xL<T, d>(K, p21, Psi, LDB);
+        T b = 0;
+#pragma unroll
+        for (int i = 0; i < d; ++i) b += K[i] * dvv[i];
+        e.b = b;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            T a = cphi[lane * LDM + c];
+#pragma unroll
+            for (int i = 0; i < d; ++i) a -= K[i] * HP[i * LDM + c];
+            e.A[c] = a;
+            e.sC[c] = (c < D - d) ? Psi[(d + lane) * LDB + d + c] : T(0);
+        }
+        solve_xLt<T, d>(x, hpc, Psi, LDB);
+        solve_xLt<T, d>(u, dvv, Psi, LDB);
+        T et = 0;
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+            e.sJ[i] = x[i];
+            et += x[i] * u[i];
+        }
+        e.eta = et;
+    }
+    wave_sync();
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// filtering operator a_i (x)_f a_j (eq. sqrt-associative-filtering), with
+//   Xi = tria([[sqrtC_i^T sqrtJ_j, I], [sqrtJ_j, 0]]),
+//   G = sqrtC_i Xi11^{-T},  F = I - G Xi21^T:
+//   A_ij = A_j F A_i,  b_ij = A_j F (b_i + sqrtC_i sqrtC_i^T eta_j) + b_j,
+//   sqrtC_ij = tria([A_j G, sqrtC_j]),
+//   eta_ij = A_i^T F^T (eta_j - sqrtJ_j sqrtJ_j^T b_i) + eta_i,
+//   sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i]).
+// (F^T = I - Xi21 Xi11^{-1} sqrtC_i^T, the factor of the eta formula.)
+// ---------------------------------------------------------------------------
+template <class C, bool STATE_ONLY>
+PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sCi)[C::D],
+                           const typename C::T (&sJj)[C::D], typename C::T (&G)[C::D], typename C::T (&F)[C::D])
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    T *M0 = sh + C::M0, *M1 = sh + C::M1;
+    put_rows<T, D, D>(M0, LDM, lane, sCi);
+    put_rows<T, D, D>(M1, LDM, lane, sJj);
+    wave_sync();
+    T w[D2];
+    if (lane < D) {
+        T t[D];
+        rowT_times<T, D, D>(t, lane, M0, LDM, M1, LDM);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = t[c];
+            w[D + c] = (c == lane) ? T(1) : T(0);
+        }
+    } else if (lane < D2) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = M1[(lane - D) * LDM + c];
+            w[D + c] = 0;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < D2; ++c) w[c] = 0;
+    }
+    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
+    T *Xi = sh + C::BIG;
+    put_rows<T, D2, D2>(Xi, LDB, lane, w);
+    wave_sync();
+    // G row = sqrtC_i row * Xi11^{-T}
+    solve_xLt<T, D>(G, sCi, Xi, LDB);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        T f = (c == lane) ? T(1) : T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) f -= G[k] * Xi[(D + c) * LDB + k];
+        F[c] = f;
+    }
+}
+
+template <class C>
+PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei, const FRow<C> &ej)
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    T G[D], F[D];
+    xi_and_G_F<C, false>(lane, sh, ei.sC, ej.sJ, G, F);
+    T *M0 = sh + C::M0, *M1 = sh + C::M1, *M2 = sh + C::M2, *M3 = sh + C::M3, *M4 = sh + C::M4;
+    T *V0 = sh + C::V0, *V1 = sh + C::V1, *V2 = sh + C::V2, *V3 = sh + C::V3, *V4 = sh + C::V4, *V5 = sh + C::V5;
+    const T *Xi = sh + C::BIG;
+    // vectors: wv = sqrtC_i^T eta_j, u = sqrtJ_j^T b_i   (M0 = sqrtC_i, M1 = sqrtJ_j)
+    if (lane < D) {
+        V0[lane] = ej.eta;
+        V1[lane] = ei.b;
+    }
+    put_rows<T, D, D>(M2, LDM, lane, F);
+    put_rows<T, D, D>(M3, LDM, lane, ei.A);
+    put_rows<T, D, D>(M4, LDM, lane, G);
+    wave_sync();
+    if (lane < D) {
+        T wv = 0, uu = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            wv += M0[k * LDM + lane] * V0[k];
+            uu += M1[k * LDM + lane] * V1[k];
+        }
+        V2[lane] = wv;
+        V3[lane] = uu;
+    }
+    wave_sync();
+    FRow<C> o;
+    zero(o);
+    T ajf[D];
+    row_times<T, D, D>(ajf, ej.A, M2, LDM);  // A_j F
+    if (lane < D) {
+        // v = b_i + sqrtC_i wv ;  z = eta_j - sqrtJ_j u
+        T v = ei.b, z = ej.eta;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            v += ei.sC[c] * V2[c];
+            z -= ej.sJ[c] * V3[c];
+        }
+        V4[lane] = v;
+        V5[lane] = z;
+    }
+    wave_sync();
+    if (lane < D) {
+        row_times<T, D, D>(o.A, ajf, M3, LDM);  // A_j F A_i
+        T bb = ej.b;
+        T y = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            bb += ajf[k] * V4[k];
+            y += M2[k * LDM + lane] * V5[k];  // (F^T z)_lane
+        }
+        o.b = bb;
+        V0[lane] = y;  // eta_j no longer needed
+    }
+    wave_sync();
+    // sqrtC_ij = tria([A_j G, sqrtC_j])
+    {
+        T w[D2];
+        if (lane < D) {
+            T t[D];
+            row_times<T, D, D>(t, ej.A, M4, LDM);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                w[c] = t[c];
+                w[D + c] = ej.sC[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < D2; ++c) w[c] = 0;
+        }
+        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.sC[c] = lane < D ? w[c] : T(0);
+    }
+    // eta_ij = A_i^T y + eta_i
+    if (lane < D) {
+        T et = ei.eta;
+#pragma unroll
+        for (int k = 0; k < D; ++k) et += M3[k * LDM + lane] * V0[k];
+        o.eta = et;
+    }
+    // sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i])
+    {
+        T w[D2];
+        if (lane < D) {
+            T t[D];
+            rowT_times<T, D, D>(t, lane, M3, LDM, Xi + D * LDB + D, LDB);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                w[c] = t[c];
+                w[D + c] = ei.sJ[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < D2; ++c) w[c] = 0;
+        }
+        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.sJ[c] = lane < D ? w[c] : T(0);
+    }
+    wave_sync();
+    return o;
+}
+
+// state (mean m, factor P) followed by aggregate a_j: the filtering operator
+// with A_i = 0, eta_i = 0, sqrtJ_i = 0; returns the new (b_ij, sqrtC_ij).
+template <class C>
+PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, const FRow<C> &ej)
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM;
+    T G[D], F[D];
+    xi_and_G_F<C, true>(lane, sh, s.P, ej.sJ, G, F);
+    T *M0 = sh + C::M0, *M2 = sh + C::M2, *M4 = sh + C::M4;
+    T *V0 = sh + C::V0, *V2 = sh + C::V2, *V4 = sh + C::V4;
+    if (lane < D) V0[lane] = ej.eta;
+    put_rows<T, D, D>(M2, LDM, lane, F);
+    put_rows<T, D, D>(M4, LDM, lane, G);
+    wave_sync();
+    if (lane < D) {
+        T wv = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) wv += M0[k * LDM + lane] * V0[k];
+        V2[lane] = wv;
+    }
+    wave_sync();
+    T ajf[D];
+    row_times<T, D, D>(ajf, ej.A, M2, LDM);
+    if (lane < D) {
+        T v = s.m;
+#pragma unroll
+        for (int c = 0; c < D; ++c) v += s.P[c] * V2[c];
+        V4[lane] = v;
+    }
+    wave_sync();
+    SRow<C> o;
+    o.m = 0;
+    if (lane < D) {
+        T bb = ej.b;
+#pragma unroll
+        for (int k = 0; k < D; ++k) bb += ajf[k] * V4[k];
+        o.m = bb;
+    }
+    T w[D2];
+    if (lane < D) {
+        T t[D];
+        row_times<T, D, D>(t, ej.A, M4, LDM);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = t[c];
+            w[D + c] = ej.sC[c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < D2; ++c) w[c] = 0;
+    }
+    tria_rows<T, D, D2>(w, lane, sh + C::TR);
+#pragma unroll
+    for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
+    return o;
+}
+
+// Kalman predict + update from a state: the same quantity as state_apply
+// with the step's own element, computed without forming the element:
+//   m- = Phi m,  sqrtP- = tria([Phi sqrtP, sqrtQ]),
+//   Psi = tria([[H sqrtP-], [sqrtP-]]),  K = Psi21 Psi11^{-1},
+//   m = m- + K (d - H m-),  sqrtP = Psi22.
+template <class C>
+PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
+                          const typename C::T *csq)
+{
+    using T = typename C::T;
+    constexpr int d = C::d, D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    T *M0 = sh + C::M0, *M1 = sh + C::M1, *V0 = sh + C::V0, *V1 = sh + C::V1;
+    put_rows<T, D, D>(M0, LDM, lane, s.P);
+    if (lane < D) V0[lane] = s.m;
+    wave_sync();
+    T mp = 0;
+    T w[D2];
+    if (lane < D) {
+        T phirow[D], t[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) phirow[k] = cphi[lane * LDM + k];
+        row_times<T, D, D>(t, phirow, M0, LDM);
+#pragma unroll
+        for (int k = 0; k < D; ++k) mp += phirow[k] * V0[k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = t[c];
+            w[D + c] = csq[lane * LDM + c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < D2; ++c) w[c] = 0;
+    }
+    tria_rows<T, D, D2>(w, lane, sh + C::TR);
+    // w[0..D-1] of lanes < D: sqrtP-
+    T pm[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) pm[c] = w[c];
+    put_rows<T, D, D>(M1, LDM, lane, pm);
+    if (lane < D) V1[lane] = mp;
+    wave_sync();
+    T x[D];
+    if (lane < d) {
+        T hrow[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) hrow[c] = sh[C::HO + lane * LDM + c];
+        row_times<T, D, D>(x, hrow, M1, LDM);
+    } else if (lane < d + D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = M1[(lane - d) * LDM + c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = 0;
+    }
+    tria_rows<T, d + D, D>(x, lane, sh + C::TR);
+    T *Psi = sh + C::BIG;
+    put_rows<T, d + D, D>(Psi, LDB, lane, x);
+    wave_sync();
+    SRow<C> o;
+    o.m = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) o.P[c] = 0;
+    if (lane < D) {
+        T res[d], p21[d], K[d];
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+            T r = sh[C::DVO + i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) r -= sh[C::HO + i * LDM + k] * V1[k];
+            res[i] = r;
+            p21[i] = Psi[(d + lane) * LDB + i];
+        }
+        solve_xL<T, d>(K, p21, Psi, LDB);
+        T m = mp;
+#pragma unroll
+        for (int i = 0; i < d; ++i) m += K[i] * res[i];
+        o.m = m;
+#pragma unroll
+        for (int c = 0; c < D - d; ++c) o.P[c] = Psi[(d + lane) * LDB + d + c];
+    }
+    wave_sync();
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// smoothing side (eq. sqrt-smoothing-elements, eq. sqrt-associative-smoothing)
+// ---------------------------------------------------------------------------
+// element of a step n < N from the filtering marginal (m^f_n, sqrtP^f_n):
+//   Pi = tria([[Phi sqrtP^f, sqrtQ], [sqrtP^f, 0]]),
+//   E = Pi21 Pi11^{-1},  g = m^f - E Phi m^f,  sqrtL = Pi22.
+template <class C>
+PARAPN_DEV ERow<C> smoother_element(int lane, typename C::T *sh, const SRow<C> &f, const typename C::T *cphi,
+                                   const typename C::T *csq)
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    T *M0 = sh + C::M0, *V0 = sh + C::V0, *V1 = sh + C::V1;
+    put_rows<T, D, D>(M0, LDM, lane, f.P);
+    if (lane < D) V0[lane] = f.m;
+    wave_sync();
+    T w[D2];
+    if (lane < D) {
+        T phirow[D], t[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) phirow[k] = cphi[lane * LDM + k];
+        row_times<T, D, D>(t, phirow, M0, LDM);
+        T pm = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) pm += phirow[k] * V0[k];
+        V1[lane] = pm;  // (Phi m^f)_lane
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = t[c];
+            w[D + c] = csq[lane * LDM + c];
+        }
+    } else if (lane < D2) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = M0[(lane - D) * LDM + c];
+            w[D + c] = 0;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < D2; ++c) w[c] = 0;
+    }
+    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
+    T *Pi = sh + C::BIG;
+    put_rows<T, D2, D2>(Pi, LDB, lane, w);
+    wave_sync();
+    ERow<C> e;
+    e.g = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
+    if (lane < D) {
+        T p21[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            p21[c] = Pi[(D + lane) * LDB + c];
+            e.L[c] = Pi[(D + lane) * LDB + D + c];
+        }
+        solve_xL<T, D>(e.E, p21, Pi, LDB);
+        T g = f.m;
+#pragma unroll
+        for (int c = 0; c < D; ++c) g -= e.E[c] * V1[c];
+        e.g = g;
+    }
+    wave_sync();
+    return e;
+}
+
+// acc (x)_s b : E = E_acc E_b, g = E_acc g_b + g_acc, sqrtL = tria([E_acc sqrtL_b, sqrtL_acc])
+template <class C, bool WITH_L>
+PARAPN_DEV ERow<C> smoother_combine(int lane, typename C::T *sh, const ERow<C> &a, const ERow<C> &b)
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM;
+    T *M0 = sh + C::M0, *M1 = sh + C::M1, *V0 = sh + C::V0;
+    put_rows<T, D, D>(M0, LDM, lane, b.E);
+    if (WITH_L) put_rows<T, D, D>(M1, LDM, lane, b.L);
+    if (lane < D) V0[lane] = b.g;
+    wave_sync();
+    ERow<C> o;
+    o.g = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) o.E[c] = o.L[c] = 0;
+    if (lane < D) {
+        row_times<T, D, D>(o.E, a.E, M0, LDM);
+        T g = a.g;
+#pragma unroll
+        for (int k = 0; k < D; ++k) g += a.E[k] * V0[k];
+        o.g = g;
+    }
+    if (WITH_L) {
+        T w[D2];
+        if (lane < D) {
+            T t[D];
+            row_times<T, D, D>(t, a.E, M1, LDM);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                w[c] = t[c];
+                w[D + c] = a.L[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < D2; ++c) w[c] = 0;
+        }
+        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.L[c] = lane < D ? w[c] : T(0);
+    }
+    wave_sync();
+    return o;
+}
+
+// element/aggregate applied to the suffix state after it:
+//   m = E m_next + g,  sqrtP = tria([E sqrtP_next, sqrtL])
+template <class C, bool WITH_L>
+PARAPN_DEV SRow<C> smoother_apply(int lane, typename C::T *sh, const ERow<C> &a, const SRow<C> &s)
+{
+    using T = typename C::T;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM;
+    T *M0 = sh + C::M0, *V0 = sh + C::V0;
+    if (WITH_L) put_rows<T, D, D>(M0, LDM, lane, s.P);
+    if (lane < D) V0[lane] = s.m;
+    wave_sync();
+    SRow<C> o;
+    o.m = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) o.P[c] = 0;
+    if (lane < D) {
+        T m = a.g;
+#pragma unroll
+        for (int k = 0; k < D; ++k) m += a.E[k] * V0[k];
+        o.m = m;
+    }
+    if (WITH_L) {
+        T w[D2];
+        if (lane < D) {
+            T t[D];
+            row_times<T, D, D>(t, a.E, M0, LDM);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                w[c] = t[c];
+                w[D + c] = a.L[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < D2; ++c) w[c] = 0;
+        }
+        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
+    }
+    wave_sync();
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <class C>
+struct KArgs {
+    using T = typename C::T;
+    int64_t N;
+    int b1, bu;
+    const T *Phi, *sQ, *m0, *S0;
+    ObsDev<C> obs;
+};
+
+#define PARAPN_GROUP_SETUP(C)                                                \
+    using T = typename C::T;                                                 \
+    __shared__ T smem[C::GPB * C::SH + 2 * C::D * C::LDM];                   \
+    T *cphi = smem + C::GPB * C::SH;                                         \
+    T *csq = cphi + C::D * C::LDM;                                           \
+    const int lane = threadIdx.x & (C::R - 1);                               \
+    const int grp = threadIdx.x / C::R;                                      \
+    T *sh = smem + grp * C::SH;                                              \
+    (void)sh;                                                                \
+    (void)lane
+
+template <class C>
+PARAPN_DEV void load_consts(typename C::T *cphi, typename C::T *csq, const typename C::T *Phi,
+                            const typename C::T *sQ)
+{
+    constexpr int D = C::D;
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
+        const int r = i / D, c = i % D;
+        cphi[r * C::LDM + c] = Phi[i];
+        csq[r * C::LDM + c] = sQ[i];
+    }
+    __syncthreads();
+}
+
+// step level, forward reduce: aggregate a_s (x)_f ... (x)_f a_{e-1}
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T *agg, int64_t nchunks)
+{
+    PARAPN_GROUP_SETUP(C);
+    load_consts<C>(cphi, csq, a.Phi, a.sQ);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nchunks) return;
+    const int64_t s = 1 + chunk * a.b1;
+    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    FRow<C> acc;
+    zero(acc);
+    for (int64_t n = s; n < e; ++n) {
+        obs_setup<C>(a.obs, n, lane, sh, cphi);
+        FRow<C> el = filter_element<C>(lane, sh, cphi, csq);
+        if (n == s)
+            acc = el;
+        else
+            acc = filter_combine<C>(lane, sh, acc, el);
+    }
+    store_frow<C>(agg + chunk * C::FE, lane, acc);
+}
+
+// upper level, forward reduce of bu aggregates
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_fwd_reduce(KArgs<C> a, const typename C::T *in, int64_t nin,
+                                                      typename C::T *out, int64_t nout)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nout) return;
+    const int64_t s = chunk * a.bu;
+    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
+    FRow<C> acc = load_frow<C>(in + s * C::FE, lane);
+    for (int64_t i = s + 1; i < e; ++i) {
+        FRow<C> el = load_frow<C>(in + i * C::FE, lane);
+        acc = filter_combine<C>(lane, sh, acc, el);
+    }
+    store_frow<C>(out + chunk * C::FE, lane, acc);
+}
+
+// top: exclusive scan of n aggregates from the initial state (m0, S0)
+template <class C>
+__global__ __launch_bounds__(C::R) void k_fwd_top(KArgs<C> a, const typename C::T *agg, int64_t n,
+                                                   typename C::T *pref)
+{
+    PARAPN_GROUP_SETUP(C);
+    if (grp != 0) return;
+    SRow<C> st;
+    st.m = 0;
+#pragma unroll
+    for (int c = 0; c < C::D; ++c) st.P[c] = 0;
+    if (lane < C::D) {
+        st.m = a.m0[lane];
+#pragma unroll
+        for (int c = 0; c < C::D; ++c) st.P[c] = a.S0[lane * C::D + c];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        store_state<C>(pref + i * C::FS, lane, st);
+        if (i + 1 < n) {
+            FRow<C> el = load_frow<C>(agg + i * C::FE, lane);
+            st = state_apply<C>(lane, sh, st, el);
+        }
+    }
+}
+
+// upper level, forward down-sweep: prefix states of bu aggregates
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_fwd_down(KArgs<C> a, const typename C::T *agg, int64_t nin,
+                                                    const typename C::T *pref_up, typename C::T *pref, int64_t nup)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nup) return;
+    const int64_t s = chunk * a.bu;
+    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
+    SRow<C> st = load_state<C>(pref_up + chunk * C::FS, lane);
+    for (int64_t i = s; i < e; ++i) {
+        store_state<C>(pref + i * C::FS, lane, st);
+        if (i + 1 < e) {
+            FRow<C> el = load_frow<C>(agg + i * C::FE, lane);
+            st = state_apply<C>(lane, sh, st, el);
+        }
+    }
+}
+
+// step level, forward down-sweep: Kalman steps from the chunk's prefix state,
+// writing the filtering marginals m^f_n, sqrtP^f_n (packed) for n in the chunk
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename C::T *pref, int64_t nchunks,
+                                                     typename C::T *mf, typename C::T *sPf)
+{
+    PARAPN_GROUP_SETUP(C);
+    load_consts<C>(cphi, csq, a.Phi, a.sQ);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nchunks) return;
+    const int64_t s = 1 + chunk * a.b1;
+    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    SRow<C> st = load_state<C>(pref + chunk * C::FS, lane);
+    if (chunk == 0 && lane < C::D) {
+        mf[lane] = st.m;
+        store_packed<C>(sPf, lane, st.P);
+    }
+    for (int64_t n = s; n < e; ++n) {
+        obs_setup<C>(a.obs, n, lane, sh, cphi);
+        st = kf_step<C>(lane, sh, st, cphi, csq);
+        if (lane < C::D) {
+            mf[n * C::D + lane] = st.m;
+            store_packed<C>(sPf + n * C::DP, lane, st.P);
+        }
+    }
+}
+
+// smoothing elements for n = 0..N: (E, g) and, with WITH_L, sqrtL (packed)
+template <class C, bool WITH_L>
+__global__ __launch_bounds__(C::NT) void k_smoother_elements(KArgs<C> a, const typename C::T *mf,
+                                                             const typename C::T *sPf, typename C::T *se,
+                                                             typename C::T *sL)
+{
+    PARAPN_GROUP_SETUP(C);
+    load_consts<C>(cphi, csq, a.Phi, a.sQ);
+    const int64_t n = (int64_t)blockIdx.x * C::GPB + grp;
+    if (n > a.N) return;
+    constexpr int D = C::D;
+    SRow<C> f;
+    f.m = lane < D ? mf[n * D + lane] : T(0);
+    load_packed<C>(f.P, sPf + n * C::DP, lane);
+    ERow<C> e;
+    if (n == a.N) {  // last element: the filtering marginal itself (E = 0)
+        e.g = f.m;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            e.E[c] = 0;
+            e.L[c] = f.P[c];
+        }
+    } else {
+        e = smoother_element<C>(lane, sh, f, cphi, csq);
+    }
+    if (lane < D) {
+        T *rec = se + n * C::SE;
+#pragma unroll
+        for (int c = 0; c < D; ++c) rec[lane * D + c] = e.E[c];
+        rec[D * D + lane] = e.g;
+        if (WITH_L) store_packed<C>(sL + n * C::DP, lane, e.L);
+    }
+}
+
+template <class C, bool WITH_L>
+PARAPN_DEV ERow<C> load_selem(const typename C::T *se, const typename C::T *sL, int64_t n, int lane)
+{
+    constexpr int D = C::D;
+    ERow<C> e;
+    e.g = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
+    if (lane < D) {
+        const typename C::T *rec = se + n * C::SE;
+#pragma unroll
+        for (int c = 0; c < D; ++c) e.E[c] = rec[lane * D + c];
+        e.g = rec[D * D + lane];
+    }
+    if (WITH_L) load_packed<C>(e.L, sL + n * C::DP, lane);
+    return e;
+}
+
+template <class C>
+PARAPN_DEV ERow<C> load_sagg(const typename C::T *rec, int lane)
+{
+    constexpr int D = C::D;
+    ERow<C> e;
+    e.g = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
+    if (lane < D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            e.E[c] = rec[lane * D + c];
+            e.L[c] = rec[D * D + D + lane * D + c];
+        }
+        e.g = rec[D * D + lane];
+    }
+    return e;
+}
+
+template <class C>
+PARAPN_DEV void store_sagg(typename C::T *rec, int lane, const ERow<C> &e)
+{
+    constexpr int D = C::D;
+    if (lane < D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            rec[lane * D + c] = e.E[c];
+            rec[D * D + D + lane * D + c] = e.L[c];
+        }
+        rec[D * D + lane] = e.g;
+    }
+}
+
+// step level, smoother reduce over steps [s, e): b_s (x)_s ... (x)_s b_{e-1}
+template <class C, bool WITH_L>
+__global__ __launch_bounds__(C::NT) void k_bwd_reduce1(KArgs<C> a, const typename C::T *se,
+                                                       const typename C::T *sL, typename C::T *agg, int64_t nchunks)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nchunks) return;
+    const int64_t s = chunk * a.b1;
+    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    ERow<C> acc = load_selem<C, WITH_L>(se, sL, s, lane);
+    for (int64_t n = s + 1; n < e; ++n) {
+        ERow<C> el = load_selem<C, WITH_L>(se, sL, n, lane);
+        acc = smoother_combine<C, WITH_L>(lane, sh, acc, el);
+    }
+    store_sagg<C>(agg + chunk * C::SA, lane, acc);
+}
+
+template <class C, bool WITH_L>
+__global__ __launch_bounds__(C::NT) void k_bwd_reduce(KArgs<C> a, const typename C::T *in, int64_t nin,
+                                                      typename C::T *out, int64_t nout)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nout) return;
+    const int64_t s = chunk * a.bu;
+    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
+    ERow<C> acc = load_sagg<C>(in + s * C::SA, lane);
+    for (int64_t i = s + 1; i < e; ++i) {
+        ERow<C> el = load_sagg<C>(in + i * C::SA, lane);
+        acc = smoother_combine<C, WITH_L>(lane, sh, acc, el);
+    }
+    store_sagg<C>(out + chunk * C::SA, lane, acc);
+}
+
+// top: exclusive suffix scan (from the right) of n aggregates; the state after
+// the last one is irrelevant because the last aggregate contains E_N = 0
+template <class C, bool WITH_L>
+__global__ __launch_bounds__(C::R) void k_bwd_top(KArgs<C> a, const typename C::T *agg, int64_t n,
+                                                   typename C::T *suf)
+{
+    PARAPN_GROUP_SETUP(C);
+    if (grp != 0) return;
+    SRow<C> st;
+    st.m = 0;
+#pragma unroll
+    for (int c = 0; c < C::D; ++c) st.P[c] = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        store_state<C>(suf + i * C::SS, lane, st);
+        if (i > 0) {
+            ERow<C> el = load_sagg<C>(agg + i * C::SA, lane);
+            st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+        }
+    }
+}
+
+template <class C, bool WITH_L>
+__global__ __launch_bounds__(C::NT) void k_bwd_down(KArgs<C> a, const typename C::T *agg, int64_t nin,
+                                                    const typename C::T *suf_up, typename C::T *suf, int64_t nup)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nup) return;
+    const int64_t s = chunk * a.bu;
+    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
+    SRow<C> st = load_state<C>(suf_up + chunk * C::SS, lane);
+    for (int64_t i = e - 1; i >= s; --i) {
+        store_state<C>(suf + i * C::SS, lane, st);
+        if (i > s) {
+            ERow<C> el = load_sagg<C>(agg + i * C::SA, lane);
+            st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+        }
+    }
+}
+
+// step level, smoother down-sweep over the chunk's steps from its suffix
+// state.  UPDATE: write the means into traj (the next linearisation point)
+// and accumulate delta = max |T0 E0 (new - old)| and max |T0 E0 new| in
+// double; otherwise write means to mout.
+template <class C, bool WITH_L, bool UPDATE>
+__global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename C::T *se, const typename C::T *sL,
+                                                     const typename C::T *suf, int64_t nchunks, typename C::T *mout,
+                                                     typename C::T *sPs, unsigned long long *dbits, double T0)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    if (chunk >= nchunks) return;
+    constexpr int D = C::D;
+    const int64_t s = chunk * a.b1;
+    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    SRow<C> st = load_state<C>(suf + chunk * C::SS, lane);
+    double dmax = 0.0, mmax = 0.0;
+    for (int64_t n = e - 1; n >= s; --n) {
+        ERow<C> el = load_selem<C, WITH_L>(se, sL, n, lane);
+        st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+        if (lane < D) {
+            if (UPDATE) {
+                if (lane % C::S == 0) {
+                    const double nw = T0 * (double)st.m;
+                    const double df = fabs(nw - T0 * (double)mout[n * D + lane]);
+                    dmax = (df > dmax || df != df) ? df : dmax;
+                    const double am = fabs(nw);
+                    mmax = (am > mmax || am != am) ? am : mmax;
+                }
+            }
+            mout[n * D + lane] = st.m;
+            if (WITH_L) store_packed<C>(sPs + n * C::DP, lane, st.P);
+        }
+    }
+    if (UPDATE) {
+        // group max through LDS, one atomic per group (non-negative doubles
+        // order like their bit patterns; NaN sorts above everything)
+        __shared__ double redbuf[C::GPB * 2 * C::R];
+        double *red = redbuf + grp * 2 * C::R;
+        red[lane] = dmax;
+        red[C::R + lane] = mmax;
+        wave_sync();
+        if (lane == 0) {
+            double x = 0.0, y = 0.0;
+            for (int i = 0; i < C::R; ++i) {
+                const double u = red[i], v = red[C::R + i];
+                x = (u > x || u != u) ? u : x;
+                y = (v > y || v != v) ? v : y;
+            }
+            atomicMax(dbits, (unsigned long long)__double_as_longlong(x));
+            atomicMax(dbits + 1, (unsigned long long)__double_as_longlong(y));
+        }
+    }
+}
+
+// batched filtering operator for the ABI entry point
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C::T *aa, const typename C::T *cc,
+                                                                typename C::T *out, int64_t count)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t k = (int64_t)blockIdx.x * C::GPB + grp;
+    if (k >= count) return;
+    FRow<C> ei = load_frow<C>(aa + k * C::FE, lane);
+    FRow<C> ej = load_frow<C>(cc + k * C::FE, lane);
+    FRow<C> o = filter_combine<C>(lane, sh, ei, ej);
+    store_frow<C>(out + k * C::FE, lane, o);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch sequences
+// ---------------------------------------------------------------------------
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Levels {
+    int L;            // number of aggregate levels (>= 1)
+    int64_t n[48];    // n[l] aggregates at level l (l = 1..L)
+    int64_t off[48];  // record offset of level l
+    int64_t total;
+};
+
+static Levels make_levels(int64_t nitems, const ScanPlan &p)
+{
+    Levels lv{};
+    lv.L = 1;
+    lv.n[1] = cdiv(nitems, p.b1);
+    lv.off[1] = 0;
+    while (lv.n[lv.L] > p.btop && lv.L < 46) {
+        lv.n[lv.L + 1] = cdiv(lv.n[lv.L], p.bu);
+        lv.off[lv.L + 1] = lv.off[lv.L] + lv.n[lv.L];
+        ++lv.L;
+    }
+    lv.total = lv.off[lv.L] + lv.n[lv.L];
+    return lv;
+}
+
+template <class C>
+static KArgs<C> make_args(const ScanPlan &p, const ModelDev &m, const ObsSpec *o)
+{
+    using T = typename C::T;
+    KArgs<C> a{};
+    a.N = p.N;
+    a.b1 = p.b1;
+    a.bu = p.bu;
+    a.Phi = (const T *)m.Phi;
+    a.sQ = (const T *)m.sQ;
+    a.m0 = (const T *)m.m0;
+    a.S0 = (const T *)m.S0;
+    if (o) {
+        a.obs.mode = o->mode;
+        a.obs.traj = (const T *)o->traj;
+        a.obs.field = o->field;
+        for (int i = 0; i < kMaxParams; ++i) a.obs.p[i] = (T)o->p[i];
+        a.obs.T0 = (T)o->T0;
+        a.obs.invT1 = (T)o->invT1;
+        a.obs.hq = (T)o->hq;
+        a.obs.H = (const T *)o->H;
+        a.obs.dv = (const T *)o->dv;
+    }
+    return a;
+}
+
+template <class C>
+static hipError_t fwd_seq(const ScanPlan &p, const ModelDev &m, const ObsSpec &o, const Work &w, hipStream_t s)
+{
+    using T = typename C::T;
+    KArgs<C> a = make_args<C>(p, m, &o);
+    Levels lv = make_levels(p.N, p);
+    T *agg = (T *)w.fagg, *pref = (T *)w.fpref;
+    auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
+    PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, agg + lv.off[1] * C::FE,
+                       lv.n[1]);
+    for (int l = 1; l < lv.L; ++l)
+        PARAPN_LAUNCH("fwd_reduce", s, k_fwd_reduce<C>, dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
+                           agg + lv.off[l] * C::FE, lv.n[l], agg + lv.off[l + 1] * C::FE, lv.n[l + 1]);
+    PARAPN_LAUNCH("fwd_top", s, k_fwd_top<C>, dim3(1), dim3(C::R), 0, s, a, agg + lv.off[lv.L] * C::FE, lv.n[lv.L],
+                       pref + lv.off[lv.L] * C::FS);
+    for (int l = lv.L - 1; l >= 1; --l)
+        PARAPN_LAUNCH("fwd_down", s, k_fwd_down<C>, dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
+                           agg + lv.off[l] * C::FE, lv.n[l], pref + lv.off[l + 1] * C::FS, pref + lv.off[l] * C::FS,
+                           lv.n[l + 1]);
+    PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, pref + lv.off[1] * C::FS,
+                       lv.n[1], (T *)w.mf, (T *)w.sPf);
+    return hipGetLastError();
+}
+
+template <class C, bool WITH_L>
+static hipError_t bwd_seq(const ScanPlan &p, const ModelDev &m, const Work &w, bool update, void *mout, double T0,
+                          hipStream_t s)
+{
+    using T = typename C::T;
+    KArgs<C> a = make_args<C>(p, m, nullptr);
+    Levels lv = make_levels(p.N + 1, p);
+    T *agg = (T *)w.sagg, *suf = (T *)w.spref;
+    auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
+    PARAPN_LAUNCH("smoother_elements", s, (k_smoother_elements<C, WITH_L>), dim3(blocks(p.N + 1)), dim3(C::NT), 0, s, a,
+                       (const T *)w.mf, (const T *)w.sPf, (T *)w.se, (T *)w.sL);
+    PARAPN_LAUNCH("bwd_reduce1", s, (k_bwd_reduce1<C, WITH_L>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, (const T *)w.se,
+                       (const T *)w.sL, agg + lv.off[1] * C::SA, lv.n[1]);
+    for (int l = 1; l < lv.L; ++l)
+        PARAPN_LAUNCH("bwd_reduce", s, (k_bwd_reduce<C, WITH_L>), dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
+                           agg + lv.off[l] * C::SA, lv.n[l], agg + lv.off[l + 1] * C::SA, lv.n[l + 1]);
+    PARAPN_LAUNCH("bwd_top", s, (k_bwd_top<C, WITH_L>), dim3(1), dim3(C::R), 0, s, a, agg + lv.off[lv.L] * C::SA, lv.n[lv.L],
+                       suf + lv.off[lv.L] * C::SS);
+    for (int l = lv.L - 1; l >= 1; --l)
+        PARAPN_LAUNCH("bwd_down", s, (k_bwd_down<C, WITH_L>), dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
+                           agg + lv.off[l] * C::SA, lv.n[l], suf + lv.off[l + 1] * C::SS, suf + lv.off[l] * C::SS,
+                           lv.n[l + 1]);
+    if (update)
+        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, true>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
+                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)w.traj,
+                           (T *)w.sPs, w.dbits, T0);
+    else
+        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, false>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
+                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)mout,
+                           (T *)w.sPs, w.dbits, T0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_unscale(int D, int64_t N, const double *Td, const T *src, const T *srcP, T *mo, T *co)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rows = (N + 1) * D;
+    if (i >= rows) return;
+    const int64_t n = i / D;
+    const int r = (int)(i % D);
+    const double t = Td ? Td[r] : 1.0;
+    if (mo) mo[i] = (T)(t * (double)src[i]);
+    if (co) {
+        const T *pr = srcP + n * (int64_t)(D * (D + 1) / 2) + r * (r + 1) / 2;
+        T *out = co + i * D;
+        for (int c = 0; c < D; ++c) out[c] = c <= r ? (T)(t * (double)pr[c]) : T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_fill_traj(int D, int64_t N, const T *row, T *traj)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (N + 1) * D) return;
+    traj[i] = row[i % D];
+}
+
+// canonical lower-triangular factor of a D x D square root (one group)
+template <class C>
+__global__ __launch_bounds__(C::R) void k_tria_square(const typename C::T *full, typename C::T *out)
+{
+    PARAPN_GROUP_SETUP(C);
+    if (grp != 0) return;
+    constexpr int D = C::D;
+    T v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = lane < D ? full[lane * D + c] : T(0);
+    tria_rows<T, D, D>(v, lane, sh + C::TR);
+    if (lane < D)
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[lane * D + c] = v[c];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over the instantiated (d, q) configurations
+// ---------------------------------------------------------------------------
+template <typename T, class F>
+static hipError_t dispatch_t(int d, int q, F &&f)
+{
+    switch (d * 10 + q) {
+    case 11: return f(Cfg<T, 1, 1>{});
+    case 12: return f(Cfg<T, 1, 2>{});
+    case 13: return f(Cfg<T, 1, 3>{});
+    case 14: return f(Cfg<T, 1, 4>{});
+    case 21: return f(Cfg<T, 2, 1>{});
+    case 22: return f(Cfg<T, 2, 2>{});
+    case 23: return f(Cfg<T, 2, 3>{});
+    case 24: return f(Cfg<T, 2, 4>{});
+    case 31: return f(Cfg<T, 3, 1>{});
+    case 32: return f(Cfg<T, 3, 2>{});
+    case 33: return f(Cfg<T, 3, 3>{});
+    case 34: return f(Cfg<T, 3, 4>{});
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_forward_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const ObsSpec &obs, const Work &w,
+                            hipStream_t s)
+{
+    return dispatch_t<T>(d, q, [&](auto c) { return fwd_seq<decltype(c)>(plan, m, obs, w, s); });
+}
+
+template <typename T>
+hipError_t launch_smoother_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const Work &w, bool with_cov,
+                             bool update_traj, void *mean_out, double T0, hipStream_t s)
+{
+    return dispatch_t<T>(d, q, [&](auto c) {
+        using C = decltype(c);
+        return with_cov ? bwd_seq<C, true>(plan, m, w, update_traj, mean_out, T0, s)
+                        : bwd_seq<C, false>(plan, m, w, update_traj, mean_out, T0, s);
+    });
+}
+
+template <typename T>
+hipError_t launch_filter_combine_t(int d, int q, int64_t count, const void *a, const void *c, void *out,
+                                   hipStream_t s)
+{
+    return dispatch_t<T>(d, q, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL(k_filter_combine_batch<C>, dim3((unsigned)cdiv(count, C::GPB)), dim3(C::NT), 0, s,
+                           (const T *)a, (const T *)c, (T *)out, count);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipStream_t s)
+{
+    return dispatch_t<T>(d, q, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL(k_tria_square<C>, dim3(1), dim3(C::R), 0, s, (const T *)full, (T *)out);
+        return hipGetLastError();
+    });
+}
+
+#ifndef PARAPN_BUILD_FP32
+#define PARAPN_BUILD_FP32 1
+#endif
+#ifndef PARAPN_BUILD_FP64
+#define PARAPN_BUILD_FP64 1
+#endif
+#ifndef PARAPN_BUILD_HELPERS
+#define PARAPN_BUILD_HELPERS 1
+#endif
+
+#define PARAPN_INSTANTIATE(T)                                                                                       \
+    template hipError_t launch_forward_t<T>(int, int, const ScanPlan &, const ModelDev &, const ObsSpec &,          \
+                                            const Work &, hipStream_t);                                            \
+    template hipError_t launch_smoother_t<T>(int, int, const ScanPlan &, const ModelDev &, const Work &, bool, bool, \
+                                             void *, double, hipStream_t);                                         \
+    template hipError_t launch_filter_combine_t<T>(int, int, int64_t, const void *, const void *, void *,          \
+                                                   hipStream_t);                                                   \
+    template hipError_t launch_tria_square_t<T>(int, int, const void *, void *, hipStream_t);
+
+#if PARAPN_BUILD_FP32
+PARAPN_INSTANTIATE(float)
+#endif
+#if PARAPN_BUILD_FP64
+PARAPN_INSTANTIATE(double)
+#endif
+
+#if PARAPN_BUILD_HELPERS
+namespace {
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct ProfAcc {
+    std::string name;
+    double ms;
+    int64_t n;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<ProfAcc> g_prof_acc;
+}  // namespace
+
+bool prof_on() { return g_prof_on; }
+
+void prof_enable(bool on)
+{
+    g_prof_on = on;
+    for (auto &r : g_prof_pending) {
+        hipEventSynchronize(r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    g_prof_acc.clear();
+}
+
+void prof_begin(const char *name, hipStream_t s, hipEvent_t *start)
+{
+    (void)name;
+    if (hipEventCreate(start) != hipSuccess) {
+        *start = nullptr;
+        return;
+    }
+    hipEventRecord(*start, s);
+}
+
+void prof_end(const char *name, hipStream_t s, hipEvent_t start)
+{
+    if (!start) return;
+    hipEvent_t stop;
+    if (hipEventCreate(&stop) != hipSuccess) {
+        hipEventDestroy(start);
+        return;
+    }
+    hipEventRecord(stop, s);
+    g_prof_pending.push_back({name, start, stop});
+}
+
+int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *launches)
+{
+    for (auto &r : g_prof_pending) {
+        hipEventSynchronize(r.b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+        bool found = false;
+        for (auto &a : g_prof_acc)
+            if (a.name == r.name) {
+                a.ms += ms;
+                a.n += 1;
+                found = true;
+            }
+        if (!found) g_prof_acc.push_back({r.name, (double)ms, 1});
+    }
+    g_prof_pending.clear();
+    int k = 0;
+    for (auto &a : g_prof_acc) {
+        if (k >= max) break;
+        std::snprintf(names + (size_t)k * name_len, name_len, "%s", a.name.c_str());
+        total_ms[k] = a.ms;
+        launches[k] = a.n;
+        ++k;
+    }
+    return (int)g_prof_acc.size();
+}
+
+int config_supported(int d, int q) { return (d >= 1 && d <= 3 && q >= 1 && q <= 4) ? 1 : -1; }
+
+size_t work_elems_fagg(int D, const ScanPlan &p)
+{
+    Levels lv = make_levels(p.N, p);
+    return (size_t)lv.total * (size_t)(3 * D * D + 2 * D);
+}
+
+size_t work_elems_sagg(int D, const ScanPlan &p)
+{
+    Levels lv = make_levels(p.N + 1, p);
+    return (size_t)lv.total * (size_t)(2 * D * D + D);
+}
+
+hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
+                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s)
+{
+    const int64_t rows = (N + 1) * D;
+    const unsigned blocks = (unsigned)cdiv(rows, 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_unscale<double>, dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
+                           (const double *)src_mean, (const double *)src_packed, (double *)mean_out,
+                           (double *)cov_out);
+    else
+        hipLaunchKernelGGL(k_unscale<float>, dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev, (const float *)src_mean,
+                           (const float *)src_packed, (float *)mean_out, (float *)cov_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_traj(int fp64, int D, int64_t N, const void *row, void *traj, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)cdiv((N + 1) * D, 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_fill_traj<double>, dim3(blocks), dim3(256), 0, s, D, N, (const double *)row,
+                           (double *)traj);
+    else
+        hipLaunchKernelGGL(k_fill_traj<float>, dim3(blocks), dim3(256), 0, s, D, N, (const float *)row,
+                           (float *)traj);
+    return hipGetLastError();
+}
+#endif
+
+}  // namespace parapn

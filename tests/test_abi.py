@@ -1,0 +1,71 @@
+"""CPU checks of the C boundary: the library loads and exports every symbol
+the public header declares; host-side argument validation (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "parapn.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(parapn_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["parapn_create", "parapn_destroy", "parapn_solve", "parapn_pararts", "parapn_workspace_size",
+              "parapn_filter_combine", "parapn_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2310_01145_amd as pp
+
+    lib = pp.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(pp.EXPORTED) == declared_functions()
+
+
+def test_workspace_size_and_validation_on_host():
+    import paper_2310_01145_amd as pp
+
+    pb = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp32")
+    n32 = pp.workspace_size(pb)
+    pb64 = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp64")
+    n64 = pp.workspace_size(pb64)
+    assert 1.9 * n32 < n64 < 2.1 * n32
+    # footprint grows linearly in N
+    pb2 = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 13, precision="fp32")
+    assert 1.9 * n32 < pp.workspace_size(pb2) < 2.1 * n32
+    bad = [
+        pp.make_problem("fhn", [0.2, 0.2], [-1.0, 1.0], 0.0, 1.0, 3, 100),         # too few params
+        pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0], 0.0, 1.0, 3, 100),          # d mismatch
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 5, 100),                   # q out of range
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 0),                     # N < 1
+        pp.make_problem("logistic", [], [0.1], 1.0, 1.0, 2, 10),                    # empty span
+        pp.make_problem(42, [], [0.1], 0.0, 1.0, 2, 10, d=1),                       # unknown field
+        pp.make_problem("logistic", [], [float("nan")], 0.0, 1.0, 2, 10),           # non-finite y0
+    ]
+    for b in bad:
+        with pytest.raises(pp.ParapnError) as e:
+            pp.workspace_size(b)
+        assert e.value.code == pp.EINVAL
+        assert pp.last_error()
+
+
+def test_no_cpu_fallback_without_library(tmp_path):
+    """The binding refuses to run when the shared library is absent."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("pp_copy", os.path.join(ROOT, "paper_2310_01145_amd",
+                                                                           "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with pytest.raises(ImportError):
+        mod.load_library(str(tmp_path / "missing.so"))
