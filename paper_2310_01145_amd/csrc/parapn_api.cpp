@@ -193,7 +193,8 @@ Layout make_layout(int D, int64_t N, int esz, bool cov, const parapn::ScanPlan &
         o = align_up(o + elems * esz);
         return r;
     };
-    L.off_traj = take(rows * D);
+    L.off_traj = align_up(o);  // FP64 trajectory in both precisions
+    o = align_up(o + rows * D * sizeof(double));
     L.off_mf = take(rows * D);
     L.off_sPf = take(rows * DP);
     L.off_se = take(rows * (D * D + D));
@@ -210,7 +211,7 @@ Layout make_layout(int D, int64_t N, int esz, bool cov, const parapn::ScanPlan &
     L.off_consts = take(3 * D * D + D);
     o = align_up(o);
     L.off_T = o;
-    o = align_up(o + D * sizeof(double));
+    o = align_up(o + 2 * D * sizeof(double));  // T, then mu0bar in double
     L.off_dbits = o;
     o = align_up(o + 2 * sizeof(unsigned long long));
     L.total = o;
@@ -351,12 +352,18 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     if (!taylor_mu0(p->field, d, prm, p->y0, q, mu0.data())) return fail(PARAPN_EINVAL, "field not available for d");
     for (int k = 0; k < D; ++k)
         if (!std::isfinite(mu0[k])) return fail(PARAPN_EINVAL, "non-finite initial derivatives");
-    std::vector<double> cst(3 * D * D + D, 0.0);  // Phi | sQ | S0 (= 0) | m0
+    // Phi | sQ | S0 (= 0) | m0: the scans run on the increment over the
+    // trajectory, whose row 0 is mu0 itself, so the initial increment is 0
+    std::vector<double> cst(3 * D * D + D, 0.0);
     for (int i = 0; i < D * D; ++i) {
         cst[i] = Phi[i];
         cst[D * D + i] = sQ[i];
     }
-    for (int k = 0; k < D; ++k) cst[3 * D * D + k] = mu0[k] / Td[k];
+    std::vector<double> Tmu(2 * D);
+    for (int k = 0; k < D; ++k) {
+        Tmu[k] = Td[k];
+        Tmu[D + k] = mu0[k] / Td[k];
+    }
     char *cdev = ws + L.off_consts;
     if (fp64) {
         PARAPN_HIP(hipMemcpyAsync(cdev, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, s), "copy constants");
@@ -365,7 +372,8 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         PARAPN_HIP(hipMemcpyAsync(cdev, cf.data(), cf.size() * 4, hipMemcpyHostToDevice, s), "copy constants");
         PARAPN_HIP(hipStreamSynchronize(s), "sync");  // cf is a local
     }
-    PARAPN_HIP(hipMemcpyAsync(ws + L.off_T, Td.data(), D * sizeof(double), hipMemcpyHostToDevice, s), "copy T");
+    PARAPN_HIP(hipMemcpyAsync(ws + L.off_T, Tmu.data(), 2 * D * sizeof(double), hipMemcpyHostToDevice, s),
+               "copy T");
 
     parapn::ModelDev m;
     m.Phi = cdev;
@@ -386,22 +394,19 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     w.spref = ws + L.off_spref;
     w.dbits = (unsigned long long *)(ws + L.off_dbits);
 
-    // initial trajectory (Alg. 2): constant mu0, or the caller's, preconditioned
+    // initial trajectory (Alg. 2): constant mu0, or the caller's; preconditioned,
+    // FP64, row 0 always mu0 (only E0 of row 0 enters the convergence test)
     if (p->init_traj) {
         const size_t rows = (size_t)p->N + 1;
         std::vector<double> tr(rows * D);
-        for (size_t n = 0; n < rows; ++n)
+        for (int k = 0; k < D; ++k) tr[k] = mu0[k] / Td[k];
+        for (size_t n = 1; n < rows; ++n)
             for (int k = 0; k < D; ++k) tr[n * D + k] = p->init_traj[n * D + k] / Td[k];
-        if (fp64) {
-            PARAPN_HIP(hipMemcpyAsync(w.traj, tr.data(), tr.size() * 8, hipMemcpyHostToDevice, s), "copy traj");
-            PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        } else {
-            std::vector<float> tf(tr.begin(), tr.end());
-            PARAPN_HIP(hipMemcpyAsync(w.traj, tf.data(), tf.size() * 4, hipMemcpyHostToDevice, s), "copy traj");
-            PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        }
+        PARAPN_HIP(hipMemcpyAsync(w.traj, tr.data(), tr.size() * 8, hipMemcpyHostToDevice, s), "copy traj");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
     } else {
-        PARAPN_HIP(parapn::launch_fill_traj(fp64, D, p->N, m.m0, w.traj, s), "fill trajectory");
+        PARAPN_HIP(parapn::launch_fill_traj(1, D, p->N, ws + L.off_T + D * sizeof(double), w.traj, s),
+                   "fill trajectory");
     }
 
     parapn::ObsSpec obs{};
@@ -410,6 +415,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     obs.field = p->field;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) obs.p[i] = prm[i];
     obs.T0 = Td[0];
+    obs.T1 = Td[1];
     obs.invT1 = 1.0 / Td[1];
     obs.hq = h / q;
 
@@ -457,7 +463,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         PARAPN_HIP(parapn::launch_smoother(fp64, d, q, plan, m, w, true, false, w.mf, Td[0], s), "covariance pass");
     }
     PARAPN_HIP(parapn::launch_unscale(fp64, D, p->N, (const double *)(ws + L.off_T), w.traj, w.sPs, mean_out,
-                                      sqrtcov_out, s),
+                                      sqrtcov_out, s, true),
                "unscale");
     PARAPN_HIP(hipStreamSynchronize(s), "sync");
     if (info) {
@@ -512,6 +518,7 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     w.sagg = ws + L.off_sagg;
     w.spref = ws + L.off_spref;
     w.dbits = (unsigned long long *)(ws + L.off_dbits);
+    w.traj = nullptr;  // a given linear model: no trajectory, no prior offsets
     parapn::ObsSpec obs{};
     obs.mode = 1;
     obs.H = H;

@@ -14,11 +14,12 @@ constexpr int kMaxParams = 16;
 struct ObsSpec {
     int mode;            // 0: linearise the vector field at the trajectory (IEKS)
                          // 1: read dense H [N][d][D] and d [N][d] from memory
-    const void *traj;    // mode 0: preconditioned trajectory [N+1][D]
+    const void *traj;    // mode 0: preconditioned FP64 trajectory [N+1][D]
     int field;           // mode 0: field id
     double p[kMaxParams];// mode 0: field parameters
     double T0;           // mode 0: scale of the E0 coordinate (y = T0 * E0 traj)
-    double invT1;        // mode 0: 1 / scale of the E1 coordinate (row scaling)
+    double T1;           // mode 0: scale of the E1 coordinate (y' = T1 * E1 traj)
+    double invT1;        // mode 0: 1 / T1 (row scaling of the observation)
     double hq;           // mode 0: T0 / T1 = h / q
     const void *H;       // mode 1
     const void *dv;      // mode 1
@@ -34,7 +35,7 @@ struct ScanPlan {
 
 // Device workspace (element type T of the path).
 struct Work {
-    void *traj;    // [N+1][D]   trajectory / smoothed means (updated in place)
+    void *traj;    // [N+1][D]   FP64 trajectory (IEKS), updated in place
     void *mf;      // [N+1][D]   filtered means
     void *sPf;     // [N+1][DP]  filtered factors, packed lower rows
     void *se;      // [N+1][D*D+D] smoothing elements (E, g)
@@ -106,7 +107,8 @@ inline hipError_t launch_tria_square(int fp64, int d, int q, const void *full, v
 // out mean [N+1][D] = Tdiag * src; out cov [N+1][D][D] = Tdiag * unpack(srcP) (either may be null;
 // Tdiag_dev null means 1)
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
-                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s);
+                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s,
+                          bool src_fp64 = false);
 hipError_t launch_fill_traj(int fp64, int D, int64_t N, const void *row, void *traj, hipStream_t s);
 // index of an instantiated (d, q) configuration, or -1
 int config_supported(int d, int q);

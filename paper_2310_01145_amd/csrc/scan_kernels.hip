@@ -54,8 +54,9 @@ struct Cfg {
     static constexpr int V5 = V4 + LDM;
     static constexpr int HO = V5 + LDM;   // H   (d x LDM)
     static constexpr int HPO = HO + d * LDM;  // H Phi (d x LDM)
-    static constexpr int DVO = HPO + d * LDM; // d (d)
-    static constexpr int SH = DVO + d + 1;
+    static constexpr int DVO = HPO + d * LDM; // residual r (d)
+    static constexpr int UO = DVO + d + 1;    // prior offset u (D)
+    static constexpr int SH = UO + LDM;
     // block: groups per block chosen so that a block's LDS stays <= 64 KiB
     static constexpr int GPB_MAX = 256 / R;
     static constexpr int GPB_FIT = (65536 / (int)sizeof(T) - 2 * D * LDM) / SH;
@@ -201,14 +202,24 @@ template <class C>
 struct ObsDev {
     using T = typename C::T;
     int mode;
-    const T *traj;
+    const double *traj;  // FP64 trajectory (linearisation point), preconditioned
     int field;
-    T p[kMaxParams];
-    T T0, invT1, hq;
+    double p[kMaxParams];
+    double T0, T1, invT1, hq;
     const T *H;
     const T *dv;
 };
 
+// The scans solve for the Gauss-Newton increment delta = Ybar - eta of the
+// preconditioned state relative to the current trajectory eta (same
+// posterior, shifted coordinates).  Per step n the linearised model is
+//   delta_n = Phi delta_{n-1} + u_n + w_n,    u_n = Phi eta_{n-1} - eta_n,
+//   Hbar_n delta_n = r_n,   Hbar_n = E1 - (h/q) F_y E0,
+//   r_n = (f(y_n) - y'_n) / T1,   y_n = T0 E0 eta_n,  y'_n = T1 E1 eta_n,
+// i.e. the EK1 model of Sec. 3.2.1 written around eta (the F_y y terms of d_n
+// cancel exactly against Hbar eta).  u_n and r_n are formed in FP64 from the
+// FP64 trajectory and then rounded to the path's precision.  In memory mode
+// (ParaRTS on a given linear model) u = 0 and r = d.
 template <class C>
 PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T *sh, const typename C::T *cphi)
 {
@@ -217,36 +228,37 @@ PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T
     T hrow[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) hrow[c] = 0;
-    T dval = 0;
+    T rval = 0, uval = 0;
     if (o.mode == 0) {
-        // EK1 at the trajectory (Sec. 3.2.1), preconditioned and row-scaled:
-        //   Hbar = E1 - (h/q) F_y E0,   dbar = (f(y) - F_y y) / T1,   y = T0 E0 traj_n
-        const T *tn = o.traj + n * D;
-        Dual<T, d> yd[d], fd[d];
+        const double *tn = o.traj + n * D;
+        const double *tp = tn - D;
+        Dual<double, d> yd[d], fd[d];
 #pragma unroll
         for (int i = 0; i < d; ++i) {
             yd[i].v = o.T0 * tn[i * S];
 #pragma unroll
-            for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? T(1) : T(0);
+            for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
         }
         field_eval<d>(o.field, o.p, yd, fd);
 #pragma unroll
         for (int i = 0; i < d; ++i)
             if (lane == i) {
-                T acc = fd[i].v;
 #pragma unroll
-                for (int j = 0; j < d; ++j) {
-                    acc -= fd[i].g[j] * yd[j].v;
-                    hrow[j * S] -= o.hq * fd[i].g[j];
-                }
+                for (int j = 0; j < d; ++j) hrow[j * S] -= (T)(o.hq * fd[i].g[j]);
                 hrow[i * S + 1] += T(1);
-                dval = acc * o.invT1;
+                rval = (T)((fd[i].v - o.T1 * tn[i * S + 1]) * o.invT1);
             }
+        if (lane < D) {
+            double u = -tn[lane];
+#pragma unroll
+            for (int k = 0; k < D; ++k) u += (double)cphi[lane * LDM + k] * tp[k];
+            uval = (T)u;
+        }
     } else if (lane < d) {
         const T *hr = o.H + ((n - 1) * d + lane) * D;
 #pragma unroll
         for (int c = 0; c < D; ++c) hrow[c] = hr[c];
-        dval = o.dv[(n - 1) * d + lane];
+        rval = o.dv[(n - 1) * d + lane];
     }
     if (lane < d) {
         T hp[D];
@@ -256,17 +268,20 @@ PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T
             sh[C::HO + lane * LDM + c] = hrow[c];
             sh[C::HPO + lane * LDM + c] = hp[c];
         }
-        sh[C::DVO + lane] = dval;
+        sh[C::DVO + lane] = rval;
     }
+    if (lane < D) sh[C::UO + lane] = uval;
     wave_sync();
 }
 
 // ---------------------------------------------------------------------------
 // square-root filtering element of a step n >= 1 with m_{n-1} = 0,
-// P_{n-1} = 0 (eq. sqrt-filtering-elements, sqrt R = 0):
+// P_{n-1} = 0 (eq. sqrt-filtering-elements, sqrt R = 0), so the predicted
+// mean is the prior offset m- = u_n and the predicted factor is sqrtQ:
 //   Psi = tria([[H sqrtQ], [sqrtQ]]),  K = Psi21 Psi11^{-1},
-//   A = (I - K H) Phi,  b = K d,  sqrtC = Psi22,
-//   sqrtJ = Phi^T H^T Psi11^{-T} (D x d, zero padded),  eta = sqrtJ Psi11^{-1} d.
+//   A = (I - K H) Phi,  b = m- - K (H m- - r),  sqrtC = Psi22,
+//   sqrtJ = Phi^T H^T Psi11^{-T} (D x d, zero padded),
+//   eta = sqrtJ Psi11^{-1} (r - H m-).
 // The initial distribution is not folded in here: it enters the scan as the
 // exclusive prefix state of step 1.
 // ---------------------------------------------------------------------------
@@ -297,15 +312,19 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
     if (lane < D) {
         const T *HP = sh + C::HPO;
         const T *dv = sh + C::DVO;
+        const T *um = sh + C::UO;
         T p21[d], K[d], hpc[d], x[d], dvv[d], u[d];
 #pragma unroll
         for (int i = 0; i < d; ++i) {
             p21[i] = Psi[(d + lane) * LDB + i];
             hpc[i] = HP[i * LDM + lane];
-            dvv[i] = dv[i];
+            T hu = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) hu += sh[C::HO + i * LDM + k] * um[k];
+            dvv[i] = dv[i] - hu;  // r - H m-
         }
         solve_xL<T, d>(K, p21, Psi, LDB);
-        T b = 0;
+        T b = um[lane];
 #pragma unroll
         for (int i = 0; i < d; ++i) b += K[i] * dvv[i];
         e.b = b;
@@ -553,9 +572,9 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
 
 // Kalman predict + update from a state: the same quantity as state_apply
 // with the step's own element, computed without forming the element:
-//   m- = Phi m,  sqrtP- = tria([Phi sqrtP, sqrtQ]),
+//   m- = Phi m + u,  sqrtP- = tria([Phi sqrtP, sqrtQ]),
 //   Psi = tria([[H sqrtP-], [sqrtP-]]),  K = Psi21 Psi11^{-1},
-//   m = m- + K (d - H m-),  sqrtP = Psi22.
+//   m = m- + K (r - H m-),  sqrtP = Psi22.
 template <class C>
 PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
                           const typename C::T *csq)
@@ -573,6 +592,7 @@ PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const 
 #pragma unroll
         for (int k = 0; k < D; ++k) phirow[k] = cphi[lane * LDM + k];
         row_times<T, D, D>(t, phirow, M0, LDM);
+        mp = sh[C::UO + lane];
 #pragma unroll
         for (int k = 0; k < D; ++k) mp += phirow[k] * V0[k];
 #pragma unroll
@@ -640,10 +660,11 @@ PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const 
 // ---------------------------------------------------------------------------
 // element of a step n < N from the filtering marginal (m^f_n, sqrtP^f_n):
 //   Pi = tria([[Phi sqrtP^f, sqrtQ], [sqrtP^f, 0]]),
-//   E = Pi21 Pi11^{-1},  g = m^f - E Phi m^f,  sqrtL = Pi22.
+//   E = Pi21 Pi11^{-1},  g = m^f - E (Phi m^f + u_{n+1}),  sqrtL = Pi22,
+// with u_{n+1} the prior offset of the next step (zero in memory mode).
 template <class C>
 PARAPN_DEV ERow<C> smoother_element(int lane, typename C::T *sh, const SRow<C> &f, const typename C::T *cphi,
-                                   const typename C::T *csq)
+                                   const typename C::T *csq, typename C::T unext)
 {
     using T = typename C::T;
     constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
@@ -657,10 +678,10 @@ PARAPN_DEV ERow<C> smoother_element(int lane, typename C::T *sh, const SRow<C> &
 #pragma unroll
         for (int k = 0; k < D; ++k) phirow[k] = cphi[lane * LDM + k];
         row_times<T, D, D>(t, phirow, M0, LDM);
-        T pm = 0;
+        T pm = unext;
 #pragma unroll
         for (int k = 0; k < D; ++k) pm += phirow[k] * V0[k];
-        V1[lane] = pm;  // (Phi m^f)_lane
+        V1[lane] = pm;  // (Phi m^f + u_{n+1})_lane
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             w[c] = t[c];
@@ -797,6 +818,7 @@ struct KArgs {
     int64_t N;
     int b1, bu;
     const T *Phi, *sQ, *m0, *S0;
+    const double *traj;  // FP64 trajectory (IEKS) or null (memory mode)
     ObsDev<C> obs;
 };
 
@@ -960,7 +982,15 @@ __global__ __launch_bounds__(C::NT) void k_smoother_elements(KArgs<C> a, const t
             e.L[c] = f.P[c];
         }
     } else {
-        e = smoother_element<C>(lane, sh, f, cphi, csq);
+        T un = 0;
+        if (a.traj && lane < D) {
+            const double *tn = a.traj + n * D;
+            double u = -tn[D + lane];
+#pragma unroll
+            for (int k = 0; k < D; ++k) u += (double)cphi[lane * C::LDM + k] * tn[k];
+            un = (T)u;
+        }
+        e = smoother_element<C>(lane, sh, f, cphi, csq, un);
     }
     if (lane < D) {
         T *rec = se + n * C::SE;
@@ -1098,13 +1128,15 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down(KArgs<C> a, const typename C
 }
 
 // step level, smoother down-sweep over the chunk's steps from its suffix
-// state.  UPDATE: write the means into traj (the next linearisation point)
-// and accumulate delta = max |T0 E0 (new - old)| and max |T0 E0 new| in
-// double; otherwise write means to mout.
+// state.  UPDATE: add the smoothed increments to the FP64 trajectory (the
+// next linearisation point) and accumulate, in double,
+//   delta = max |T0 E0 increment|  and  max |T0 E0 trajectory|;
+// otherwise write the smoothed means to mout.
 template <class C, bool WITH_L, bool UPDATE>
 __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename C::T *se, const typename C::T *sL,
                                                      const typename C::T *suf, int64_t nchunks, typename C::T *mout,
-                                                     typename C::T *sPs, unsigned long long *dbits, double T0)
+                                                     double *trajd, typename C::T *sPs, unsigned long long *dbits,
+                                                     double T0)
 {
     PARAPN_GROUP_SETUP(C);
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
@@ -1119,15 +1151,17 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
         st = smoother_apply<C, WITH_L>(lane, sh, el, st);
         if (lane < D) {
             if (UPDATE) {
+                const double nw = trajd[n * D + lane] + (double)st.m;
                 if (lane % C::S == 0) {
-                    const double nw = T0 * (double)st.m;
-                    const double df = fabs(nw - T0 * (double)mout[n * D + lane]);
+                    const double df = fabs(T0 * (double)st.m);
                     dmax = (df > dmax || df != df) ? df : dmax;
-                    const double am = fabs(nw);
+                    const double am = fabs(T0 * nw);
                     mmax = (am > mmax || am != am) ? am : mmax;
                 }
+                trajd[n * D + lane] = nw;
+            } else {
+                mout[n * D + lane] = st.m;
             }
-            mout[n * D + lane] = st.m;
             if (WITH_L) store_packed<C>(sPs + n * C::DP, lane, st.P);
         }
     }
@@ -1207,12 +1241,13 @@ static KArgs<C> make_args(const ScanPlan &p, const ModelDev &m, const ObsSpec *o
     a.S0 = (const T *)m.S0;
     if (o) {
         a.obs.mode = o->mode;
-        a.obs.traj = (const T *)o->traj;
+        a.obs.traj = (const double *)o->traj;
         a.obs.field = o->field;
-        for (int i = 0; i < kMaxParams; ++i) a.obs.p[i] = (T)o->p[i];
-        a.obs.T0 = (T)o->T0;
-        a.obs.invT1 = (T)o->invT1;
-        a.obs.hq = (T)o->hq;
+        for (int i = 0; i < kMaxParams; ++i) a.obs.p[i] = o->p[i];
+        a.obs.T0 = o->T0;
+        a.obs.T1 = o->T1;
+        a.obs.invT1 = o->invT1;
+        a.obs.hq = o->hq;
         a.obs.H = (const T *)o->H;
         a.obs.dv = (const T *)o->dv;
     }
@@ -1249,6 +1284,7 @@ static hipError_t bwd_seq(const ScanPlan &p, const ModelDev &m, const Work &w, b
 {
     using T = typename C::T;
     KArgs<C> a = make_args<C>(p, m, nullptr);
+    a.traj = (const double *)w.traj;
     Levels lv = make_levels(p.N + 1, p);
     T *agg = (T *)w.sagg, *suf = (T *)w.spref;
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
@@ -1267,20 +1303,20 @@ static hipError_t bwd_seq(const ScanPlan &p, const ModelDev &m, const Work &w, b
                            lv.n[l + 1]);
     if (update)
         PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, true>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
-                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)w.traj,
-                           (T *)w.sPs, w.dbits, T0);
+                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)nullptr,
+                           (double *)w.traj, (T *)w.sPs, w.dbits, T0);
     else
         PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, false>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
                            (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)mout,
-                           (T *)w.sPs, w.dbits, T0);
+                           (double *)nullptr, (T *)w.sPs, w.dbits, T0);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_unscale(int D, int64_t N, const double *Td, const T *src, const T *srcP, T *mo, T *co)
+template <typename T, typename TS>
+__global__ void k_unscale(int D, int64_t N, const double *Td, const TS *src, const T *srcP, T *mo, T *co)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t rows = (N + 1) * D;
@@ -1505,17 +1541,20 @@ size_t work_elems_sagg(int D, const ScanPlan &p)
 }
 
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
-                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s)
+                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s, bool src_fp64)
 {
     const int64_t rows = (N + 1) * D;
     const unsigned blocks = (unsigned)cdiv(rows, 256);
     if (fp64)
-        hipLaunchKernelGGL(k_unscale<double>, dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
+        hipLaunchKernelGGL((k_unscale<double, double>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
                            (const double *)src_mean, (const double *)src_packed, (double *)mean_out,
                            (double *)cov_out);
+    else if (src_fp64)
+        hipLaunchKernelGGL((k_unscale<float, double>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
+                           (const double *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out);
     else
-        hipLaunchKernelGGL(k_unscale<float>, dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev, (const float *)src_mean,
-                           (const float *)src_packed, (float *)mean_out, (float *)cov_out);
+        hipLaunchKernelGGL((k_unscale<float, float>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
+                           (const float *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out);
     return hipGetLastError();
 }
 
