@@ -4,7 +4,8 @@ Flops count a multiply-add as 2.  The counts follow the formulas each kernel
 evaluates (Householder tria of an nr x nc stack, dense products, triangular
 solves), not the instructions the lanes issue: work a kernel repeats for
 SIMD uniformity (e.g. updating already-finished rows in tria) is excluded.
-Bytes are the compulsory HBM traffic of the kernel's inputs and outputs.
+Bytes are the compulsory HBM traffic of the kernel's inputs and outputs (the
+trajectory is FP64: the forward step kernels read rows n-1 and n).
 """
 from __future__ import annotations
 
@@ -35,9 +36,14 @@ def filter_element(D, d):
             + 2 * D * d)
 
 
-def filter_combine(D):
-    return (mm(D, D, D) + tria(2 * D, 2 * D) + trsolve(D, D) + mm(D, D, D) + 4 * D * D + 2 * mm(D, D, D)
-            + 8 * D * D + mm(D, D, D) + tria(D, 2 * D) + 2 * D * D + mm(D, D, D) + tria(D, 2 * D))
+def filter_combine(D, nj=None, ncj=None):
+    """Filtering operator with nj (ncj) leading columns of sqrtJ_j (sqrtC_j)
+    that can be nonzero: D, D for aggregates; d, D - d for one step's element."""
+    nj = D if nj is None else nj
+    ncj = D if ncj is None else ncj
+    return (mm(D, D, nj) + tria(2 * D, D + nj) + trsolve(D, D) + mm(D, D, D) + 2 * D * D + 2 * D * nj
+            + 2 * mm(D, D, D) + 6 * D * D + 2 * D * nj + mm(D, D, D) + tria(D, D + ncj) + 2 * D * D
+            + mm(D, D, nj) + tria(D, D + nj))
 
 
 def state_apply(D):
@@ -45,13 +51,11 @@ def state_apply(D):
             + 4 * D * D + mm(D, D, D) + tria(D, 2 * D))
 
 
-def kf_step(D, d):
-    return (mm(D, D, D) + 2 * D * D + tria(D, 2 * D) + mm(d, D, D) + tria(d + D, D) + 2 * d * D + trsolve(D, d)
-            + 2 * D * d)
-
-
-def smoother_element(D):
-    return mm(D, D, D) + 2 * D * D + tria(2 * D, 2 * D) + trsolve(D, D) + 2 * D * D
+def kf_step_with_smoothing_element(D, d):
+    """Kalman step whose prediction is the leading block of the 2D x 2D
+    smoothing-element tria, plus E, g of the previous step."""
+    return (mm(D, D, D) + 2 * D * D + tria(2 * D, 2 * D) + trsolve(D, D) + 2 * D * D + mm(d, D, D)
+            + tria(d + D, D) + 2 * d * D + trsolve(D, d) + 2 * D * d)
 
 
 def smoother_combine(D, with_cov=False):
@@ -62,21 +66,25 @@ def smoother_apply(D, with_cov=False):
     return 2 * D * D + ((mm(D, D, D) + tria(D, 2 * D)) if with_cov else 0)
 
 
-def per_step(d, q, esize, b1=8):
-    """{kernel: (flops per step, bytes per step)} for a means-only iteration."""
+def per_step(d, q, esize, b1=32, bs1=8):
+    """{kernel: (flops per step, bytes per step)} for a means-only iteration,
+    with forward chunks of b1 steps and reverse chunks of bs1 steps.  The tree
+    kernels are charged per step as their per-aggregate work / b1."""
     D = d * (q + 1)
     DP = D * (D + 1) // 2
     FE, FS, SE, SA = 3 * D * D + 2 * D, D + D * D, D * D + D, 2 * D * D + D
     s = esize
     return {
-        "fwd_reduce1": (obs_setup(D, d) + filter_element(D, d) + filter_combine(D) * (b1 - 1) / b1,
-                        s * (d + FE / b1)),
-        "fwd_down1": (obs_setup(D, d) + kf_step(D, d), s * (d + FS / b1 + D + DP)),
-        "smoother_elements": (smoother_element(D), s * (D + DP + SE)),
-        "bwd_reduce1": (smoother_combine(D) * (b1 - 1) / b1, s * (SE + SA / b1)),
-        "bwd_down1": (smoother_apply(D), s * (SE + 2 * D + FS / b1)),
+        "fwd_reduce1": (obs_setup(D, d) + filter_element(D, d) + filter_combine(D, d, D - d) * (b1 - 1) / b1,
+                        16 * D + s * FE / b1),
+        "fwd_tree_up": (filter_combine(D) / b1, s * 2 * FE / b1),
+        "fwd_tree_down": (state_apply(D) / b1, s * (FE + 2 * FS) / b1),
+        "fwd_down1": (obs_setup(D, d) + kf_step_with_smoothing_element(D, d),
+                      16 * D + s * (FS / b1 + SE + DP)),
+        "bwd_reduce1": (smoother_combine(D) * (bs1 - 1) / bs1, s * (SE + SA / bs1)),
+        "bwd_down1": (smoother_apply(D), s * (SE + FS / bs1) + 16 * D),
     }
 
 
-def iteration_flops(d, q, b1=8):
+def iteration_flops(d, q, b1=32):
     return sum(v[0] for v in per_step(d, q, 4, b1).values())

@@ -172,11 +172,17 @@ struct Layout {
     size_t off_consts, off_T, off_dbits, total;
 };
 
+// Forward chunk: long enough that the step-level aggregates (folded with the
+// cheaper single-element operator) leave little work for the upper tree levels,
+// short enough that about 8192 groups keep every SIMD busy.
 parapn::ScanPlan default_plan(int64_t N)
 {
     parapn::ScanPlan p;
     p.N = N;
-    p.b1 = 8;
+    int b1 = 4;
+    while (b1 < 32 && N / (2 * b1) >= 8192) b1 *= 2;
+    p.b1 = b1;
+    p.bs1 = 8;
     p.bu = 8;
     p.btop = 16;
     return p;
@@ -198,12 +204,11 @@ Layout make_layout(int D, int64_t N, int esz, bool cov, const parapn::ScanPlan &
     L.off_mf = take(rows * D);
     L.off_sPf = take(rows * DP);
     L.off_se = take(rows * (D * D + D));
-    L.off_sL = cov ? take(rows * DP) : 0;
+    L.off_sL = take(rows * DP);
     L.off_sPs = cov ? take(rows * DP) : 0;
     const size_t fagg = parapn::work_elems_fagg(D, plan);
-    const size_t frec = fagg / (3 * D * D + 2 * D);
     L.off_fagg = take(fagg);
-    L.off_fpref = take(frec * (D + D * D));
+    L.off_fpref = take(parapn::work_records_fpref(plan) * (D + D * D));
     const size_t sagg = parapn::work_elems_sagg(D, plan);
     const size_t srec = sagg / (2 * D * D + D);
     L.off_sagg = take(sagg);
@@ -352,8 +357,9 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     if (!taylor_mu0(p->field, d, prm, p->y0, q, mu0.data())) return fail(PARAPN_EINVAL, "field not available for d");
     for (int k = 0; k < D; ++k)
         if (!std::isfinite(mu0[k])) return fail(PARAPN_EINVAL, "non-finite initial derivatives");
-    // Phi | sQ | S0 (= 0) | m0: the scans run on the increment over the
-    // trajectory, whose row 0 is mu0 itself, so the initial increment is 0
+    // Phi | sQ | m0 (= 0) | S0 (= 0): the scans run on the increment over the
+    // trajectory, whose row 0 is mu0 itself, so the initial increment is 0;
+    // (m0, S0) is one contiguous initial-state record
     std::vector<double> cst(3 * D * D + D, 0.0);
     for (int i = 0; i < D * D; ++i) {
         cst[i] = Phi[i];
@@ -378,15 +384,16 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     parapn::ModelDev m;
     m.Phi = cdev;
     m.sQ = cdev + (size_t)D * D * esz;
-    m.S0 = cdev + (size_t)2 * D * D * esz;
-    m.m0 = cdev + (size_t)3 * D * D * esz;
+    m.m0 = cdev + (size_t)2 * D * D * esz;
+    m.S0 = cdev + (size_t)(2 * D * D + D) * esz;
+    m.init = m.m0;
 
     parapn::Work w{};
     w.traj = ws + L.off_traj;
     w.mf = ws + L.off_mf;
     w.sPf = ws + L.off_sPf;
     w.se = ws + L.off_se;
-    w.sL = want_cov ? ws + L.off_sL : nullptr;
+    w.sL = ws + L.off_sL;
     w.sPs = want_cov ? ws + L.off_sPs : nullptr;
     w.fagg = ws + L.off_fagg;
     w.fpref = ws + L.off_fpref;
@@ -499,13 +506,17 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     int rc = ensure_ws(ctx, L.total);
     if (rc) return rc;
     char *ws = (char *)ctx->ws;
-    char *S0c = ws + L.off_consts;  // canonical lower factor of Sigma0
+    // initial-state record: mu0 followed by the canonical lower factor of Sigma0
+    char *init = ws + L.off_consts;
+    char *S0c = init + (size_t)D * esz;
+    PARAPN_HIP(hipMemcpyAsync(init, mu0, (size_t)D * esz, hipMemcpyDeviceToDevice, s), "copy mu0");
     PARAPN_HIP(parapn::launch_tria_square(fp64, d, q, sqrt_sigma0, S0c, s), "canonicalise sqrt_sigma0");
     parapn::ModelDev m;
     m.Phi = Phi;
     m.sQ = sqrtQ;
-    m.m0 = mu0;
+    m.m0 = init;
     m.S0 = S0c;
+    m.init = init;
     parapn::Work w{};
     w.traj = ws + L.off_traj;
     w.mf = ws + L.off_mf;
@@ -513,6 +524,8 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     w.se = ws + L.off_se;
     w.sL = ws + L.off_sL;
     w.sPs = ws + L.off_sPs;
+    w.filt_mf = (filt_mean_out || filt_sqrtcov_out) ? w.mf : nullptr;
+    w.filt_sPf = (filt_mean_out || filt_sqrtcov_out) ? w.sPf : nullptr;
     w.fagg = ws + L.off_fagg;
     w.fpref = ws + L.off_fpref;
     w.sagg = ws + L.off_sagg;

@@ -28,7 +28,8 @@ struct ObsSpec {
 // Chunk sizes of the hierarchical scans.
 struct ScanPlan {
     int64_t N;     // steps (elements n = 1..N for the filter, 0..N for the smoother)
-    int b1;        // steps per group in the step-level kernels
+    int b1;        // steps per group in the forward step-level kernels
+    int bs1;       // steps per group in the reverse step-level kernels (8)
     int bu;        // aggregates per group in the upper levels
     int btop;      // largest count handled by the single-group top scan
 };
@@ -39,8 +40,10 @@ struct Work {
     void *mf;      // [N+1][D]   filtered means
     void *sPf;     // [N+1][DP]  filtered factors, packed lower rows
     void *se;      // [N+1][D*D+D] smoothing elements (E, g)
-    void *sL;      // [N+1][DP]  smoothing element factors (covariance pass)
+    void *sL;      // [N+1][DP]  smoothing element factors
     void *sPs;     // [N+1][DP]  smoothed factors (covariance pass)
+    void *filt_mf; // [N+1][D]   filtered means, or null when not wanted
+    void *filt_sPf;// [N+1][DP]  filtered factors, or null when not wanted
     void *fagg;    // filter aggregates, all levels
     void *fpref;   // filter prefix states, all levels
     void *sagg;    // smoother aggregates, all levels
@@ -55,6 +58,7 @@ struct ModelDev {
     const void *sQ;
     const void *m0;
     const void *S0;
+    const void *init;  // the initial state as one record: m0 [D] followed by S0 [D][D]
 };
 
 struct Dims {
@@ -64,6 +68,7 @@ struct Dims {
 // workspace sizes in elements for a plan
 size_t work_elems_fagg(int D, const ScanPlan &p);
 size_t work_elems_sagg(int D, const ScanPlan &p);
+size_t work_records_fpref(const ScanPlan &p);
 
 // Launch sequences.  Each returns hipSuccess or the first launch error.
 // T selects the precision (float or double) via `fp64`.

@@ -22,46 +22,67 @@
 #include "parapn_internal.h"
 #include "rowalg.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <string>
 #include <vector>
 
 namespace parapn {
 
-template <typename T_, int d_, int q_>
+constexpr int pow2floor(int x)
+{
+    int p = 1;
+    while (2 * p <= x) p <<= 1;
+    return p;
+}
+
+// Configuration of one (precision, d, q).  Filter-side kernels give each
+// element 2D rows (R = next power of two >= 2D lanes); the smoother-side
+// kernels only need D rows and use RS lanes.
+template <typename T_, int d_, int q_, int RS_ = 0>
 struct Cfg {
     using T = T_;
     static constexpr int d = d_, q = q_, S = q_ + 1, D = d_ * (q_ + 1);
     static constexpr int D2 = 2 * D;
     static constexpr int DP = D * (D + 1) / 2;
-    static constexpr int R = pow2ceil(D2);  // lanes per group
+    static constexpr int B1 = 8;  // steps per group in the smoother's step-level kernels (prefetched)
+    static constexpr int R = RS_ ? RS_ : pow2ceil(D2);  // lanes per group
     static constexpr int LDM = D + 1;       // LDS row stride of D-wide blocks
     static constexpr int LDB = D2 + 1;      // LDS row stride of 2D-wide blocks
-    // per-group LDS layout (in T units)
+    // per-group LDS layout (in T units).  The smoother side (RS_ != 0) only
+    // uses TR, M0, M1 and V0; its other regions have size zero.
+    static constexpr int F1 = RS_ ? 0 : 1;
     static constexpr int TR = 0;
     static constexpr int BIG = TR + 2 * (D2 + 1);
-    static constexpr int M0 = BIG + D2 * LDB;
+    static constexpr int M0 = BIG + F1 * D2 * LDB;
     static constexpr int M1 = M0 + D * LDM;
     static constexpr int M2 = M1 + D * LDM;
-    static constexpr int M3 = M2 + D * LDM;
-    static constexpr int M4 = M3 + D * LDM;
-    static constexpr int M5 = M4 + D * LDM;
-    static constexpr int V0 = M5 + D * LDM;
+    static constexpr int M3 = M2 + F1 * D * LDM;
+    static constexpr int M4 = M3 + F1 * D * LDM;
+    static constexpr int M5 = M4 + F1 * D * LDM;
+    static constexpr int V0 = M5 + F1 * D * LDM;
     static constexpr int V1 = V0 + LDM;
-    static constexpr int V2 = V1 + LDM;
-    static constexpr int V3 = V2 + LDM;
-    static constexpr int V4 = V3 + LDM;
-    static constexpr int V5 = V4 + LDM;
-    static constexpr int HO = V5 + LDM;   // H   (d x LDM)
-    static constexpr int HPO = HO + d * LDM;  // H Phi (d x LDM)
-    static constexpr int DVO = HPO + d * LDM; // residual r (d)
-    static constexpr int UO = DVO + d + 1;    // prior offset u (D)
-    static constexpr int SH = UO + LDM;
+    static constexpr int V2 = V1 + F1 * LDM;
+    static constexpr int V3 = V2 + F1 * LDM;
+    static constexpr int V4 = V3 + F1 * LDM;
+    static constexpr int V5 = V4 + F1 * LDM;
+    static constexpr int HO = V5 + F1 * LDM;        // H   (d x LDM)
+    static constexpr int HPO = HO + F1 * d * LDM;   // H Phi (d x LDM)
+    static constexpr int DVO = HPO + F1 * d * LDM;  // residual r (d)
+    static constexpr int UO = DVO + F1 * (d + 1);   // prior offset u (D)
+    static constexpr int SH = UO + F1 * LDM;
     // block: groups per block chosen so that a block's LDS stays <= 64 KiB
-    static constexpr int GPB_MAX = 256 / R;
-    static constexpr int GPB_FIT = (65536 / (int)sizeof(T) - 2 * D * LDM) / SH;
-    static constexpr int GPB = GPB_FIT >= GPB_MAX ? GPB_MAX : (GPB_FIT >= 8 ? 8 : (GPB_FIT >= 4 ? 4 : (GPB_FIT >= 2 ? 2 : 1)));
+    static constexpr int FE_ = 3 * D * D + 2 * D;
+    // filter side: at most 16 groups per block (the tree width the workspace sizing covers)
+    static constexpr int GPB_MAX = RS_ ? 256 / R : (256 / R < 16 ? 256 / R : 16);
+    // room for the group scratch plus (filter side) one exchanged element per
+    // group in the tree kernels; a block stays within 64 KiB of LDS
+    static constexpr int GPB_FIT = (65536 / (int)sizeof(T) - 2 * D * LDM) / (SH + (RS_ ? 0 : FE_));
+    static constexpr int GPB_P = pow2floor(GPB_FIT < GPB_MAX ? GPB_FIT : GPB_MAX);
+    static constexpr int GPB = GPB_P >= 2 ? GPB_P : 2;
     static constexpr int NT = GPB * R;
+    // tree width of the upper scan levels (one leaf per group of a block)
+    static constexpr int W = GPB;
     // record sizes (T units)
     static constexpr int FE = 3 * D * D + 2 * D;  // filter element / aggregate: A, b, sqrtC, eta, sqrtJ
     static constexpr int FS = D + D * D;          // filter state: mean, factor
@@ -360,38 +381,40 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
 //   sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i]).
 // (F^T = I - Xi21 Xi11^{-1} sqrtC_i^T, the factor of the eta formula.)
 // ---------------------------------------------------------------------------
-template <class C, bool STATE_ONLY>
+// NJ: number of leading columns of sqrtJ_j that can be nonzero (D for an
+// aggregate, d for a single step's element, whose sqrtJ is D x d).  The
+// remaining columns of the first block of the Xi stack are zero and are left
+// out of the tria; Xi11, Xi21 are unchanged and Xi22 keeps its NJ columns.
+template <class C, int NJ>
 PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sCi)[C::D],
                            const typename C::T (&sJj)[C::D], typename C::T (&G)[C::D], typename C::T (&F)[C::D])
 {
     using T = typename C::T;
-    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB, NC = NJ + D;
     T *M0 = sh + C::M0, *M1 = sh + C::M1;
     put_rows<T, D, D>(M0, LDM, lane, sCi);
     put_rows<T, D, D>(M1, LDM, lane, sJj);
     wave_sync();
-    T w[D2];
+    T w[NC];
     if (lane < D) {
-        T t[D];
-        rowT_times<T, D, D>(t, lane, M0, LDM, M1, LDM);
+        T t[NJ];
+        rowT_times<T, D, NJ>(t, lane, M0, LDM, M1, LDM);
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            w[c] = t[c];
-            w[D + c] = (c == lane) ? T(1) : T(0);
-        }
+        for (int c = 0; c < NJ; ++c) w[c] = t[c];
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[NJ + c] = (c == lane) ? T(1) : T(0);
     } else if (lane < D2) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            w[c] = M1[(lane - D) * LDM + c];
-            w[D + c] = 0;
-        }
+        for (int c = 0; c < NJ; ++c) w[c] = M1[(lane - D) * LDM + c];
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[NJ + c] = 0;
     } else {
 #pragma unroll
-        for (int c = 0; c < D2; ++c) w[c] = 0;
+        for (int c = 0; c < NC; ++c) w[c] = 0;
     }
-    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
+    tria_rows<T, D2, NC>(w, lane, sh + C::TR);
     T *Xi = sh + C::BIG;
-    put_rows<T, D2, D2>(Xi, LDB, lane, w);
+    put_rows<T, D2, NC>(Xi, LDB, lane, w);
     wave_sync();
     // G row = sqrtC_i row * Xi11^{-T}
     solve_xLt<T, D>(G, sCi, Xi, LDB);
@@ -404,13 +427,15 @@ PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sC
     }
 }
 
-template <class C>
+// NJ, NCJ: leading columns of sqrtJ_j and sqrtC_j that can be nonzero
+// (D, D for aggregates; d, D - d for a single step's element).
+template <class C, int NJ, int NCJ>
 PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei, const FRow<C> &ej)
 {
     using T = typename C::T;
-    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
+    constexpr int D = C::D, LDM = C::LDM, LDB = C::LDB;
     T G[D], F[D];
-    xi_and_G_F<C, false>(lane, sh, ei.sC, ej.sJ, G, F);
+    xi_and_G_F<C, NJ>(lane, sh, ei.sC, ej.sJ, G, F);
     T *M0 = sh + C::M0, *M1 = sh + C::M1, *M2 = sh + C::M2, *M3 = sh + C::M3, *M4 = sh + C::M4;
     T *V0 = sh + C::V0, *V1 = sh + C::V1, *V2 = sh + C::V2, *V3 = sh + C::V3, *V4 = sh + C::V4, *V5 = sh + C::V5;
     const T *Xi = sh + C::BIG;
@@ -426,10 +451,10 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     if (lane < D) {
         T wv = 0, uu = 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            wv += M0[k * LDM + lane] * V0[k];
-            uu += M1[k * LDM + lane] * V1[k];
-        }
+        for (int k = 0; k < D; ++k) wv += M0[k * LDM + lane] * V0[k];
+        if (lane < NJ)
+#pragma unroll
+            for (int k = 0; k < D; ++k) uu += M1[k * LDM + lane] * V1[k];
         V2[lane] = wv;
         V3[lane] = uu;
     }
@@ -442,10 +467,9 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
         // v = b_i + sqrtC_i wv ;  z = eta_j - sqrtJ_j u
         T v = ei.b, z = ej.eta;
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            v += ei.sC[c] * V2[c];
-            z -= ej.sJ[c] * V3[c];
-        }
+        for (int c = 0; c < D; ++c) v += ei.sC[c] * V2[c];
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) z -= ej.sJ[c] * V3[c];
         V4[lane] = v;
         V5[lane] = z;
     }
@@ -465,20 +489,19 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     wave_sync();
     // sqrtC_ij = tria([A_j G, sqrtC_j])
     {
-        T w[D2];
+        T w[D + NCJ];
         if (lane < D) {
             T t[D];
             row_times<T, D, D>(t, ej.A, M4, LDM);
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                w[c] = t[c];
-                w[D + c] = ej.sC[c];
-            }
+            for (int c = 0; c < D; ++c) w[c] = t[c];
+#pragma unroll
+            for (int c = 0; c < NCJ; ++c) w[D + c] = ej.sC[c];
         } else {
 #pragma unroll
-            for (int c = 0; c < D2; ++c) w[c] = 0;
+            for (int c = 0; c < D + NCJ; ++c) w[c] = 0;
         }
-        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+        tria_rows<T, D, D + NCJ>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sC[c] = lane < D ? w[c] : T(0);
     }
@@ -489,22 +512,21 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
         for (int k = 0; k < D; ++k) et += M3[k * LDM + lane] * V0[k];
         o.eta = et;
     }
-    // sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i])
+    // sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i]),  Xi22 has NJ columns
     {
-        T w[D2];
+        T w[NJ + D];
         if (lane < D) {
-            T t[D];
-            rowT_times<T, D, D>(t, lane, M3, LDM, Xi + D * LDB + D, LDB);
+            T t[NJ];
+            rowT_times<T, D, NJ>(t, lane, M3, LDM, Xi + D * LDB + D, LDB);
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                w[c] = t[c];
-                w[D + c] = ei.sJ[c];
-            }
+            for (int c = 0; c < NJ; ++c) w[c] = t[c];
+#pragma unroll
+            for (int c = 0; c < D; ++c) w[NJ + c] = ei.sJ[c];
         } else {
 #pragma unroll
-            for (int c = 0; c < D2; ++c) w[c] = 0;
+            for (int c = 0; c < NJ + D; ++c) w[c] = 0;
         }
-        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+        tria_rows<T, D, NJ + D>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sJ[c] = lane < D ? w[c] : T(0);
     }
@@ -520,7 +542,7 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
     using T = typename C::T;
     constexpr int D = C::D, D2 = C::D2, LDM = C::LDM;
     T G[D], F[D];
-    xi_and_G_F<C, true>(lane, sh, s.P, ej.sJ, G, F);
+    xi_and_G_F<C, C::D>(lane, sh, s.P, ej.sJ, G, F);
     T *M0 = sh + C::M0, *M2 = sh + C::M2, *M4 = sh + C::M4;
     T *V0 = sh + C::V0, *V2 = sh + C::V2, *V4 = sh + C::V4;
     if (lane < D) V0[lane] = ej.eta;
@@ -570,18 +592,25 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
     return o;
 }
 
-// Kalman predict + update from a state: the same quantity as state_apply
-// with the step's own element, computed without forming the element:
-//   m- = Phi m + u,  sqrtP- = tria([Phi sqrtP, sqrtQ]),
+// One Kalman step from the filtering marginal (m, sqrtP) of step n-1 --
+// the filtering operator applied to a prefix state, which has A = 0, eta = 0,
+// J = 0 -- together with the smoothing element of step n-1
+// (eq. sqrt-smoothing-elements).  The stacked tria
+//   Pi = tria([[Phi sqrtP, sqrtQ], [sqrtP, 0]])   (2D x 2D)
+// gives Pi11 = tria([Phi sqrtP, sqrtQ]), the predicted factor of step n (its
+// first D reflections are the prediction's), and
+//   E_{n-1} = Pi21 Pi11^{-1},  g_{n-1} = m - E_{n-1} m-,  sqrtL_{n-1} = Pi22,
+// with the predicted mean m- = Phi m + u_n.  The update is
 //   Psi = tria([[H sqrtP-], [sqrtP-]]),  K = Psi21 Psi11^{-1},
 //   m = m- + K (r - H m-),  sqrtP = Psi22.
+// The smoothing element comes back in lanes D..2D-1 (row lane - D).
 template <class C>
-PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
-                          const typename C::T *csq)
+PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
+                              const typename C::T *csq, ERow<C> &eo)
 {
     using T = typename C::T;
     constexpr int d = C::d, D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
-    T *M0 = sh + C::M0, *M1 = sh + C::M1, *V0 = sh + C::V0, *V1 = sh + C::V1;
+    T *M0 = sh + C::M0, *V0 = sh + C::V0, *V1 = sh + C::V1;
     put_rows<T, D, D>(M0, LDM, lane, s.P);
     if (lane < D) V0[lane] = s.m;
     wave_sync();
@@ -600,31 +629,52 @@ PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const 
             w[c] = t[c];
             w[D + c] = csq[lane * LDM + c];
         }
+    } else if (lane < D2) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            w[c] = M0[(lane - D) * LDM + c];
+            w[D + c] = 0;
+        }
     } else {
 #pragma unroll
         for (int c = 0; c < D2; ++c) w[c] = 0;
     }
-    tria_rows<T, D, D2>(w, lane, sh + C::TR);
-    // w[0..D-1] of lanes < D: sqrtP-
-    T pm[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) pm[c] = w[c];
-    put_rows<T, D, D>(M1, LDM, lane, pm);
+    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
+    T *Pi = sh + C::BIG;
+    put_rows<T, D2, D2>(Pi, LDB, lane, w);
     if (lane < D) V1[lane] = mp;
     wave_sync();
+    eo.g = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) eo.E[c] = eo.L[c] = 0;
+    if (lane >= D && lane < D2) {
+        T p21[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            p21[c] = w[c];
+            eo.L[c] = w[D + c];
+        }
+        solve_xL<T, D>(eo.E, p21, Pi, LDB);
+        T g = V0[lane - D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) g -= eo.E[c] * V1[c];
+        eo.g = g;
+    }
+    // update with the predicted factor Pi11 (rows 0..D-1 of Pi)
     T x[D];
     if (lane < d) {
         T hrow[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) hrow[c] = sh[C::HO + lane * LDM + c];
-        row_times<T, D, D>(x, hrow, M1, LDM);
+        row_times<T, D, D>(x, hrow, Pi, LDB);
     } else if (lane < d + D) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = M1[(lane - d) * LDM + c];
+        for (int c = 0; c < D; ++c) x[c] = Pi[(lane - d) * LDB + c];
     } else {
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = 0;
     }
+    wave_sync();
     tria_rows<T, d + D, D>(x, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
     put_rows<T, d + D, D>(Psi, LDB, lane, x);
@@ -658,70 +708,6 @@ PARAPN_DEV SRow<C> kf_step(int lane, typename C::T *sh, const SRow<C> &s, const 
 // ---------------------------------------------------------------------------
 // smoothing side (eq. sqrt-smoothing-elements, eq. sqrt-associative-smoothing)
 // ---------------------------------------------------------------------------
-// element of a step n < N from the filtering marginal (m^f_n, sqrtP^f_n):
-//   Pi = tria([[Phi sqrtP^f, sqrtQ], [sqrtP^f, 0]]),
-//   E = Pi21 Pi11^{-1},  g = m^f - E (Phi m^f + u_{n+1}),  sqrtL = Pi22,
-// with u_{n+1} the prior offset of the next step (zero in memory mode).
-template <class C>
-PARAPN_DEV ERow<C> smoother_element(int lane, typename C::T *sh, const SRow<C> &f, const typename C::T *cphi,
-                                   const typename C::T *csq, typename C::T unext)
-{
-    using T = typename C::T;
-    constexpr int D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
-    T *M0 = sh + C::M0, *V0 = sh + C::V0, *V1 = sh + C::V1;
-    put_rows<T, D, D>(M0, LDM, lane, f.P);
-    if (lane < D) V0[lane] = f.m;
-    wave_sync();
-    T w[D2];
-    if (lane < D) {
-        T phirow[D], t[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) phirow[k] = cphi[lane * LDM + k];
-        row_times<T, D, D>(t, phirow, M0, LDM);
-        T pm = unext;
-#pragma unroll
-        for (int k = 0; k < D; ++k) pm += phirow[k] * V0[k];
-        V1[lane] = pm;  // (Phi m^f + u_{n+1})_lane
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            w[c] = t[c];
-            w[D + c] = csq[lane * LDM + c];
-        }
-    } else if (lane < D2) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            w[c] = M0[(lane - D) * LDM + c];
-            w[D + c] = 0;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < D2; ++c) w[c] = 0;
-    }
-    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
-    T *Pi = sh + C::BIG;
-    put_rows<T, D2, D2>(Pi, LDB, lane, w);
-    wave_sync();
-    ERow<C> e;
-    e.g = 0;
-#pragma unroll
-    for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
-    if (lane < D) {
-        T p21[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            p21[c] = Pi[(D + lane) * LDB + c];
-            e.L[c] = Pi[(D + lane) * LDB + D + c];
-        }
-        solve_xL<T, D>(e.E, p21, Pi, LDB);
-        T g = f.m;
-#pragma unroll
-        for (int c = 0; c < D; ++c) g -= e.E[c] * V1[c];
-        e.g = g;
-    }
-    wave_sync();
-    return e;
-}
-
 // acc (x)_s b : E = E_acc E_b, g = E_acc g_b + g_acc, sqrtL = tria([E_acc sqrtL_b, sqrtL_acc])
 template <class C, bool WITH_L>
 PARAPN_DEV ERow<C> smoother_combine(int lane, typename C::T *sh, const ERow<C> &a, const ERow<C> &b)
@@ -864,140 +850,121 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
         if (n == s)
             acc = el;
         else
-            acc = filter_combine<C>(lane, sh, acc, el);
+            acc = filter_combine<C, C::d, C::D - C::d>(lane, sh, acc, el);
     }
     store_frow<C>(agg + chunk * C::FE, lane, acc);
 }
 
-// upper level, forward reduce of bu aggregates
+// Upper levels of the forward scan as in-workgroup trees: one leaf
+// aggregate per group, W leaves per block.  The up-sweep combines pairs at
+// doubling strides (depth log2 W) and keeps every left child for the
+// down-sweep; the down-sweep gives each right child the state of its parent
+// followed by its left sibling (Blelloch's schedule).  Node index of a left
+// child at stride s (s = 1, 2, ..) within a block: off(s) + g / (2s) with
+// off(s) = W - W/s, W - 1 nodes per block.
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_reduce(KArgs<C> a, const typename C::T *in, int64_t nin,
-                                                      typename C::T *out, int64_t nout)
+PARAPN_DEV int tree_node(int s, int g)
 {
-    PARAPN_GROUP_SETUP(C);
-    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nout) return;
-    const int64_t s = chunk * a.bu;
-    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
-    FRow<C> acc = load_frow<C>(in + s * C::FE, lane);
-    for (int64_t i = s + 1; i < e; ++i) {
-        FRow<C> el = load_frow<C>(in + i * C::FE, lane);
-        acc = filter_combine<C>(lane, sh, acc, el);
-    }
-    store_frow<C>(out + chunk * C::FE, lane, acc);
+    return C::W - C::W / s + g / (2 * s);
 }
 
-// top: exclusive scan of n aggregates from the initial state (m0, S0)
 template <class C>
-__global__ __launch_bounds__(C::R) void k_fwd_top(KArgs<C> a, const typename C::T *agg, int64_t n,
-                                                   typename C::T *pref)
+__global__ __launch_bounds__(C::NT) void k_fwd_tree_up(const typename C::T *in, int64_t nin, typename C::T *out,
+                                                       typename C::T *part)
 {
     PARAPN_GROUP_SETUP(C);
-    if (grp != 0) return;
-    SRow<C> st;
-    st.m = 0;
-#pragma unroll
-    for (int c = 0; c < C::D; ++c) st.P[c] = 0;
-    if (lane < C::D) {
-        st.m = a.m0[lane];
-#pragma unroll
-        for (int c = 0; c < C::D; ++c) st.P[c] = a.S0[lane * C::D + c];
-    }
-    for (int64_t i = 0; i < n; ++i) {
-        store_state<C>(pref + i * C::FS, lane, st);
-        if (i + 1 < n) {
-            FRow<C> el = load_frow<C>(agg + i * C::FE, lane);
-            st = state_apply<C>(lane, sh, st, el);
+    __shared__ T xch[C::GPB * C::FE];
+    const int64_t base = (int64_t)blockIdx.x * C::W;
+    const int64_t leaf = base + grp;
+    FRow<C> acc;
+    if (leaf < nin)
+        acc = load_frow<C>(in + leaf * C::FE, lane);
+    else
+        zero(acc);
+    for (int s = 1; s < C::W; s <<= 1) {
+        if (grp % (2 * s) == s && leaf < nin) store_frow<C>(xch + grp * C::FE, lane, acc);
+        __syncthreads();
+        if (grp % (2 * s) == 0 && leaf < nin) {
+            store_frow<C>(part + ((int64_t)blockIdx.x * (C::W - 1) + tree_node<C>(s, grp)) * C::FE, lane, acc);
+            if (leaf + s < nin) {
+                FRow<C> r = load_frow<C>(xch + (grp + s) * C::FE, lane);
+                acc = filter_combine<C, C::D, C::D>(lane, sh, acc, r);
+            }
         }
+        __syncthreads();
     }
+    if (grp == 0 && out) store_frow<C>(out + blockIdx.x * C::FE, lane, acc);
 }
 
-// upper level, forward down-sweep: prefix states of bu aggregates
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_down(KArgs<C> a, const typename C::T *agg, int64_t nin,
-                                                    const typename C::T *pref_up, typename C::T *pref, int64_t nup)
+__global__ __launch_bounds__(C::NT) void k_fwd_tree_down(int64_t nin, const typename C::T *part,
+                                                         const typename C::T *pref_up, typename C::T *pref)
 {
     PARAPN_GROUP_SETUP(C);
-    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nup) return;
-    const int64_t s = chunk * a.bu;
-    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
-    SRow<C> st = load_state<C>(pref_up + chunk * C::FS, lane);
-    for (int64_t i = s; i < e; ++i) {
-        store_state<C>(pref + i * C::FS, lane, st);
-        if (i + 1 < e) {
-            FRow<C> el = load_frow<C>(agg + i * C::FE, lane);
-            st = state_apply<C>(lane, sh, st, el);
+    __shared__ T xch[C::GPB * C::FS];
+    const int64_t base = (int64_t)blockIdx.x * C::W;
+    const int64_t leaf = base + grp;
+    SRow<C> st = load_state<C>(pref_up + (int64_t)blockIdx.x * C::FS, lane);
+    for (int s = C::W / 2; s >= 1; s >>= 1) {
+        if (grp % (2 * s) == 0 && leaf + s < nin) {
+            FRow<C> left =
+                load_frow<C>(part + ((int64_t)blockIdx.x * (C::W - 1) + tree_node<C>(s, grp)) * C::FE, lane);
+            SRow<C> r = state_apply<C>(lane, sh, st, left);
+            store_state<C>(xch + (grp + s) * C::FS, lane, r);
         }
+        __syncthreads();
+        if (grp % (2 * s) == s && leaf < nin) st = load_state<C>(xch + grp * C::FS, lane);
+        __syncthreads();
     }
+    if (leaf < nin) store_state<C>(pref + leaf * C::FS, lane, st);
 }
 
-// step level, forward down-sweep: Kalman steps from the chunk's prefix state,
-// writing the filtering marginals m^f_n, sqrtP^f_n (packed) for n in the chunk
+// step level, forward down-sweep: Kalman steps from the chunk's prefix state.
+// The smoothing element of a step is formed from its filtering marginal
+// inside the next step's Kalman step, so a chunk covering steps s..e-1 writes
+// the elements (E, g) and sqrtL of steps s-1..e-2; the chunk holding step N
+// also writes the last element (E = 0, g = m^f_N, sqrtL = sqrtP^f_N).
+// Filtering marginals are written only when mf is given.
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename C::T *pref, int64_t nchunks,
-                                                     typename C::T *mf, typename C::T *sPf)
+                                                     typename C::T *se, typename C::T *sL, typename C::T *mf,
+                                                     typename C::T *sPf)
 {
     PARAPN_GROUP_SETUP(C);
     load_consts<C>(cphi, csq, a.Phi, a.sQ);
+    constexpr int D = C::D;
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= nchunks) return;
     const int64_t s = 1 + chunk * a.b1;
     const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
     SRow<C> st = load_state<C>(pref + chunk * C::FS, lane);
-    if (chunk == 0 && lane < C::D) {
+    if (chunk == 0 && mf && lane < D) {
         mf[lane] = st.m;
         store_packed<C>(sPf, lane, st.P);
     }
     for (int64_t n = s; n < e; ++n) {
         obs_setup<C>(a.obs, n, lane, sh, cphi);
-        st = kf_step<C>(lane, sh, st, cphi, csq);
-        if (lane < C::D) {
-            mf[n * C::D + lane] = st.m;
+        ERow<C> eo;
+        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo);
+        if (lane >= D && lane < C::D2) {
+            const int r = lane - D;
+            T *rec = se + (n - 1) * C::SE;
+#pragma unroll
+            for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
+            rec[D * D + r] = eo.g;
+            store_packed<C>(sL + (n - 1) * C::DP, r, eo.L);
+        }
+        if (mf && lane < D) {
+            mf[n * D + lane] = st.m;
             store_packed<C>(sPf + n * C::DP, lane, st.P);
         }
     }
-}
-
-// smoothing elements for n = 0..N: (E, g) and, with WITH_L, sqrtL (packed)
-template <class C, bool WITH_L>
-__global__ __launch_bounds__(C::NT) void k_smoother_elements(KArgs<C> a, const typename C::T *mf,
-                                                             const typename C::T *sPf, typename C::T *se,
-                                                             typename C::T *sL)
-{
-    PARAPN_GROUP_SETUP(C);
-    load_consts<C>(cphi, csq, a.Phi, a.sQ);
-    const int64_t n = (int64_t)blockIdx.x * C::GPB + grp;
-    if (n > a.N) return;
-    constexpr int D = C::D;
-    SRow<C> f;
-    f.m = lane < D ? mf[n * D + lane] : T(0);
-    load_packed<C>(f.P, sPf + n * C::DP, lane);
-    ERow<C> e;
-    if (n == a.N) {  // last element: the filtering marginal itself (E = 0)
-        e.g = f.m;
+    if (e == a.N + 1 && lane < D) {
+        T *rec = se + a.N * C::SE;
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            e.E[c] = 0;
-            e.L[c] = f.P[c];
-        }
-    } else {
-        T un = 0;
-        if (a.traj && lane < D) {
-            const double *tn = a.traj + n * D;
-            double u = -tn[D + lane];
-#pragma unroll
-            for (int k = 0; k < D; ++k) u += (double)cphi[lane * C::LDM + k] * tn[k];
-            un = (T)u;
-        }
-        e = smoother_element<C>(lane, sh, f, cphi, csq, un);
-    }
-    if (lane < D) {
-        T *rec = se + n * C::SE;
-#pragma unroll
-        for (int c = 0; c < D; ++c) rec[lane * D + c] = e.E[c];
-        rec[D * D + lane] = e.g;
-        if (WITH_L) store_packed<C>(sL + n * C::DP, lane, e.L);
+        for (int c = 0; c < D; ++c) rec[lane * D + c] = 0;
+        rec[D * D + lane] = st.m;
+        store_packed<C>(sL + a.N * C::DP, lane, st.P);
     }
 }
 
@@ -1060,13 +1027,23 @@ __global__ __launch_bounds__(C::NT) void k_bwd_reduce1(KArgs<C> a, const typenam
     PARAPN_GROUP_SETUP(C);
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= nchunks) return;
-    const int64_t s = chunk * a.b1;
-    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
-    ERow<C> acc = load_selem<C, WITH_L>(se, sL, s, lane);
-    for (int64_t n = s + 1; n < e; ++n) {
-        ERow<C> el = load_selem<C, WITH_L>(se, sL, n, lane);
-        acc = smoother_combine<C, WITH_L>(lane, sh, acc, el);
+    const int64_t s = chunk * C::B1;
+    const int cnt = (int)(s + C::B1 <= a.N + 1 ? C::B1 : a.N + 1 - s);
+    // the chunk's elements are loaded up front so the fold does not wait on
+    // memory (unless they would not fit in registers: factors at large D)
+    constexpr bool PREFETCH = !WITH_L || C::D <= 8;
+    constexpr int NB = PREFETCH ? C::B1 : 1;
+    ERow<C> els[NB];
+    if (PREFETCH) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, s + i, lane);
     }
+    ERow<C> acc = load_selem<C, WITH_L>(se, sL, s, lane);
+#pragma unroll
+    for (int i = 1; i < C::B1; ++i)
+        if (i < cnt) acc = smoother_combine<C, WITH_L>(lane, sh, acc, PREFETCH ? els[i % NB] :
+                                                       load_selem<C, WITH_L>(se, sL, s + i, lane));
     store_sagg<C>(agg + chunk * C::SA, lane, acc);
 }
 
@@ -1142,16 +1119,32 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= nchunks) return;
     constexpr int D = C::D;
-    const int64_t s = chunk * a.b1;
-    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    const int64_t s = chunk * C::B1;
+    const int cnt = (int)(s + C::B1 <= a.N + 1 ? C::B1 : a.N + 1 - s);
+    constexpr bool PREFETCH = !WITH_L || C::D <= 8;
+    constexpr int NB = PREFETCH ? C::B1 : 1;
+    ERow<C> els[NB];
+    if (PREFETCH) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, s + i, lane);
+    }
+    double told[C::B1];
+    if (UPDATE) {
+#pragma unroll
+        for (int i = 0; i < C::B1; ++i) told[i] = (i < cnt && lane < D) ? trajd[(s + i) * D + lane] : 0.0;
+    }
     SRow<C> st = load_state<C>(suf + chunk * C::SS, lane);
     double dmax = 0.0, mmax = 0.0;
-    for (int64_t n = e - 1; n >= s; --n) {
-        ERow<C> el = load_selem<C, WITH_L>(se, sL, n, lane);
-        st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+#pragma unroll
+    for (int i = C::B1 - 1; i >= 0; --i) {
+        if (i >= cnt) continue;
+        const int64_t n = s + i;
+        st = smoother_apply<C, WITH_L>(lane, sh, PREFETCH ? els[i % NB] : load_selem<C, WITH_L>(se, sL, n, lane),
+                                       st);
         if (lane < D) {
             if (UPDATE) {
-                const double nw = trajd[n * D + lane] + (double)st.m;
+                const double nw = told[i] + (double)st.m;
                 if (lane % C::S == 0) {
                     const double df = fabs(T0 * (double)st.m);
                     dmax = (df > dmax || df != df) ? df : dmax;
@@ -1196,7 +1189,7 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
     if (k >= count) return;
     FRow<C> ei = load_frow<C>(aa + k * C::FE, lane);
     FRow<C> ej = load_frow<C>(cc + k * C::FE, lane);
-    FRow<C> o = filter_combine<C>(lane, sh, ei, ej);
+    FRow<C> o = filter_combine<C, C::D, C::D>(lane, sh, ei, ej);
     store_frow<C>(out + k * C::FE, lane, o);
 }
 
@@ -1212,14 +1205,43 @@ struct Levels {
     int64_t total;
 };
 
-static Levels make_levels(int64_t nitems, const ScanPlan &p)
+// forward scan levels: n[1] = cdiv(N, b1) step aggregates, then trees of
+// width W until at most W remain (the top tree).  poff[l]: record offset of
+// the tree partials of the launch that reduces level l (l = 1..L; level L is
+// the single-block top tree).
+struct TreeLevels {
+    int L;
+    int64_t n[48], off[48], poff[48];
+    int64_t total, ptotal;
+};
+
+static TreeLevels make_tree_levels(int64_t N, int b1, int W)
+{
+    TreeLevels t{};
+    t.L = 1;
+    t.n[1] = (N + b1 - 1) / b1;
+    t.off[1] = 0;
+    t.poff[1] = 0;
+    while (t.n[t.L] > W && t.L < 46) {
+        const int64_t nb = (t.n[t.L] + W - 1) / W;
+        t.n[t.L + 1] = nb;
+        t.off[t.L + 1] = t.off[t.L] + t.n[t.L];
+        t.poff[t.L + 1] = t.poff[t.L] + nb * (W - 1);
+        ++t.L;
+    }
+    t.total = t.off[t.L] + t.n[t.L];
+    t.ptotal = t.poff[t.L] + (W - 1);
+    return t;
+}
+
+static Levels make_levels(int64_t nitems, int b1, int bu, int btop)
 {
     Levels lv{};
     lv.L = 1;
-    lv.n[1] = cdiv(nitems, p.b1);
+    lv.n[1] = cdiv(nitems, b1);
     lv.off[1] = 0;
-    while (lv.n[lv.L] > p.btop && lv.L < 46) {
-        lv.n[lv.L + 1] = cdiv(lv.n[lv.L], p.bu);
+    while (lv.n[lv.L] > btop && lv.L < 46) {
+        lv.n[lv.L + 1] = cdiv(lv.n[lv.L], bu);
         lv.off[lv.L + 1] = lv.off[lv.L] + lv.n[lv.L];
         ++lv.L;
     }
@@ -1258,38 +1280,44 @@ template <class C>
 static hipError_t fwd_seq(const ScanPlan &p, const ModelDev &m, const ObsSpec &o, const Work &w, hipStream_t s)
 {
     using T = typename C::T;
+    if (p.b1 < 1) return hipErrorInvalidValue;
     KArgs<C> a = make_args<C>(p, m, &o);
-    Levels lv = make_levels(p.N, p);
+    TreeLevels lv = make_tree_levels(p.N, p.b1, C::W);
     T *agg = (T *)w.fagg, *pref = (T *)w.fpref;
+    T *part = agg + lv.total * C::FE;  // the sizing reserves W = 2 worth of partials
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
-    PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, agg + lv.off[1] * C::FE,
-                       lv.n[1]);
+    PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
+                  agg + lv.off[1] * C::FE, lv.n[1]);
     for (int l = 1; l < lv.L; ++l)
-        PARAPN_LAUNCH("fwd_reduce", s, k_fwd_reduce<C>, dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
-                           agg + lv.off[l] * C::FE, lv.n[l], agg + lv.off[l + 1] * C::FE, lv.n[l + 1]);
-    PARAPN_LAUNCH("fwd_top", s, k_fwd_top<C>, dim3(1), dim3(C::R), 0, s, a, agg + lv.off[lv.L] * C::FE, lv.n[lv.L],
-                       pref + lv.off[lv.L] * C::FS);
+        PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)lv.n[l + 1]), dim3(C::NT), 0, s,
+                      agg + lv.off[l] * C::FE, lv.n[l], agg + lv.off[l + 1] * C::FE, part + lv.poff[l] * C::FE);
+    // top: one block from the initial state (m0, S0)
+    PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3(1), dim3(C::NT), 0, s, agg + lv.off[lv.L] * C::FE,
+                  lv.n[lv.L], (T *)nullptr, part + lv.poff[lv.L] * C::FE);
+    PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3(1), dim3(C::NT), 0, s, lv.n[lv.L],
+                  part + lv.poff[lv.L] * C::FE, (const T *)m.init, pref + lv.off[lv.L] * C::FS);
     for (int l = lv.L - 1; l >= 1; --l)
-        PARAPN_LAUNCH("fwd_down", s, k_fwd_down<C>, dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
-                           agg + lv.off[l] * C::FE, lv.n[l], pref + lv.off[l + 1] * C::FS, pref + lv.off[l] * C::FS,
-                           lv.n[l + 1]);
-    PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, pref + lv.off[1] * C::FS,
-                       lv.n[1], (T *)w.mf, (T *)w.sPf);
+        PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)lv.n[l + 1]), dim3(C::NT), 0, s,
+                      lv.n[l], part + lv.poff[l] * C::FE, pref + lv.off[l + 1] * C::FS, pref + lv.off[l] * C::FS);
+    PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
+                  pref + lv.off[1] * C::FS, lv.n[1], (T *)w.se, (T *)w.sL, (T *)w.filt_mf, (T *)w.filt_sPf);
     return hipGetLastError();
 }
 
-template <class C, bool WITH_L>
+template <class CF, bool WITH_L>
 static hipError_t bwd_seq(const ScanPlan &p, const ModelDev &m, const Work &w, bool update, void *mout, double T0,
                           hipStream_t s)
 {
+    // the reverse scan works on D rows: groups of next-power-of-two(D) lanes
+    using C = Cfg<typename CF::T, CF::d, CF::q, pow2ceil(CF::D)>;
     using T = typename C::T;
+    if (p.bs1 != C::B1) return hipErrorInvalidValue;
     KArgs<C> a = make_args<C>(p, m, nullptr);
     a.traj = (const double *)w.traj;
-    Levels lv = make_levels(p.N + 1, p);
+    a.b1 = p.bs1;
+    Levels lv = make_levels(p.N + 1, p.bs1, p.bu, p.btop);
     T *agg = (T *)w.sagg, *suf = (T *)w.spref;
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
-    PARAPN_LAUNCH("smoother_elements", s, (k_smoother_elements<C, WITH_L>), dim3(blocks(p.N + 1)), dim3(C::NT), 0, s, a,
-                       (const T *)w.mf, (const T *)w.sPf, (T *)w.se, (T *)w.sL);
     PARAPN_LAUNCH("bwd_reduce1", s, (k_bwd_reduce1<C, WITH_L>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, (const T *)w.se,
                        (const T *)w.sL, agg + lv.off[1] * C::SA, lv.n[1]);
     for (int l = 1; l < lv.L; ++l)
@@ -1528,15 +1556,27 @@ int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *lau
 
 int config_supported(int d, int q) { return (d >= 1 && d <= 3 && q >= 1 && q <= 4) ? 1 : -1; }
 
+// sizes cover every tree width a configuration may use (W = 2, 4, 8, 16)
 size_t work_elems_fagg(int D, const ScanPlan &p)
 {
-    Levels lv = make_levels(p.N, p);
-    return (size_t)lv.total * (size_t)(3 * D * D + 2 * D);
+    int64_t rec = 0;
+    for (int W = 2; W <= 16; W *= 2) {
+        TreeLevels lv = make_tree_levels(p.N, p.b1, W);
+        rec = std::max<int64_t>(rec, lv.total + lv.ptotal);
+    }
+    return (size_t)rec * (size_t)(3 * D * D + 2 * D);
+}
+
+size_t work_records_fpref(const ScanPlan &p)
+{
+    int64_t rec = 0;
+    for (int W = 2; W <= 16; W *= 2) rec = std::max<int64_t>(rec, make_tree_levels(p.N, p.b1, W).total);
+    return (size_t)rec;
 }
 
 size_t work_elems_sagg(int D, const ScanPlan &p)
 {
-    Levels lv = make_levels(p.N + 1, p);
+    Levels lv = make_levels(p.N + 1, p.bs1, p.bu, p.btop);
     return (size_t)lv.total * (size_t)(2 * D * D + D);
 }
 
