@@ -30,7 +30,9 @@ FIELDS = {
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_pararts",
-            "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_read", "parapn_last_error"]
+            "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_read", "parapn_server_create",
+            "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
+            "parapn_server_poll", "parapn_server_footprint", "parapn_server_stats", "parapn_last_error"]
 
 
 class ParapnError(RuntimeError):
@@ -68,6 +70,18 @@ class Info(ctypes.Structure):
     ]
 
 
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("req_id", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("final_delta", ctypes.c_double),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 _lib = None
 _ctx = {}
 
@@ -99,6 +113,23 @@ def load_library(path: str = LIB_PATH):
     L.parapn_profile_read.argtypes = [i32, ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
     L.parapn_profile_read.restype = ctypes.c_int
+    L.parapn_server_create.argtypes = [ctypes.POINTER(vp), vp, i32, sz, vp]
+    L.parapn_server_create.restype = ctypes.c_int
+    L.parapn_server_destroy.argtypes = [vp]
+    L.parapn_server_destroy.restype = None
+    L.parapn_server_clock.argtypes = []
+    L.parapn_server_clock.restype = ctypes.c_double
+    L.parapn_server_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_uint64, vp]
+    L.parapn_server_submit.restype = ctypes.c_int
+    L.parapn_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.parapn_server_step.restype = ctypes.c_int
+    L.parapn_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)]
+    L.parapn_server_poll.restype = ctypes.c_int
+    L.parapn_server_footprint.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz)]
+    L.parapn_server_footprint.restype = ctypes.c_int
+    L.parapn_server_stats.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+    L.parapn_server_stats.restype = ctypes.c_int
     L.parapn_last_error.argtypes = []
     L.parapn_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -269,3 +300,84 @@ def profile_read(max_kernels: int = 64):
         nm = names.raw[k * name_len:(k + 1) * name_len].split(b"\0", 1)[0].decode()
         out[nm] = (tot[k], cnt[k])
     return out
+
+
+class Server:
+    """Continuous-batching server over the C ABI (parapn_server_*): submit
+    IVPs at any time, call ``step()`` to run one Gauss-Newton iteration for
+    every admitted request, ``poll()`` for completions.  Output tensors are
+    allocated at submission and kept until the completion is polled."""
+
+    def __init__(self, max_slots=64, budget=0, device=0, stream=None, ctx_budget=0):
+        torch = _torch()
+        self._L = load_library()
+        self._device = device
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _check(self._L.parapn_server_create(ctypes.byref(h), context(device, ctx_budget), int(max_slots), int(budget),
+                                            ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
+               fixed_iters=0, d=None):
+        torch = _torch()
+        pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
+                          fixed_iters=fixed_iters, d=d)
+        D = pb.d * (pb.q + 1)
+        mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=torch.device("cuda", self._device))
+        _check(self._L.parapn_server_submit(self._h, ctypes.byref(pb), int(req_id), _dptr(mean)))
+        self._pending[int(req_id)] = mean
+        return mean
+
+    def step(self):
+        """One iteration for all active requests; returns (n_active, n_queued)."""
+        na, nq = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.parapn_server_step(self._h, ctypes.byref(na), ctypes.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, max_records=1024):
+        """List of completion dicts (req_id, status, iterations, final_delta,
+        t_submit, t_start, t_done, mean)."""
+        buf = (Completion * max_records)()
+        n = ctypes.c_int32()
+        _check(self._L.parapn_server_poll(self._h, buf, max_records, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            c = buf[k]
+            out.append({"req_id": c.req_id, "status": c.status, "iterations": c.iterations,
+                        "final_delta": c.final_delta, "t_submit": c.t_submit, "t_start": c.t_start,
+                        "t_done": c.t_done, "mean": self._pending.pop(c.req_id, None)})
+        return out
+
+    def clock(self):
+        return self._L.parapn_server_clock()
+
+    def stats(self):
+        """{'used_bytes', 'peak_bytes', 'admitted', 'completed'}."""
+        u, pk = ctypes.c_size_t(), ctypes.c_size_t()
+        a, c = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._L.parapn_server_stats(self._h, ctypes.byref(u), ctypes.byref(pk), ctypes.byref(a),
+                                           ctypes.byref(c)))
+        return {"used_bytes": u.value, "peak_bytes": pk.value, "admitted": a.value, "completed": c.value}
+
+
+    def close(self):
+        if self._h is not None:
+            self._L.parapn_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_footprint(field, params, y0, t0, t1, q, N, *, precision="fp32", d=None) -> int:
+    """Bytes that server admission charges for this request."""
+    pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, d=d)
+    n = ctypes.c_size_t()
+    _check(load_library().parapn_server_footprint(ctypes.byref(pb), ctypes.byref(n)))
+    return n.value

@@ -6,9 +6,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -167,60 +170,190 @@ void precond_diag(int d, int q, double h, std::vector<double> &T)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct Layout {
-    size_t off_traj, off_mf, off_sPf, off_se, off_sL, off_sPs, off_fagg, off_fpref, off_sagg, off_spref;
-    size_t off_consts, off_T, off_dbits, total;
+
+// Byte offsets of one pack's scratch inside the context workspace.
+struct PackLayout {
+    size_t se, sL, sPs, mf, sPf, fagg, fpart, fpref, sagg, spref, consts, reqs, ftab, stab, dbits, extra, total;
 };
 
-// Forward chunk: long enough that the step-level aggregates (folded with the
-// cheaper single-element operator) leave little work for the upper tree levels,
-// short enough that about 8192 groups keep every SIMD busy.
-parapn::ScanPlan default_plan(int64_t N)
-{
-    parapn::ScanPlan p;
-    p.N = N;
-    int b1 = 4;
-    while (b1 < 32 && N / (2 * b1) >= 8192) b1 *= 2;
-    p.b1 = b1;
-    p.bs1 = 8;
-    p.bu = 8;
-    p.btop = 16;
-    return p;
-}
-
-Layout make_layout(int D, int64_t N, int esz, bool cov, const parapn::ScanPlan &plan)
+PackLayout pack_scratch_layout(int D, int esz, const parapn::Pack &pk, int nreq, bool cov, size_t extra_bytes)
 {
     const size_t DP = (size_t)D * (D + 1) / 2;
-    const size_t rows = (size_t)N + 1;
-    Layout L{};
+    const size_t FEF = (size_t)3 * D * D + 2 * D + 1, FS = (size_t)D + D * D, SAF = (size_t)2 * D * D + D + 1;
+    PackLayout L{};
     size_t o = 0;
-    auto take = [&](size_t elems) {
+    auto take = [&](size_t bytes) {
         size_t r = o;
-        o = align_up(o + elems * esz);
+        o = align_up(o + bytes);
         return r;
     };
-    L.off_traj = align_up(o);  // FP64 trajectory in both precisions
-    o = align_up(o + rows * D * sizeof(double));
-    L.off_mf = take(rows * D);
-    L.off_sPf = take(rows * DP);
-    L.off_se = take(rows * (D * D + D));
-    L.off_sL = take(rows * DP);
-    L.off_sPs = cov ? take(rows * DP) : 0;
-    const size_t fagg = parapn::work_elems_fagg(D, plan);
-    L.off_fagg = take(fagg);
-    L.off_fpref = take(parapn::work_records_fpref(plan) * (D + D * D));
-    const size_t sagg = parapn::work_elems_sagg(D, plan);
-    const size_t srec = sagg / (2 * D * D + D);
-    L.off_sagg = take(sagg);
-    L.off_spref = take(srec * (D + D * D));
-    L.off_consts = take(3 * D * D + D);
-    o = align_up(o);
-    L.off_T = o;
-    o = align_up(o + 2 * D * sizeof(double));  // T, then mu0bar in double
-    L.off_dbits = o;
-    o = align_up(o + 2 * sizeof(unsigned long long));
+    L.se = take((size_t)pk.rows * (D * D + D + 1) * esz);
+    L.sL = take((size_t)pk.rows * DP * esz);
+    L.sPs = cov ? take((size_t)pk.rows * DP * esz) : 0;
+    L.mf = take((size_t)pk.rows * D * esz);
+    L.sPf = take((size_t)pk.rows * DP * esz);
+    L.fagg = take((size_t)pk.frecs * FEF * esz);
+    L.fpart = take((size_t)pk.fprecs * FEF * esz);
+    L.fpref = take((size_t)pk.frecs * FS * esz);
+    L.sagg = take((size_t)pk.srecs * SAF * esz);
+    L.spref = take((size_t)pk.srecs * FS * esz);
+    L.consts = take((size_t)(3 * D * D + D) * esz);
+    L.reqs = take((size_t)nreq * sizeof(parapn::ReqDev));
+    L.ftab = take((size_t)nreq * sizeof(parapn::ScanTab));
+    L.stab = take((size_t)nreq * sizeof(parapn::ScanTab));
+    L.dbits = take((size_t)nreq * 2 * sizeof(unsigned long long));
+    L.extra = take(extra_bytes);
     L.total = o;
     return L;
+}
+
+// One pack ready to run: device-table images (in the byte layout of the
+// workspace region from L.reqs to L.dbits), pack totals and scratch layout.
+struct PackPlan {
+    std::vector<parapn::ReqDev> reqs;
+    std::vector<parapn::ScanTab> ftab, stab;
+    std::vector<unsigned char> image;
+    parapn::Pack pk;
+    PackLayout L;
+};
+
+// reqs: N, field, scales and trajectory of each request
+int plan_pack(int fp64, int d, int q, const std::vector<parapn::ReqDev> &reqs, bool cov, size_t extra,
+              PackPlan &pl)
+{
+    const int nreq = (int)reqs.size();
+    const int D = d * (q + 1), esz = fp64 ? 8 : 4;
+    pl.reqs = reqs;
+    pl.ftab.assign(nreq, parapn::ScanTab{});
+    pl.stab.assign(nreq, parapn::ScanTab{});
+    pl.pk = parapn::Pack{};
+    pl.pk.bu = 8;
+    pl.pk.btop = 16;
+    if (parapn::pack_layout(fp64, d, q, pl.reqs.data(), pl.ftab.data(), pl.stab.data(), nreq, &pl.pk) != 0)
+        return fail(PARAPN_EINVAL, "problem too long for the scan levels of this build");
+    pl.L = pack_scratch_layout(D, esz, pl.pk, nreq, cov, extra);
+    return PARAPN_OK;
+}
+
+// Fill the device pointers of the plan for a workspace at ws and build the
+// image of its tables.
+void bind_plan(PackPlan &pl, char *ws)
+{
+    const int nreq = (int)pl.reqs.size();
+    unsigned long long *dbits = (unsigned long long *)(ws + pl.L.dbits);
+    for (int i = 0; i < nreq; ++i) pl.reqs[i].dbits = dbits + 2 * i;
+    pl.pk.reqs = (const parapn::ReqDev *)(ws + pl.L.reqs);
+    pl.pk.ftab = (const parapn::ScanTab *)(ws + pl.L.ftab);
+    pl.pk.stab = (const parapn::ScanTab *)(ws + pl.L.stab);
+    pl.image.assign(pl.L.dbits - pl.L.reqs, 0);
+    std::memcpy(pl.image.data(), pl.reqs.data(), nreq * sizeof(parapn::ReqDev));
+    std::memcpy(pl.image.data() + (pl.L.ftab - pl.L.reqs), pl.ftab.data(), nreq * sizeof(parapn::ScanTab));
+    std::memcpy(pl.image.data() + (pl.L.stab - pl.L.reqs), pl.stab.data(), nreq * sizeof(parapn::ScanTab));
+}
+
+// Host-side description of one IVP being solved (Alg. 2).
+struct Solve {
+    int field, d, q, D, precision;
+    int64_t N;
+    double t0, t1, h, tol;
+    int max_iter, fixed_iters;
+    double params[PARAPN_MAX_PARAMS];
+    std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
+    // iteration state
+    int iter = 0;
+    int status = PARAPN_MAXITER;
+    bool done = false, converged = false;
+    double delta = 0.0, tol_used = 0.0;
+    std::vector<double> deltas;
+};
+
+int prepare(const parapn_problem *p, Solve &sv)
+{
+    sv.field = p->field;
+    sv.d = p->d;
+    sv.q = p->q;
+    sv.D = p->d * (p->q + 1);
+    sv.precision = p->precision;
+    sv.N = p->N;
+    sv.t0 = p->t0;
+    sv.t1 = p->t1;
+    sv.h = (p->t1 - p->t0) / (double)p->N;
+    sv.tol = p->tol;
+    sv.max_iter = p->max_iter;
+    sv.fixed_iters = p->fixed_iters;
+    for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
+    precond_diag(sv.d, sv.q, sv.h, sv.Td);
+    sv.mu0.assign(sv.D, 0.0);
+    if (!taylor_mu0(sv.field, sv.d, sv.params, p->y0, sv.q, sv.mu0.data()))
+        return fail(PARAPN_EINVAL, "field not available for d");
+    sv.mu0b.resize(sv.D);
+    for (int k = 0; k < sv.D; ++k) {
+        if (!std::isfinite(sv.mu0[k])) return fail(PARAPN_EINVAL, "non-finite initial derivatives");
+        sv.mu0b[k] = sv.mu0[k] / sv.Td[k];
+    }
+    return PARAPN_OK;
+}
+
+void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parapn::ReqDev &r)
+{
+    std::memset(&r, 0, sizeof(r));
+    r.field = sv.field;
+    for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) r.p[i] = sv.params[i];
+    r.T0 = sv.Td[0];
+    r.T1 = sv.Td[1];
+    r.invT1 = 1.0 / sv.Td[1];
+    r.hq = sv.h / sv.q;
+    r.traj = traj;
+    r.dbits = dbits;
+    r.N = sv.N;
+}
+
+// Upload the (precision, d, q) constants: Phi | sqrtQ | initial increment
+// state (0, 0) -- the scans run on the increment over a trajectory whose
+// row 0 is mu0 itself.
+int upload_consts(int d, int q, bool fp64, char *dst, hipStream_t s)
+{
+    const int D = d * (q + 1);
+    std::vector<double> Phi, sQ;
+    prior_blocks(d, q, Phi, sQ);
+    std::vector<double> cst(3 * D * D + D, 0.0);
+    for (int i = 0; i < D * D; ++i) {
+        cst[i] = Phi[i];
+        cst[D * D + i] = sQ[i];
+    }
+    if (fp64) {
+        PARAPN_HIP(hipMemcpyAsync(dst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, s), "copy constants");
+    } else {
+        std::vector<float> cf(cst.begin(), cst.end());
+        PARAPN_HIP(hipMemcpyAsync(dst, cf.data(), cf.size() * 4, hipMemcpyHostToDevice, s), "copy constants");
+    }
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    return PARAPN_OK;
+}
+
+parapn::ModelDev model_from(char *cdev, int D, int esz)
+{
+    parapn::ModelDev m;
+    m.Phi = cdev;
+    m.sQ = cdev + (size_t)D * D * esz;
+    m.init = cdev + (size_t)2 * D * D * esz;
+    return m;
+}
+
+parapn::Work work_from(char *ws, const PackLayout &L, bool cov)
+{
+    parapn::Work w{};
+    w.se = ws + L.se;
+    w.sL = ws + L.sL;
+    w.sPs = cov ? ws + L.sPs : nullptr;
+    w.mf = ws + L.mf;
+    w.sPf = ws + L.sPf;
+    w.fagg = ws + L.fagg;
+    w.fpart = ws + L.fpart;
+    w.fpref = ws + L.fpref;
+    w.sagg = ws + L.sagg;
+    w.spref = ws + L.spref;
+    return w;
 }
 
 }  // namespace
@@ -230,7 +363,14 @@ struct parapn_ctx {
     size_t budget;
     void *ws;
     size_t ws_bytes;
-    unsigned long long *host_bits;  // pinned, 2 entries
+    unsigned long long *host_bits;  // pinned
+    size_t host_bits_n;
+    // what the workspace already holds: constants and request table of the
+    // last pack (skip re-uploading them on the next iteration of that pack)
+    const void *consts_at;
+    int consts_key;
+    const void *reqs_at;
+    std::vector<unsigned char> reqs_key;  // bytes of the table last copied
 };
 
 static int ensure_ws(parapn_ctx *ctx, size_t bytes)
@@ -244,12 +384,26 @@ static int ensure_ws(parapn_ctx *ctx, size_t bytes)
         ctx->ws = nullptr;
         ctx->ws_bytes = 0;
     }
+    ctx->consts_at = nullptr;
+    ctx->reqs_at = nullptr;
     hipError_t e = hipMalloc(&ctx->ws, bytes);
     if (e != hipSuccess) {
         ctx->ws = nullptr;
         return fail(PARAPN_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
     }
     ctx->ws_bytes = bytes;
+    return PARAPN_OK;
+}
+
+static int ensure_host_bits(parapn_ctx *ctx, size_t n)
+{
+    if (n <= ctx->host_bits_n) return PARAPN_OK;
+    if (ctx->host_bits) hipHostFree(ctx->host_bits);
+    ctx->host_bits = nullptr;
+    ctx->host_bits_n = 0;
+    PARAPN_HIP(hipHostMalloc((void **)&ctx->host_bits, n * sizeof(unsigned long long), hipHostMallocDefault),
+               "hipHostMalloc");
+    ctx->host_bits_n = n;
     return PARAPN_OK;
 }
 
@@ -280,6 +434,123 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     return PARAPN_OK;
 }
 
+// One IEKS iteration (linearise, both scans, trajectory update) for a pack
+// of solves sharing (precision, d, q).  trajs[i] are their resident FP64
+// trajectories.  Reads back each solve's delta and advances its state.
+// fixed: a plan the caller already sized the workspace for (else the pack is
+// planned here and the workspace grown to fit it).
+static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
+                          PackPlan *fixed = nullptr)
+{
+    const int nreq = (int)sv.size();
+    const Solve &s0 = *sv[0];
+    const bool fp64 = s0.precision == PARAPN_FP64;
+    const int esz = fp64 ? 8 : 4, D = s0.D;
+    PackPlan local;
+    PackPlan *pl = fixed;
+    int rc;
+    if (!pl) {
+        std::vector<parapn::ReqDev> reqs(nreq);
+        for (int i = 0; i < nreq; ++i) fill_reqdev(*sv[i], trajs[i], nullptr, reqs[i]);
+        rc = plan_pack(fp64, s0.d, s0.q, reqs, false, 0, local);
+        if (rc) return rc;
+        rc = ensure_ws(ctx, local.L.total);
+        if (rc) return rc;
+        pl = &local;
+    }
+    rc = ensure_host_bits(ctx, 2 * (size_t)nreq);
+    if (rc) return rc;
+    char *ws = (char *)ctx->ws;
+    bind_plan(*pl, ws);
+    const PackLayout &L = pl->L;
+    const int ckey = (s0.d * 8 + s0.q) * 2 + (fp64 ? 1 : 0);
+    if (ctx->consts_at != ws + L.consts || ctx->consts_key != ckey) {
+        rc = upload_consts(s0.d, s0.q, fp64, ws + L.consts, s);
+        if (rc) return rc;
+        ctx->consts_at = ws + L.consts;
+        ctx->consts_key = ckey;
+    }
+    if (ctx->reqs_at != ws + L.reqs || ctx->reqs_key != pl->image) {
+        PARAPN_HIP(hipMemcpyAsync(ws + L.reqs, pl->image.data(), pl->image.size(), hipMemcpyHostToDevice, s),
+                   "copy request tables");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        ctx->reqs_at = ws + L.reqs;
+        ctx->reqs_key = pl->image;
+    }
+    unsigned long long *dbits = (unsigned long long *)(ws + L.dbits);
+    PARAPN_HIP(hipMemsetAsync(dbits, 0, 2 * nreq * sizeof(unsigned long long), s), "memset");
+    parapn::Pack pk = pl->pk;
+    pk.mode = 0;
+    const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
+    const parapn::Work w = work_from(ws, L, false);
+    PARAPN_HIP(parapn::launch_forward(fp64, s0.d, s0.q, pk, m, w, s), "forward scan");
+    PARAPN_HIP(parapn::launch_smoother(fp64, s0.d, s0.q, pk, m, w, false, true, nullptr, s), "reverse scan");
+    PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, dbits, 2 * nreq * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              s),
+               "read delta");
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    for (int i = 0; i < nreq; ++i) {
+        Solve &v = *sv[i];
+        double delta, mmax;
+        std::memcpy(&delta, ctx->host_bits + 2 * i, 8);
+        std::memcpy(&mmax, ctx->host_bits + 2 * i + 1, 8);
+        v.iter += 1;
+        v.delta = delta;
+        v.deltas.push_back(delta);
+        const int limit = v.fixed_iters > 0 ? v.fixed_iters : v.max_iter;
+        if (!std::isfinite(delta)) {
+            v.status = PARAPN_ENONFINITE;
+            v.done = true;
+            continue;
+        }
+        v.tol_used = v.precision == PARAPN_FP64 ? v.tol : std::fmax(v.tol, std::ldexp(mmax, -20));
+        if (v.fixed_iters > 0) {
+            if (v.iter >= limit) {
+                v.status = PARAPN_OK;
+                v.done = true;
+            }
+        } else if (delta < v.tol_used) {
+            v.status = PARAPN_OK;
+            v.converged = true;
+            v.done = true;
+        } else if (v.iter >= limit) {
+            v.status = PARAPN_MAXITER;
+            v.done = true;
+        }
+    }
+    return PARAPN_OK;
+}
+
+// resident per-solve device buffer: trajectory [N+1][D], then T and mu0/T
+static size_t resident_bytes(const Solve &sv) { return align_up(((size_t)(sv.N + 1) * sv.D + 2 * sv.D) * 8); }
+
+static int init_resident(const Solve &sv, double *buf, const double *init_traj, hipStream_t s)
+{
+    const int D = sv.D;
+    double *traj = buf, *tail = buf + (size_t)(sv.N + 1) * D;
+    std::vector<double> Tmu(2 * D);
+    for (int k = 0; k < D; ++k) {
+        Tmu[k] = sv.Td[k];
+        Tmu[D + k] = sv.mu0b[k];
+    }
+    PARAPN_HIP(hipMemcpyAsync(tail, Tmu.data(), 2 * D * sizeof(double), hipMemcpyHostToDevice, s), "copy T");
+    if (init_traj) {
+        // the caller's trajectory, preconditioned; row 0 is always mu0 (only its
+        // E0 part enters the convergence test)
+        const size_t rows = (size_t)sv.N + 1;
+        std::vector<double> tr(rows * D);
+        for (int k = 0; k < D; ++k) tr[k] = sv.mu0b[k];
+        for (size_t n = 1; n < rows; ++n)
+            for (int k = 0; k < D; ++k) tr[n * D + k] = init_traj[n * D + k] / sv.Td[k];
+        PARAPN_HIP(hipMemcpyAsync(traj, tr.data(), tr.size() * 8, hipMemcpyHostToDevice, s), "copy traj");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    } else {
+        PARAPN_HIP(parapn::launch_fill_traj(D, sv.N, tail + D, traj, s), "fill trajectory");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");  // Tmu is a local
+    }
+    return PARAPN_OK;
+}
+
 extern "C" {
 
 const char *parapn_last_error(void) { return g_err.c_str(); }
@@ -294,10 +565,10 @@ int parapn_create(parapn_ctx **out, int device, size_t budget)
     parapn_ctx *c = new parapn_ctx{};
     c->device = device;
     c->budget = budget;
-    hipError_t e = hipHostMalloc((void **)&c->host_bits, 2 * sizeof(unsigned long long), hipHostMallocDefault);
-    if (e != hipSuccess) {
+    int rc = ensure_host_bits(c, 64);
+    if (rc) {
         delete c;
-        return hip_fail(e, "hipHostMalloc");
+        return rc;
     }
     *out = c;
     return PARAPN_OK;
@@ -321,8 +592,13 @@ int parapn_workspace_size(const parapn_problem *p, size_t *bytes)
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
-    const int esz = p->precision == PARAPN_FP64 ? 8 : 4;
-    *bytes = make_layout(D, p->N, esz, true, default_plan(p->N)).total;
+    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
+    r[0].N = p->N;
+    const size_t resident = align_up(((size_t)(p->N + 1) * D + 2 * D) * 8);
+    PackPlan pl;
+    rc = plan_pack(p->precision == PARAPN_FP64, p->d, q, r, true, resident, pl);
+    if (rc) return rc;
+    *bytes = pl.L.total;
     return PARAPN_OK;
 }
 
@@ -334,154 +610,66 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
-    const int d = p->d, S = q + 1;
     const bool fp64 = p->precision == PARAPN_FP64;
     const int esz = fp64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stream;
     PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-
-    const parapn::ScanPlan plan = default_plan(p->N);
+    Solve sv;
+    rc = prepare(p, sv);
+    if (rc) return rc;
     const bool want_cov = sqrtcov_out != nullptr;
-    const Layout L = make_layout(D, p->N, esz, want_cov, plan);
+
+    // the workspace holds the pack scratch (sized with the covariance pass)
+    // and, in its extra region, the resident trajectory
+    PackPlan pl;
+    std::vector<parapn::ReqDev> r(1);
+    fill_reqdev(sv, nullptr, nullptr, r[0]);
+    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv), pl);
+    if (rc) return rc;
+    const PackLayout &L = pl.L;
     rc = ensure_ws(ctx, L.total);
     if (rc) return rc;
     char *ws = (char *)ctx->ws;
+    double *traj = (double *)(ws + L.extra);
+    pl.reqs[0].traj = traj;
+    rc = init_resident(sv, traj, p->init_traj, s);
+    if (rc) return rc;
 
-    // FP64 host constants
-    const double h = (p->t1 - p->t0) / (double)p->N;
-    std::vector<double> Phi, sQ, Td, mu0(D);
-    prior_blocks(d, q, Phi, sQ);
-    precond_diag(d, q, h, Td);
-    double prm[PARAPN_MAX_PARAMS] = {0};
-    for (int i = 0; i < p->n_params && i < PARAPN_MAX_PARAMS; ++i) prm[i] = p->params[i];
-    if (!taylor_mu0(p->field, d, prm, p->y0, q, mu0.data())) return fail(PARAPN_EINVAL, "field not available for d");
-    for (int k = 0; k < D; ++k)
-        if (!std::isfinite(mu0[k])) return fail(PARAPN_EINVAL, "non-finite initial derivatives");
-    // Phi | sQ | m0 (= 0) | S0 (= 0): the scans run on the increment over the
-    // trajectory, whose row 0 is mu0 itself, so the initial increment is 0;
-    // (m0, S0) is one contiguous initial-state record
-    std::vector<double> cst(3 * D * D + D, 0.0);
-    for (int i = 0; i < D * D; ++i) {
-        cst[i] = Phi[i];
-        cst[D * D + i] = sQ[i];
+    std::vector<Solve *> one{&sv};
+    std::vector<double *> trajs{traj};
+    while (!sv.done) {
+        rc = pack_iteration(ctx, one, trajs, s, &pl);
+        if (rc) return rc;
     }
-    std::vector<double> Tmu(2 * D);
-    for (int k = 0; k < D; ++k) {
-        Tmu[k] = Td[k];
-        Tmu[D + k] = mu0[k] / Td[k];
-    }
-    char *cdev = ws + L.off_consts;
-    if (fp64) {
-        PARAPN_HIP(hipMemcpyAsync(cdev, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, s), "copy constants");
-    } else {
-        std::vector<float> cf(cst.begin(), cst.end());
-        PARAPN_HIP(hipMemcpyAsync(cdev, cf.data(), cf.size() * 4, hipMemcpyHostToDevice, s), "copy constants");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");  // cf is a local
-    }
-    PARAPN_HIP(hipMemcpyAsync(ws + L.off_T, Tmu.data(), 2 * D * sizeof(double), hipMemcpyHostToDevice, s),
-               "copy T");
-
-    parapn::ModelDev m;
-    m.Phi = cdev;
-    m.sQ = cdev + (size_t)D * D * esz;
-    m.m0 = cdev + (size_t)2 * D * D * esz;
-    m.S0 = cdev + (size_t)(2 * D * D + D) * esz;
-    m.init = m.m0;
-
-    parapn::Work w{};
-    w.traj = ws + L.off_traj;
-    w.mf = ws + L.off_mf;
-    w.sPf = ws + L.off_sPf;
-    w.se = ws + L.off_se;
-    w.sL = ws + L.off_sL;
-    w.sPs = want_cov ? ws + L.off_sPs : nullptr;
-    w.fagg = ws + L.off_fagg;
-    w.fpref = ws + L.off_fpref;
-    w.sagg = ws + L.off_sagg;
-    w.spref = ws + L.off_spref;
-    w.dbits = (unsigned long long *)(ws + L.off_dbits);
-
-    // initial trajectory (Alg. 2): constant mu0, or the caller's; preconditioned,
-    // FP64, row 0 always mu0 (only E0 of row 0 enters the convergence test)
-    if (p->init_traj) {
-        const size_t rows = (size_t)p->N + 1;
-        std::vector<double> tr(rows * D);
-        for (int k = 0; k < D; ++k) tr[k] = mu0[k] / Td[k];
-        for (size_t n = 1; n < rows; ++n)
-            for (int k = 0; k < D; ++k) tr[n * D + k] = p->init_traj[n * D + k] / Td[k];
-        PARAPN_HIP(hipMemcpyAsync(w.traj, tr.data(), tr.size() * 8, hipMemcpyHostToDevice, s), "copy traj");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");
-    } else {
-        PARAPN_HIP(parapn::launch_fill_traj(1, D, p->N, ws + L.off_T + D * sizeof(double), w.traj, s),
-                   "fill trajectory");
-    }
-
-    parapn::ObsSpec obs{};
-    obs.mode = 0;
-    obs.traj = w.traj;
-    obs.field = p->field;
-    for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) obs.p[i] = prm[i];
-    obs.T0 = Td[0];
-    obs.T1 = Td[1];
-    obs.invT1 = 1.0 / Td[1];
-    obs.hq = h / q;
-
-    const int limit = p->fixed_iters > 0 ? p->fixed_iters : p->max_iter;
-    int status = PARAPN_MAXITER, k = 0;
-    double delta = 0.0, tol_used = p->tol;
-    for (k = 1; k <= limit; ++k) {
-        PARAPN_HIP(hipMemsetAsync(w.dbits, 0, 2 * sizeof(unsigned long long), s), "memset");
-        PARAPN_HIP(parapn::launch_forward(fp64, d, q, plan, m, obs, w, s), "forward scan");
-        PARAPN_HIP(parapn::launch_smoother(fp64, d, q, plan, m, w, false, true, nullptr, Td[0], s), "reverse scan");
-        PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, w.dbits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
-                   "read delta");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        unsigned long long b0 = ctx->host_bits[0], b1 = ctx->host_bits[1];
-        double mmax;
-        std::memcpy(&delta, &b0, 8);
-        std::memcpy(&mmax, &b1, 8);
-        if (info && info->delta_history && k <= (p->max_iter > limit ? p->max_iter : limit))
-            info->delta_history[k - 1] = delta;
-        if (!std::isfinite(delta)) {
-            status = PARAPN_ENONFINITE;
-            break;
-        }
-        tol_used = fp64 ? p->tol : std::fmax(p->tol, std::ldexp(mmax, -20));
-        if (p->fixed_iters > 0) {
-            if (k == limit) {
-                status = PARAPN_OK;
-                break;
-            }
-            continue;
-        }
-        if (delta < tol_used) {
-            status = PARAPN_OK;
-            break;
-        }
-        if (k == limit) {
-            status = PARAPN_MAXITER;
-            break;
-        }
-    }
-    if (k > limit) k = limit;
+    const double *Tdev = traj + (size_t)(sv.N + 1) * D;
     if (want_cov) {
-        // the smoothing factors of the last linearisation, from the filtering
-        // marginals still in the workspace (the means are not needed again)
-        PARAPN_HIP(parapn::launch_smoother(fp64, d, q, plan, m, w, true, false, w.mf, Td[0], s), "covariance pass");
+        // smoothed factors of the last linearisation: the reverse scan with
+        // factors over the smoothing elements still in the workspace (the
+        // means go to scratch; the trajectory already holds them).  The
+        // constants and request tables are in place from the iterations.
+        parapn::Pack pk = pl.pk;
+        const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
+        const parapn::Work w = work_from(ws, L, true);
+        PARAPN_HIP(parapn::launch_smoother(fp64, sv.d, sv.q, pk, m, w, true, false, w.mf, s), "covariance pass");
+        PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, w.sPs, mean_out, sqrtcov_out, s, true),
+                   "unscale");
+    } else {
+        PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, nullptr, mean_out, nullptr, s, true),
+                   "unscale");
     }
-    PARAPN_HIP(parapn::launch_unscale(fp64, D, p->N, (const double *)(ws + L.off_T), w.traj, w.sPs, mean_out,
-                                      sqrtcov_out, s, true),
-               "unscale");
     PARAPN_HIP(hipStreamSynchronize(s), "sync");
     if (info) {
-        info->iterations = k;
-        info->converged = status == PARAPN_OK && p->fixed_iters <= 0;
-        info->final_delta = delta;
-        info->tol_used = tol_used;
+        info->iterations = sv.iter;
+        info->converged = sv.converged ? 1 : 0;
+        info->final_delta = sv.delta;
+        info->tol_used = sv.tol_used;
+        if (info->delta_history) {
+            const int cap = std::max(sv.max_iter, sv.fixed_iters);
+            for (int k = 0; k < (int)sv.deltas.size() && k < cap; ++k) info->delta_history[k] = sv.deltas[k];
+        }
     }
-    if (status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
-    (void)S;
-    return status;
+    if (sv.status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
+    return sv.status;
 }
 
 int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
@@ -501,46 +689,41 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     const int esz = fp64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stream;
     PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    const parapn::ScanPlan plan = default_plan(N);
-    const Layout L = make_layout(D, N, esz, true, plan);
-    int rc = ensure_ws(ctx, L.total);
+    PackPlan pl;
+    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
+    r[0].N = N;
+    int rc = plan_pack(fp64, d, q, r, true, 0, pl);
+    if (rc) return rc;
+    const PackLayout &L = pl.L;
+    rc = ensure_ws(ctx, L.total);
     if (rc) return rc;
     char *ws = (char *)ctx->ws;
+    bind_plan(pl, ws);
+    ctx->consts_at = nullptr;  // both regions are overwritten below
+    ctx->reqs_at = nullptr;
     // initial-state record: mu0 followed by the canonical lower factor of Sigma0
-    char *init = ws + L.off_consts;
-    char *S0c = init + (size_t)D * esz;
+    char *init = ws + L.consts;
     PARAPN_HIP(hipMemcpyAsync(init, mu0, (size_t)D * esz, hipMemcpyDeviceToDevice, s), "copy mu0");
-    PARAPN_HIP(parapn::launch_tria_square(fp64, d, q, sqrt_sigma0, S0c, s), "canonicalise sqrt_sigma0");
+    PARAPN_HIP(parapn::launch_tria_square(fp64, d, q, sqrt_sigma0, init + (size_t)D * esz, s),
+               "canonicalise sqrt_sigma0");
+    PARAPN_HIP(hipMemcpyAsync(ws + L.reqs, pl.image.data(), pl.image.size(), hipMemcpyHostToDevice, s),
+               "copy request tables");
     parapn::ModelDev m;
     m.Phi = Phi;
     m.sQ = sqrtQ;
-    m.m0 = init;
-    m.S0 = S0c;
     m.init = init;
-    parapn::Work w{};
-    w.traj = ws + L.off_traj;
-    w.mf = ws + L.off_mf;
-    w.sPf = ws + L.off_sPf;
-    w.se = ws + L.off_se;
-    w.sL = ws + L.off_sL;
-    w.sPs = ws + L.off_sPs;
+    parapn::Work w = work_from(ws, L, true);
     w.filt_mf = (filt_mean_out || filt_sqrtcov_out) ? w.mf : nullptr;
     w.filt_sPf = (filt_mean_out || filt_sqrtcov_out) ? w.sPf : nullptr;
-    w.fagg = ws + L.off_fagg;
-    w.fpref = ws + L.off_fpref;
-    w.sagg = ws + L.off_sagg;
-    w.spref = ws + L.off_spref;
-    w.dbits = (unsigned long long *)(ws + L.off_dbits);
-    w.traj = nullptr;  // a given linear model: no trajectory, no prior offsets
-    parapn::ObsSpec obs{};
-    obs.mode = 1;
-    obs.H = H;
-    obs.dv = dvec;
-    PARAPN_HIP(parapn::launch_forward(fp64, d, q, plan, m, obs, w, s), "forward scan");
+    parapn::Pack pk = pl.pk;
+    pk.mode = 1;
+    pk.H = H;
+    pk.dv = dvec;
+    PARAPN_HIP(parapn::launch_forward(fp64, d, q, pk, m, w, s), "forward scan");
     if (filt_mean_out || filt_sqrtcov_out)
         PARAPN_HIP(parapn::launch_unscale(fp64, D, N, nullptr, w.mf, w.sPf, filt_mean_out, filt_sqrtcov_out, s),
                    "filtered outputs");
-    PARAPN_HIP(parapn::launch_smoother(fp64, d, q, plan, m, w, true, false, mean_out, 1.0, s), "reverse scan");
+    PARAPN_HIP(parapn::launch_smoother(fp64, d, q, pk, m, w, true, false, mean_out, s), "reverse scan");
     if (sqrtcov_out)
         PARAPN_HIP(parapn::launch_unscale(fp64, D, N, nullptr, nullptr, w.sPs, nullptr, sqrtcov_out, s),
                    "smoothed factors");
@@ -584,6 +767,226 @@ int parapn_profile_read(int32_t max, char *names, int32_t name_len, double *tota
         return fail(PARAPN_EINVAL, "bad arguments");
     int n = parapn::prof_read(max, names, name_len, total_ms, launches);
     if (n_out) *n_out = n;
+    return PARAPN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// continuous-batching server
+// ---------------------------------------------------------------------------
+namespace {
+
+double now_seconds()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServedReq {
+    uint64_t id;
+    Solve sv;
+    void *mean_out;
+    double *resident;  // device: trajectory, T, mu0/T
+    size_t bytes;      // admitted footprint (resident + pack scratch share)
+    double t_submit, t_start;
+};
+
+}  // namespace
+
+struct parapn_server {
+    parapn_ctx *ctx;
+    hipStream_t stream;
+    int max_slots;
+    size_t budget, used, peak;
+    int64_t admitted, completed;
+    std::deque<ServedReq *> queue;
+    std::vector<ServedReq *> active;
+    std::deque<parapn_completion> done;
+};
+
+// admitted footprint of a request: its resident trajectory plus its scan
+// scratch, which in a pack is the same region it would use alone
+static size_t footprint(const Solve &sv)
+{
+    std::vector<parapn::ReqDev> r(1);
+    fill_reqdev(sv, nullptr, nullptr, r[0]);
+    PackPlan pl;
+    if (plan_pack(sv.precision == PARAPN_FP64, sv.d, sv.q, r, false, 0, pl) != PARAPN_OK) return SIZE_MAX;
+    return resident_bytes(sv) + pl.L.total;
+}
+
+extern "C" {
+
+int parapn_server_create(parapn_server **out, parapn_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes,
+                         void *stream)
+{
+    if (!out || !ctx) return fail(PARAPN_EINVAL, "NULL argument");
+    if (max_slots < 1) return fail(PARAPN_EINVAL, "max_slots must be >= 1");
+    parapn_server *sv = new parapn_server{};
+    sv->ctx = ctx;
+    sv->stream = (hipStream_t)stream;
+    sv->max_slots = max_slots;
+    sv->budget = hbm_budget_bytes;
+    sv->used = 0;
+    *out = sv;
+    return PARAPN_OK;
+}
+
+void parapn_server_destroy(parapn_server *srv)
+{
+    if (!srv) return;
+    hipSetDevice(srv->ctx->device);
+    hipStreamSynchronize(srv->stream);
+    for (ServedReq *r : srv->active) {
+        if (r->resident) hipFree(r->resident);
+        delete r;
+    }
+    for (ServedReq *r : srv->queue) delete r;
+    delete srv;
+}
+
+double parapn_server_clock(void) { return now_seconds(); }
+
+int parapn_server_footprint(const parapn_problem *p, size_t *bytes)
+{
+    int q, D;
+    int rc = check_problem(p, &q, &D);
+    if (rc) return rc;
+    if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
+    Solve sv;
+    rc = prepare(p, sv);
+    if (rc) return rc;
+    *bytes = footprint(sv);
+    return *bytes == SIZE_MAX ? PARAPN_EINVAL : PARAPN_OK;
+}
+
+int parapn_server_stats(parapn_server *srv, size_t *used_bytes, size_t *peak_bytes, int64_t *admitted,
+                        int64_t *completed)
+{
+    if (!srv) return fail(PARAPN_EINVAL, "server is NULL");
+    if (used_bytes) *used_bytes = srv->used;
+    if (peak_bytes) *peak_bytes = srv->peak;
+    if (admitted) *admitted = srv->admitted;
+    if (completed) *completed = srv->completed;
+    return PARAPN_OK;
+}
+
+int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t req_id, void *mean_out)
+{
+    if (!srv) return fail(PARAPN_EINVAL, "server is NULL");
+    int q, D;
+    int rc = check_problem(p, &q, &D);
+    if (rc) return rc;
+    if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
+    if (p->init_traj) return fail(PARAPN_EINVAL, "served requests start from the constant trajectory");
+    ServedReq *r = new ServedReq{};
+    r->id = req_id;
+    rc = prepare(p, r->sv);
+    if (rc) {
+        delete r;
+        return rc;
+    }
+    r->mean_out = mean_out;
+    r->bytes = footprint(r->sv);
+    if (r->bytes == SIZE_MAX) {  // the reason is already recorded
+        delete r;
+        return PARAPN_EINVAL;
+    }
+    if (srv->budget && r->bytes > srv->budget) {
+        delete r;
+        return fail(PARAPN_ENOMEM, "request footprint exceeds the server budget");
+    }
+    r->t_submit = now_seconds();
+    srv->queue.push_back(r);
+    return PARAPN_OK;
+}
+
+int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
+{
+    if (!srv) return fail(PARAPN_EINVAL, "server is NULL");
+    hipStream_t s = srv->stream;
+    PARAPN_HIP(hipSetDevice(srv->ctx->device), "hipSetDevice");
+    // admission in arrival order, by slots and HBM footprint
+    while (!srv->queue.empty() && (int)srv->active.size() < srv->max_slots) {
+        ServedReq *r = srv->queue.front();
+        if (srv->budget && srv->used + r->bytes > srv->budget) break;
+        hipError_t e = hipMalloc((void **)&r->resident, resident_bytes(r->sv));
+        if (e != hipSuccess) {
+            r->resident = nullptr;
+            break;  // wait for memory to free up
+        }
+        int rc = init_resident(r->sv, r->resident, nullptr, s);
+        if (rc) return rc;
+        r->t_start = now_seconds();
+        srv->used += r->bytes;
+        srv->peak = std::max(srv->peak, srv->used);
+        srv->admitted += 1;
+        srv->queue.pop_front();
+        srv->active.push_back(r);
+    }
+    // one IEKS iteration for every active request, one pack per (precision, d, q)
+    std::vector<int> order(srv->active.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::vector<bool> taken(order.size(), false);
+    for (size_t i = 0; i < order.size(); ++i) {
+        if (taken[i]) continue;
+        const Solve &k = srv->active[i]->sv;
+        std::vector<Solve *> pack;
+        std::vector<double *> trajs;
+        for (size_t j = i; j < order.size(); ++j) {
+            const Solve &o = srv->active[j]->sv;
+            if (!taken[j] && o.precision == k.precision && o.d == k.d && o.q == k.q) {
+                taken[j] = true;
+                pack.push_back(&srv->active[j]->sv);
+                trajs.push_back(srv->active[j]->resident);
+            }
+        }
+        int rc = pack_iteration(srv->ctx, pack, trajs, s);
+        if (rc) return rc;
+    }
+    // retire finished requests: write their means, free their memory
+    std::vector<ServedReq *> still;
+    for (ServedReq *r : srv->active) {
+        if (!r->sv.done) {
+            still.push_back(r);
+            continue;
+        }
+        const Solve &v = r->sv;
+        const double *Tdev = r->resident + (size_t)(v.N + 1) * v.D;
+        PARAPN_HIP(parapn::launch_unscale(v.precision == PARAPN_FP64, v.D, v.N, Tdev, r->resident, nullptr,
+                                          r->mean_out, nullptr, s, true),
+                   "unscale");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        PARAPN_HIP(hipFree(r->resident), "hipFree");
+        srv->used -= r->bytes;
+        parapn_completion c{};
+        c.req_id = r->id;
+        c.status = v.status;
+        c.iterations = v.iter;
+        c.final_delta = v.delta;
+        c.t_submit = r->t_submit;
+        c.t_start = r->t_start;
+        c.t_done = now_seconds();
+        srv->done.push_back(c);
+        srv->completed += 1;
+        delete r;
+    }
+    srv->active.swap(still);
+    if (n_active) *n_active = (int32_t)srv->active.size();
+    if (n_queued) *n_queued = (int32_t)srv->queue.size();
+    return PARAPN_OK;
+}
+
+int parapn_server_poll(parapn_server *srv, parapn_completion *out, int32_t max, int32_t *n_out)
+{
+    if (!srv || (max > 0 && !out)) return fail(PARAPN_EINVAL, "bad arguments");
+    int k = 0;
+    while (k < max && !srv->done.empty()) {
+        out[k++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    if (n_out) *n_out = k;
     return PARAPN_OK;
 }
 

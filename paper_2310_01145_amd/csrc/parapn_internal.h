@@ -9,78 +9,102 @@
 namespace parapn {
 
 constexpr int kMaxParams = 16;
+constexpr int kMaxLevels = 24;  // scan levels per request (tree width >= 2, <= 2^24 chunks)
 
-// How the observation (H_n, d_n) of step n is obtained.
-struct ObsSpec {
-    int mode;            // 0: linearise the vector field at the trajectory (IEKS)
-                         // 1: read dense H [N][d][D] and d [N][d] from memory
-    const void *traj;    // mode 0: preconditioned FP64 trajectory [N+1][D]
-    int field;           // mode 0: field id
-    double p[kMaxParams];// mode 0: field parameters
-    double T0;           // mode 0: scale of the E0 coordinate (y = T0 * E0 traj)
-    double T1;           // mode 0: scale of the E1 coordinate (y' = T1 * E1 traj)
-    double invT1;        // mode 0: 1 / T1 (row scaling of the observation)
-    double hq;           // mode 0: T0 / T1 = h / q
-    const void *H;       // mode 1
-    const void *dv;      // mode 1
+// One request of a pack (device-side table, filled by the host).
+struct ReqDev {
+    int field;
+    int pad_;
+    double p[kMaxParams];
+    double T0, T1, invT1, hq;   // scales of the E0 / E1 coordinates and h/q
+    double *traj;               // FP64 preconditioned trajectory [N+1][D]; null for a given linear model
+    unsigned long long *dbits;  // 2 entries: bit patterns of delta and max |E0 mu| (doubles)
+    int64_t N;                  // steps of this request
+    int64_t row;                // packed row of its step 0 in the per-step scratch arrays
+    int64_t fchunk;             // index of its first forward step-level chunk
+    int64_t schunk;             // index of its first reverse step-level chunk
+    int32_t b1;                 // its forward chunk length (a function of N alone)
+    int32_t pad2_;
 };
 
-// Chunk sizes of the hierarchical scans.
-struct ScanPlan {
-    int64_t N;     // steps (elements n = 1..N for the filter, 0..N for the smoother)
-    int b1;        // steps per group in the forward step-level kernels
-    int bs1;       // steps per group in the reverse step-level kernels (8)
-    int bu;        // aggregates per group in the upper levels
-    int btop;      // largest count handled by the single-group top scan
+// The levels of one request's scan in one direction, laid out exactly as for
+// the request alone.  Level 1 holds its step-level chunk aggregates; launch l
+// (l = 1 .. L-1) folds level l into level l+1; level L is scanned by one
+// group or block per request.  Records of all levels sit in the request's own
+// region of the pack array (from base; tree partials of the forward scan from
+// pbase).
+struct ScanTab {
+    int32_t L;
+    int32_t pad_;
+    int64_t base, pbase;
+    int32_t n[kMaxLevels + 1];     // nodes at level l
+    int32_t off[kMaxLevels + 1];   // record offset of level l in the request's region
+    int32_t poff[kMaxLevels + 1];  // forward: record offset of launch l's tree partials
+    int32_t first[kMaxLevels + 1]; // launch l: pack-wide index of the request's first block (forward) or group
+                                   // (reverse); for launches it takes no part in, the running count
 };
 
-// Device workspace (element type T of the path).
+// A pack: requests of one (precision, d, q), scanned together.  Every
+// request is scanned with its own chunking and its own tree of levels, so its
+// arithmetic is that of a solve of it alone; the launches of one level serve
+// all requests that have that level.
+struct Pack {
+    const ReqDev *reqs;  // device tables, nreq entries each, ordered by row
+    const ScanTab *ftab, *stab;
+    int nreq;
+    int64_t rows;        // sum over requests of N_r + 1
+    int64_t nf, ns;      // forward / reverse step-level chunks
+    int bu, btop;        // reverse upper levels: fold bu per group until <= btop remain
+    int Lf, Ls;          // most levels of any request, forward / reverse
+    int64_t fblocks[kMaxLevels + 1];  // blocks of forward tree launch l
+    int64_t sgroups[kMaxLevels + 1];  // groups of reverse launch l
+    int64_t frecs, fprecs, srecs;     // records: forward aggregates (= prefix states), tree partials, reverse
+    int mode;            // 0: linearise the vector field at the trajectories; 1: H, d given (one request)
+    const void *H;       // mode 1: [N][dobs][D]
+    const void *dv;      // mode 1: [N][dobs]
+};
+
+// forward chunk length of a request of N steps
+int forward_chunk(int64_t N);
+// Host: fill chunk indices, rows and b1 of the requests, their scan tables
+// and the pack totals (the device pointers of pk are left alone).  Returns 0,
+// or -1 if a request needs more than kMaxLevels levels.
+int pack_layout(int fp64, int d, int q, ReqDev *reqs, ScanTab *ftab, ScanTab *stab, int nreq, Pack *pk);
+
+// Device workspace of one pack (element type T of the path).
 struct Work {
-    void *traj;    // [N+1][D]   FP64 trajectory (IEKS), updated in place
-    void *mf;      // [N+1][D]   filtered means
-    void *sPf;     // [N+1][DP]  filtered factors, packed lower rows
-    void *se;      // [N+1][D*D+D] smoothing elements (E, g)
-    void *sL;      // [N+1][DP]  smoothing element factors
-    void *sPs;     // [N+1][DP]  smoothed factors (covariance pass)
-    void *filt_mf; // [N+1][D]   filtered means, or null when not wanted
-    void *filt_sPf;// [N+1][DP]  filtered factors, or null when not wanted
-    void *fagg;    // filter aggregates, all levels
-    void *fpref;   // filter prefix states, all levels
+    void *se;      // [rows][D*D+D+1] smoothing elements (E, g, last-flag)
+    void *sL;      // [rows][DP]      smoothing element factors
+    void *sPs;     // [rows][DP]      smoothed factors (covariance pass), or null
+    void *mf;      // [rows][D]       scratch / filtered means
+    void *sPf;     // [rows][DP]      filtered factors
+    void *filt_mf; // filtered means wanted: = mf, else null
+    void *filt_sPf;// filtered factors wanted: = sPf, else null
+    void *fagg;    // filter aggregates, all levels [frecs]
+    void *fpart;   // filter tree partials [fprecs]
+    void *fpref;   // filter prefix states, all levels [frecs]
     void *sagg;    // smoother aggregates, all levels
     void *spref;   // smoother suffix states, all levels
-    unsigned long long *dbits;  // [2] bit patterns of delta and max|E0 mu| (double)
 };
 
-// Constant model data on the device (element type T): Phi, sqrtQ [D][D],
-// initial filter state m0 [D], sqrtS0 [D][D].
+// Constant model data on the device (element type T): Phi, sqrtQ [D][D] and
+// the initial state record m0 [D] followed by S0 [D][D].
 struct ModelDev {
     const void *Phi;
     const void *sQ;
-    const void *m0;
-    const void *S0;
-    const void *init;  // the initial state as one record: m0 [D] followed by S0 [D][D]
+    const void *init;
 };
 
-struct Dims {
-    int d, q, D, DP;
-};
-
-// workspace sizes in elements for a plan
-size_t work_elems_fagg(int D, const ScanPlan &p);
-size_t work_elems_sagg(int D, const ScanPlan &p);
-size_t work_records_fpref(const ScanPlan &p);
 
 // Launch sequences.  Each returns hipSuccess or the first launch error.
-// T selects the precision (float or double) via `fp64`.
 template <typename T>
-hipError_t launch_forward_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const ObsSpec &obs, const Work &w,
-                            hipStream_t s);
-// Reverse scan.  with_cov: also build smoothing factors and write sPs.
-// update_traj: write smoothed means into w.traj and accumulate delta (IEKS);
-// otherwise write them to mean_out ([N+1][D]).
+hipError_t launch_forward_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s);
+// Reverse scan.  with_cov: also the smoothed factors (into w.sPs).  update:
+// add the smoothed increments to each request's trajectory and accumulate its
+// delta; otherwise write the smoothed means to mean_out ([rows][D]).
 template <typename T>
-hipError_t launch_smoother_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const Work &w, bool with_cov,
-                             bool update_traj, void *mean_out, double T0, hipStream_t s);
+hipError_t launch_smoother_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, bool with_cov,
+                             bool update, void *mean_out, hipStream_t s);
 template <typename T>
 hipError_t launch_filter_combine_t(int d, int q, int64_t count, const void *a, const void *c, void *out,
                                    hipStream_t s);
@@ -88,16 +112,16 @@ hipError_t launch_filter_combine_t(int d, int q, int64_t count, const void *a, c
 template <typename T>
 hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipStream_t s);
 
-inline hipError_t launch_forward(int fp64, int d, int q, const ScanPlan &plan, const ModelDev &m, const ObsSpec &obs,
-                                 const Work &w, hipStream_t s)
+inline hipError_t launch_forward(int fp64, int d, int q, const Pack &pk, const ModelDev &m, const Work &w,
+                                 hipStream_t s)
 {
-    return fp64 ? launch_forward_t<double>(d, q, plan, m, obs, w, s) : launch_forward_t<float>(d, q, plan, m, obs, w, s);
+    return fp64 ? launch_forward_t<double>(d, q, pk, m, w, s) : launch_forward_t<float>(d, q, pk, m, w, s);
 }
-inline hipError_t launch_smoother(int fp64, int d, int q, const ScanPlan &plan, const ModelDev &m, const Work &w,
-                                  bool with_cov, bool update_traj, void *mean_out, double T0, hipStream_t s)
+inline hipError_t launch_smoother(int fp64, int d, int q, const Pack &pk, const ModelDev &m, const Work &w,
+                                  bool with_cov, bool update, void *mean_out, hipStream_t s)
 {
-    return fp64 ? launch_smoother_t<double>(d, q, plan, m, w, with_cov, update_traj, mean_out, T0, s)
-                : launch_smoother_t<float>(d, q, plan, m, w, with_cov, update_traj, mean_out, T0, s);
+    return fp64 ? launch_smoother_t<double>(d, q, pk, m, w, with_cov, update, mean_out, s)
+                : launch_smoother_t<float>(d, q, pk, m, w, with_cov, update, mean_out, s);
 }
 inline hipError_t launch_filter_combine(int fp64, int d, int q, int64_t count, const void *a, const void *c,
                                         void *out, hipStream_t s)
@@ -109,12 +133,12 @@ inline hipError_t launch_tria_square(int fp64, int d, int q, const void *full, v
 {
     return fp64 ? launch_tria_square_t<double>(d, q, full, out, s) : launch_tria_square_t<float>(d, q, full, out, s);
 }
-// out mean [N+1][D] = Tdiag * src; out cov [N+1][D][D] = Tdiag * unpack(srcP) (either may be null;
-// Tdiag_dev null means 1)
+// mean_out [N+1][D] = Tdiag * src (src FP64 when src_fp64); cov_out [N+1][D][D]
+// = Tdiag * unpack(srcP); either output may be null; Tdiag_dev null means 1
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
                           const void *src_packed, void *mean_out, void *cov_out, hipStream_t s,
                           bool src_fp64 = false);
-hipError_t launch_fill_traj(int fp64, int D, int64_t N, const void *row, void *traj, hipStream_t s);
+hipError_t launch_fill_traj(int D, int64_t N, const double *row, double *traj, hipStream_t s);
 // index of an instantiated (d, q) configuration, or -1
 int config_supported(int d, int q);
 

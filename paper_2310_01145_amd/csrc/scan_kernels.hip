@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,8 @@ struct Cfg {
     static constexpr int SE = D * D + D;          // smoothing element (E, g)
     static constexpr int SA = 2 * D * D + D;      // smoothing aggregate: E, g, sqrtL
     static constexpr int SS = D + D * D;          // smoother state: mean, factor
+    // stored records carry one trailing flag (request boundary)
+    static constexpr int FEF = FE + 1, SEF = SE + 1, SAF = SA + 1;
     static_assert(R <= 64, "a group must fit in one wavefront");
 };
 
@@ -103,6 +106,7 @@ struct FRow {
     T sC[C::D];
     T eta;
     T sJ[C::D];
+    T flag;  // nonzero: contains the first step of a request (nothing before it matters)
 };
 
 template <class C>
@@ -118,6 +122,7 @@ struct ERow {  // smoothing element / aggregate row
     T E[C::D];
     T g;
     T L[C::D];
+    T flag;  // nonzero: contains the last step of a request (nothing after it matters)
 };
 
 template <class C>
@@ -125,15 +130,16 @@ PARAPN_DEV void zero(FRow<C> &e)
 {
 #pragma unroll
     for (int c = 0; c < C::D; ++c) e.A[c] = e.sC[c] = e.sJ[c] = 0;
-    e.b = e.eta = 0;
+    e.b = e.eta = e.flag = 0;
 }
 
-template <class C>
+template <class C, bool FLAG = true>
 PARAPN_DEV FRow<C> load_frow(const typename C::T *rec, int r)
 {
     constexpr int D = C::D;
     FRow<C> e;
     zero(e);
+    if (FLAG) e.flag = rec[C::FE];
     if (r < D) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -147,10 +153,11 @@ PARAPN_DEV FRow<C> load_frow(const typename C::T *rec, int r)
     return e;
 }
 
-template <class C>
+template <class C, bool FLAG = true>
 PARAPN_DEV void store_frow(typename C::T *rec, int r, const FRow<C> &e)
 {
     constexpr int D = C::D;
+    if (FLAG && r == 0) rec[C::FE] = e.flag;
     if (r < D) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -219,18 +226,6 @@ PARAPN_DEV void store_packed(typename C::T *p, int r, const typename C::T (&v)[C
 // the observation of one step, placed in the group's LDS:
 //   H (d x D), H Phi (d x D), d (d)
 // ---------------------------------------------------------------------------
-template <class C>
-struct ObsDev {
-    using T = typename C::T;
-    int mode;
-    const double *traj;  // FP64 trajectory (linearisation point), preconditioned
-    int field;
-    double p[kMaxParams];
-    double T0, T1, invT1, hq;
-    const T *H;
-    const T *dv;
-};
-
 // The scans solve for the Gauss-Newton increment delta = Ybar - eta of the
 // preconditioned state relative to the current trajectory eta (same
 // posterior, shifted coordinates).  Per step n the linearised model is
@@ -242,7 +237,8 @@ struct ObsDev {
 // FP64 trajectory and then rounded to the path's precision.  In memory mode
 // (ParaRTS on a given linear model) u = 0 and r = d.
 template <class C>
-PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T *sh, const typename C::T *cphi)
+PARAPN_DEV void obs_setup(const Pack &pk, const ReqDev &o, int64_t n, int lane, typename C::T *sh,
+                          const typename C::T *cphi)
 {
     using T = typename C::T;
     constexpr int d = C::d, D = C::D, S = C::S, LDM = C::LDM;
@@ -250,7 +246,7 @@ PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T
 #pragma unroll
     for (int c = 0; c < D; ++c) hrow[c] = 0;
     T rval = 0, uval = 0;
-    if (o.mode == 0) {
+    if (pk.mode == 0) {
         const double *tn = o.traj + n * D;
         const double *tp = tn - D;
         Dual<double, d> yd[d], fd[d];
@@ -276,10 +272,10 @@ PARAPN_DEV void obs_setup(const ObsDev<C> &o, int64_t n, int lane, typename C::T
             uval = (T)u;
         }
     } else if (lane < d) {
-        const T *hr = o.H + ((n - 1) * d + lane) * D;
+        const T *hr = (const T *)pk.H + ((n - 1) * d + lane) * D;
 #pragma unroll
         for (int c = 0; c < D; ++c) hrow[c] = hr[c];
-        rval = o.dv[(n - 1) * d + lane];
+        rval = ((const T *)pk.dv)[(n - 1) * d + lane];
     }
     if (lane < d) {
         T hp[D];
@@ -796,16 +792,97 @@ PARAPN_DEV SRow<C> smoother_apply(int lane, typename C::T *sh, const ERow<C> &a,
 }
 
 // ---------------------------------------------------------------------------
+// request boundaries inside a pack
+// ---------------------------------------------------------------------------
+// A request's first filtering element is p(Y1 | Z1), which does not depend on
+// anything earlier (A = 0, eta = 0, J = 0), and its last smoothing element is
+// p(Y_N | Z_{1:N}) (E = 0).  Folding across a boundary with the plain
+// operators would give the same result up to 0 * x terms; the flags make the
+// boundary exact even when a neighbouring request holds NaN or Inf.
+template <class C, int NJ, int NCJ>
+PARAPN_DEV FRow<C> fcombine(int lane, typename C::T *sh, const FRow<C> &ei, const FRow<C> &ej)
+{
+    if (ej.flag != 0) return ej;
+    FRow<C> o = filter_combine<C, NJ, NCJ>(lane, sh, ei, ej);
+    o.flag = ei.flag;
+    return o;
+}
+
+template <class C>
+PARAPN_DEV SRow<C> sapply(int lane, typename C::T *sh, const SRow<C> &st, const FRow<C> &ej)
+{
+    if (ej.flag != 0) {
+        SRow<C> o;
+        o.m = ej.b;
+#pragma unroll
+        for (int c = 0; c < C::D; ++c) o.P[c] = ej.sC[c];
+        return o;
+    }
+    return state_apply<C>(lane, sh, st, ej);
+}
+
+template <class C, bool WITH_L>
+PARAPN_DEV ERow<C> scombine(int lane, typename C::T *sh, const ERow<C> &a, const ERow<C> &b)
+{
+    if (a.flag != 0) return a;
+    ERow<C> o = smoother_combine<C, WITH_L>(lane, sh, a, b);
+    o.flag = b.flag;
+    return o;
+}
+
+template <class C, bool WITH_L>
+PARAPN_DEV SRow<C> sm_apply(int lane, typename C::T *sh, const ERow<C> &a, const SRow<C> &st)
+{
+    if (a.flag != 0) {
+        SRow<C> o;
+        o.m = a.g;
+#pragma unroll
+        for (int c = 0; c < C::D; ++c) o.P[c] = a.L[c];
+        return o;
+    }
+    return smoother_apply<C, WITH_L>(lane, sh, a, st);
+}
+
+// request owning step-level chunk c (requests are ordered by chunk index)
+template <bool FORWARD>
+PARAPN_DEV int find_req(const ReqDev *reqs, int nreq, int64_t c)
+{
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t first = FORWARD ? reqs[mid].fchunk : reqs[mid].schunk;
+        if (first <= c)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// request taking part in level launch l that owns pack-wide block or group b:
+// the last request whose first index at l is <= b (requests that take no part
+// in launch l own an empty range, and are never the last such request)
+PARAPN_DEV int find_tab(const ScanTab *t, int nreq, int l, int64_t b)
+{
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t[mid].first[l] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 template <class C>
 struct KArgs {
     using T = typename C::T;
-    int64_t N;
-    int b1, bu;
-    const T *Phi, *sQ, *m0, *S0;
-    const double *traj;  // FP64 trajectory (IEKS) or null (memory mode)
-    ObsDev<C> obs;
+    Pack pk;
+    const T *Phi, *sQ, *init;
 };
 
 #define PARAPN_GROUP_SETUP(C)                                                \
@@ -832,27 +909,47 @@ PARAPN_DEV void load_consts(typename C::T *cphi, typename C::T *csq, const typen
     __syncthreads();
 }
 
-// step level, forward reduce: aggregate a_s (x)_f ... (x)_f a_{e-1}
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T *agg, int64_t nchunks)
+PARAPN_DEV SRow<C> init_state(const typename C::T *init, int lane)
+{
+    return load_state<C>(init, lane);
+}
+
+// step level, forward reduce: the aggregate of one chunk of a request's
+// steps, a_s (x)_f ... (x)_f a_{e-1}, the elements built on the fly.  A
+// request's first element is the initial state combined with its step-1
+// element (the paper's a_1 = p(Y1 | Z1)) and carries the boundary flag.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T *agg)
 {
     PARAPN_GROUP_SETUP(C);
     load_consts<C>(cphi, csq, a.Phi, a.sQ);
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nchunks) return;
-    const int64_t s = 1 + chunk * a.b1;
-    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
+    if (chunk >= a.pk.nf) return;
+    const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
+    const ReqDev &q = a.pk.reqs[ri];
+    const int64_t lc = chunk - q.fchunk;
+    const int64_t s = 1 + lc * q.b1;
+    const int64_t e = s + q.b1 <= q.N + 1 ? s + q.b1 : q.N + 1;
     FRow<C> acc;
     zero(acc);
     for (int64_t n = s; n < e; ++n) {
-        obs_setup<C>(a.obs, n, lane, sh, cphi);
+        obs_setup<C>(a.pk, q, n, lane, sh, cphi);
         FRow<C> el = filter_element<C>(lane, sh, cphi, csq);
+        if (n == 1) {
+            SRow<C> st = state_apply<C>(lane, sh, init_state<C>(a.init, lane), el);
+            zero(el);
+            el.b = st.m;
+#pragma unroll
+            for (int c = 0; c < C::D; ++c) el.sC[c] = st.P[c];
+            el.flag = 1;
+        }
         if (n == s)
             acc = el;
         else
             acc = filter_combine<C, C::d, C::D - C::d>(lane, sh, acc, el);
     }
-    store_frow<C>(agg + chunk * C::FE, lane, acc);
+    store_frow<C>(agg + (a.pk.ftab[ri].base + lc) * C::FEF, lane, acc);
 }
 
 // Upper levels of the forward scan as in-workgroup trees: one leaf
@@ -868,103 +965,143 @@ PARAPN_DEV int tree_node(int s, int g)
     return C::W - C::W / s + g / (2 * s);
 }
 
+// Request, block within its level, and level of one block of a tree launch:
+// launch level >= 1 folds level `level` into level+1 for every request that
+// has it; level 0 is the top (one block per request, on its last level).
+struct TreePos {
+    int r;
+    int l;
+    int64_t lb;
+};
+
+PARAPN_DEV TreePos tree_pos(const ScanTab *tab, int nreq, int level)
+{
+    TreePos p;
+    if (level > 0) {
+        p.r = find_tab(tab, nreq, level, blockIdx.x);
+        p.l = level;
+        p.lb = (int64_t)blockIdx.x - tab[p.r].first[level];
+    } else {
+        p.r = blockIdx.x;
+        p.l = tab[p.r].L;
+        p.lb = 0;
+    }
+    return p;
+}
+
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_tree_up(const typename C::T *in, int64_t nin, typename C::T *out,
-                                                       typename C::T *part)
+__global__ __launch_bounds__(C::NT) void k_fwd_tree_up(Pack pk, typename C::T *agg, typename C::T *part, int level)
 {
     PARAPN_GROUP_SETUP(C);
-    __shared__ T xch[C::GPB * C::FE];
-    const int64_t base = (int64_t)blockIdx.x * C::W;
-    const int64_t leaf = base + grp;
+    __shared__ T xch[C::GPB * C::FEF];
+    const TreePos tp = tree_pos(pk.ftab, pk.nreq, level);
+    const ScanTab &t = pk.ftab[tp.r];
+    const T *in = agg + (t.base + t.off[tp.l]) * C::FEF;
+    const int64_t nin = t.n[tp.l];
+    T *pp = part + (t.pbase + t.poff[tp.l] + tp.lb * (C::W - 1)) * C::FEF;
+    const int64_t leaf = tp.lb * C::W + grp;
     FRow<C> acc;
     if (leaf < nin)
-        acc = load_frow<C>(in + leaf * C::FE, lane);
+        acc = load_frow<C>(in + leaf * C::FEF, lane);
     else
         zero(acc);
     for (int s = 1; s < C::W; s <<= 1) {
-        if (grp % (2 * s) == s && leaf < nin) store_frow<C>(xch + grp * C::FE, lane, acc);
+        if (grp % (2 * s) == s && leaf < nin) store_frow<C>(xch + grp * C::FEF, lane, acc);
         __syncthreads();
         if (grp % (2 * s) == 0 && leaf < nin) {
-            store_frow<C>(part + ((int64_t)blockIdx.x * (C::W - 1) + tree_node<C>(s, grp)) * C::FE, lane, acc);
+            store_frow<C>(pp + tree_node<C>(s, grp) * C::FEF, lane, acc);
             if (leaf + s < nin) {
-                FRow<C> r = load_frow<C>(xch + (grp + s) * C::FE, lane);
-                acc = filter_combine<C, C::D, C::D>(lane, sh, acc, r);
+                FRow<C> r = load_frow<C>(xch + (grp + s) * C::FEF, lane);
+                acc = fcombine<C, C::D, C::D>(lane, sh, acc, r);
             }
         }
         __syncthreads();
     }
-    if (grp == 0 && out) store_frow<C>(out + blockIdx.x * C::FE, lane, acc);
+    if (grp == 0 && level > 0) store_frow<C>(agg + (t.base + t.off[tp.l + 1] + tp.lb) * C::FEF, lane, acc);
 }
 
+// down-sweep of one tree: the block's incoming state is the prefix state of
+// its node one level up (the top tree starts from the initial state)
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_tree_down(int64_t nin, const typename C::T *part,
-                                                         const typename C::T *pref_up, typename C::T *pref)
+__global__ __launch_bounds__(C::NT) void k_fwd_tree_down(Pack pk, const typename C::T *part, typename C::T *pref,
+                                                         const typename C::T *init, int level)
 {
     PARAPN_GROUP_SETUP(C);
     __shared__ T xch[C::GPB * C::FS];
-    const int64_t base = (int64_t)blockIdx.x * C::W;
-    const int64_t leaf = base + grp;
-    SRow<C> st = load_state<C>(pref_up + (int64_t)blockIdx.x * C::FS, lane);
+    const TreePos tp = tree_pos(pk.ftab, pk.nreq, level);
+    const ScanTab &t = pk.ftab[tp.r];
+    const int64_t nin = t.n[tp.l];
+    const T *pp = part + (t.pbase + t.poff[tp.l] + tp.lb * (C::W - 1)) * C::FEF;
+    const int64_t leaf = tp.lb * C::W + grp;
+    SRow<C> st = level > 0 ? load_state<C>(pref + (t.base + t.off[tp.l + 1] + tp.lb) * C::FS, lane)
+                           : load_state<C>(init, lane);
     for (int s = C::W / 2; s >= 1; s >>= 1) {
         if (grp % (2 * s) == 0 && leaf + s < nin) {
-            FRow<C> left =
-                load_frow<C>(part + ((int64_t)blockIdx.x * (C::W - 1) + tree_node<C>(s, grp)) * C::FE, lane);
-            SRow<C> r = state_apply<C>(lane, sh, st, left);
+            FRow<C> left = load_frow<C>(pp + tree_node<C>(s, grp) * C::FEF, lane);
+            SRow<C> r = sapply<C>(lane, sh, st, left);
             store_state<C>(xch + (grp + s) * C::FS, lane, r);
         }
         __syncthreads();
         if (grp % (2 * s) == s && leaf < nin) st = load_state<C>(xch + grp * C::FS, lane);
         __syncthreads();
     }
-    if (leaf < nin) store_state<C>(pref + leaf * C::FS, lane, st);
+    if (leaf < nin) store_state<C>(pref + (t.base + t.off[tp.l] + leaf) * C::FS, lane, st);
 }
 
-// step level, forward down-sweep: Kalman steps from the chunk's prefix state.
-// The smoothing element of a step is formed from its filtering marginal
-// inside the next step's Kalman step, so a chunk covering steps s..e-1 writes
-// the elements (E, g) and sqrtL of steps s-1..e-2; the chunk holding step N
-// also writes the last element (E = 0, g = m^f_N, sqrtL = sqrtP^f_N).
+// step level, forward down-sweep: Kalman steps from the chunk's prefix state
+// (a request's first chunk starts from the initial state).  The smoothing
+// element of a step is formed from its filtering marginal inside the next
+// step's Kalman step, so a chunk covering steps s..e-1 writes the elements
+// (E, g) and sqrtL of steps s-1..e-2; the chunk holding step N also writes
+// the last element (E = 0, g = m^f_N, sqrtL = sqrtP^f_N, boundary flag).
 // Filtering marginals are written only when mf is given.
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename C::T *pref, int64_t nchunks,
-                                                     typename C::T *se, typename C::T *sL, typename C::T *mf,
-                                                     typename C::T *sPf)
+__global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename C::T *pref, typename C::T *se,
+                                                     typename C::T *sL, typename C::T *mf, typename C::T *sPf)
 {
     PARAPN_GROUP_SETUP(C);
     load_consts<C>(cphi, csq, a.Phi, a.sQ);
     constexpr int D = C::D;
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nchunks) return;
-    const int64_t s = 1 + chunk * a.b1;
-    const int64_t e = s + a.b1 <= a.N + 1 ? s + a.b1 : a.N + 1;
-    SRow<C> st = load_state<C>(pref + chunk * C::FS, lane);
-    if (chunk == 0 && mf && lane < D) {
-        mf[lane] = st.m;
-        store_packed<C>(sPf, lane, st.P);
+    if (chunk >= a.pk.nf) return;
+    const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
+    const ReqDev &q = a.pk.reqs[ri];
+    const int64_t lc = chunk - q.fchunk;
+    const int64_t s = 1 + lc * q.b1;
+    const int64_t e = s + q.b1 <= q.N + 1 ? s + q.b1 : q.N + 1;
+    SRow<C> st = s == 1 ? init_state<C>(a.init, lane)
+                        : load_state<C>(pref + (a.pk.ftab[ri].base + lc) * C::FS, lane);
+    if (s == 1 && mf && lane < D) {
+        mf[q.row * D + lane] = st.m;
+        store_packed<C>(sPf + q.row * C::DP, lane, st.P);
     }
     for (int64_t n = s; n < e; ++n) {
-        obs_setup<C>(a.obs, n, lane, sh, cphi);
+        obs_setup<C>(a.pk, q, n, lane, sh, cphi);
         ERow<C> eo;
         st = kf_step_se<C>(lane, sh, st, cphi, csq, eo);
+        const int64_t row = q.row + n - 1;
         if (lane >= D && lane < C::D2) {
             const int r = lane - D;
-            T *rec = se + (n - 1) * C::SE;
+            T *rec = se + row * C::SEF;
 #pragma unroll
             for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
             rec[D * D + r] = eo.g;
-            store_packed<C>(sL + (n - 1) * C::DP, r, eo.L);
+            if (r == 0) rec[C::SE] = 0;
+            store_packed<C>(sL + row * C::DP, r, eo.L);
         }
         if (mf && lane < D) {
-            mf[n * D + lane] = st.m;
-            store_packed<C>(sPf + n * C::DP, lane, st.P);
+            mf[(row + 1) * D + lane] = st.m;
+            store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
         }
     }
-    if (e == a.N + 1 && lane < D) {
-        T *rec = se + a.N * C::SE;
+    if (e == q.N + 1 && lane < D) {
+        const int64_t row = q.row + q.N;
+        T *rec = se + row * C::SEF;
 #pragma unroll
         for (int c = 0; c < D; ++c) rec[lane * D + c] = 0;
         rec[D * D + lane] = st.m;
-        store_packed<C>(sL + a.N * C::DP, lane, st.P);
+        if (lane == 0) rec[C::SE] = 1;
+        store_packed<C>(sL + row * C::DP, lane, st.P);
     }
 }
 
@@ -976,8 +1113,9 @@ PARAPN_DEV ERow<C> load_selem(const typename C::T *se, const typename C::T *sL, 
     e.g = 0;
 #pragma unroll
     for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
+    e.flag = se[n * C::SEF + C::SE];
     if (lane < D) {
-        const typename C::T *rec = se + n * C::SE;
+        const typename C::T *rec = se + n * C::SEF;
 #pragma unroll
         for (int c = 0; c < D; ++c) e.E[c] = rec[lane * D + c];
         e.g = rec[D * D + lane];
@@ -994,6 +1132,7 @@ PARAPN_DEV ERow<C> load_sagg(const typename C::T *rec, int lane)
     e.g = 0;
 #pragma unroll
     for (int c = 0; c < D; ++c) e.E[c] = e.L[c] = 0;
+    e.flag = rec[C::SA];
     if (lane < D) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -1009,6 +1148,7 @@ template <class C>
 PARAPN_DEV void store_sagg(typename C::T *rec, int lane, const ERow<C> &e)
 {
     constexpr int D = C::D;
+    if (lane == 0) rec[C::SA] = e.flag;
     if (lane < D) {
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -1019,16 +1159,22 @@ PARAPN_DEV void store_sagg(typename C::T *rec, int lane, const ERow<C> &e)
     }
 }
 
-// step level, smoother reduce over steps [s, e): b_s (x)_s ... (x)_s b_{e-1}
+
+// step level, smoother reduce over one chunk of a request's steps:
+// b_s (x)_s ... (x)_s b_{e-1}
 template <class C, bool WITH_L>
 __global__ __launch_bounds__(C::NT) void k_bwd_reduce1(KArgs<C> a, const typename C::T *se,
-                                                       const typename C::T *sL, typename C::T *agg, int64_t nchunks)
+                                                       const typename C::T *sL, typename C::T *agg)
 {
     PARAPN_GROUP_SETUP(C);
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nchunks) return;
-    const int64_t s = chunk * C::B1;
-    const int cnt = (int)(s + C::B1 <= a.N + 1 ? C::B1 : a.N + 1 - s);
+    if (chunk >= a.pk.ns) return;
+    const int ri = find_req<false>(a.pk.reqs, a.pk.nreq, chunk);
+    const ReqDev &q = a.pk.reqs[ri];
+    const int64_t lc = chunk - q.schunk;
+    const int64_t s = lc * C::B1;
+    const int cnt = (int)(s + C::B1 <= q.N + 1 ? C::B1 : q.N + 1 - s);
+    const int64_t row0 = q.row + s;
     // the chunk's elements are loaded up front so the fold does not wait on
     // memory (unless they would not fit in registers: factors at large D)
     constexpr bool PREFETCH = !WITH_L || C::D <= 8;
@@ -1037,125 +1183,145 @@ __global__ __launch_bounds__(C::NT) void k_bwd_reduce1(KArgs<C> a, const typenam
     if (PREFETCH) {
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, s + i, lane);
+            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, row0 + i, lane);
     }
-    ERow<C> acc = load_selem<C, WITH_L>(se, sL, s, lane);
+    ERow<C> acc = load_selem<C, WITH_L>(se, sL, row0, lane);
 #pragma unroll
     for (int i = 1; i < C::B1; ++i)
-        if (i < cnt) acc = smoother_combine<C, WITH_L>(lane, sh, acc, PREFETCH ? els[i % NB] :
-                                                       load_selem<C, WITH_L>(se, sL, s + i, lane));
-    store_sagg<C>(agg + chunk * C::SA, lane, acc);
+        if (i < cnt)
+            acc = scombine<C, WITH_L>(lane, sh, acc,
+                                      PREFETCH ? els[i % NB] : load_selem<C, WITH_L>(se, sL, row0 + i, lane));
+    store_sagg<C>(agg + (a.pk.stab[ri].base + lc) * C::SAF, lane, acc);
 }
 
+// reverse launch l >= 1: one group per node of level l+1 of each request
+// that has it, folding bu consecutive level-l aggregates
 template <class C, bool WITH_L>
-__global__ __launch_bounds__(C::NT) void k_bwd_reduce(KArgs<C> a, const typename C::T *in, int64_t nin,
-                                                      typename C::T *out, int64_t nout)
+__global__ __launch_bounds__(C::NT) void k_bwd_reduce(Pack pk, typename C::T *agg, int level)
 {
     PARAPN_GROUP_SETUP(C);
-    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nout) return;
-    const int64_t s = chunk * a.bu;
-    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
-    ERow<C> acc = load_sagg<C>(in + s * C::SA, lane);
+    const int64_t g = (int64_t)blockIdx.x * C::GPB + grp;
+    if (g >= pk.sgroups[level]) return;
+    const ScanTab &t = pk.stab[find_tab(pk.stab, pk.nreq, level, g)];
+    const int64_t lg = g - t.first[level];
+    const T *in = agg + (t.base + t.off[level]) * C::SAF;
+    const int64_t nin = t.n[level];
+    const int64_t s = lg * pk.bu;
+    const int64_t e = s + pk.bu <= nin ? s + pk.bu : nin;
+    ERow<C> acc = load_sagg<C>(in + s * C::SAF, lane);
     for (int64_t i = s + 1; i < e; ++i) {
-        ERow<C> el = load_sagg<C>(in + i * C::SA, lane);
-        acc = smoother_combine<C, WITH_L>(lane, sh, acc, el);
+        ERow<C> el = load_sagg<C>(in + i * C::SAF, lane);
+        acc = scombine<C, WITH_L>(lane, sh, acc, el);
     }
-    store_sagg<C>(out + chunk * C::SA, lane, acc);
+    store_sagg<C>(agg + (t.base + t.off[level + 1] + lg) * C::SAF, lane, acc);
 }
 
-// top: exclusive suffix scan (from the right) of n aggregates; the state after
-// the last one is irrelevant because the last aggregate contains E_N = 0
+// top: one block (one group) per request: exclusive suffix scan, from the
+// right, of the aggregates of its last level; the state after its last
+// aggregate is irrelevant because that aggregate holds the request's last
+// element
 template <class C, bool WITH_L>
-__global__ __launch_bounds__(C::R) void k_bwd_top(KArgs<C> a, const typename C::T *agg, int64_t n,
-                                                   typename C::T *suf)
+__global__ __launch_bounds__(C::R) void k_bwd_top(Pack pk, const typename C::T *agg, typename C::T *suf)
 {
     PARAPN_GROUP_SETUP(C);
     if (grp != 0) return;
+    const ScanTab &t = pk.stab[blockIdx.x];
+    const int l = t.L;
+    const T *a = agg + (t.base + t.off[l]) * C::SAF;
+    T *o = suf + (t.base + t.off[l]) * C::SS;
     SRow<C> st;
     st.m = 0;
 #pragma unroll
     for (int c = 0; c < C::D; ++c) st.P[c] = 0;
-    for (int64_t i = n - 1; i >= 0; --i) {
-        store_state<C>(suf + i * C::SS, lane, st);
+    for (int64_t i = t.n[l] - 1; i >= 0; --i) {
+        store_state<C>(o + i * C::SS, lane, st);
         if (i > 0) {
-            ERow<C> el = load_sagg<C>(agg + i * C::SA, lane);
-            st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+            ERow<C> el = load_sagg<C>(a + i * C::SAF, lane);
+            st = sm_apply<C, WITH_L>(lane, sh, el, st);
         }
     }
 }
 
 template <class C, bool WITH_L>
-__global__ __launch_bounds__(C::NT) void k_bwd_down(KArgs<C> a, const typename C::T *agg, int64_t nin,
-                                                    const typename C::T *suf_up, typename C::T *suf, int64_t nup)
+__global__ __launch_bounds__(C::NT) void k_bwd_down(Pack pk, const typename C::T *agg, typename C::T *suf,
+                                                    int level)
 {
     PARAPN_GROUP_SETUP(C);
-    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nup) return;
-    const int64_t s = chunk * a.bu;
-    const int64_t e = s + a.bu <= nin ? s + a.bu : nin;
-    SRow<C> st = load_state<C>(suf_up + chunk * C::SS, lane);
+    const int64_t g = (int64_t)blockIdx.x * C::GPB + grp;
+    if (g >= pk.sgroups[level]) return;
+    const ScanTab &t = pk.stab[find_tab(pk.stab, pk.nreq, level, g)];
+    const int64_t lg = g - t.first[level];
+    const T *a = agg + (t.base + t.off[level]) * C::SAF;
+    T *o = suf + (t.base + t.off[level]) * C::SS;
+    const int64_t nin = t.n[level];
+    const int64_t s = lg * pk.bu;
+    const int64_t e = s + pk.bu <= nin ? s + pk.bu : nin;
+    SRow<C> st = load_state<C>(suf + (t.base + t.off[level + 1] + lg) * C::SS, lane);
     for (int64_t i = e - 1; i >= s; --i) {
-        store_state<C>(suf + i * C::SS, lane, st);
+        store_state<C>(o + i * C::SS, lane, st);
         if (i > s) {
-            ERow<C> el = load_sagg<C>(agg + i * C::SA, lane);
-            st = smoother_apply<C, WITH_L>(lane, sh, el, st);
+            ERow<C> el = load_sagg<C>(a + i * C::SAF, lane);
+            st = sm_apply<C, WITH_L>(lane, sh, el, st);
         }
     }
 }
 
-// step level, smoother down-sweep over the chunk's steps from its suffix
-// state.  UPDATE: add the smoothed increments to the FP64 trajectory (the
-// next linearisation point) and accumulate, in double,
-//   delta = max |T0 E0 increment|  and  max |T0 E0 trajectory|;
-// otherwise write the smoothed means to mout.
+// step level, smoother down-sweep over one chunk of a request's steps from
+// its suffix state.  UPDATE: add the smoothed increments to the request's
+// FP64 trajectory (the next linearisation point) and accumulate, in double,
+//   delta = max |T0 E0 increment|  and  max |T0 E0 trajectory|
+// into the request's counters; otherwise write the smoothed means to mout
+// (packed rows).
 template <class C, bool WITH_L, bool UPDATE>
 __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename C::T *se, const typename C::T *sL,
-                                                     const typename C::T *suf, int64_t nchunks, typename C::T *mout,
-                                                     double *trajd, typename C::T *sPs, unsigned long long *dbits,
-                                                     double T0)
+                                                     const typename C::T *suf, typename C::T *mout,
+                                                     typename C::T *sPs)
 {
     PARAPN_GROUP_SETUP(C);
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= nchunks) return;
+    if (chunk >= a.pk.ns) return;
     constexpr int D = C::D;
-    const int64_t s = chunk * C::B1;
-    const int cnt = (int)(s + C::B1 <= a.N + 1 ? C::B1 : a.N + 1 - s);
+    const int ri = find_req<false>(a.pk.reqs, a.pk.nreq, chunk);
+    const ReqDev &q = a.pk.reqs[ri];
+    const int64_t lc = chunk - q.schunk;
+    const int64_t s = lc * C::B1;
+    const int cnt = (int)(s + C::B1 <= q.N + 1 ? C::B1 : q.N + 1 - s);
+    const int64_t row0 = q.row + s;
     constexpr bool PREFETCH = !WITH_L || C::D <= 8;
     constexpr int NB = PREFETCH ? C::B1 : 1;
     ERow<C> els[NB];
     if (PREFETCH) {
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, s + i, lane);
+            if (i < cnt) els[i] = load_selem<C, WITH_L>(se, sL, row0 + i, lane);
     }
     double told[C::B1];
     if (UPDATE) {
 #pragma unroll
-        for (int i = 0; i < C::B1; ++i) told[i] = (i < cnt && lane < D) ? trajd[(s + i) * D + lane] : 0.0;
+        for (int i = 0; i < C::B1; ++i) told[i] = (i < cnt && lane < D) ? q.traj[(s + i) * D + lane] : 0.0;
     }
-    SRow<C> st = load_state<C>(suf + chunk * C::SS, lane);
+    SRow<C> st = load_state<C>(suf + (a.pk.stab[ri].base + lc) * C::SS, lane);
     double dmax = 0.0, mmax = 0.0;
 #pragma unroll
     for (int i = C::B1 - 1; i >= 0; --i) {
         if (i >= cnt) continue;
         const int64_t n = s + i;
-        st = smoother_apply<C, WITH_L>(lane, sh, PREFETCH ? els[i % NB] : load_selem<C, WITH_L>(se, sL, n, lane),
-                                       st);
+        st = sm_apply<C, WITH_L>(lane, sh,
+                                 PREFETCH ? els[i % NB] : load_selem<C, WITH_L>(se, sL, row0 + i, lane), st);
         if (lane < D) {
             if (UPDATE) {
                 const double nw = told[i] + (double)st.m;
                 if (lane % C::S == 0) {
-                    const double df = fabs(T0 * (double)st.m);
+                    const double df = fabs(q.T0 * (double)st.m);
                     dmax = (df > dmax || df != df) ? df : dmax;
-                    const double am = fabs(T0 * nw);
+                    const double am = fabs(q.T0 * nw);
                     mmax = (am > mmax || am != am) ? am : mmax;
                 }
-                trajd[n * D + lane] = nw;
+                q.traj[n * D + lane] = nw;
             } else {
-                mout[n * D + lane] = st.m;
+                mout[(row0 + i) * D + lane] = st.m;
             }
-            if (WITH_L) store_packed<C>(sPs + n * C::DP, lane, st.P);
+            if (WITH_L) store_packed<C>(sPs + (row0 + i) * C::DP, lane, st.P);
         }
     }
     if (UPDATE) {
@@ -1173,8 +1339,8 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
                 x = (u > x || u != u) ? u : x;
                 y = (v > y || v != v) ? v : y;
             }
-            atomicMax(dbits, (unsigned long long)__double_as_longlong(x));
-            atomicMax(dbits + 1, (unsigned long long)__double_as_longlong(y));
+            atomicMax(q.dbits, (unsigned long long)__double_as_longlong(x));
+            atomicMax(q.dbits + 1, (unsigned long long)__double_as_longlong(y));
         }
     }
 }
@@ -1187,11 +1353,12 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
     PARAPN_GROUP_SETUP(C);
     const int64_t k = (int64_t)blockIdx.x * C::GPB + grp;
     if (k >= count) return;
-    FRow<C> ei = load_frow<C>(aa + k * C::FE, lane);
-    FRow<C> ej = load_frow<C>(cc + k * C::FE, lane);
+    FRow<C> ei = load_frow<C, false>(aa + k * C::FE, lane);
+    FRow<C> ej = load_frow<C, false>(cc + k * C::FE, lane);
     FRow<C> o = filter_combine<C, C::D, C::D>(lane, sh, ei, ej);
-    store_frow<C>(out + k * C::FE, lane, o);
+    store_frow<C, false>(out + k * C::FE, lane, o);
 }
+
 
 // ---------------------------------------------------------------------------
 // host-side launch sequences
@@ -1205,21 +1372,21 @@ struct Levels {
     int64_t total;
 };
 
-// forward scan levels: n[1] = cdiv(N, b1) step aggregates, then trees of
-// width W until at most W remain (the top tree).  poff[l]: record offset of
-// the tree partials of the launch that reduces level l (l = 1..L; level L is
-// the single-block top tree).
+// forward scan levels: n[1] step-level aggregates, then trees of width W
+// until at most W remain (the top tree).  poff[l]: record offset of the tree
+// partials of the launch that reduces level l (l = 1..L; level L is the
+// single-block top tree).
 struct TreeLevels {
     int L;
     int64_t n[48], off[48], poff[48];
     int64_t total, ptotal;
 };
 
-static TreeLevels make_tree_levels(int64_t N, int b1, int W)
+static TreeLevels make_tree_levels(int64_t n1, int W)
 {
     TreeLevels t{};
     t.L = 1;
-    t.n[1] = (N + b1 - 1) / b1;
+    t.n[1] = n1;
     t.off[1] = 0;
     t.poff[1] = 0;
     while (t.n[t.L] > W && t.L < 46) {
@@ -1234,11 +1401,11 @@ static TreeLevels make_tree_levels(int64_t N, int b1, int W)
     return t;
 }
 
-static Levels make_levels(int64_t nitems, int b1, int bu, int btop)
+static Levels make_levels(int64_t n1, int bu, int btop)
 {
     Levels lv{};
     lv.L = 1;
-    lv.n[1] = cdiv(nitems, b1);
+    lv.n[1] = n1;
     lv.off[1] = 0;
     while (lv.n[lv.L] > btop && lv.L < 46) {
         lv.n[lv.L + 1] = cdiv(lv.n[lv.L], bu);
@@ -1250,93 +1417,71 @@ static Levels make_levels(int64_t nitems, int b1, int bu, int btop)
 }
 
 template <class C>
-static KArgs<C> make_args(const ScanPlan &p, const ModelDev &m, const ObsSpec *o)
+static KArgs<C> make_args(const Pack &pk, const ModelDev &m)
 {
     using T = typename C::T;
     KArgs<C> a{};
-    a.N = p.N;
-    a.b1 = p.b1;
-    a.bu = p.bu;
+    a.pk = pk;
     a.Phi = (const T *)m.Phi;
     a.sQ = (const T *)m.sQ;
-    a.m0 = (const T *)m.m0;
-    a.S0 = (const T *)m.S0;
-    if (o) {
-        a.obs.mode = o->mode;
-        a.obs.traj = (const double *)o->traj;
-        a.obs.field = o->field;
-        for (int i = 0; i < kMaxParams; ++i) a.obs.p[i] = o->p[i];
-        a.obs.T0 = o->T0;
-        a.obs.T1 = o->T1;
-        a.obs.invT1 = o->invT1;
-        a.obs.hq = o->hq;
-        a.obs.H = (const T *)o->H;
-        a.obs.dv = (const T *)o->dv;
-    }
+    a.init = (const T *)m.init;
     return a;
 }
 
 template <class C>
-static hipError_t fwd_seq(const ScanPlan &p, const ModelDev &m, const ObsSpec &o, const Work &w, hipStream_t s)
+static hipError_t fwd_seq(const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
 {
     using T = typename C::T;
-    if (p.b1 < 1) return hipErrorInvalidValue;
-    KArgs<C> a = make_args<C>(p, m, &o);
-    TreeLevels lv = make_tree_levels(p.N, p.b1, C::W);
-    T *agg = (T *)w.fagg, *pref = (T *)w.fpref;
-    T *part = agg + lv.total * C::FE;  // the sizing reserves W = 2 worth of partials
+    if (pk.nf < 1 || pk.nreq < 1 || pk.Lf < 1 || pk.Lf > kMaxLevels) return hipErrorInvalidValue;
+    KArgs<C> a = make_args<C>(pk, m);
+    T *agg = (T *)w.fagg, *part = (T *)w.fpart, *pref = (T *)w.fpref;
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
-    PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
-                  agg + lv.off[1] * C::FE, lv.n[1]);
-    for (int l = 1; l < lv.L; ++l)
-        PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)lv.n[l + 1]), dim3(C::NT), 0, s,
-                      agg + lv.off[l] * C::FE, lv.n[l], agg + lv.off[l + 1] * C::FE, part + lv.poff[l] * C::FE);
-    // top: one block from the initial state (m0, S0)
-    PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3(1), dim3(C::NT), 0, s, agg + lv.off[lv.L] * C::FE,
-                  lv.n[lv.L], (T *)nullptr, part + lv.poff[lv.L] * C::FE);
-    PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3(1), dim3(C::NT), 0, s, lv.n[lv.L],
-                  part + lv.poff[lv.L] * C::FE, (const T *)m.init, pref + lv.off[lv.L] * C::FS);
-    for (int l = lv.L - 1; l >= 1; --l)
-        PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)lv.n[l + 1]), dim3(C::NT), 0, s,
-                      lv.n[l], part + lv.poff[l] * C::FE, pref + lv.off[l + 1] * C::FS, pref + lv.off[l] * C::FS);
-    PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
-                  pref + lv.off[1] * C::FS, lv.n[1], (T *)w.se, (T *)w.sL, (T *)w.filt_mf, (T *)w.filt_sPf);
+    PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(pk.nf)), dim3(C::NT), 0, s, a, agg);
+    for (int l = 1; l < pk.Lf; ++l)
+        if (pk.fblocks[l] > 0)
+            PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)pk.fblocks[l]), dim3(C::NT), 0, s, pk,
+                          agg, part, l);
+    // top trees, one block per request, from the initial state
+    PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)pk.nreq), dim3(C::NT), 0, s, pk, agg, part, 0);
+    PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)pk.nreq), dim3(C::NT), 0, s, pk,
+                  (const T *)part, pref, (const T *)m.init, 0);
+    for (int l = pk.Lf - 1; l >= 1; --l)
+        if (pk.fblocks[l] > 0)
+            PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)pk.fblocks[l]), dim3(C::NT), 0, s,
+                          pk, (const T *)part, pref, (const T *)m.init, l);
+    PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(pk.nf)), dim3(C::NT), 0, s, a, (const T *)pref,
+                  (T *)w.se, (T *)w.sL, (T *)w.filt_mf, (T *)w.filt_sPf);
     return hipGetLastError();
 }
 
 template <class CF, bool WITH_L>
-static hipError_t bwd_seq(const ScanPlan &p, const ModelDev &m, const Work &w, bool update, void *mout, double T0,
-                          hipStream_t s)
+static hipError_t bwd_seq(const Pack &pk, const ModelDev &m, const Work &w, bool update, void *mout, hipStream_t s)
 {
     // the reverse scan works on D rows: groups of next-power-of-two(D) lanes
     using C = Cfg<typename CF::T, CF::d, CF::q, pow2ceil(CF::D)>;
     using T = typename C::T;
-    if (p.bs1 != C::B1) return hipErrorInvalidValue;
-    KArgs<C> a = make_args<C>(p, m, nullptr);
-    a.traj = (const double *)w.traj;
-    a.b1 = p.bs1;
-    Levels lv = make_levels(p.N + 1, p.bs1, p.bu, p.btop);
+    if (pk.ns < 1 || pk.nreq < 1 || pk.Ls < 1 || pk.Ls > kMaxLevels) return hipErrorInvalidValue;
+    KArgs<C> a = make_args<C>(pk, m);
     T *agg = (T *)w.sagg, *suf = (T *)w.spref;
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
-    PARAPN_LAUNCH("bwd_reduce1", s, (k_bwd_reduce1<C, WITH_L>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a, (const T *)w.se,
-                       (const T *)w.sL, agg + lv.off[1] * C::SA, lv.n[1]);
-    for (int l = 1; l < lv.L; ++l)
-        PARAPN_LAUNCH("bwd_reduce", s, (k_bwd_reduce<C, WITH_L>), dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
-                           agg + lv.off[l] * C::SA, lv.n[l], agg + lv.off[l + 1] * C::SA, lv.n[l + 1]);
-    PARAPN_LAUNCH("bwd_top", s, (k_bwd_top<C, WITH_L>), dim3(1), dim3(C::R), 0, s, a, agg + lv.off[lv.L] * C::SA, lv.n[lv.L],
-                       suf + lv.off[lv.L] * C::SS);
-    for (int l = lv.L - 1; l >= 1; --l)
-        PARAPN_LAUNCH("bwd_down", s, (k_bwd_down<C, WITH_L>), dim3(blocks(lv.n[l + 1])), dim3(C::NT), 0, s, a,
-                           agg + lv.off[l] * C::SA, lv.n[l], suf + lv.off[l + 1] * C::SS, suf + lv.off[l] * C::SS,
-                           lv.n[l + 1]);
+    PARAPN_LAUNCH("bwd_reduce1", s, (k_bwd_reduce1<C, WITH_L>), dim3(blocks(pk.ns)), dim3(C::NT), 0, s, a,
+                  (const T *)w.se, (const T *)w.sL, agg);
+    for (int l = 1; l < pk.Ls; ++l)
+        if (pk.sgroups[l] > 0)
+            PARAPN_LAUNCH("bwd_reduce", s, (k_bwd_reduce<C, WITH_L>), dim3(blocks(pk.sgroups[l])), dim3(C::NT), 0, s,
+                          pk, agg, l);
+    PARAPN_LAUNCH("bwd_top", s, (k_bwd_top<C, WITH_L>), dim3((unsigned)pk.nreq), dim3(C::R), 0, s, pk,
+                  (const T *)agg, suf);
+    for (int l = pk.Ls - 1; l >= 1; --l)
+        if (pk.sgroups[l] > 0)
+            PARAPN_LAUNCH("bwd_down", s, (k_bwd_down<C, WITH_L>), dim3(blocks(pk.sgroups[l])), dim3(C::NT), 0, s, pk,
+                          (const T *)agg, suf, l);
     if (update)
-        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, true>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
-                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)nullptr,
-                           (double *)w.traj, (T *)w.sPs, w.dbits, T0);
+        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, true>), dim3(blocks(pk.ns)), dim3(C::NT), 0, s, a,
+                      (const T *)w.se, (const T *)w.sL, (const T *)suf, (T *)nullptr, (T *)w.sPs);
     else
-        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, false>), dim3(blocks(lv.n[1])), dim3(C::NT), 0, s, a,
-                           (const T *)w.se, (const T *)w.sL, suf + lv.off[1] * C::SS, lv.n[1], (T *)mout,
-                           (double *)nullptr, (T *)w.sPs, w.dbits, T0);
+        PARAPN_LAUNCH("bwd_down1", s, (k_bwd_down1<C, WITH_L, false>), dim3(blocks(pk.ns)), dim3(C::NT), 0, s, a,
+                      (const T *)w.se, (const T *)w.sL, (const T *)suf, (T *)mout, (T *)w.sPs);
     return hipGetLastError();
 }
 
@@ -1408,20 +1553,19 @@ static hipError_t dispatch_t(int d, int q, F &&f)
 }
 
 template <typename T>
-hipError_t launch_forward_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const ObsSpec &obs, const Work &w,
-                            hipStream_t s)
+hipError_t launch_forward_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
 {
-    return dispatch_t<T>(d, q, [&](auto c) { return fwd_seq<decltype(c)>(plan, m, obs, w, s); });
+    return dispatch_t<T>(d, q, [&](auto c) { return fwd_seq<decltype(c)>(pk, m, w, s); });
 }
 
 template <typename T>
-hipError_t launch_smoother_t(int d, int q, const ScanPlan &plan, const ModelDev &m, const Work &w, bool with_cov,
-                             bool update_traj, void *mean_out, double T0, hipStream_t s)
+hipError_t launch_smoother_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, bool with_cov,
+                             bool update, void *mean_out, hipStream_t s)
 {
     return dispatch_t<T>(d, q, [&](auto c) {
         using C = decltype(c);
-        return with_cov ? bwd_seq<C, true>(plan, m, w, update_traj, mean_out, T0, s)
-                        : bwd_seq<C, false>(plan, m, w, update_traj, mean_out, T0, s);
+        return with_cov ? bwd_seq<C, true>(pk, m, w, update, mean_out, s)
+                        : bwd_seq<C, false>(pk, m, w, update, mean_out, s);
     });
 }
 
@@ -1458,10 +1602,9 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
 #endif
 
 #define PARAPN_INSTANTIATE(T)                                                                                       \
-    template hipError_t launch_forward_t<T>(int, int, const ScanPlan &, const ModelDev &, const ObsSpec &,          \
-                                            const Work &, hipStream_t);                                            \
-    template hipError_t launch_smoother_t<T>(int, int, const ScanPlan &, const ModelDev &, const Work &, bool, bool, \
-                                             void *, double, hipStream_t);                                         \
+    template hipError_t launch_forward_t<T>(int, int, const Pack &, const ModelDev &, const Work &, hipStream_t);  \
+    template hipError_t launch_smoother_t<T>(int, int, const Pack &, const ModelDev &, const Work &, bool, bool,    \
+                                             void *, hipStream_t);                                                 \
     template hipError_t launch_filter_combine_t<T>(int, int, int64_t, const void *, const void *, void *,          \
                                                    hipStream_t);                                                   \
     template hipError_t launch_tria_square_t<T>(int, int, const void *, void *, hipStream_t);
@@ -1556,28 +1699,97 @@ int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *lau
 
 int config_supported(int d, int q) { return (d >= 1 && d <= 3 && q >= 1 && q <= 4) ? 1 : -1; }
 
-// sizes cover every tree width a configuration may use (W = 2, 4, 8, 16)
-size_t work_elems_fagg(int D, const ScanPlan &p)
+int forward_chunk(int64_t N)
 {
-    int64_t rec = 0;
-    for (int W = 2; W <= 16; W *= 2) {
-        TreeLevels lv = make_tree_levels(p.N, p.b1, W);
-        rec = std::max<int64_t>(rec, lv.total + lv.ptotal);
+    // long enough that the step-level aggregates (folded with the cheaper
+    // single-element operator) leave little work for the upper levels, short
+    // enough that about 8192 groups keep every SIMD busy
+    int b1 = 4;
+    while (b1 < 32 && N / (2 * b1) >= 8192) b1 *= 2;
+    return b1;
+}
+
+template <typename T>
+static int tree_width_t(int d, int q)
+{
+    switch (d * 10 + q) {
+    case 11: return Cfg<T, 1, 1>::W;
+    case 12: return Cfg<T, 1, 2>::W;
+    case 13: return Cfg<T, 1, 3>::W;
+    case 14: return Cfg<T, 1, 4>::W;
+    case 21: return Cfg<T, 2, 1>::W;
+    case 22: return Cfg<T, 2, 2>::W;
+    case 23: return Cfg<T, 2, 3>::W;
+    case 24: return Cfg<T, 2, 4>::W;
+    case 31: return Cfg<T, 3, 1>::W;
+    case 32: return Cfg<T, 3, 2>::W;
+    case 33: return Cfg<T, 3, 3>::W;
+    case 34: return Cfg<T, 3, 4>::W;
     }
-    return (size_t)rec * (size_t)(3 * D * D + 2 * D);
+    return -1;
 }
 
-size_t work_records_fpref(const ScanPlan &p)
+int pack_layout(int fp64, int d, int q, ReqDev *reqs, ScanTab *ftab, ScanTab *stab, int nreq, Pack *pk)
 {
-    int64_t rec = 0;
-    for (int W = 2; W <= 16; W *= 2) rec = std::max<int64_t>(rec, make_tree_levels(p.N, p.b1, W).total);
-    return (size_t)rec;
-}
-
-size_t work_elems_sagg(int D, const ScanPlan &p)
-{
-    Levels lv = make_levels(p.N + 1, p.bs1, p.bu, p.btop);
-    return (size_t)lv.total * (size_t)(2 * D * D + D);
+    const int W = fp64 ? tree_width_t<double>(d, q) : tree_width_t<float>(d, q);
+    constexpr int BS = Cfg<float, 1, 1>::B1;
+    if (W < 2 || nreq < 1 || pk->bu < 2 || pk->btop < 1) return -1;
+    int64_t f = 0, sm = 0, r = 0, fr = 0, fpr = 0, sr = 0;
+    pk->Lf = pk->Ls = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) pk->fblocks[l] = pk->sgroups[l] = 0;
+    for (int i = 0; i < nreq; ++i) {
+        ReqDev &rq = reqs[i];
+        if (rq.N < 1) return -1;
+        rq.b1 = forward_chunk(rq.N);
+        rq.fchunk = f;
+        rq.schunk = sm;
+        rq.row = r;
+        const int64_t n1f = cdiv(rq.N, rq.b1), n1s = cdiv(rq.N + 1, BS);
+        const TreeLevels tl = make_tree_levels(n1f, W);
+        const Levels sl = make_levels(n1s, pk->bu, pk->btop);
+        if (tl.L > kMaxLevels || sl.L > kMaxLevels) return -1;
+        ScanTab &a = ftab[i];
+        std::memset(&a, 0, sizeof(a));
+        a.L = tl.L;
+        a.base = fr;
+        a.pbase = fpr;
+        for (int l = 1; l <= tl.L; ++l) {
+            a.n[l] = (int32_t)tl.n[l];
+            a.off[l] = (int32_t)tl.off[l];
+            a.poff[l] = (int32_t)tl.poff[l];
+        }
+        for (int l = 1; l <= kMaxLevels; ++l) {
+            a.first[l] = (int32_t)pk->fblocks[l];
+            if (l < tl.L) pk->fblocks[l] += tl.n[l + 1];
+        }
+        ScanTab &b = stab[i];
+        std::memset(&b, 0, sizeof(b));
+        b.L = sl.L;
+        b.base = sr;
+        for (int l = 1; l <= sl.L; ++l) {
+            b.n[l] = (int32_t)sl.n[l];
+            b.off[l] = (int32_t)sl.off[l];
+        }
+        for (int l = 1; l <= kMaxLevels; ++l) {
+            b.first[l] = (int32_t)pk->sgroups[l];
+            if (l < sl.L) pk->sgroups[l] += sl.n[l + 1];
+        }
+        fr += tl.total;
+        fpr += tl.ptotal;
+        sr += sl.total;
+        pk->Lf = std::max(pk->Lf, tl.L);
+        pk->Ls = std::max(pk->Ls, sl.L);
+        f += n1f;
+        sm += n1s;
+        r += rq.N + 1;
+    }
+    pk->nf = f;
+    pk->ns = sm;
+    pk->rows = r;
+    pk->frecs = fr;
+    pk->fprecs = fpr;
+    pk->srecs = sr;
+    return 0;
 }
 
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
@@ -1598,15 +1810,10 @@ hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, c
     return hipGetLastError();
 }
 
-hipError_t launch_fill_traj(int fp64, int D, int64_t N, const void *row, void *traj, hipStream_t s)
+hipError_t launch_fill_traj(int D, int64_t N, const double *row, double *traj, hipStream_t s)
 {
     const unsigned blocks = (unsigned)cdiv((N + 1) * D, 256);
-    if (fp64)
-        hipLaunchKernelGGL(k_fill_traj<double>, dim3(blocks), dim3(256), 0, s, D, N, (const double *)row,
-                           (double *)traj);
-    else
-        hipLaunchKernelGGL(k_fill_traj<float>, dim3(blocks), dim3(256), 0, s, D, N, (const float *)row,
-                           (float *)traj);
+    hipLaunchKernelGGL(k_fill_traj<double>, dim3(blocks), dim3(256), 0, s, D, N, row, traj);
     return hipGetLastError();
 }
 #endif

@@ -69,3 +69,30 @@ def test_no_cpu_fallback_without_library(tmp_path):
     spec.loader.exec_module(mod)
     with pytest.raises(ImportError):
         mod.load_library(str(tmp_path / "missing.so"))
+
+
+def test_server_host_validation():
+    """Server entry points reject bad arguments before any device work."""
+    import paper_2310_01145_amd as pp
+
+    L = pp.load_library()
+    h = ctypes.c_void_p()
+    assert L.parapn_server_create(ctypes.byref(h), None, 4, 0, None) == pp.EINVAL
+    assert L.parapn_server_submit(None, None, 0, None) == pp.EINVAL
+    assert L.parapn_server_step(None, None, None) == pp.EINVAL
+    assert L.parapn_server_poll(None, None, 0, None) == pp.EINVAL
+    assert L.parapn_server_stats(None, None, None, None, None) == pp.EINVAL
+    L.parapn_server_destroy(None)
+    t0 = L.parapn_server_clock()
+    assert L.parapn_server_clock() >= t0
+    # the admission footprint: linear in N, doubled elements in FP64
+    f1 = pp.server_footprint("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp32")
+    f2 = pp.server_footprint("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 13, precision="fp32")
+    f64 = pp.server_footprint("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp64")
+    assert 1.9 * f1 < f2 < 2.1 * f1 and 1.5 * f1 < f64 < 2.5 * f1
+    # it covers at least the resident FP64 trajectory and the per-step scratch
+    D, N = 8, 1 << 12
+    assert f1 > (N + 1) * D * 8 + (N + 1) * (D * D + D) * 4
+    with pytest.raises(pp.ParapnError) as e:
+        pp.server_footprint("logistic", [], [0.1], 0.0, 1.0, 2, 0)
+    assert e.value.code == pp.EINVAL

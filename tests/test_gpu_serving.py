@@ -1,0 +1,188 @@
+"""Continuous-batching server (parapn_server_*): each request's result is the
+same alone and in the mix, a non-finite neighbour does not leak into other
+requests, and admission respects the slot and HBM-footprint limits.
+
+A pack scans every request with its own chunking and its own tree of levels
+(the launches of a level serve all requests that have it), so a request's
+arithmetic does not depend on its neighbours: alone and in the mix, results
+must be bitwise equal, in both precisions.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+
+    import paper_2310_01145_amd as m
+
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+def np_(t):
+    return t.double().cpu().numpy()
+
+
+def same(a, b):
+    """bitwise equality of two device tensors (NaN patterns included)"""
+    import torch
+
+    iv = {4: torch.int32, 8: torch.int64}
+    return (a.shape == b.shape and a.dtype == b.dtype
+            and torch.equal(a.view(iv[a.element_size()]), b.view(iv[b.element_size()])))
+
+
+def relerr_e0(x, ref, q):
+    x, ref = np.asarray(x)[:, :: q + 1], np.asarray(ref)[:, :: q + 1]
+    return np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def req(field, params, y0, t1, q, N, prec, k=0, tol=1e-10, max_iter=20):
+    return dict(field=field, params=params, y0=y0, t0=0.0, t1=t1, q=q, N=N, precision=prec, fixed_iters=k,
+                tol=tol, max_iter=max_iter)
+
+
+def serve_all(pp, reqs, max_slots=64, budget=0, max_steps=2000):
+    srv = pp.Server(max_slots=max_slots, budget=budget)
+    for i, r in enumerate(reqs):
+        srv.submit(i, **r)
+    done = {}
+    steps = 0
+    while len(done) < len(reqs):
+        srv.step()
+        for c in srv.poll():
+            done[c["req_id"]] = c
+        steps += 1
+        assert steps < max_steps, "server did not drain"
+    stats = srv.stats()
+    srv.close()
+    return done, stats
+
+
+def alone(pp, r):
+    return pp.solve(r["field"], r["params"], r["y0"], r["t0"], r["t1"], r["q"], r["N"], precision=r["precision"],
+                    fixed_iters=r["fixed_iters"], tol=r["tol"], max_iter=r["max_iter"])
+
+
+MIX = [
+    req("logistic", [], [0.01], 10.0, 2, 1000, "fp64", k=6),
+    req("logistic", [], [0.01], 10.0, 3, 257, "fp64", k=6),
+    req("van_der_pol", [1.0], [2.0, 0.0], 6.3, 2, 100, "fp64", k=6),
+    req("rigid_body", [], [1.0, 0.0, 0.9], 20.0, 2, 150, "fp64", k=6),
+    req("logistic", [], [0.02], 8.0, 2, 64, "fp64", k=6),
+    req("logistic", [], [0.01], 10.0, 2, 513, "fp32", k=8),
+    req("van_der_pol", [1.0], [2.0, 0.0], 6.3, 2, 300, "fp32", k=6),
+    req("van_der_pol", [1.5], [1.0, 0.5], 5.0, 2, 77, "fp64", k=6),
+    req("logistic", [], [0.01], 10.0, 2, 1, "fp64", k=3),
+    req("logistic", [], [0.05], 10.0, 2, 9, "fp32", k=4),
+]
+
+
+def test_each_request_is_the_same_alone_and_in_the_mix(pp):
+    done, stats = serve_all(pp, MIX)
+    assert stats["admitted"] == len(MIX) and stats["completed"] == len(MIX) and stats["used_bytes"] == 0
+    for i, r in enumerate(MIX):
+        c = done[i]
+        a = alone(pp, r)
+        assert c["status"] == a["status"] == pp.OK, (i, c["status"], a["status"])
+        assert c["iterations"] == a["iterations"] == r["fixed_iters"]
+        assert c["final_delta"] == a["final_delta"]
+        assert same(c["mean"], a["mean"]), (i, relerr_e0(np_(c["mean"]), np_(a["mean"]), r["q"]))
+
+
+def test_served_fp64_matches_the_oracle(pp):
+    r = req("logistic", [], [0.01], 10.0, 2, 1000, "fp64", tol=1e-10)
+    ref = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 1000, max_iter=20, tol=1e-10)
+    done, _ = serve_all(pp, [r, MIX[2], MIX[5]])
+    c = done[0]
+    assert c["status"] == pp.OK and c["iterations"] == ref["iterations"]
+    assert relerr_e0(np_(c["mean"]), ref["mean"], 2) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonfinite_neighbour_does_not_leak(pp, prec):
+    """Lorenz on [0, 200] from the constant trajectory overflows in its first
+    iteration (its linearisation at y0 grows like exp(11.5 t)); rigid-body
+    requests of the same (precision, d, q) share its pack."""
+    q = 2
+    good = [req("rigid_body", [], [1.0, 0.0, 0.9], 20.0, q, 150, prec, k=5),
+            req("rigid_body", [], [0.5, 0.8, 0.2], 10.0, q, 333, prec, k=5)]
+    bad = req("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 200.0, q, 1000, prec, k=5)
+    mix = [good[0], bad, good[1]]
+    done, _ = serve_all(pp, mix)
+    assert done[1]["status"] == pp.ENONFINITE
+    assert not np.isfinite(np_(done[1]["mean"])).all()
+    for i in (0, 2):
+        a = alone(pp, mix[i])
+        assert done[i]["status"] == pp.OK
+        assert np.isfinite(np_(done[i]["mean"])).all()
+        assert same(done[i]["mean"], a["mean"])
+
+
+def test_admission_by_hbm_footprint(pp):
+    reqs = [req("logistic", [], [0.01 * (i + 1)], 10.0, 2, 4000, "fp32", k=4) for i in range(5)]
+    fp = pp.server_footprint("logistic", [], [0.01], 0.0, 10.0, 2, 4000, precision="fp32")
+    assert fp > 0
+    budget = 2 * fp + fp // 2  # room for two requests at a time
+    done, stats = serve_all(pp, reqs, budget=budget)
+    assert stats["peak_bytes"] <= budget and stats["peak_bytes"] == 2 * fp
+    ivals = sorted((c["t_start"], c["t_done"]) for c in done.values())
+    for s, _ in ivals:
+        live = sum(1 for s2, e2 in ivals if s2 <= s < e2)
+        assert live <= 2
+    # arrival order is kept
+    starts = [done[i]["t_start"] for i in range(len(reqs))]
+    assert starts == sorted(starts)
+
+
+def test_admission_by_slots(pp):
+    reqs = [req("logistic", [], [0.01], 10.0, 2, 200 + 50 * i, "fp64", k=3) for i in range(4)]
+    done, _ = serve_all(pp, reqs, max_slots=1)
+    order = sorted(done.values(), key=lambda c: c["t_start"])
+    for a, b in zip(order, order[1:]):
+        assert b["t_start"] >= a["t_done"]
+
+
+def test_request_larger_than_budget_is_refused(pp):
+    srv = pp.Server(max_slots=4, budget=1 << 16)
+    with pytest.raises(pp.ParapnError) as e:
+        srv.submit(0, "logistic", [], [0.01], 0.0, 10.0, 2, 100000, precision="fp32")
+    assert e.value.code == pp.ENOMEM
+    srv.close()
+
+
+def test_late_arrival_joins_and_finishes_first(pp):
+    """Continuous batching: a short request submitted while a long one is
+    iterating is admitted at the next step, shares its iterations, and
+    completes first; both results equal their solves alone."""
+    long_r = req("logistic", [], [0.01], 10.0, 2, 20000, "fp32", k=12)
+    short_r = req("logistic", [], [0.03], 10.0, 2, 300, "fp32", k=3)
+    srv = pp.Server(max_slots=8)
+    srv.submit(0, **long_r)
+    done = {}
+    for _ in range(2):
+        srv.step()
+        done.update({c["req_id"]: c for c in srv.poll()})
+    srv.submit(1, **short_r)
+    steps = 0
+    while len(done) < 2:
+        na, nq = srv.step()
+        if steps == 0:
+            assert na == 2 and nq == 0
+        done.update({c["req_id"]: c for c in srv.poll()})
+        steps += 1
+        assert steps < 100
+    srv.close()
+    assert done[1]["t_done"] < done[0]["t_done"]
+    assert done[1]["t_start"] < done[0]["t_done"]
+    for i, r in ((0, long_r), (1, short_r)):
+        assert same(done[i]["mean"], alone(pp, r)["mean"])
