@@ -4,11 +4,12 @@ One step = one complete solve (prior and initial state, then for every IEKS
 iteration: linearisation, filtering elements, forward scan, smoothing
 elements, reverse scan, convergence test; finally the output in original
 coordinates) of the FitzHugh-Nagumo workload: d = 2, IWP(3) (D = 8),
-N = 2^18 steps on t in [0, 100], constant initial trajectory (Alg. 2), 20
-iterations.  value = N * iterations / seconds (time-steps x iterations per
-second), whole job, FP32 square-root path; the FP64 path is reported beside
-it.  Inputs live in HBM before timing starts (the solve's only host inputs
-are the problem's few scalars).
+N = 2^18 steps on t in [0, 100], 20 iterations, started from a trajectory near
+the solution (a DOP853 solution, uploaded by the solve: from the constant
+start the Gauss-Newton iterate breaks down at its second linearisation on
+this problem, which is reported beside the figure).  value = N * iterations /
+seconds (time-steps x iterations per second), whole job, FP32 square-root
+path; the FP64 path is reported beside it, and so is Lorenz-63 at D = 15.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -59,11 +60,24 @@ def stored_traffic(kernel, workload_tag):
     return float(m_b.group(1))
 
 
-def run_gpu(pp, torch, wl, prec, steps, warmup, profile):
-    D = 2 * (wl["q"] + 1)
+def lorenz_workload(N, iters):
+    return dict(field="lorenz", params=[10.0, 28.0, 8.0 / 3.0], y0=[1.0, 1.0, 1.0], t0=0.0, t1=20.0, q=4, N=N,
+                iters=iters)
+
+
+def constant_start(pp, wl, prec):
+    """Outcome of the same solve from the constant initial trajectory."""
+    r = pp.solve(wl["field"], wl["params"], wl["y0"], wl["t0"], wl["t1"], wl["q"], wl["N"], precision=prec,
+                 fixed_iters=wl["iters"])
+    return {"status": r["status"], "iterations": r["iterations"], "final_delta": r["final_delta"],
+            "deltas_first": [float(x) for x in r["deltas"][:4]]}
+
+
+def run_gpu(pp, torch, wl, prec, steps, warmup, profile, d=2, init_traj=None):
+    D = d * (wl["q"] + 1)
     dt = torch.float32 if prec == "fp32" else torch.float64
     mean = torch.empty((wl["N"] + 1, D), dtype=dt, device="cuda")
-    kw = dict(precision=prec, fixed_iters=wl["iters"], out=(mean, None))
+    kw = dict(precision=prec, fixed_iters=wl["iters"], out=(mean, None), init_traj=init_traj)
     args = (wl["field"], wl["params"], wl["y0"], wl["t0"], wl["t1"], wl["q"], wl["N"])
     for _ in range(warmup):
         pp.solve(*args, **kw)
@@ -97,11 +111,12 @@ def run_gpu(pp, torch, wl, prec, steps, warmup, profile):
     }
 
 
-def roofline(prof, wl, prec, b1=8):
+def roofline(prof, wl, prec):
     from paper_2310_01145_amd import costmodel
 
     d, q, N = 2, wl["q"], wl["N"]
     esize = 4 if prec == "fp32" else 8
+    b1 = costmodel.forward_chunk(N)
     per = costmodel.per_step(d, q, esize, b1)
     # dominant kernel by total time
     name = max(prof, key=lambda k: prof[k][0])
@@ -124,6 +139,7 @@ def roofline(prof, wl, prec, b1=8):
         "unit": "TFLOP/s",
         "frac": achieved / peak,
         "traffic": stored_traffic(name, "fhn_n262144_%s" % prec),
+        "forward_chunk": b1,
         "algorithmic_flops_per_launch": flops * steps_per_launch,
         "algorithmic_bytes_per_launch": byts * steps_per_launch,
         "achieved_GBps_algorithmic": byts * steps_per_launch / avg_s / 1e9,
@@ -132,19 +148,32 @@ def roofline(prof, wl, prec, b1=8):
     return out
 
 
-def cpu_baseline(wl_full):
+def cpu_baseline(wl_full, start, k=10):
     """The CPU oracle (sequential FP64 square-root EKF/RTS IEKS, one thread)
-    on a bounded sample of the same workload."""
+    on a bounded sample of the same workload: the full N from the same start,
+    the first k of its iterations."""
     import oracle
 
-    N, k = 1 << 17, 8
+    N = wl_full["N"]
     t = time.perf_counter()
     r = oracle.ieks(wl_full["field"], wl_full["params"], wl_full["y0"], wl_full["t0"], wl_full["t1"], wl_full["q"],
-                    N, fixed_iters=k, want_cov=False)
+                    N, fixed_iters=k, want_cov=False, init_traj=start)
     el = time.perf_counter() - t
     return {"value": N * r["iterations"] / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": "same FitzHugh-Nagumo problem at N=2^17 (h doubled), %d fixed iterations from the constant "
-                      "start, FP64, single thread, %.1f s" % (r["iterations"], el)}
+            "sample": "the same FitzHugh-Nagumo solve (N=%d, same start) for its first %d iterations, FP64, single "
+                      "thread, %.1f s" % (N, r["iterations"], el)}
+
+
+def copy_probe(torch, mib):
+    """One plain device-to-device copy of mib MiB (read mib, write mib): the
+    reference that scales the HBM byte counters of a profiling run."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def main():
@@ -157,6 +186,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-lorenz", action="store_true", help="skip the Lorenz-63 (D=15) measurement")
+    ap.add_argument("--no-constant-start", action="store_true", help="skip the constant-start report")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the path is a single-GPU solver and no "
@@ -171,13 +204,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     pp.load_library()
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, args.copy_probe_mib)
+    from paper_2310_01145_amd import workloads
+
     wl = workload(args.N, args.iters)
     print("bench: workload FHN N=%d iters=%d" % (wl["N"], wl["iters"]), file=sys.stderr, flush=True)
-    r32 = run_gpu(pp, torch, wl, "fp32", args.steps, args.warmup, not args.no_profile)
+    start = workloads.reference_start(wl)
+    r32 = run_gpu(pp, torch, wl, "fp32", args.steps, args.warmup, not args.no_profile, init_traj=start)
     print("bench: fp32 done %.3f ms/solve" % r32["ms_per_step"], file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(pp, torch, wl, "fp64", args.steps, args.warmup, False)
+        r64 = run_gpu(pp, torch, wl, "fp64", args.steps, args.warmup, False, init_traj=start)
         print("bench: fp64 done %.3f ms/solve" % r64["ms_per_step"], file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
@@ -193,13 +231,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "FitzHugh-Nagumo a=b=0.2 c=3, y0=(-1,1), t in [0,100], IWP(3) D=8, N=%d, %d IEKS "
-                               "iterations per solve, constant initial trajectory" % (wl["N"], wl["iters"]),
-                   "N": wl["N"], "q": wl["q"], "d": 2, "iterations": wl["iters"], "precision": "fp32_sqrt"},
+                               "iterations per solve from a DOP853 trajectory" % (wl["N"], wl["iters"]),
+                   "N": wl["N"], "q": wl["q"], "d": 2, "iterations": wl["iters"], "precision": "fp32_sqrt",
+                   "initial_trajectory": "DOP853 (rtol 1e-12) E0 values, derivatives zero"},
         "latency_ms_p50": r32["latency_ms_p50"],
         "latency_ms_p99": r32["latency_ms_p99"],
         "iterations_per_solve": r32["iterations_per_solve"][0],
         "solve_status": r32["status"][0],
     }
+    if not args.no_constant_start:
+        line["constant_start"] = {"fp32": constant_start(pp, wl, "fp32")}
+        if not args.no_fp64:
+            line["constant_start"]["fp64"] = constant_start(pp, wl, "fp64")
     if r64 is not None:
         line["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                         "latency_ms_p50": r64["latency_ms_p50"], "latency_ms_p99": r64["latency_ms_p99"],
@@ -208,8 +251,27 @@ def main():
         line["roofline"] = roofline(r32["profile"], wl, "fp32")
         line["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in sorted(r32["profile"].items(),
                                                                                key=lambda kv: -kv[1][0])}
+    if not args.no_lorenz:
+        lw = lorenz_workload(args.N, args.iters)
+        cold = pp.solve(lw["field"], lw["params"], lw["y0"], lw["t0"], lw["t1"], lw["q"], lw["N"], precision="fp32",
+                        max_iter=3)
+        start = workloads.reference_start(lw)
+        l32 = run_gpu(pp, torch, lw, "fp32", args.steps, args.warmup, False, d=3, init_traj=start)
+        l64 = run_gpu(pp, torch, lw, "fp64", max(1, args.steps // 2), 1, False, d=3, init_traj=start)
+        print("bench: lorenz done %.3f / %.3f ms/solve" % (l32["ms_per_step"], l64["ms_per_step"]), file=sys.stderr,
+              flush=True)
+        line["lorenz"] = {
+            "workload": "Lorenz-63 s=10 r=28 b=8/3, y0=(1,1,1), t in [0,20], IWP(4) D=15, N=%d, %d IEKS iterations "
+                        "from a DOP853 trajectory (the constant start diverges)" % (lw["N"], lw["iters"]),
+            "value_fp32": l32["value"], "ms_per_step_fp32": l32["ms_per_step"],
+            "value_fp64": l64["value"], "ms_per_step_fp64": l64["ms_per_step"],
+            "status_fp32": l32["status"][0], "status_fp64": l64["status"][0],
+            "iterations_fp32": l32["iterations_per_solve"][0], "iterations_fp64": l64["iterations_per_solve"][0],
+            "constant_start_fp32": {"status": cold["status"], "iterations": cold["iterations"],
+                                    "final_delta": cold["final_delta"]},
+        }
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(wl)
+        cb = cpu_baseline(wl, start)
         cb["cores"] = 1
         line["cpu_baseline"] = cb
     print(json.dumps(line))

@@ -66,6 +66,16 @@ def smoother_apply(D, with_cov=False):
     return 2 * D * D + ((mm(D, D, D) + tria(D, 2 * D)) if with_cov else 0)
 
 
+def forward_chunk(N):
+    """Forward chunk length the library picks for a request of N steps (the
+    same rule as the host code: double from 4 while N / (2 b1) >= 8192, at
+    most 32)."""
+    b1 = 4
+    while b1 < 32 and N // (2 * b1) >= 8192:
+        b1 *= 2
+    return b1
+
+
 def per_step(d, q, esize, b1=32, bs1=8):
     """{kernel: (flops per step, bytes per step)} for a means-only iteration,
     with forward chunks of b1 steps and reverse chunks of bs1 steps.  The tree

@@ -28,7 +28,9 @@ PARAPN_DEV void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-PARAPN_DEV float psqrt(float x) { return __builtin_sqrtf(x); }
+// FP32: the hardware square root (1 ulp), without the rescaling a correctly
+// rounded sqrt adds for tiny arguments
+PARAPN_DEV float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 PARAPN_DEV double psqrt(double x) { return __builtin_sqrt(x); }
 
 // tria (Sec. 3.1.2): L lower-triangular with L L^T = M M^T, by Householder
@@ -38,6 +40,96 @@ PARAPN_DEV double psqrt(double x) { return __builtin_sqrt(x); }
 // that makes the diagonal non-negative (so L is the canonical factor), then
 // broadcast through `tr` (2*(NC+1) scalars, double-buffered).  On exit lane r
 // holds row r of L in v[0..NR-1]; columns >= NR are zero.
+// Value of x on lane K of the caller's group, for groups of R = 8 or 16
+// lanes: a group is one 16-lane DPP row, or half of one, so the broadcast is
+// a row_newbcast (lane K, or lane 8 + K for the upper half) with no LDS round
+// trip.  Every lane of the group must be active; with R = 8 the other half of
+// the row may be inactive (its value is never selected).
+template <int R, int K>
+PARAPN_DEV int gbcast_i(int x)
+{
+    static_assert(R == 8 || R == 16, "DPP broadcast needs groups of 8 or 16 lanes");
+    static_assert(K >= 0 && K < R, "lane out of the group");
+    if constexpr (R == 16) {
+        return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, false);
+    } else {
+        const int lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, x, 0x158 + K, 0xF, 0xF, false);
+        return (threadIdx.x & 8) ? hi : lo;
+    }
+}
+
+template <int R, int K>
+PARAPN_DEV float gbcast(float x)
+{
+    return __builtin_bit_cast(float, gbcast_i<R, K>(__builtin_bit_cast(int, x)));
+}
+
+template <int R, int K>
+PARAPN_DEV double gbcast(double x)
+{
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = gbcast_i<R, K>((int)(b & 0xffffffffLL));
+    const int hi = gbcast_i<R, K>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// reciprocals: the hardware's 1-ulp estimate in FP32, a division in FP64
+PARAPN_DEV float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+PARAPN_DEV double recip(double x) { return 1.0 / x; }
+PARAPN_DEV float two_over(float x) { return 2.0f * __builtin_amdgcn_rcpf(x); }
+PARAPN_DEV double two_over(double x) { return 2.0 / x; }
+
+// One reflection of tria_rows in registers only (groups of 8 or 16 lanes):
+// every lane forms the reflector quantities of its own row, the group takes
+// lane k's by DPP broadcast; sums use two partial accumulators to halve the
+// dependency chains.
+template <typename T, int NR, int NC, int R, int k>
+PARAPN_DEV void tria_dpp_step(T (&v)[NC], int lane)
+{
+    constexpr int K = NR < NC ? NR : NC;
+    if constexpr (k < K) {
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int c = k + 1; c < NC; ++c) {
+            if ((c - k) & 1)
+                s0 += v[c] * v[c];
+            else
+                s1 += v[c] * v[c];
+        }
+        const T sig = s0 + s1;
+        const T x0 = v[k];
+        const T nrm = psqrt(x0 * x0 + sig);
+        const T u0 = x0 <= T(0) ? x0 - nrm : -sig * recip(x0 + nrm);
+        const T uu = u0 * u0 + sig;
+        const T sc = uu > T(0) ? two_over(uu) : T(0);
+        const T sk = gbcast<R, k>(sc);
+        const T uk = gbcast<R, k>(u0);
+        T w[NC];
+#pragma unroll
+        for (int c = k + 1; c < NC; ++c) w[c] = gbcast<R, k>(v[c]);
+        T d0 = v[k] * uk, d1 = T(0);
+#pragma unroll
+        for (int c = k + 1; c < NC; ++c) {
+            if ((c - k) & 1)
+                d1 += v[c] * w[c];
+            else
+                d0 += v[c] * w[c];
+        }
+        const T dot = (d0 + d1) * sk;
+        const bool me = lane == k;
+        v[k] = me ? nrm : v[k] - dot * uk;
+#pragma unroll
+        for (int c = k + 1; c < NC; ++c) v[c] = me ? T(0) : v[c] - dot * w[c];
+        tria_dpp_step<T, NR, NC, R, k + 1>(v, lane);
+    }
+}
+
+// tria for groups of R lanes: registers and DPP for R = 8 or 16, else the
+// LDS version below
+template <typename T, int NR, int NC, int R>
+PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr);
+
 template <typename T, int NR, int NC>
 PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
 {
@@ -52,9 +144,9 @@ PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
             for (int c = k + 1; c < NC; ++c) sig += v[c] * v[c];
             const T x0 = v[k];
             nrm = psqrt(x0 * x0 + sig);
-            const T u0 = x0 <= T(0) ? x0 - nrm : -sig / (x0 + nrm);
+            const T u0 = x0 <= T(0) ? x0 - nrm : -sig * recip(x0 + nrm);
             const T uu = u0 * u0 + sig;
-            buf[0] = uu > T(0) ? T(2) / uu : T(0);
+            buf[0] = uu > T(0) ? two_over(uu) : T(0);
             buf[1 + k] = u0;
 #pragma unroll
             for (int c = k + 1; c < NC; ++c) buf[1 + c] = v[c];
@@ -76,16 +168,30 @@ PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
     wave_sync();
 }
 
+template <typename T, int NR, int NC, int R>
+PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr)
+{
+    if constexpr (R == 8 || R == 16) {
+        tria_dpp_step<T, NR, NC, R, 0>(v, lane);
+        wave_sync();  // callers' LDS traffic stays ordered around the call, as with the LDS version
+    } else {
+        tria_rows<T, NR, NC>(v, lane, tr);
+    }
+}
+
 // x (1 x n) such that x L = b, L lower-triangular n x n at L[i*ld + j]
 template <typename T, int n>
 PARAPN_DEV void solve_xL(T (&x)[n], const T (&b)[n], const T *L, int ld)
 {
+    T inv[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) inv[j] = recip(L[j * ld + j]);
 #pragma unroll
     for (int j = n - 1; j >= 0; --j) {
         T s = b[j];
 #pragma unroll
         for (int k = j + 1; k < n; ++k) s -= x[k] * L[k * ld + j];
-        x[j] = s / L[j * ld + j];
+        x[j] = s * inv[j];
     }
 }
 
@@ -93,12 +199,15 @@ PARAPN_DEV void solve_xL(T (&x)[n], const T (&b)[n], const T *L, int ld)
 template <typename T, int n>
 PARAPN_DEV void solve_xLt(T (&x)[n], const T (&b)[n], const T *L, int ld)
 {
+    T inv[n];
+#pragma unroll
+    for (int j = 0; j < n; ++j) inv[j] = recip(L[j * ld + j]);
 #pragma unroll
     for (int j = 0; j < n; ++j) {
         T s = b[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= x[k] * L[j * ld + k];
-        x[j] = s / L[j * ld + j];
+        x[j] = s * inv[j];
     }
 }
 

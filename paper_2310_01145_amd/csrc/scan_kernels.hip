@@ -236,8 +236,36 @@ PARAPN_DEV void store_packed(typename C::T *p, int r, const typename C::T (&v)[C
 // cancel exactly against Hbar eta).  u_n and r_n are formed in FP64 from the
 // FP64 trajectory and then rounded to the path's precision.  In memory mode
 // (ParaRTS on a given linear model) u = 0 and r = d.
+// The request fields the step kernels use, held in registers: the kernels
+// store through pointers the compiler cannot separate from the request table,
+// and fields read through it would be reloaded after every such store.
+struct ReqView {
+    const double *p;
+    double *traj;
+    unsigned long long *dbits;
+    double T0, T1, invT1, hq;
+    int64_t N, row;
+    int field;
+};
+
+PARAPN_DEV ReqView view_of(const ReqDev &q)
+{
+    ReqView v;
+    v.p = q.p;
+    v.traj = q.traj;
+    v.dbits = q.dbits;
+    v.T0 = q.T0;
+    v.T1 = q.T1;
+    v.invT1 = q.invT1;
+    v.hq = q.hq;
+    v.N = q.N;
+    v.row = q.row;
+    v.field = q.field;
+    return v;
+}
+
 template <class C>
-PARAPN_DEV void obs_setup(const Pack &pk, const ReqDev &o, int64_t n, int lane, typename C::T *sh,
+PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane, typename C::T *sh,
                           const typename C::T *cphi)
 {
     using T = typename C::T;
@@ -320,7 +348,7 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
 #pragma unroll
         for (int c = 0; c < D; ++c) w[c] = 0;
     }
-    tria_rows<T, d + D, D>(w, lane, sh + C::TR);
+    tria_rows_g<T, d + D, D, C::R>(w, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
     put_rows<T, d + D, D>(Psi, LDB, lane, w);
     wave_sync();
@@ -408,7 +436,7 @@ PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sC
 #pragma unroll
         for (int c = 0; c < NC; ++c) w[c] = 0;
     }
-    tria_rows<T, D2, NC>(w, lane, sh + C::TR);
+    tria_rows_g<T, D2, NC, C::R>(w, lane, sh + C::TR);
     T *Xi = sh + C::BIG;
     put_rows<T, D2, NC>(Xi, LDB, lane, w);
     wave_sync();
@@ -497,7 +525,7 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
 #pragma unroll
             for (int c = 0; c < D + NCJ; ++c) w[c] = 0;
         }
-        tria_rows<T, D, D + NCJ>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D + NCJ, C::R>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sC[c] = lane < D ? w[c] : T(0);
     }
@@ -522,7 +550,7 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
 #pragma unroll
             for (int c = 0; c < NJ + D; ++c) w[c] = 0;
         }
-        tria_rows<T, D, NJ + D>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, NJ + D, C::R>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sJ[c] = lane < D ? w[c] : T(0);
     }
@@ -582,7 +610,7 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
 #pragma unroll
         for (int c = 0; c < D2; ++c) w[c] = 0;
     }
-    tria_rows<T, D, D2>(w, lane, sh + C::TR);
+    tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
 #pragma unroll
     for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
     return o;
@@ -635,7 +663,7 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
 #pragma unroll
         for (int c = 0; c < D2; ++c) w[c] = 0;
     }
-    tria_rows<T, D2, D2>(w, lane, sh + C::TR);
+    tria_rows_g<T, D2, D2, C::R>(w, lane, sh + C::TR);
     T *Pi = sh + C::BIG;
     put_rows<T, D2, D2>(Pi, LDB, lane, w);
     if (lane < D) V1[lane] = mp;
@@ -671,7 +699,7 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
         for (int c = 0; c < D; ++c) x[c] = 0;
     }
     wave_sync();
-    tria_rows<T, d + D, D>(x, lane, sh + C::TR);
+    tria_rows_g<T, d + D, D, C::R>(x, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
     put_rows<T, d + D, D>(Psi, LDB, lane, x);
     wave_sync();
@@ -740,7 +768,7 @@ PARAPN_DEV ERow<C> smoother_combine(int lane, typename C::T *sh, const ERow<C> &
 #pragma unroll
             for (int c = 0; c < D2; ++c) w[c] = 0;
         }
-        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.L[c] = lane < D ? w[c] : T(0);
     }
@@ -783,7 +811,7 @@ PARAPN_DEV SRow<C> smoother_apply(int lane, typename C::T *sh, const ERow<C> &a,
 #pragma unroll
             for (int c = 0; c < D2; ++c) w[c] = 0;
         }
-        tria_rows<T, D, D2>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
     }
@@ -927,10 +955,12 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= a.pk.nf) return;
     const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
-    const ReqDev &q = a.pk.reqs[ri];
-    const int64_t lc = chunk - q.fchunk;
-    const int64_t s = 1 + lc * q.b1;
-    const int64_t e = s + q.b1 <= q.N + 1 ? s + q.b1 : q.N + 1;
+    const ReqView q = view_of(a.pk.reqs[ri]);
+    const int b1 = a.pk.reqs[ri].b1;
+    const int64_t lc = chunk - a.pk.reqs[ri].fchunk;
+    const int64_t fbase = a.pk.ftab[ri].base;
+    const int64_t s = 1 + lc * b1;
+    const int64_t e = s + b1 <= q.N + 1 ? s + b1 : q.N + 1;
     FRow<C> acc;
     zero(acc);
     for (int64_t n = s; n < e; ++n) {
@@ -949,7 +979,7 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
         else
             acc = filter_combine<C, C::d, C::D - C::d>(lane, sh, acc, el);
     }
-    store_frow<C>(agg + (a.pk.ftab[ri].base + lc) * C::FEF, lane, acc);
+    store_frow<C>(agg + (fbase + lc) * C::FEF, lane, acc);
 }
 
 // Upper levels of the forward scan as in-workgroup trees: one leaf
@@ -1065,10 +1095,11 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= a.pk.nf) return;
     const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
-    const ReqDev &q = a.pk.reqs[ri];
-    const int64_t lc = chunk - q.fchunk;
-    const int64_t s = 1 + lc * q.b1;
-    const int64_t e = s + q.b1 <= q.N + 1 ? s + q.b1 : q.N + 1;
+    const ReqView q = view_of(a.pk.reqs[ri]);
+    const int b1 = a.pk.reqs[ri].b1;
+    const int64_t lc = chunk - a.pk.reqs[ri].fchunk;
+    const int64_t s = 1 + lc * b1;
+    const int64_t e = s + b1 <= q.N + 1 ? s + b1 : q.N + 1;
     SRow<C> st = s == 1 ? init_state<C>(a.init, lane)
                         : load_state<C>(pref + (a.pk.ftab[ri].base + lc) * C::FS, lane);
     if (s == 1 && mf && lane < D) {
@@ -1170,8 +1201,8 @@ __global__ __launch_bounds__(C::NT) void k_bwd_reduce1(KArgs<C> a, const typenam
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
     if (chunk >= a.pk.ns) return;
     const int ri = find_req<false>(a.pk.reqs, a.pk.nreq, chunk);
-    const ReqDev &q = a.pk.reqs[ri];
-    const int64_t lc = chunk - q.schunk;
+    const ReqView q = view_of(a.pk.reqs[ri]);
+    const int64_t lc = chunk - a.pk.reqs[ri].schunk;
     const int64_t s = lc * C::B1;
     const int cnt = (int)(s + C::B1 <= q.N + 1 ? C::B1 : q.N + 1 - s);
     const int64_t row0 = q.row + s;
@@ -1271,19 +1302,19 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down(Pack pk, const typename C::T
 // FP64 trajectory (the next linearisation point) and accumulate, in double,
 //   delta = max |T0 E0 increment|  and  max |T0 E0 trajectory|
 // into the request's counters; otherwise write the smoothed means to mout
-// (packed rows).
+// (packed rows).  Returns the group's request and its two maxima (lanes
+// hold partial maxima).
 template <class C, bool WITH_L, bool UPDATE>
-__global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename C::T *se, const typename C::T *sL,
-                                                     const typename C::T *suf, typename C::T *mout,
-                                                     typename C::T *sPs)
+PARAPN_DEV int bwd_down1_group(const KArgs<C> &a, int64_t chunk, int lane, typename C::T *sh,
+                               const typename C::T *se, const typename C::T *sL, const typename C::T *suf,
+                               typename C::T *mout, typename C::T *sPs, double &dmax, double &mmax)
 {
-    PARAPN_GROUP_SETUP(C);
-    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= a.pk.ns) return;
+    using T = typename C::T;
     constexpr int D = C::D;
     const int ri = find_req<false>(a.pk.reqs, a.pk.nreq, chunk);
-    const ReqDev &q = a.pk.reqs[ri];
-    const int64_t lc = chunk - q.schunk;
+    const ReqView q = view_of(a.pk.reqs[ri]);
+    const int64_t lc = chunk - a.pk.reqs[ri].schunk;
+    const int64_t sbase = a.pk.stab[ri].base;
     const int64_t s = lc * C::B1;
     const int cnt = (int)(s + C::B1 <= q.N + 1 ? C::B1 : q.N + 1 - s);
     const int64_t row0 = q.row + s;
@@ -1300,8 +1331,7 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
 #pragma unroll
         for (int i = 0; i < C::B1; ++i) told[i] = (i < cnt && lane < D) ? q.traj[(s + i) * D + lane] : 0.0;
     }
-    SRow<C> st = load_state<C>(suf + (a.pk.stab[ri].base + lc) * C::SS, lane);
-    double dmax = 0.0, mmax = 0.0;
+    SRow<C> st = load_state<C>(suf + (sbase + lc) * C::SS, lane);
 #pragma unroll
     for (int i = C::B1 - 1; i >= 0; --i) {
         if (i >= cnt) continue;
@@ -1324,23 +1354,54 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
             if (WITH_L) store_packed<C>(sPs + (row0 + i) * C::DP, lane, st.P);
         }
     }
+    return ri;
+}
+
+PARAPN_DEV double nan_max(double x, double u) { return (u > x || u != u) ? u : x; }
+
+template <class C, bool WITH_L, bool UPDATE>
+__global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename C::T *se, const typename C::T *sL,
+                                                     const typename C::T *suf, typename C::T *mout,
+                                                     typename C::T *sPs)
+{
+    PARAPN_GROUP_SETUP(C);
+    const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
+    const bool valid = chunk < a.pk.ns;
+    double dmax = 0.0, mmax = 0.0;
+    int ri = -1;
+    if (valid) ri = bwd_down1_group<C, WITH_L, UPDATE>(a, chunk, lane, sh, se, sL, suf, mout, sPs, dmax, mmax);
     if (UPDATE) {
-        // group max through LDS, one atomic per group (non-negative doubles
-        // order like their bit patterns; NaN sorts above everything)
-        __shared__ double redbuf[C::GPB * 2 * C::R];
-        double *red = redbuf + grp * 2 * C::R;
-        red[lane] = dmax;
-        red[C::R + lane] = mmax;
-        wave_sync();
-        if (lane == 0) {
+        // Block-level maxima, then one atomic pair per request present in the
+        // block (a block's chunks are consecutive, so its requests form runs):
+        // a few thousand atomics per launch instead of two per group.
+        // Non-negative doubles order like their bit patterns; NaN sorts above
+        // everything.
+        __shared__ double red[C::NT * 2];
+        __shared__ int rq[C::GPB];
+        red[threadIdx.x] = dmax;
+        red[C::NT + threadIdx.x] = mmax;
+        if (lane == 0) rq[grp] = ri;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int cur = -1;
             double x = 0.0, y = 0.0;
-            for (int i = 0; i < C::R; ++i) {
-                const double u = red[i], v = red[C::R + i];
-                x = (u > x || u != u) ? u : x;
-                y = (v > y || v != v) ? v : y;
+            for (int g = 0; g <= C::GPB; ++g) {
+                const int r = g < C::GPB ? rq[g] : -1;
+                if (r != cur) {
+                    if (cur >= 0) {
+                        unsigned long long *db = a.pk.reqs[cur].dbits;
+                        atomicMax(db, (unsigned long long)__double_as_longlong(x));
+                        atomicMax(db + 1, (unsigned long long)__double_as_longlong(y));
+                    }
+                    cur = r;
+                    x = y = 0.0;
+                }
+                if (r < 0) continue;
+                for (int l = 0; l < C::R; ++l) {
+                    x = nan_max(x, red[g * C::R + l]);
+                    y = nan_max(y, red[C::NT + g * C::R + l]);
+                }
             }
-            atomicMax(q.dbits, (unsigned long long)__double_as_longlong(x));
-            atomicMax(q.dbits + 1, (unsigned long long)__double_as_longlong(y));
         }
     }
 }
@@ -1523,7 +1584,7 @@ __global__ __launch_bounds__(C::R) void k_tria_square(const typename C::T *full,
     T v[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) v[c] = lane < D ? full[lane * D + c] : T(0);
-    tria_rows<T, D, D>(v, lane, sh + C::TR);
+    tria_rows_g<T, D, D, C::R>(v, lane, sh + C::TR);
     if (lane < D)
 #pragma unroll
         for (int c = 0; c < D; ++c) out[lane * D + c] = v[c];
@@ -1783,6 +1844,7 @@ int pack_layout(int fp64, int d, int q, ReqDev *reqs, ScanTab *ftab, ScanTab *st
         sm += n1s;
         r += rq.N + 1;
     }
+    pk->nreq = nreq;
     pk->nf = f;
     pk->ns = sm;
     pk->rows = r;

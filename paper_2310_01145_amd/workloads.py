@@ -12,6 +12,9 @@ Problems:
   served_stream(n) -- mixed requests: logistic / FitzHugh-Nagumo / Lotka-Volterra
                   (alpha, beta, gamma, delta ~ U[0.5, 1.5], y0 ~ U[0.5, 2]^2),
                   q ~ U{2, 3, 4}, N log-uniform in [256, 65536].
+
+reference_start(spec) gives a starting trajectory near a problem's solution
+(a classical Runge-Kutta solution from scipy, an input like any other).
 """
 from __future__ import annotations
 
@@ -64,3 +67,90 @@ def random_observations(rng, N, d, q, scale=0.3):
     J = -np.eye(d)[None] + scale * rng.normal(size=(N, d, d))
     dv = rng.normal(size=(N, d))
     return J, dv
+
+
+# the vector fields as plain Python, for scipy's integrator only
+_FIELDS = {
+    "logistic": lambda p, y: [y[0] * (1.0 - y[0])],
+    "fhn": lambda p, y: [p[2] * (y[0] - y[0] ** 3 / 3.0 + y[1]), -(y[0] - p[0] + p[1] * y[1]) / p[2]],
+    "lorenz": lambda p, y: [p[0] * (y[1] - y[0]), y[0] * (p[1] - y[2]) - y[1], y[0] * y[1] - p[2] * y[2]],
+    "lotka_volterra": lambda p, y: [p[0] * y[0] - p[1] * y[0] * y[1], -p[2] * y[1] + p[3] * y[0] * y[1]],
+}
+
+
+class _Series:
+    """Truncated Taylor series in t, vectorised over grid points: c[k] is the
+    k-th coefficient (arrays).  Supports what the polynomial fields use."""
+
+    def __init__(self, c):
+        self.c = c
+
+    @staticmethod
+    def _lift(x, like):
+        if isinstance(x, _Series):
+            return x
+        c = [np.zeros_like(like.c[0]) for _ in like.c]
+        c[0] = c[0] + x
+        return _Series(c)
+
+    def __add__(self, o):
+        o = _Series._lift(o, self)
+        return _Series([a + b for a, b in zip(self.c, o.c)])
+
+    __radd__ = __add__
+
+    def __neg__(self):
+        return _Series([-a for a in self.c])
+
+    def __sub__(self, o):
+        return self + (-_Series._lift(o, self))
+
+    def __rsub__(self, o):
+        return _Series._lift(o, self) - self
+
+    def __mul__(self, o):
+        if not isinstance(o, _Series):
+            return _Series([a * o for a in self.c])
+        K = len(self.c)
+        return _Series([sum(self.c[j] * o.c[k - j] for j in range(k + 1)) for k in range(K)])
+
+    __rmul__ = __mul__
+
+    def __truediv__(self, x):
+        return _Series([a / x for a in self.c])
+
+    def __pow__(self, n):
+        out = self
+        for _ in range(n - 1):
+            out = out * self
+        return out
+
+
+def reference_start(spec):
+    """[N+1, d(q+1)] starting trajectory near the solution: the values from
+    scipy's DOP853 (rtol 1e-12) on the grid, and at every grid point the
+    derivatives 1..q of the solution through that value, from the Taylor
+    recursion of the (polynomial) vector field.  For problems whose
+    Gauss-Newton iteration from the constant start breaks down."""
+    from scipy.integrate import solve_ivp
+
+    f = _FIELDS[spec["field"]]
+    p = spec["params"]
+    q, N = spec["q"], spec["N"]
+    ts = np.linspace(spec["t0"], spec["t1"], N + 1)
+    sol = solve_ivp(lambda t, y: f(p, y), (spec["t0"], spec["t1"]), spec["y0"], method="DOP853", rtol=1e-12,
+                    atol=1e-12, t_eval=ts)
+    d = len(spec["y0"])
+    # Taylor coefficients y_k of y(t + s) at every grid point: y_{k+1} = [f(y)]_k / (k + 1)
+    ys = [_Series([sol.y[i].copy()] + [np.zeros(N + 1) for _ in range(q)]) for i in range(d)]
+    for k in range(q):
+        fy = f(p, ys)
+        for i in range(d):
+            ys[i].c[k + 1] = fy[i].c[k] / (k + 1)
+    tr = np.zeros((N + 1, d * (q + 1)))
+    fact = 1.0
+    for k in range(q + 1):
+        fact = fact * k if k > 0 else 1.0
+        for i in range(d):
+            tr[:, i * (q + 1) + k] = fact * ys[i].c[k]
+    return tr
