@@ -47,14 +47,15 @@ def kernel_source_sha():
 
 
 def stored_traffic(kernel, workload_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload_tag))
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "scan_kernels_%s_counters.md" % workload_tag)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_sha = re.search(r"kernel_source_sha:\s*(\w+)", txt)
-    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_b = re.search(r"traffic_bytes_per_launch %s:\s*([0-9.eE+]+)" % re.escape(kernel), txt)
     if not m_sha or not m_b or m_sha.group(1) != kernel_source_sha():
         return None
     return float(m_b.group(1))
@@ -63,6 +64,41 @@ def stored_traffic(kernel, workload_tag):
 def lorenz_workload(N, iters):
     return dict(field="lorenz", params=[10.0, 28.0, 8.0 / 3.0], y0=[1.0, 1.0, 1.0], t0=0.0, t1=20.0, q=4, N=N,
                 iters=iters)
+
+
+def logistic_latency(pp, torch, reps=100):
+    """C0: the logistic problem (N = 1000, q = 2, constant start) solved to
+    Delta < 1e-10 (at most 20 iterations), repeated; per-solve latency."""
+    out = {}
+    for prec in ("fp64", "fp32"):
+        lat, it = [], []
+        for i in range(reps + 3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            r = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 1000, precision=prec, tol=1e-10, max_iter=20)
+            torch.cuda.synchronize()
+            if i >= 3:
+                lat.append(time.perf_counter() - a)
+                it.append(r["iterations"])
+        out[prec] = {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                     "iterations": int(np.median(it)), "status": r["status"], "solves": reps}
+    return out
+
+
+def n_sweep(pp, torch, iters, steps=3):
+    """C1 throughput against N (FP32 and FP64), from the reference start."""
+    from paper_2310_01145_amd import workloads
+
+    out = []
+    for e in range(12, 19):
+        wl = workload(1 << e, iters)
+        start = torch.tensor(workloads.reference_start(wl), dtype=torch.float64, device="cuda")
+        row = {"N": 1 << e}
+        for prec in ("fp32", "fp64"):
+            r = run_gpu(pp, torch, wl, prec, steps, 1, False, init_traj=start)
+            row[prec] = {"value": r["value"], "ms_per_solve": r["ms_per_step"], "status": r["status"][0]}
+        out.append(row)
+    return out
 
 
 def constant_start(pp, wl, prec):
@@ -148,6 +184,27 @@ def roofline(prof, wl, prec):
     return out
 
 
+def scan_kernel_table(prof, wl, prec):
+    """Per step-level kernel: live average launch time, algorithmic GB/s and
+    TFLOP/s, and their fractions of the HBM and vector peaks."""
+    from paper_2310_01145_amd import costmodel
+
+    esize = 4 if prec == "fp32" else 8
+    per = costmodel.per_step(2, wl["q"], esize, costmodel.forward_chunk(wl["N"]))
+    peak = PEAK["f32" if esize == 4 else "f64"]
+    out = {}
+    for name, (flops, byts) in per.items():
+        if name not in prof:
+            continue
+        total_ms, launches = prof[name]
+        avg_s = total_ms * 1e-3 / launches
+        gbps = byts * wl["N"] / avg_s
+        out[name] = {"avg_launch_us": avg_s * 1e6, "GBps": gbps / 1e9, "hbm_frac": gbps / HBM_PEAK,
+                     "TFLOPs": flops * wl["N"] / avg_s / 1e12, "alu_frac": flops * wl["N"] / avg_s / peak,
+                     "traffic_bytes_measured": stored_traffic(name, "fhn_n%d_%s" % (wl["N"], prec))}
+    return out
+
+
 def cpu_baseline(wl_full, start, k=10):
     """The CPU oracle (sequential FP64 square-root EKF/RTS IEKS, one thread)
     on a bounded sample of the same workload: the full N from the same start,
@@ -157,7 +214,7 @@ def cpu_baseline(wl_full, start, k=10):
     N = wl_full["N"]
     t = time.perf_counter()
     r = oracle.ieks(wl_full["field"], wl_full["params"], wl_full["y0"], wl_full["t0"], wl_full["t1"], wl_full["q"],
-                    N, fixed_iters=k, want_cov=False, init_traj=start)
+                    N, fixed_iters=k, want_cov=False, init_traj=start.cpu().numpy())
     el = time.perf_counter() - t
     return {"value": N * r["iterations"] / el, "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": "the same FitzHugh-Nagumo solve (N=%d, same start) for its first %d iterations, FP64, single "
@@ -188,6 +245,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-lorenz", action="store_true", help="skip the Lorenz-63 (D=15) measurement")
     ap.add_argument("--no-constant-start", action="store_true", help="skip the constant-start report")
+    ap.add_argument("--no-extras", action="store_true", help="skip the logistic latency and the N sweep")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,7 +268,8 @@ def main():
 
     wl = workload(args.N, args.iters)
     print("bench: workload FHN N=%d iters=%d" % (wl["N"], wl["iters"]), file=sys.stderr, flush=True)
-    start = workloads.reference_start(wl)
+    # the starting trajectory is an input: resident in HBM before timing
+    start = torch.tensor(workloads.reference_start(wl), dtype=torch.float64, device="cuda")
     r32 = run_gpu(pp, torch, wl, "fp32", args.steps, args.warmup, not args.no_profile, init_traj=start)
     print("bench: fp32 done %.3f ms/solve" % r32["ms_per_step"], file=sys.stderr, flush=True)
     r64 = None
@@ -249,13 +308,14 @@ def main():
                         "iterations_per_solve": r64["iterations_per_solve"][0], "solve_status": r64["status"][0]}
     if r32["profile"]:
         line["roofline"] = roofline(r32["profile"], wl, "fp32")
+        line["scan_kernels"] = scan_kernel_table(r32["profile"], wl, "fp32")
         line["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in sorted(r32["profile"].items(),
                                                                                key=lambda kv: -kv[1][0])}
     if not args.no_lorenz:
         lw = lorenz_workload(args.N, args.iters)
         cold = pp.solve(lw["field"], lw["params"], lw["y0"], lw["t0"], lw["t1"], lw["q"], lw["N"], precision="fp32",
                         max_iter=3)
-        start = workloads.reference_start(lw)
+        start = torch.tensor(workloads.reference_start(lw), dtype=torch.float64, device="cuda")
         l32 = run_gpu(pp, torch, lw, "fp32", args.steps, args.warmup, False, d=3, init_traj=start)
         l64 = run_gpu(pp, torch, lw, "fp64", max(1, args.steps // 2), 1, False, d=3, init_traj=start)
         print("bench: lorenz done %.3f / %.3f ms/solve" % (l32["ms_per_step"], l64["ms_per_step"]), file=sys.stderr,
@@ -270,6 +330,10 @@ def main():
             "constant_start_fp32": {"status": cold["status"], "iterations": cold["iterations"],
                                     "final_delta": cold["final_delta"]},
         }
+    if not args.no_extras:
+        line["logistic_c0"] = logistic_latency(pp, torch)
+        line["fhn_n_sweep"] = n_sweep(pp, torch, args.iters)
+        print("bench: extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, start)
         cb["cores"] = 1

@@ -86,8 +86,11 @@ typedef struct {
     int32_t max_iter;      /* iteration cap, >= 1                                      */
     int32_t fixed_iters;   /* > 0: run exactly this many iterations, ignore tol        */
     int32_t precision;     /* PARAPN_FP64 or PARAPN_FP32_SQRT                          */
-    const double *init_traj; /* host [N+1][D] starting trajectory in original
-                              * coordinates, or NULL for the constant mu0 of Alg. 2  */
+    const double *init_traj; /* [N+1][D] starting trajectory in original coordinates
+                              * (row 0 is replaced by mu0), or NULL for the constant
+                              * mu0 of Alg. 2                                       */
+    int32_t init_on_device;  /* 0: init_traj is host memory; 1: device memory on the
+                              * context's device (read on the solve's stream)       */
 } parapn_problem;
 
 typedef struct {

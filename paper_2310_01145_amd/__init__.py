@@ -57,6 +57,7 @@ class Problem(ctypes.Structure):
         ("fixed_iters", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("init_traj", ctypes.POINTER(ctypes.c_double)),
+        ("init_on_device", ctypes.c_int32),
     ]
 
 
@@ -197,7 +198,17 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.fixed_iters = int(fixed_iters)
     pb.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     keep = [y0, prm]
-    if init_traj is not None:
+    pb.init_on_device = 0
+    if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
+        # a device tensor [N+1, D] of float64, read on the solve's stream
+        D = pb.d * (pb.q + 1)
+        if init_traj.dtype != _torch().float64 or tuple(init_traj.shape) != (pb.N + 1, D) \
+                or not init_traj.is_contiguous():
+            raise ValueError("device init_traj must be a contiguous float64 tensor of shape (N+1, D)")
+        pb.init_traj = ctypes.cast(ctypes.c_void_p(init_traj.data_ptr()), ctypes.POINTER(ctypes.c_double))
+        pb.init_on_device = 1
+        keep.append(init_traj)
+    elif init_traj is not None:
         it = np.ascontiguousarray(np.asarray(init_traj, dtype=np.float64))
         pb.init_traj = it.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         keep.append(it)

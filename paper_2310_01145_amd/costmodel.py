@@ -79,20 +79,22 @@ def forward_chunk(N):
 def per_step(d, q, esize, b1=32, bs1=8):
     """{kernel: (flops per step, bytes per step)} for a means-only iteration,
     with forward chunks of b1 steps and reverse chunks of bs1 steps.  The tree
-    kernels are charged per step as their per-aggregate work / b1."""
+    kernels are charged per step as their per-aggregate work / b1.  Bytes
+    count each FP64 trajectory row once per kernel (steps n-1 and n share
+    rows) and the stored records with their flag word."""
     D = d * (q + 1)
     DP = D * (D + 1) // 2
-    FE, FS, SE, SA = 3 * D * D + 2 * D, D + D * D, D * D + D, 2 * D * D + D
+    FEF, FS, SEF, SAF = 3 * D * D + 2 * D + 1, D + D * D, D * D + D + 1, 2 * D * D + D + 1
     s = esize
     return {
         "fwd_reduce1": (obs_setup(D, d) + filter_element(D, d) + filter_combine(D, d, D - d) * (b1 - 1) / b1,
-                        16 * D + s * FE / b1),
-        "fwd_tree_up": (filter_combine(D) / b1, s * 2 * FE / b1),
-        "fwd_tree_down": (state_apply(D) / b1, s * (FE + 2 * FS) / b1),
+                        8 * D + s * FEF / b1),
+        "fwd_tree_up": (filter_combine(D) / b1, s * 2 * FEF / b1),
+        "fwd_tree_down": (state_apply(D) / b1, s * (FEF + 2 * FS) / b1),
         "fwd_down1": (obs_setup(D, d) + kf_step_with_smoothing_element(D, d),
-                      16 * D + s * (FS / b1 + SE + DP)),
-        "bwd_reduce1": (smoother_combine(D) * (bs1 - 1) / bs1, s * (SE + SA / bs1)),
-        "bwd_down1": (smoother_apply(D), s * (SE + FS / bs1) + 16 * D),
+                      8 * D + s * (FS / b1 + SEF + DP)),
+        "bwd_reduce1": (smoother_combine(D) * (bs1 - 1) / bs1, s * (SEF + SAF / bs1)),
+        "bwd_down1": (smoother_apply(D), s * (SEF + FS / bs1) + 16 * D),
     }
 
 

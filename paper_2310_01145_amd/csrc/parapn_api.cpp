@@ -427,6 +427,7 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (p->max_iter < 1 && p->fixed_iters < 1) return fail(PARAPN_EINVAL, "max_iter must be >= 1");
     if (p->precision != PARAPN_FP64 && p->precision != PARAPN_FP32_SQRT)
         return fail(PARAPN_EINVAL, "unknown precision");
+    if (p->init_on_device != 0 && p->init_on_device != 1) return fail(PARAPN_EINVAL, "init_on_device must be 0 or 1");
     for (int i = 0; i < p->d; ++i)
         if (!std::isfinite(p->y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
     *q_out = p->q;
@@ -435,12 +436,13 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
 }
 
 // One IEKS iteration (linearise, both scans, trajectory update) for a pack
-// of solves sharing (precision, d, q).  trajs[i] are their resident FP64
-// trajectories.  Reads back each solve's delta and advances its state.
-// fixed: a plan the caller already sized the workspace for (else the pack is
-// planned here and the workspace grown to fit it).
-static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
-                          PackPlan *fixed = nullptr)
+// of solves sharing (precision, d, q), enqueued on s.  trajs[i] are their
+// resident FP64 trajectories.  The pack's delta counters are copied
+// (asynchronously) to ctx->host_bits[slot .. slot + 2 nreq), which the
+// caller has sized.  fixed: a plan the caller already sized the workspace
+// for (else the pack is planned here and the workspace grown to fit it).
+static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
+                        PackPlan *fixed, size_t slot)
 {
     const int nreq = (int)sv.size();
     const Solve &s0 = *sv[0];
@@ -458,8 +460,7 @@ static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector
         if (rc) return rc;
         pl = &local;
     }
-    rc = ensure_host_bits(ctx, 2 * (size_t)nreq);
-    if (rc) return rc;
+    if (slot + 2 * (size_t)nreq > ctx->host_bits_n) return fail(PARAPN_EINVAL, "internal: delta slots");
     char *ws = (char *)ctx->ws;
     bind_plan(*pl, ws);
     const PackLayout &L = pl->L;
@@ -485,15 +486,22 @@ static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector
     const parapn::Work w = work_from(ws, L, false);
     PARAPN_HIP(parapn::launch_forward(fp64, s0.d, s0.q, pk, m, w, s), "forward scan");
     PARAPN_HIP(parapn::launch_smoother(fp64, s0.d, s0.q, pk, m, w, false, true, nullptr, s), "reverse scan");
-    PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, dbits, 2 * nreq * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                              s),
+    PARAPN_HIP(hipMemcpyAsync(ctx->host_bits + slot, dbits, 2 * nreq * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s),
                "read delta");
-    PARAPN_HIP(hipStreamSynchronize(s), "sync");
-    for (int i = 0; i < nreq; ++i) {
+    return PARAPN_OK;
+}
+
+// Advance each solve's state from its iteration's counters (bits: 2 per
+// request, delta and max |E0 trajectory|, as doubles).
+static void pack_finish(std::vector<Solve *> &sv, const unsigned long long *bits)
+{
+    for (size_t i = 0; i < sv.size(); ++i) {
         Solve &v = *sv[i];
+        if (v.done) continue;
         double delta, mmax;
-        std::memcpy(&delta, ctx->host_bits + 2 * i, 8);
-        std::memcpy(&mmax, ctx->host_bits + 2 * i + 1, 8);
+        std::memcpy(&delta, bits + 2 * i, 8);
+        std::memcpy(&mmax, bits + 2 * i + 1, 8);
         v.iter += 1;
         v.delta = delta;
         v.deltas.push_back(delta);
@@ -518,13 +526,25 @@ static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector
             v.done = true;
         }
     }
+}
+
+// One iteration with its read-back: every solve's state is current after it.
+static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
+                          PackPlan *fixed = nullptr)
+{
+    int rc = ensure_host_bits(ctx, 2 * sv.size());
+    if (rc) return rc;
+    rc = pack_enqueue(ctx, sv, trajs, s, fixed, 0);
+    if (rc) return rc;
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    pack_finish(sv, ctx->host_bits);
     return PARAPN_OK;
 }
 
 // resident per-solve device buffer: trajectory [N+1][D], then T and mu0/T
 static size_t resident_bytes(const Solve &sv) { return align_up(((size_t)(sv.N + 1) * sv.D + 2 * sv.D) * 8); }
 
-static int init_resident(const Solve &sv, double *buf, const double *init_traj, hipStream_t s)
+static int init_resident(const Solve &sv, double *buf, const double *init_traj, bool on_device, hipStream_t s)
 {
     const int D = sv.D;
     double *traj = buf, *tail = buf + (size_t)(sv.N + 1) * D;
@@ -534,20 +554,18 @@ static int init_resident(const Solve &sv, double *buf, const double *init_traj, 
         Tmu[D + k] = sv.mu0b[k];
     }
     PARAPN_HIP(hipMemcpyAsync(tail, Tmu.data(), 2 * D * sizeof(double), hipMemcpyHostToDevice, s), "copy T");
-    if (init_traj) {
-        // the caller's trajectory, preconditioned; row 0 is always mu0 (only its
-        // E0 part enters the convergence test)
-        const size_t rows = (size_t)sv.N + 1;
-        std::vector<double> tr(rows * D);
-        for (int k = 0; k < D; ++k) tr[k] = sv.mu0b[k];
-        for (size_t n = 1; n < rows; ++n)
-            for (int k = 0; k < D; ++k) tr[n * D + k] = init_traj[n * D + k] / sv.Td[k];
-        PARAPN_HIP(hipMemcpyAsync(traj, tr.data(), tr.size() * 8, hipMemcpyHostToDevice, s), "copy traj");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");
-    } else {
-        PARAPN_HIP(parapn::launch_fill_traj(D, sv.N, tail + D, traj, s), "fill trajectory");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");  // Tmu is a local
+    const double *init = nullptr;
+    if (init_traj && on_device) {
+        init = init_traj;
+    } else if (init_traj) {
+        // the caller's host trajectory, preconditioned in place on the device
+        PARAPN_HIP(hipMemcpyAsync(traj, init_traj, (size_t)(sv.N + 1) * D * sizeof(double), hipMemcpyHostToDevice, s),
+                   "copy traj");
+        init = traj;
     }
+    // row 0 is always mu0 (only its E0 part enters the convergence test)
+    PARAPN_HIP(parapn::launch_init_traj(D, sv.N, init, tail, traj, s), "initial trajectory");
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");  // Tmu is a local
     return PARAPN_OK;
 }
 
@@ -632,11 +650,24 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     char *ws = (char *)ctx->ws;
     double *traj = (double *)(ws + L.extra);
     pl.reqs[0].traj = traj;
-    rc = init_resident(sv, traj, p->init_traj, s);
+    rc = init_resident(sv, traj, p->init_traj, p->init_on_device != 0, s);
     if (rc) return rc;
 
     std::vector<Solve *> one{&sv};
     std::vector<double *> trajs{traj};
+    if (sv.fixed_iters > 0) {
+        // the iteration count is known: queue every iteration, each copying
+        // its counters to its own slot, and read them all after one wait
+        // (iterations after a non-finite one change nothing that is returned)
+        rc = ensure_host_bits(ctx, 2 * (size_t)sv.fixed_iters);
+        if (rc) return rc;
+        for (int it = 0; it < sv.fixed_iters; ++it) {
+            rc = pack_enqueue(ctx, one, trajs, s, &pl, 2 * (size_t)it);
+            if (rc) return rc;
+        }
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        for (int it = 0; it < sv.fixed_iters && !sv.done; ++it) pack_finish(one, ctx->host_bits + 2 * it);
+    }
     while (!sv.done) {
         rc = pack_iteration(ctx, one, trajs, s, &pl);
         if (rc) return rc;
@@ -916,7 +947,7 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
             r->resident = nullptr;
             break;  // wait for memory to free up
         }
-        int rc = init_resident(r->sv, r->resident, nullptr, s);
+        int rc = init_resident(r->sv, r->resident, nullptr, false, s);
         if (rc) return rc;
         r->t_start = now_seconds();
         srv->used += r->bytes;

@@ -138,7 +138,8 @@ inline hipError_t launch_tria_square(int fp64, int d, int q, const void *full, v
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
                           const void *src_packed, void *mean_out, void *cov_out, hipStream_t s,
                           bool src_fp64 = false);
-hipError_t launch_fill_traj(int D, int64_t N, const double *row, double *traj, hipStream_t s);
+// traj [N+1][D] = preconditioned starting trajectory (k_init_traj)
+hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s);
 // index of an instantiated (d, q) configuration, or -1
 int config_supported(int d, int q);
 

@@ -84,30 +84,63 @@ PARAPN_DEV double two_over(double x) { return 2.0 / x; }
 // every lane forms the reflector quantities of its own row, the group takes
 // lane k's by DPP broadcast; sums use two partial accumulators to halve the
 // dependency chains.
-template <typename T, int NR, int NC, int R, int k>
+// Reflector of row x = v[k..NC-1] (every lane for its own row): returns the
+// new diagonal |x|, and u0, the scale 2/(u.u) and the tail a so that the
+// reflector is u = (u0, a[k+1..]).  SAFE (FP32 only): x is first divided by
+// max|x| (the reflection does not depend on the scale of u), so neither a
+// huge nor a tiny remaining tail over- or underflows its squares -- an
+// underflowed norm would leave a zero on the diagonal of the factor.
+template <typename T, int NC, bool SAFE>
+PARAPN_DEV T reflector(const T (&v)[NC], int k, T &u0, T &sc, T (&a)[NC])
+{
+    T m = T(1);
+    if constexpr (SAFE) {
+        static_assert(sizeof(T) == 4, "scaled reflectors are for FP32");
+        T m0 = __builtin_fabsf(v[k]), m1 = T(0);
+#pragma unroll
+        for (int c = k + 1; c < NC; ++c) {
+            if ((c - k) & 1)
+                m1 = __builtin_fmaxf(m1, __builtin_fabsf(v[c]));
+            else
+                m0 = __builtin_fmaxf(m0, __builtin_fabsf(v[c]));
+        }
+        m = __builtin_fmaxf(m0, m1);
+        const T scale = m > T(0) ? recip(m) : T(0);
+#pragma unroll
+        for (int c = k; c < NC; ++c) a[c] = v[c] * scale;
+    } else {
+#pragma unroll
+        for (int c = k; c < NC; ++c) a[c] = v[c];
+    }
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int c = k + 1; c < NC; ++c) {
+        if ((c - k) & 1)
+            s0 += a[c] * a[c];
+        else
+            s1 += a[c] * a[c];
+    }
+    const T sig = s0 + s1;
+    const T x0 = a[k];
+    const T nrm = psqrt(x0 * x0 + sig);
+    u0 = x0 <= T(0) ? x0 - nrm : -sig * recip(x0 + nrm);
+    const T uu = u0 * u0 + sig;
+    sc = uu > T(0) ? two_over(uu) : T(0);
+    return nrm * m;
+}
+
+template <typename T, int NR, int NC, int R, bool SAFE, int k>
 PARAPN_DEV void tria_dpp_step(T (&v)[NC], int lane)
 {
     constexpr int K = NR < NC ? NR : NC;
     if constexpr (k < K) {
-        T s0 = T(0), s1 = T(0);
-#pragma unroll
-        for (int c = k + 1; c < NC; ++c) {
-            if ((c - k) & 1)
-                s0 += v[c] * v[c];
-            else
-                s1 += v[c] * v[c];
-        }
-        const T sig = s0 + s1;
-        const T x0 = v[k];
-        const T nrm = psqrt(x0 * x0 + sig);
-        const T u0 = x0 <= T(0) ? x0 - nrm : -sig * recip(x0 + nrm);
-        const T uu = u0 * u0 + sig;
-        const T sc = uu > T(0) ? two_over(uu) : T(0);
+        T u0, sc, a[NC];
+        const T nrm = reflector<T, NC, SAFE>(v, k, u0, sc, a);
         const T sk = gbcast<R, k>(sc);
         const T uk = gbcast<R, k>(u0);
         T w[NC];
 #pragma unroll
-        for (int c = k + 1; c < NC; ++c) w[c] = gbcast<R, k>(v[c]);
+        for (int c = k + 1; c < NC; ++c) w[c] = gbcast<R, k>(a[c]);
         T d0 = v[k] * uk, d1 = T(0);
 #pragma unroll
         for (int c = k + 1; c < NC; ++c) {
@@ -121,16 +154,16 @@ PARAPN_DEV void tria_dpp_step(T (&v)[NC], int lane)
         v[k] = me ? nrm : v[k] - dot * uk;
 #pragma unroll
         for (int c = k + 1; c < NC; ++c) v[c] = me ? T(0) : v[c] - dot * w[c];
-        tria_dpp_step<T, NR, NC, R, k + 1>(v, lane);
+        tria_dpp_step<T, NR, NC, R, SAFE, k + 1>(v, lane);
     }
 }
 
 // tria for groups of R lanes: registers and DPP for R = 8 or 16, else the
 // LDS version below
-template <typename T, int NR, int NC, int R>
+template <typename T, int NR, int NC, int R, bool SAFE = false>
 PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr);
 
-template <typename T, int NR, int NC>
+template <typename T, int NR, int NC, bool SAFE = false>
 PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
 {
     constexpr int K = NR < NC ? NR : NC;
@@ -139,17 +172,12 @@ PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
         T *buf = tr + (k & 1) * (NC + 1);
         T nrm = T(0);
         if (lane == k) {
-            T sig = T(0);
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c) sig += v[c] * v[c];
-            const T x0 = v[k];
-            nrm = psqrt(x0 * x0 + sig);
-            const T u0 = x0 <= T(0) ? x0 - nrm : -sig * recip(x0 + nrm);
-            const T uu = u0 * u0 + sig;
-            buf[0] = uu > T(0) ? two_over(uu) : T(0);
+            T u0, sc, a[NC];
+            nrm = reflector<T, NC, SAFE>(v, k, u0, sc, a);
+            buf[0] = sc;
             buf[1 + k] = u0;
 #pragma unroll
-            for (int c = k + 1; c < NC; ++c) buf[1 + c] = v[c];
+            for (int c = k + 1; c < NC; ++c) buf[1 + c] = a[c];
         }
         wave_sync();
         const T s = buf[0];
@@ -168,14 +196,32 @@ PARAPN_DEV void tria_rows(T (&v)[NC], int lane, T *tr)
     wave_sync();
 }
 
-template <typename T, int NR, int NC, int R>
+// In FP32 every row is first scaled by a power of two (exactly) so that its
+// largest entry is below 1, and the result scaled back: tria(S M) = S tria(M)
+// for a positive diagonal S, and the reflections preserve each row's norm,
+// so squares of large entries stay in range.  SAFE additionally scales each
+// reflector (small remaining tails).  FP64 runs on the rows as they are.
+template <typename T, int NR, int NC, int R, bool SAFE>
 PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr)
 {
+    int e = 0;
+    if constexpr (sizeof(T) == 4 && !SAFE) {
+        T m = T(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) m = __builtin_fmaxf(m, __builtin_fabsf(v[c]));
+        e = m > T(0) ? __builtin_amdgcn_frexp_expf(m) : 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = __builtin_amdgcn_ldexpf(v[c], -e);
+    }
     if constexpr (R == 8 || R == 16) {
-        tria_dpp_step<T, NR, NC, R, 0>(v, lane);
+        tria_dpp_step<T, NR, NC, R, SAFE, 0>(v, lane);
         wave_sync();  // callers' LDS traffic stays ordered around the call, as with the LDS version
     } else {
-        tria_rows<T, NR, NC>(v, lane, tr);
+        tria_rows<T, NR, NC, SAFE>(v, lane, tr);
+    }
+    if constexpr (sizeof(T) == 4 && !SAFE) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = __builtin_amdgcn_ldexpf(v[c], e);
     }
 }
 

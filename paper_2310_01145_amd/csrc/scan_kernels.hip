@@ -90,6 +90,10 @@ struct Cfg {
     static constexpr int SE = D * D + D;          // smoothing element (E, g)
     static constexpr int SA = 2 * D * D + D;      // smoothing aggregate: E, g, sqrtL
     static constexpr int SS = D + D * D;          // smoother state: mean, factor
+    // FP32 with the IWP(4) prior: every Householder reflector is formed from
+    // its row scaled to unit max (the preconditioned quantities span a range
+    // whose squares leave FP32); other configurations scale whole rows once
+    static constexpr bool SAFE = sizeof(T_) == 4 && q_ >= 4;
     // stored records carry one trailing flag (request boundary)
     static constexpr int FEF = FE + 1, SEF = SE + 1, SAF = SA + 1;
     static_assert(R <= 64, "a group must fit in one wavefront");
@@ -348,7 +352,7 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
 #pragma unroll
         for (int c = 0; c < D; ++c) w[c] = 0;
     }
-    tria_rows_g<T, d + D, D, C::R>(w, lane, sh + C::TR);
+    tria_rows_g<T, d + D, D, C::R, C::SAFE>(w, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
     put_rows<T, d + D, D>(Psi, LDB, lane, w);
     wave_sync();
@@ -436,7 +440,7 @@ PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sC
 #pragma unroll
         for (int c = 0; c < NC; ++c) w[c] = 0;
     }
-    tria_rows_g<T, D2, NC, C::R>(w, lane, sh + C::TR);
+    tria_rows_g<T, D2, NC, C::R, C::SAFE>(w, lane, sh + C::TR);
     T *Xi = sh + C::BIG;
     put_rows<T, D2, NC>(Xi, LDB, lane, w);
     wave_sync();
@@ -525,7 +529,7 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
 #pragma unroll
             for (int c = 0; c < D + NCJ; ++c) w[c] = 0;
         }
-        tria_rows_g<T, D, D + NCJ, C::R>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D + NCJ, C::R, C::SAFE>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sC[c] = lane < D ? w[c] : T(0);
     }
@@ -550,7 +554,7 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
 #pragma unroll
             for (int c = 0; c < NJ + D; ++c) w[c] = 0;
         }
-        tria_rows_g<T, D, NJ + D, C::R>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, NJ + D, C::R, C::SAFE>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.sJ[c] = lane < D ? w[c] : T(0);
     }
@@ -610,7 +614,7 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
 #pragma unroll
         for (int c = 0; c < D2; ++c) w[c] = 0;
     }
-    tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
+    tria_rows_g<T, D, D2, C::R, C::SAFE>(w, lane, sh + C::TR);
 #pragma unroll
     for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
     return o;
@@ -663,7 +667,7 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
 #pragma unroll
         for (int c = 0; c < D2; ++c) w[c] = 0;
     }
-    tria_rows_g<T, D2, D2, C::R>(w, lane, sh + C::TR);
+    tria_rows_g<T, D2, D2, C::R, C::SAFE>(w, lane, sh + C::TR);
     T *Pi = sh + C::BIG;
     put_rows<T, D2, D2>(Pi, LDB, lane, w);
     if (lane < D) V1[lane] = mp;
@@ -699,7 +703,7 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
         for (int c = 0; c < D; ++c) x[c] = 0;
     }
     wave_sync();
-    tria_rows_g<T, d + D, D, C::R>(x, lane, sh + C::TR);
+    tria_rows_g<T, d + D, D, C::R, C::SAFE>(x, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
     put_rows<T, d + D, D>(Psi, LDB, lane, x);
     wave_sync();
@@ -768,7 +772,7 @@ PARAPN_DEV ERow<C> smoother_combine(int lane, typename C::T *sh, const ERow<C> &
 #pragma unroll
             for (int c = 0; c < D2; ++c) w[c] = 0;
         }
-        tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D2, C::R, C::SAFE>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.L[c] = lane < D ? w[c] : T(0);
     }
@@ -811,7 +815,7 @@ PARAPN_DEV SRow<C> smoother_apply(int lane, typename C::T *sh, const ERow<C> &a,
 #pragma unroll
             for (int c = 0; c < D2; ++c) w[c] = 0;
         }
-        tria_rows_g<T, D, D2, C::R>(w, lane, sh + C::TR);
+        tria_rows_g<T, D, D2, C::R, C::SAFE>(w, lane, sh + C::TR);
 #pragma unroll
         for (int c = 0; c < D; ++c) o.P[c] = lane < D ? w[c] : T(0);
     }
@@ -1566,12 +1570,16 @@ __global__ void k_unscale(int D, int64_t N, const double *Td, const TS *src, con
     }
 }
 
+// preconditioned starting trajectory: row 0 is mu0/T; rows n >= 1 are
+// init[n] / T (element-wise, may run in place), or mu0/T when init is null.
+// Td holds T followed by mu0/T.
 template <typename T>
-__global__ void k_fill_traj(int D, int64_t N, const T *row, T *traj)
+__global__ void k_init_traj(int D, int64_t N, const T *init, const T *Td, T *traj)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (N + 1) * D) return;
-    traj[i] = row[i % D];
+    const int k = (int)(i % D);
+    traj[i] = (i < D || !init) ? Td[D + k] : init[i] / Td[k];
 }
 
 // canonical lower-triangular factor of a D x D square root (one group)
@@ -1584,7 +1592,7 @@ __global__ __launch_bounds__(C::R) void k_tria_square(const typename C::T *full,
     T v[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) v[c] = lane < D ? full[lane * D + c] : T(0);
-    tria_rows_g<T, D, D, C::R>(v, lane, sh + C::TR);
+    tria_rows_g<T, D, D, C::R, C::SAFE>(v, lane, sh + C::TR);
     if (lane < D)
 #pragma unroll
         for (int c = 0; c < D; ++c) out[lane * D + c] = v[c];
@@ -1691,52 +1699,28 @@ struct ProfAcc {
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
 std::vector<ProfAcc> g_prof_acc;
-}  // namespace
+std::vector<hipEvent_t> g_prof_free;  // recorded-and-read events, reused
 
-bool prof_on() { return g_prof_on; }
-
-void prof_enable(bool on)
+hipEvent_t prof_event()
 {
-    g_prof_on = on;
-    for (auto &r : g_prof_pending) {
-        hipEventSynchronize(r.b);
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+    if (!g_prof_free.empty()) {
+        hipEvent_t e = g_prof_free.back();
+        g_prof_free.pop_back();
+        return e;
     }
-    g_prof_pending.clear();
-    g_prof_acc.clear();
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
 }
 
-void prof_begin(const char *name, hipStream_t s, hipEvent_t *start)
-{
-    (void)name;
-    if (hipEventCreate(start) != hipSuccess) {
-        *start = nullptr;
-        return;
-    }
-    hipEventRecord(*start, s);
-}
-
-void prof_end(const char *name, hipStream_t s, hipEvent_t start)
-{
-    if (!start) return;
-    hipEvent_t stop;
-    if (hipEventCreate(&stop) != hipSuccess) {
-        hipEventDestroy(start);
-        return;
-    }
-    hipEventRecord(stop, s);
-    g_prof_pending.push_back({name, start, stop});
-}
-
-int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *launches)
+void prof_resolve()
 {
     for (auto &r : g_prof_pending) {
         hipEventSynchronize(r.b);
         float ms = 0.f;
         hipEventElapsedTime(&ms, r.a, r.b);
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        g_prof_free.push_back(r.a);
+        g_prof_free.push_back(r.b);
         bool found = false;
         for (auto &a : g_prof_acc)
             if (a.name == r.name) {
@@ -1747,6 +1731,42 @@ int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *lau
         if (!found) g_prof_acc.push_back({r.name, (double)ms, 1});
     }
     g_prof_pending.clear();
+}
+}  // namespace
+
+bool prof_on() { return g_prof_on; }
+
+void prof_enable(bool on)
+{
+    g_prof_on = on;
+    prof_resolve();
+    g_prof_acc.clear();
+}
+
+void prof_begin(const char *name, hipStream_t s, hipEvent_t *start)
+{
+    (void)name;
+    *start = prof_event();
+    if (*start) hipEventRecord(*start, s);
+}
+
+void prof_end(const char *name, hipStream_t s, hipEvent_t start)
+{
+    if (!start) return;
+    hipEvent_t stop = prof_event();
+    if (!stop) {
+        g_prof_free.push_back(start);
+        return;
+    }
+    hipEventRecord(stop, s);
+    g_prof_pending.push_back({name, start, stop});
+    // bound the number of events in flight: resolve once many are pending
+    if (g_prof_pending.size() >= 4096) prof_resolve();
+}
+
+int prof_read(int max, char *names, int name_len, double *total_ms, int64_t *launches)
+{
+    prof_resolve();
     int k = 0;
     for (auto &a : g_prof_acc) {
         if (k >= max) break;
@@ -1872,10 +1892,10 @@ hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, c
     return hipGetLastError();
 }
 
-hipError_t launch_fill_traj(int D, int64_t N, const double *row, double *traj, hipStream_t s)
+hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s)
 {
     const unsigned blocks = (unsigned)cdiv((N + 1) * D, 256);
-    hipLaunchKernelGGL(k_fill_traj<double>, dim3(blocks), dim3(256), 0, s, D, N, row, traj);
+    hipLaunchKernelGGL(k_init_traj<double>, dim3(blocks), dim3(256), 0, s, D, N, init, Td, traj);
     return hipGetLastError();
 }
 #endif

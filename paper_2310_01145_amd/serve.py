@@ -108,7 +108,8 @@ def pct(x, p):
     return float(np.percentile(x, p)) if len(x) else None
 
 
-def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1e-10, max_iter=20):
+def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1e-10, max_iter=20,
+        saturate=True):
     import torch
 
     import paper_2310_01145_amd as pp
@@ -144,6 +145,15 @@ def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1
     lat_s, st_s, it_s, wait_s, span_s, steps, stats = run_served(pp, torch, reqs, arr, tol=tol, max_iter=max_iter,
                                                                  max_slots=max_slots, budget=budget,
                                                                  on_done=compare)
+    sat = None
+    if saturate:
+        # every request present at time 0: the server's own throughput
+        z = np.zeros(n_requests)
+        lat_z, st_z, it_z, _, span_z, steps_z, stats_z = run_served(pp, torch, reqs, z, tol=tol, max_iter=max_iter,
+                                                                    max_slots=max_slots, budget=budget)
+        sat = {"req_per_s": n_requests / span_z, "steps_x_iters_per_s": float((Ns * it_z).sum()) / span_z,
+               "makespan_s": span_z, "server_steps": steps_z, "peak_admitted_bytes": stats_z["peak_bytes"],
+               "p50_latency_s": pct(lat_z, 50), "p99_latency_s": pct(lat_z, 99)}
     both_ok = (st_s == pp.OK) & (st_p == pp.OK)
     work_p = float((Ns * it_p).sum())
     work_s = float((Ns * it_s).sum())
@@ -176,6 +186,7 @@ def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1
             "max_slots": max_slots, "budget_bytes": budget,
             "status": status_counts(st_s),
         },
+        "served_fp32_saturated": sat,
         "fp32_vs_fp64_e0_relerr": {
             "compared": int(np.isfinite(errs[both_ok]).sum()),
             "max": float(np.nanmax(errs[both_ok])) if both_ok.any() else None,

@@ -262,3 +262,20 @@ def test_nonfinite_is_reported(pp):
     assert r["status"] in (pp.ENONFINITE, pp.MAXITER)
     if r["status"] == pp.MAXITER:
         assert not r["converged"]
+
+
+def test_device_start_equals_host_start(pp):
+    """A starting trajectory already in device memory gives the same solve,
+    bit for bit, as the same trajectory passed from the host."""
+    import torch
+
+    spec = wl.fhn(N=2048)
+    tr = truth_trajectory(spec)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    for prec in ("fp64", "fp32"):
+        a = pp.solve(*args, precision=prec, fixed_iters=3, init_traj=tr)
+        b = pp.solve(*args, precision=prec, fixed_iters=3,
+                     init_traj=torch.tensor(tr, dtype=torch.float64, device="cuda"))
+        assert a["iterations"] == b["iterations"] == 3
+        assert np.array_equal(a["deltas"], b["deltas"])
+        assert torch.equal(a["mean"], b["mean"])
