@@ -158,6 +158,61 @@ PARAPN_DEV void tria_dpp_step(T (&v)[NC], int lane)
     }
 }
 
+// Two independent trias (NR rows each) in lock step: one reflection of each
+// per step, so the dependency chains of the two overlap.
+template <typename T, int NR, int NC1, int NC2, int R, bool SAFE, int k>
+PARAPN_DEV void tria2_dpp_step(T (&v1)[NC1], T (&v2)[NC2], int lane)
+{
+    constexpr int K1 = NR < NC1 ? NR : NC1, K2 = NR < NC2 ? NR : NC2;
+    constexpr int K = K1 > K2 ? K1 : K2;
+    if constexpr (k < K) {
+        const bool me = lane == k;
+        if constexpr (k < K1) {
+            T u0, sc, a[NC1];
+            const T nrm = reflector<T, NC1, SAFE>(v1, k, u0, sc, a);
+            const T sk = gbcast<R, k>(sc);
+            const T uk = gbcast<R, k>(u0);
+            T w[NC1];
+#pragma unroll
+            for (int c = k + 1; c < NC1; ++c) w[c] = gbcast<R, k>(a[c]);
+            T d0 = v1[k] * uk, d1 = T(0);
+#pragma unroll
+            for (int c = k + 1; c < NC1; ++c) {
+                if ((c - k) & 1)
+                    d1 += v1[c] * w[c];
+                else
+                    d0 += v1[c] * w[c];
+            }
+            const T dot = (d0 + d1) * sk;
+            v1[k] = me ? nrm : v1[k] - dot * uk;
+#pragma unroll
+            for (int c = k + 1; c < NC1; ++c) v1[c] = me ? T(0) : v1[c] - dot * w[c];
+        }
+        if constexpr (k < K2) {
+            T u0, sc, a[NC2];
+            const T nrm = reflector<T, NC2, SAFE>(v2, k, u0, sc, a);
+            const T sk = gbcast<R, k>(sc);
+            const T uk = gbcast<R, k>(u0);
+            T w[NC2];
+#pragma unroll
+            for (int c = k + 1; c < NC2; ++c) w[c] = gbcast<R, k>(a[c]);
+            T d0 = v2[k] * uk, d1 = T(0);
+#pragma unroll
+            for (int c = k + 1; c < NC2; ++c) {
+                if ((c - k) & 1)
+                    d1 += v2[c] * w[c];
+                else
+                    d0 += v2[c] * w[c];
+            }
+            const T dot = (d0 + d1) * sk;
+            v2[k] = me ? nrm : v2[k] - dot * uk;
+#pragma unroll
+            for (int c = k + 1; c < NC2; ++c) v2[c] = me ? T(0) : v2[c] - dot * w[c];
+        }
+        tria2_dpp_step<T, NR, NC1, NC2, R, SAFE, k + 1>(v1, v2, lane);
+    }
+}
+
 // tria for groups of R lanes: registers and DPP for R = 8 or 16, else the
 // LDS version below
 template <typename T, int NR, int NC, int R, bool SAFE = false>
@@ -222,6 +277,39 @@ PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr)
     if constexpr (sizeof(T) == 4 && !SAFE) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = __builtin_amdgcn_ldexpf(v[c], e);
+    }
+}
+
+// tria of two independent NR-row matrices (same layout rules as tria_rows_g)
+template <typename T, int NR, int NC1, int NC2, int R, bool SAFE = false>
+PARAPN_DEV void tria2_rows_g(T (&v1)[NC1], T (&v2)[NC2], int lane, T *tr)
+{
+    if constexpr (R == 8 || R == 16) {
+        int e1 = 0, e2 = 0;
+        if constexpr (sizeof(T) == 4 && !SAFE) {
+            T m1 = T(0), m2 = T(0);
+#pragma unroll
+            for (int c = 0; c < NC1; ++c) m1 = __builtin_fmaxf(m1, __builtin_fabsf(v1[c]));
+#pragma unroll
+            for (int c = 0; c < NC2; ++c) m2 = __builtin_fmaxf(m2, __builtin_fabsf(v2[c]));
+            e1 = m1 > T(0) ? __builtin_amdgcn_frexp_expf(m1) : 0;
+            e2 = m2 > T(0) ? __builtin_amdgcn_frexp_expf(m2) : 0;
+#pragma unroll
+            for (int c = 0; c < NC1; ++c) v1[c] = __builtin_amdgcn_ldexpf(v1[c], -e1);
+#pragma unroll
+            for (int c = 0; c < NC2; ++c) v2[c] = __builtin_amdgcn_ldexpf(v2[c], -e2);
+        }
+        tria2_dpp_step<T, NR, NC1, NC2, R, SAFE, 0>(v1, v2, lane);
+        wave_sync();
+        if constexpr (sizeof(T) == 4 && !SAFE) {
+#pragma unroll
+            for (int c = 0; c < NC1; ++c) v1[c] = __builtin_amdgcn_ldexpf(v1[c], e1);
+#pragma unroll
+            for (int c = 0; c < NC2; ++c) v2[c] = __builtin_amdgcn_ldexpf(v2[c], e2);
+        }
+    } else {
+        tria_rows_g<T, NR, NC1, R, SAFE>(v1, lane, tr);
+        tria_rows_g<T, NR, NC2, R, SAFE>(v2, lane, tr);
     }
 }
 

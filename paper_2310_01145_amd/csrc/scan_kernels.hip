@@ -515,9 +515,10 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
         V0[lane] = y;  // eta_j no longer needed
     }
     wave_sync();
-    // sqrtC_ij = tria([A_j G, sqrtC_j])
+    // sqrtC_ij = tria([A_j G, sqrtC_j]) and sqrtJ_ij = tria([A_i^T Xi22,
+    // sqrtJ_i]) (Xi22 has NJ columns), two independent trias run together
     {
-        T w[D + NCJ];
+        T w[D + NCJ], wj[NJ + D];
         if (lane < D) {
             T t[D];
             row_times<T, D, D>(t, ej.A, M4, LDM);
@@ -525,38 +526,29 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
             for (int c = 0; c < D; ++c) w[c] = t[c];
 #pragma unroll
             for (int c = 0; c < NCJ; ++c) w[D + c] = ej.sC[c];
+            T tj[NJ];
+            rowT_times<T, D, NJ>(tj, lane, M3, LDM, Xi + D * LDB + D, LDB);
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) wj[c] = tj[c];
+#pragma unroll
+            for (int c = 0; c < D; ++c) wj[NJ + c] = ei.sJ[c];
+            // eta_ij = A_i^T y + eta_i
+            T et = ei.eta;
+#pragma unroll
+            for (int k = 0; k < D; ++k) et += M3[k * LDM + lane] * V0[k];
+            o.eta = et;
         } else {
 #pragma unroll
             for (int c = 0; c < D + NCJ; ++c) w[c] = 0;
+#pragma unroll
+            for (int c = 0; c < NJ + D; ++c) wj[c] = 0;
         }
-        tria_rows_g<T, D, D + NCJ, C::R, C::SAFE>(w, lane, sh + C::TR);
+        tria2_rows_g<T, D, D + NCJ, NJ + D, C::R, C::SAFE>(w, wj, lane, sh + C::TR);
 #pragma unroll
-        for (int c = 0; c < D; ++c) o.sC[c] = lane < D ? w[c] : T(0);
-    }
-    // eta_ij = A_i^T y + eta_i
-    if (lane < D) {
-        T et = ei.eta;
-#pragma unroll
-        for (int k = 0; k < D; ++k) et += M3[k * LDM + lane] * V0[k];
-        o.eta = et;
-    }
-    // sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i]),  Xi22 has NJ columns
-    {
-        T w[NJ + D];
-        if (lane < D) {
-            T t[NJ];
-            rowT_times<T, D, NJ>(t, lane, M3, LDM, Xi + D * LDB + D, LDB);
-#pragma unroll
-            for (int c = 0; c < NJ; ++c) w[c] = t[c];
-#pragma unroll
-            for (int c = 0; c < D; ++c) w[NJ + c] = ei.sJ[c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < NJ + D; ++c) w[c] = 0;
+        for (int c = 0; c < D; ++c) {
+            o.sC[c] = lane < D ? w[c] : T(0);
+            o.sJ[c] = lane < D ? wj[c] : T(0);
         }
-        tria_rows_g<T, D, NJ + D, C::R, C::SAFE>(w, lane, sh + C::TR);
-#pragma unroll
-        for (int c = 0; c < D; ++c) o.sJ[c] = lane < D ? w[c] : T(0);
     }
     wave_sync();
     return o;
@@ -1380,11 +1372,20 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
         // a few thousand atomics per launch instead of two per group.
         // Non-negative doubles order like their bit patterns; NaN sorts above
         // everything.
-        __shared__ double red[C::NT * 2];
+        // group maxima first, across the group's lanes (XOR shuffles stay
+        // inside the group: R is a power of two within one wavefront)
+#pragma unroll
+        for (int off = C::R / 2; off >= 1; off >>= 1) {
+            dmax = nan_max(dmax, __shfl_xor(dmax, off));
+            mmax = nan_max(mmax, __shfl_xor(mmax, off));
+        }
+        __shared__ double red[C::GPB * 2];
         __shared__ int rq[C::GPB];
-        red[threadIdx.x] = dmax;
-        red[C::NT + threadIdx.x] = mmax;
-        if (lane == 0) rq[grp] = ri;
+        if (lane == 0) {
+            red[grp] = dmax;
+            red[C::GPB + grp] = mmax;
+            rq[grp] = ri;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int cur = -1;
@@ -1401,10 +1402,8 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down1(KArgs<C> a, const typename 
                     x = y = 0.0;
                 }
                 if (r < 0) continue;
-                for (int l = 0; l < C::R; ++l) {
-                    x = nan_max(x, red[g * C::R + l]);
-                    y = nan_max(y, red[C::NT + g * C::R + l]);
-                }
+                x = nan_max(x, red[g]);
+                y = nan_max(y, red[C::GPB + g]);
             }
         }
     }
