@@ -91,6 +91,15 @@ typedef struct {
                               * mu0 of Alg. 2                                       */
     int32_t init_on_device;  /* 0: init_traj is host memory; 1: device memory on the
                               * context's device (read on the solve's stream)       */
+    double lm_sigma;         /* >= 0.  > 0: Levenberg-Marquardt damping of each Gauss-
+                              * Newton step (the globalisation the paper leaves to
+                              * future work): every step n >= 1 gets the pseudo-
+                              * observation E0 Y_n = E0 (current iterate)_n with
+                              * standard deviation lm_sigma / sqrt(h) in the units of
+                              * y.  The fixed point is unchanged; the scans stay well
+                              * conditioned at unstable iterates.  Factors
+                              * (sqrtcov_out) then come from one more, undamped pass
+                              * at the final iterate.  0: plain Alg. 2.             */
 } parapn_problem;
 
 typedef struct {

@@ -76,6 +76,11 @@ def lib():
         L.orc_kf_rts.restype = i
         L.orc_ieks.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, P, P, P, ctypes.POINTER(ctypes.c_int)]
         L.orc_ieks.restype = i
+        L.orc_kf_rts_noise.argtypes = [i, i, l, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_kf_rts_noise.restype = i
+        L.orc_ieks_lm.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, P, P, P,
+                                  ctypes.POINTER(ctypes.c_int)]
+        L.orc_ieks_lm.restype = i
         L.orc_filter_element.argtypes = [i, i, P, P, P, P, P, P, i, P, P, P, P, P]
         L.orc_filter_combine.argtypes = [i] + [P] * 15
         L.orc_smoother_element.argtypes = [i, P, P, P, P, i, P, P, P]
@@ -157,24 +162,33 @@ def precond_model(d, q, h):
     return PhiB, sQB, T
 
 
-def kf_rts(mu0, S0, Phi, sqrtQ, H, dv):
-    """Sequential square-root KF + RTS.  H is [N, dobs, D], dv [N, dobs].
+def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None):
+    """Sequential square-root KF + RTS.  H is [N, dobs, D], dv [N, dobs];
+    rstd (dobs) optional per-row observation noise standard deviations.
     Returns (mf, sPf, ms, sPs), stacks over n = 0..N."""
     mu0, S0, Phi, sqrtQ, H, dv = map(_f64, (mu0, S0, Phi, sqrtQ, H, dv))
     N, dobs, D = H.shape
     mf, ms = np.zeros((N + 1, D)), np.zeros((N + 1, D))
     sPf, sPs = np.zeros((N + 1, D, D)), np.zeros((N + 1, D, D))
-    rc = lib().orc_kf_rts(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
-                          _p(ms), _p(sPs))
+    if rstd is None:
+        rc = lib().orc_kf_rts(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
+                              _p(ms), _p(sPs))
+    else:
+        rs = _f64(rstd).ravel()
+        assert rs.size == dobs
+        rc = lib().orc_kf_rts_noise(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(rs),
+                                    _p(mf), _p(sPf), _p(ms), _p(sPs))
     if rc != 0:
         raise FloatingPointError("non-finite values in the sequential smoother")
     return mf, sPf, ms, sPs
 
 
 def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
-         want_cov=True):
+         want_cov=True, lm_sigma=0.0):
     """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
-    sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas."""
+    sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas.
+    lm_sigma > 0: Levenberg-Marquardt damping, a pseudo-observation of each
+    step's E0 at the current iterate with std lm_sigma / sqrt(h)."""
     y0 = _f64(y0).ravel()
     params = _f64(params if len(params) else [0.0]).ravel()
     dd = y0.size if d is None else d
@@ -188,9 +202,9 @@ def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fix
     hist = np.zeros(max(max_iter, fixed_iters, 1))
     iters = ctypes.c_int(0)
     init = _f64(init_traj) if init_traj is not None else None
-    rc = lib().orc_ieks(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter, float(tol),
-                        fixed_iters, _p(init) if init is not None else None, _p(mean),
-                        _p(cov) if cov is not None else None, _p(hist), ctypes.byref(iters))
+    rc = lib().orc_ieks_lm(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
+                           float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
+                           _p(mean), _p(cov) if cov is not None else None, _p(hist), ctypes.byref(iters))
     if rc == -1:
         raise ValueError("bad problem")
     k = iters.value

@@ -461,9 +461,12 @@ static void precond_model(int d, int q, double h, double *PhiB, double *sQB, dou
  * H is [N][dobs][D], dv is [N][dobs].  Outputs are [N+1] stacks; row 0 holds
  * (mu0, S0) for the filter.  Smoothed marginals include n = 0 (conditioned on
  * all data).  Returns 0, or -4 when a non-finite value appears. */
-int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
-               const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf,
-               double *ms, double *sPs)
+/* Observation rows may carry independent noise: rstd[r] is the standard
+ * deviation of row r (NULL or 0: noiseless).  The update factor then comes
+ * from tria([[H sqrtP-, diag(rstd)], [sqrtP-, 0]]). */
+int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+                     const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
+                     double *sPf, double *ms, double *sPs)
 {
     int n2 = dobs + D;
     double *mp = dalloc(D), *sPp = dalloc(D * D), *M = dalloc((long)n2 * n2), *Psi = dalloc((long)n2 * n2);
@@ -488,8 +491,10 @@ int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, con
         /* update: Psi = tria([[H sqrtP-, 0], [sqrtP-, 0]]) */
         memset(M, 0, sizeof(double) * n2 * n2);
         mm(dobs, D, D, Hn, 0, sPp, 0, tmp);
-        for (int r = 0; r < dobs; ++r)
+        for (int r = 0; r < dobs; ++r) {
             for (int c = 0; c < D; ++c) M[r * n2 + c] = tmp[r * D + c];
+            M[r * n2 + D + r] = rstd ? rstd[r] : 0.0;
+        }
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) M[(dobs + r) * n2 + c] = sPp[r * D + c];
         orc_tria(n2, n2, M, Psi);
@@ -554,6 +559,13 @@ int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, con
     return bad ? -4 : 0;
 }
 
+int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+               const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf,
+               double *ms, double *sPs)
+{
+    return orc_kf_rts_noise(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs);
+}
+
 /* ------------------------------------------------------------------------ */
 /* IEKS (Alg. 2) with the sequential smoother                                */
 /* ------------------------------------------------------------------------ */
@@ -567,9 +579,15 @@ int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, con
  * or after max_iter iterations.  delta_hist[k-1] receives delta_k.
  * Returns 0 (converged or fixed count done), 1 (iteration cap), -1 (bad
  * arguments) or -4 (non-finite values). */
-int orc_ieks(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
-             int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
-             double *mean_out, double *sqrtcov_out, double *delta_hist, int *iters_out)
+/* Alg. 2, optionally damped: lm_sigma > 0 adds to every step n >= 1 the
+ * pseudo-observation E0 Y_n = E0 (current iterate)_n with standard deviation
+ * lm_sigma / sqrt(h) per coordinate in the units of y (Levenberg-Marquardt
+ * damping of the Gauss-Newton step, which the paper leaves as future work;
+ * the fixed point is unchanged).  When damped, the returned factors come
+ * from one more, undamped linearise-and-smooth pass at the final iterate. */
+int orc_ieks_lm(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+                int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+                double lm_sigma, double *mean_out, double *sqrtcov_out, double *delta_hist, int *iters_out)
 {
     int d = orc_field_dim(field, d_req, nparams);
     if (d < 1 || q < 1 || N < 1 || !(t1 > t0)) return -1;
@@ -583,24 +601,27 @@ int orc_ieks(int field, const double *params, int nparams, int d_req, const doub
     double *eta = dalloc((N + 1) * D);
     for (long n = 0; n <= N; ++n)
         for (int k = 0; k < D; ++k) eta[n * D + k] = init_traj ? init_traj[n * D + k] / T[k] : mu0b[k];
-    double *H = dalloc(N * d * D), *dv = dalloc(N * d);
+    const int lm = lm_sigma > 0.0;
+    const int dobs = lm ? 2 * d : d;
+    double *H = dalloc(N * dobs * D), *dv = dalloc(N * dobs), *rstd = dalloc(dobs);
     double *mf = dalloc((N + 1) * D), *sPf = dalloc((N + 1) * D * D);
     double *ms = dalloc((N + 1) * D), *sPs = dalloc((N + 1) * D * D);
     double *S0 = dalloc(D * D), *y = dalloc(d), *fy = dalloc(d), *Jy = dalloc(d * d);
     /* scales: E0 coordinate T[i*S+0], E1 coordinate T[i*S+1] (same for all i) */
     double T0 = T[0], T1 = T[1];
+    for (int r = 0; r < dobs; ++r) rstd[r] = r < d ? 0.0 : lm_sigma / (sqrt(h) * T0);
     int status = 0, k = 0;
     int limit = fixed_iters > 0 ? fixed_iters : max_iter;
     for (k = 1; k <= limit; ++k) {
         /* EK1 linearisation at every grid point (Sec. 3.2.1), then the
          * preconditioned observation  (H T) Ybar = d  with rows divided by T1:
          *   Hbar = E1 - (T0/T1) F_y E0,   dbar = (f - F_y y) / T1 */
-        memset(H, 0, sizeof(double) * N * d * D);
+        memset(H, 0, sizeof(double) * N * dobs * D);
         for (long n = 1; n <= N; ++n) {
             for (int i = 0; i < d; ++i) y[i] = T0 * eta[n * D + i * S];
             orc_field_f(field, params, d, y, fy);
             orc_field_jac(field, params, d, y, Jy);
-            double *Hn = H + (n - 1) * d * D, *dn = dv + (n - 1) * d;
+            double *Hn = H + (n - 1) * dobs * D, *dn = dv + (n - 1) * dobs;
             for (int i = 0; i < d; ++i) {
                 double s = fy[i];
                 for (int j = 0; j < d; ++j) s -= Jy[i * d + j] * y[j];
@@ -608,8 +629,12 @@ int orc_ieks(int field, const double *params, int nparams, int d_req, const doub
                 Hn[i * D + i * S + 1] += 1.0;
                 for (int j = 0; j < d; ++j) Hn[i * D + j * S] -= Jy[i * d + j] * T0 / T1;
             }
+            for (int i = 0; i < d && lm; ++i) { /* damping rows: E0 Y_n = E0 eta_n */
+                Hn[(d + i) * D + i * S] = 1.0;
+                dn[d + i] = eta[n * D + i * S];
+            }
         }
-        int rc = orc_kf_rts(D, d, N, mu0b, S0, PhiB, sQB, H, dv, mf, sPf, ms, sPs);
+        int rc = orc_kf_rts_noise(D, dobs, N, mu0b, S0, PhiB, sQB, H, dv, rstd, mf, sPf, ms, sPs);
         double delta = 0.0;
         for (long n = 0; n <= N; ++n)
             for (int i = 0; i < d; ++i) {
@@ -624,13 +649,35 @@ int orc_ieks(int field, const double *params, int nparams, int d_req, const doub
     }
     if (k > limit) k = limit;
     if (iters_out) *iters_out = k;
+    if (lm && sqrtcov_out && status != -4) {
+        /* factors of the undamped model linearised at the final iterate */
+        double *msk = dalloc((N + 1) * D);
+        memcpy(msk, ms, sizeof(double) * (N + 1) * D);
+        memset(H, 0, sizeof(double) * N * dobs * D);
+        for (long n = 1; n <= N; ++n) {
+            for (int i = 0; i < d; ++i) y[i] = T0 * eta[n * D + i * S];
+            orc_field_f(field, params, d, y, fy);
+            orc_field_jac(field, params, d, y, Jy);
+            double *Hn = H + (n - 1) * d * D, *dn = dv + (n - 1) * d;
+            for (int i = 0; i < d; ++i) {
+                double s = fy[i];
+                for (int j = 0; j < d; ++j) s -= Jy[i * d + j] * y[j];
+                dn[i] = s / T1;
+                Hn[i * D + i * S + 1] += 1.0;
+                for (int j = 0; j < d; ++j) Hn[i * D + j * S] -= Jy[i * d + j] * T0 / T1;
+            }
+        }
+        orc_kf_rts(D, d, N, mu0b, S0, PhiB, sQB, H, dv, mf, sPf, ms, sPs);
+        memcpy(ms, msk, sizeof(double) * (N + 1) * D);
+        free(msk);
+    }
     for (long n = 0; n <= N; ++n)
         for (int r = 0; r < D; ++r) {
             mean_out[n * D + r] = T[r] * ms[n * D + r];
             if (sqrtcov_out)
                 for (int c = 0; c < D; ++c) sqrtcov_out[(n * D + r) * D + c] = T[r] * sPs[(n * D + r) * D + c];
         }
-    free(PhiB); free(sQB); free(T); free(mu0); free(mu0b); free(eta); free(H); free(dv);
+    free(PhiB); free(sQB); free(T); free(mu0); free(mu0b); free(eta); free(H); free(dv); free(rstd);
     free(mf); free(sPf); free(ms); free(sPs); free(S0); free(y); free(fy); free(Jy);
     return status;
 }
@@ -833,4 +880,12 @@ void orc_smoother_combine(int D, const double *Ei, const double *gi, const doubl
     orc_tria(D, 2 * D, W, sL);
     free(t);
     free(W);
+}
+
+int orc_ieks(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+             int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+             double *mean_out, double *sqrtcov_out, double *delta_hist, int *iters_out)
+{
+    return orc_ieks_lm(field, params, nparams, d_req, y0, t0, t1, q, N, max_iter, tol, fixed_iters, init_traj, 0.0,
+                       mean_out, sqrtcov_out, delta_hist, iters_out);
 }

@@ -58,6 +58,7 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("init_traj", ctypes.POINTER(ctypes.c_double)),
         ("init_on_device", ctypes.c_int32),
+        ("lm_sigma", ctypes.c_double),
     ]
 
 
@@ -179,7 +180,7 @@ def _dtype(precision):
 
 
 def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                 init_traj=None, d=None):
+                 init_traj=None, d=None, lm_sigma=0.0):
     """Build the ctypes Problem (keeps the host arrays alive on the object)."""
     fid = FIELDS[field] if isinstance(field, str) else int(field)
     y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
@@ -197,6 +198,7 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.max_iter = int(max_iter)
     pb.fixed_iters = int(fixed_iters)
     pb.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    pb.lm_sigma = float(lm_sigma)
     keep = [y0, prm]
     pb.init_on_device = 0
     if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
@@ -225,15 +227,16 @@ def workspace_size(problem: Problem) -> int:
 
 
 def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-          init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None):
+          init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0):
     """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
     (original coordinates, torch tensor on the device), ``sqrtcov``
     [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
-    ``converged``, ``tol_used``."""
+    ``converged``, ``tol_used``.  ``lm_sigma`` > 0 damps each Gauss-Newton
+    step (Levenberg-Marquardt, see parapn_problem.lm_sigma)."""
     torch = _torch()
     L = load_library()
     pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                      fixed_iters=fixed_iters, init_traj=init_traj, d=d)
+                      fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma)
     D = pb.d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -331,10 +334,10 @@ class Server:
         self._pending = {}
 
     def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
-               fixed_iters=0, d=None):
+               fixed_iters=0, d=None, lm_sigma=0.0):
         torch = _torch()
         pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                          fixed_iters=fixed_iters, d=d)
+                          fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma)
         D = pb.d * (pb.q + 1)
         mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=torch.device("cuda", self._device))
         _check(self._L.parapn_server_submit(self._h, ctypes.byref(pb), int(req_id), _dptr(mean)))

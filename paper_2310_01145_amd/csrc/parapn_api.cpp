@@ -219,7 +219,7 @@ struct PackPlan {
 
 // reqs: N, field, scales and trajectory of each request
 int plan_pack(int fp64, int d, int q, const std::vector<parapn::ReqDev> &reqs, bool cov, size_t extra,
-              PackPlan &pl)
+              PackPlan &pl, bool lm = false)
 {
     const int nreq = (int)reqs.size();
     const int D = d * (q + 1), esz = fp64 ? 8 : 4;
@@ -229,6 +229,7 @@ int plan_pack(int fp64, int d, int q, const std::vector<parapn::ReqDev> &reqs, b
     pl.pk = parapn::Pack{};
     pl.pk.bu = 8;
     pl.pk.btop = 16;
+    pl.pk.lm = lm ? 1 : 0;
     if (parapn::pack_layout(fp64, d, q, pl.reqs.data(), pl.ftab.data(), pl.stab.data(), nreq, &pl.pk) != 0)
         return fail(PARAPN_EINVAL, "problem too long for the scan levels of this build");
     pl.L = pack_scratch_layout(D, esz, pl.pk, nreq, cov, extra);
@@ -256,6 +257,7 @@ struct Solve {
     int field, d, q, D, precision;
     int64_t N;
     double t0, t1, h, tol;
+    double lm_sigma, lm_s;  // damping (0: none) and its preconditioned per-step std
     int max_iter, fixed_iters;
     double params[PARAPN_MAX_PARAMS];
     std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
@@ -281,11 +283,13 @@ int prepare(const parapn_problem *p, Solve &sv)
     sv.tol = p->tol;
     sv.max_iter = p->max_iter;
     sv.fixed_iters = p->fixed_iters;
+    sv.lm_sigma = p->lm_sigma;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
     precond_diag(sv.d, sv.q, sv.h, sv.Td);
     sv.mu0.assign(sv.D, 0.0);
     if (!taylor_mu0(sv.field, sv.d, sv.params, p->y0, sv.q, sv.mu0.data()))
         return fail(PARAPN_EINVAL, "field not available for d");
+    sv.lm_s = sv.lm_sigma > 0.0 ? sv.lm_sigma / (std::sqrt(sv.h) * sv.Td[0]) : 0.0;
     sv.mu0b.resize(sv.D);
     for (int k = 0; k < sv.D; ++k) {
         if (!std::isfinite(sv.mu0[k])) return fail(PARAPN_EINVAL, "non-finite initial derivatives");
@@ -303,6 +307,7 @@ void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parap
     r.T1 = sv.Td[1];
     r.invT1 = 1.0 / sv.Td[1];
     r.hq = sv.h / sv.q;
+    r.lm_s = sv.lm_s;
     r.traj = traj;
     r.dbits = dbits;
     r.N = sv.N;
@@ -428,6 +433,7 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (p->precision != PARAPN_FP64 && p->precision != PARAPN_FP32_SQRT)
         return fail(PARAPN_EINVAL, "unknown precision");
     if (p->init_on_device != 0 && p->init_on_device != 1) return fail(PARAPN_EINVAL, "init_on_device must be 0 or 1");
+    if (!(p->lm_sigma >= 0.0) || !std::isfinite(p->lm_sigma)) return fail(PARAPN_EINVAL, "lm_sigma must be finite and >= 0");
     for (int i = 0; i < p->d; ++i)
         if (!std::isfinite(p->y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
     *q_out = p->q;
@@ -454,7 +460,7 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
     if (!pl) {
         std::vector<parapn::ReqDev> reqs(nreq);
         for (int i = 0; i < nreq; ++i) fill_reqdev(*sv[i], trajs[i], nullptr, reqs[i]);
-        rc = plan_pack(fp64, s0.d, s0.q, reqs, false, 0, local);
+        rc = plan_pack(fp64, s0.d, s0.q, reqs, false, 0, local, s0.lm_sigma > 0.0);
         if (rc) return rc;
         rc = ensure_ws(ctx, local.L.total);
         if (rc) return rc;
@@ -482,6 +488,7 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
     PARAPN_HIP(hipMemsetAsync(dbits, 0, 2 * nreq * sizeof(unsigned long long), s), "memset");
     parapn::Pack pk = pl->pk;
     pk.mode = 0;
+    pk.lm = s0.lm_sigma > 0.0 ? 1 : 0;
     const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
     const parapn::Work w = work_from(ws, L, false);
     PARAPN_HIP(parapn::launch_forward(fp64, s0.d, s0.q, pk, m, w, s), "forward scan");
@@ -642,7 +649,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     PackPlan pl;
     std::vector<parapn::ReqDev> r(1);
     fill_reqdev(sv, nullptr, nullptr, r[0]);
-    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv), pl);
+    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv), pl, sv.lm_sigma > 0.0);
     if (rc) return rc;
     const PackLayout &L = pl.L;
     rc = ensure_ws(ctx, L.total);
@@ -681,6 +688,12 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         parapn::Pack pk = pl.pk;
         const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
         const parapn::Work w = work_from(ws, L, true);
+        if (pk.lm && sv.status != PARAPN_ENONFINITE) {
+            // damped iterations: the factors come from an undamped
+            // linearise-and-filter pass at the final iterate
+            pk.lm = 0;
+            PARAPN_HIP(parapn::launch_forward(fp64, sv.d, sv.q, pk, m, w, s), "undamped forward scan");
+        }
         PARAPN_HIP(parapn::launch_smoother(fp64, sv.d, sv.q, pk, m, w, true, false, w.mf, s), "covariance pass");
         PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, w.sPs, mean_out, sqrtcov_out, s, true),
                    "unscale");
@@ -956,7 +969,7 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
         srv->queue.pop_front();
         srv->active.push_back(r);
     }
-    // one IEKS iteration for every active request, one pack per (precision, d, q)
+    // one IEKS iteration for every active request, one pack per (precision, d, q, damped or not)
     std::vector<int> order(srv->active.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::vector<bool> taken(order.size(), false);
@@ -967,7 +980,8 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
         std::vector<double *> trajs;
         for (size_t j = i; j < order.size(); ++j) {
             const Solve &o = srv->active[j]->sv;
-            if (!taken[j] && o.precision == k.precision && o.d == k.d && o.q == k.q) {
+            if (!taken[j] && o.precision == k.precision && o.d == k.d && o.q == k.q &&
+                (o.lm_sigma > 0.0) == (k.lm_sigma > 0.0)) {
                 taken[j] = true;
                 pack.push_back(&srv->active[j]->sv);
                 trajs.push_back(srv->active[j]->resident);

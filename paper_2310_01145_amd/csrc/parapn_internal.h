@@ -17,6 +17,7 @@ struct ReqDev {
     int pad_;
     double p[kMaxParams];
     double T0, T1, invT1, hq;   // scales of the E0 / E1 coordinates and h/q
+    double lm_s;                // damping: std of the E0 pseudo-observations (preconditioned), packs with lm only
     double *traj;               // FP64 preconditioned trajectory [N+1][D]; null for a given linear model
     unsigned long long *dbits;  // 2 entries: bit patterns of delta and max |E0 mu| (doubles)
     int64_t N;                  // steps of this request
@@ -60,6 +61,7 @@ struct Pack {
     int64_t sgroups[kMaxLevels + 1];  // groups of reverse launch l
     int64_t frecs, fprecs, srecs;     // records: forward aggregates (= prefix states), tree partials, reverse
     int mode;            // 0: linearise the vector field at the trajectories; 1: H, d given (one request)
+    int lm;              // 1: every request is damped (Levenberg-Marquardt rows, mode 0 only)
     const void *H;       // mode 1: [N][dobs][D]
     const void *dv;      // mode 1: [N][dobs]
 };

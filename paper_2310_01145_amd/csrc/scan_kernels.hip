@@ -40,10 +40,16 @@ constexpr int pow2floor(int x)
 // Configuration of one (precision, d, q).  Filter-side kernels give each
 // element 2D rows (R = next power of two >= 2D lanes); the smoother-side
 // kernels only need D rows and use RS lanes.
-template <typename T_, int d_, int q_, int RS_ = 0>
+template <typename T_, int d_, int q_, int RS_ = 0, bool LM_ = false>
 struct Cfg {
     using T = T_;
     static constexpr int d = d_, q = q_, S = q_ + 1, D = d_ * (q_ + 1);
+    // Levenberg-Marquardt damping: d more observation rows (E0 of the
+    // increment, observed as 0) with noise, carried in NZ extra columns of the
+    // update trias
+    static constexpr bool LM = LM_;
+    static constexpr int DO = LM_ ? 2 * d_ : d_;
+    static constexpr int NZ = LM_ ? d_ : 0;
     static constexpr int D2 = 2 * D;
     static constexpr int DP = D * (D + 1) / 2;
     static constexpr int B1 = 8;  // steps per group in the smoother's step-level kernels (prefetched)
@@ -67,10 +73,10 @@ struct Cfg {
     static constexpr int V3 = V2 + F1 * LDM;
     static constexpr int V4 = V3 + F1 * LDM;
     static constexpr int V5 = V4 + F1 * LDM;
-    static constexpr int HO = V5 + F1 * LDM;        // H   (d x LDM)
-    static constexpr int HPO = HO + F1 * d * LDM;   // H Phi (d x LDM)
-    static constexpr int DVO = HPO + F1 * d * LDM;  // residual r (d)
-    static constexpr int UO = DVO + F1 * (d + 1);   // prior offset u (D)
+    static constexpr int HO = V5 + F1 * LDM;         // H   (DO x LDM)
+    static constexpr int HPO = HO + F1 * DO * LDM;   // H Phi (DO x LDM)
+    static constexpr int DVO = HPO + F1 * DO * LDM;  // residual r (DO), then the damping std
+    static constexpr int UO = DVO + F1 * (DO + 1);   // prior offset u (D)
     static constexpr int SH = UO + F1 * LDM;
     // block: groups per block chosen so that a block's LDS stays <= 64 KiB
     static constexpr int FE_ = 3 * D * D + 2 * D;
@@ -93,7 +99,7 @@ struct Cfg {
     // FP32 with the IWP(4) prior: every Householder reflector is formed from
     // its row scaled to unit max (the preconditioned quantities span a range
     // whose squares leave FP32); other configurations scale whole rows once
-    static constexpr bool SAFE = sizeof(T_) == 4 && q_ >= 4;
+    static constexpr bool SAFE = sizeof(T_) == 4 && (q_ >= 4 || LM_);
     // stored records carry one trailing flag (request boundary)
     static constexpr int FEF = FE + 1, SEF = SE + 1, SAF = SA + 1;
     static_assert(R <= 64, "a group must fit in one wavefront");
@@ -247,7 +253,7 @@ struct ReqView {
     const double *p;
     double *traj;
     unsigned long long *dbits;
-    double T0, T1, invT1, hq;
+    double T0, T1, invT1, hq, lm_s;
     int64_t N, row;
     int field;
 };
@@ -262,6 +268,7 @@ PARAPN_DEV ReqView view_of(const ReqDev &q)
     v.T1 = q.T1;
     v.invT1 = q.invT1;
     v.hq = q.hq;
+    v.lm_s = q.lm_s;
     v.N = q.N;
     v.row = q.row;
     v.field = q.field;
@@ -297,6 +304,12 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
                 hrow[i * S + 1] += T(1);
                 rval = (T)((fd[i].v - o.T1 * tn[i * S + 1]) * o.invT1);
             }
+        if constexpr (C::LM) {
+            // damping rows: E0 of the increment is observed as 0
+#pragma unroll
+            for (int i = 0; i < d; ++i)
+                if (lane == d + i) hrow[i * S] = T(1);
+        }
         if (lane < D) {
             double u = -tn[lane];
 #pragma unroll
@@ -309,7 +322,7 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
         for (int c = 0; c < D; ++c) hrow[c] = hr[c];
         rval = ((const T *)pk.dv)[(n - 1) * d + lane];
     }
-    if (lane < d) {
+    if (lane < C::DO) {
         T hp[D];
         row_times<T, D, D>(hp, hrow, cphi, LDM);
 #pragma unroll
@@ -319,6 +332,7 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
         }
         sh[C::DVO + lane] = rval;
     }
+    if (C::LM && lane == 0) sh[C::DVO + C::DO] = (T)o.lm_s;
     if (lane < D) sh[C::UO + lane] = uval;
     wave_sync();
 }
@@ -338,23 +352,31 @@ template <class C>
 PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C::T *cphi, const typename C::T *csq)
 {
     using T = typename C::T;
-    constexpr int d = C::d, D = C::D, LDM = C::LDM, LDB = C::LDB;
-    T w[D];
-    if (lane < d) {
-        T hrow[D];
+    constexpr int d = C::d, D = C::D, DO = C::DO, NZ = C::NZ, LDM = C::LDM, LDB = C::LDB;
+    // tria([[H sqrtQ, sqrtR], [sqrtQ, 0]]); sqrtR = 0 except the damping rows
+    T w[D + NZ];
+#pragma unroll
+    for (int c = 0; c < D + NZ; ++c) w[c] = 0;
+    if (lane < DO) {
+        T hrow[D], t[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) hrow[c] = sh[C::HO + lane * LDM + c];
-        row_times<T, D, D>(w, hrow, csq, LDM);
-    } else if (lane < d + D) {
+        row_times<T, D, D>(t, hrow, csq, LDM);
 #pragma unroll
-        for (int c = 0; c < D; ++c) w[c] = csq[(lane - d) * LDM + c];
-    } else {
+        for (int c = 0; c < D; ++c) w[c] = t[c];
+        if constexpr (NZ > 0) {
+            const T sn = sh[C::DVO + DO];
 #pragma unroll
-        for (int c = 0; c < D; ++c) w[c] = 0;
+            for (int i = 0; i < NZ; ++i)
+                if (lane == d + i) w[D + i] = sn;
+        }
+    } else if (lane < DO + D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) w[c] = csq[(lane - DO) * LDM + c];
     }
-    tria_rows_g<T, d + D, D, C::R, C::SAFE>(w, lane, sh + C::TR);
+    tria_rows_g<T, DO + D, D + NZ, C::R, C::SAFE>(w, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
-    put_rows<T, d + D, D>(Psi, LDB, lane, w);
+    put_rows<T, DO + D, D + NZ>(Psi, LDB, lane, w);
     wave_sync();
     FRow<C> e;
     zero(e);
@@ -362,34 +384,34 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
         const T *HP = sh + C::HPO;
         const T *dv = sh + C::DVO;
         const T *um = sh + C::UO;
-        T p21[d], K[d], hpc[d], x[d], dvv[d], u[d];
+        T p21[DO], K[DO], hpc[DO], x[DO], dvv[DO], u[DO];
 #pragma unroll
-        for (int i = 0; i < d; ++i) {
-            p21[i] = Psi[(d + lane) * LDB + i];
+        for (int i = 0; i < DO; ++i) {
+            p21[i] = Psi[(DO + lane) * LDB + i];
             hpc[i] = HP[i * LDM + lane];
             T hu = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) hu += sh[C::HO + i * LDM + k] * um[k];
             dvv[i] = dv[i] - hu;  // r - H m-
         }
-        solve_xL<T, d>(K, p21, Psi, LDB);
+        solve_xL<T, DO>(K, p21, Psi, LDB);
         T b = um[lane];
 #pragma unroll
-        for (int i = 0; i < d; ++i) b += K[i] * dvv[i];
+        for (int i = 0; i < DO; ++i) b += K[i] * dvv[i];
         e.b = b;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             T a = cphi[lane * LDM + c];
 #pragma unroll
-            for (int i = 0; i < d; ++i) a -= K[i] * HP[i * LDM + c];
+            for (int i = 0; i < DO; ++i) a -= K[i] * HP[i * LDM + c];
             e.A[c] = a;
-            e.sC[c] = (c < D - d) ? Psi[(d + lane) * LDB + d + c] : T(0);
+            e.sC[c] = (c < D - d) ? Psi[(DO + lane) * LDB + DO + c] : T(0);
         }
-        solve_xLt<T, d>(x, hpc, Psi, LDB);
-        solve_xLt<T, d>(u, dvv, Psi, LDB);
+        solve_xLt<T, DO>(x, hpc, Psi, LDB);
+        solve_xLt<T, DO>(u, dvv, Psi, LDB);
         T et = 0;
 #pragma unroll
-        for (int i = 0; i < d; ++i) {
+        for (int i = 0; i < DO; ++i) {
             e.sJ[i] = x[i];
             et += x[i] * u[i];
         }
@@ -680,46 +702,55 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
         for (int c = 0; c < D; ++c) g -= eo.E[c] * V1[c];
         eo.g = g;
     }
-    // update with the predicted factor Pi11 (rows 0..D-1 of Pi)
-    T x[D];
-    if (lane < d) {
-        T hrow[D];
+    // update with the predicted factor Pi11 (rows 0..D-1 of Pi):
+    // tria([[H Pi11, sqrtR], [Pi11, 0]])
+    constexpr int DO = C::DO, NZ = C::NZ;
+    T x[D + NZ];
+#pragma unroll
+    for (int c = 0; c < D + NZ; ++c) x[c] = 0;
+    if (lane < DO) {
+        T hrow[D], t[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) hrow[c] = sh[C::HO + lane * LDM + c];
-        row_times<T, D, D>(x, hrow, Pi, LDB);
-    } else if (lane < d + D) {
+        row_times<T, D, D>(t, hrow, Pi, LDB);
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = Pi[(lane - d) * LDB + c];
-    } else {
+        for (int c = 0; c < D; ++c) x[c] = t[c];
+        if constexpr (NZ > 0) {
+            const T sn = sh[C::DVO + DO];
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = 0;
+            for (int i = 0; i < NZ; ++i)
+                if (lane == d + i) x[D + i] = sn;
+        }
+    } else if (lane < DO + D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = Pi[(lane - DO) * LDB + c];
     }
     wave_sync();
-    tria_rows_g<T, d + D, D, C::R, C::SAFE>(x, lane, sh + C::TR);
+    tria_rows_g<T, DO + D, D + NZ, C::R, C::SAFE>(x, lane, sh + C::TR);
     T *Psi = sh + C::BIG;
-    put_rows<T, d + D, D>(Psi, LDB, lane, x);
+    put_rows<T, DO + D, D + NZ>(Psi, LDB, lane, x);
     wave_sync();
     SRow<C> o;
     o.m = 0;
 #pragma unroll
     for (int c = 0; c < D; ++c) o.P[c] = 0;
     if (lane < D) {
-        T res[d], p21[d], K[d];
+        T res[DO], p21[DO], K[DO];
 #pragma unroll
-        for (int i = 0; i < d; ++i) {
+        for (int i = 0; i < DO; ++i) {
             T r = sh[C::DVO + i];
 #pragma unroll
             for (int k = 0; k < D; ++k) r -= sh[C::HO + i * LDM + k] * V1[k];
             res[i] = r;
-            p21[i] = Psi[(d + lane) * LDB + i];
+            p21[i] = Psi[(DO + lane) * LDB + i];
         }
-        solve_xL<T, d>(K, p21, Psi, LDB);
+        solve_xL<T, DO>(K, p21, Psi, LDB);
         T m = mp;
 #pragma unroll
-        for (int i = 0; i < d; ++i) m += K[i] * res[i];
+        for (int i = 0; i < DO; ++i) m += K[i] * res[i];
         o.m = m;
 #pragma unroll
-        for (int c = 0; c < D - d; ++c) o.P[c] = Psi[(d + lane) * LDB + d + c];
+        for (int c = 0; c < D - d; ++c) o.P[c] = Psi[(DO + lane) * LDB + DO + c];
     }
     wave_sync();
     return o;
@@ -973,7 +1004,7 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
         if (n == s)
             acc = el;
         else
-            acc = filter_combine<C, C::d, C::D - C::d>(lane, sh, acc, el);
+            acc = filter_combine<C, C::DO, C::D - C::d>(lane, sh, acc, el);
     }
     store_frow<C>(agg + (fbase + lc) * C::FEF, lane, acc);
 }
@@ -1496,22 +1527,26 @@ template <class C>
 static hipError_t fwd_seq(const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
 {
     using T = typename C::T;
+    // the upper levels do not depend on damping (same records, same tree width)
+    using CT = Cfg<T, C::d, C::q>;
     if (pk.nf < 1 || pk.nreq < 1 || pk.Lf < 1 || pk.Lf > kMaxLevels) return hipErrorInvalidValue;
+    if (C::LM && pk.mode != 0) return hipErrorInvalidValue;
     KArgs<C> a = make_args<C>(pk, m);
     T *agg = (T *)w.fagg, *part = (T *)w.fpart, *pref = (T *)w.fpref;
     auto blocks = [](int64_t groups) { return (unsigned)cdiv(groups, C::GPB); };
     PARAPN_LAUNCH("fwd_reduce1", s, k_fwd_reduce1<C>, dim3(blocks(pk.nf)), dim3(C::NT), 0, s, a, agg);
     for (int l = 1; l < pk.Lf; ++l)
         if (pk.fblocks[l] > 0)
-            PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)pk.fblocks[l]), dim3(C::NT), 0, s, pk,
+            PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<CT>, dim3((unsigned)pk.fblocks[l]), dim3(CT::NT), 0, s, pk,
                           agg, part, l);
     // top trees, one block per request, from the initial state
-    PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<C>, dim3((unsigned)pk.nreq), dim3(C::NT), 0, s, pk, agg, part, 0);
-    PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)pk.nreq), dim3(C::NT), 0, s, pk,
+    PARAPN_LAUNCH("fwd_tree_up", s, k_fwd_tree_up<CT>, dim3((unsigned)pk.nreq), dim3(CT::NT), 0, s, pk, agg, part,
+                  0);
+    PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<CT>, dim3((unsigned)pk.nreq), dim3(CT::NT), 0, s, pk,
                   (const T *)part, pref, (const T *)m.init, 0);
     for (int l = pk.Lf - 1; l >= 1; --l)
         if (pk.fblocks[l] > 0)
-            PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<C>, dim3((unsigned)pk.fblocks[l]), dim3(C::NT), 0, s,
+            PARAPN_LAUNCH("fwd_tree_down", s, k_fwd_tree_down<CT>, dim3((unsigned)pk.fblocks[l]), dim3(CT::NT), 0, s,
                           pk, (const T *)part, pref, (const T *)m.init, l);
     PARAPN_LAUNCH("fwd_down1", s, k_fwd_down1<C>, dim3(blocks(pk.nf)), dim3(C::NT), 0, s, a, (const T *)pref,
                   (T *)w.se, (T *)w.sL, (T *)w.filt_mf, (T *)w.filt_sPf);
@@ -1623,7 +1658,10 @@ static hipError_t dispatch_t(int d, int q, F &&f)
 template <typename T>
 hipError_t launch_forward_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
 {
-    return dispatch_t<T>(d, q, [&](auto c) { return fwd_seq<decltype(c)>(pk, m, w, s); });
+    return dispatch_t<T>(d, q, [&](auto c) {
+        using C = decltype(c);
+        return pk.lm ? fwd_seq<Cfg<T, C::d, C::q, 0, true>>(pk, m, w, s) : fwd_seq<C>(pk, m, w, s);
+    });
 }
 
 template <typename T>

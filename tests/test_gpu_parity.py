@@ -279,3 +279,47 @@ def test_device_start_equals_host_start(pp):
         assert a["iterations"] == b["iterations"] == 3
         assert np.array_equal(a["deltas"], b["deltas"])
         assert torch.equal(a["mean"], b["mean"])
+
+
+# ---------------------------------------------------------------------------
+# Levenberg-Marquardt damping (parapn_problem.lm_sigma)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("spec,k", [(dict(name="logistic", field="logistic", params=[], y0=[0.01], t0=0.0, t1=10.0,
+                                          q=2, N=300), 6),
+                                    (dict(name="vdp", field="van_der_pol", params=[1.0], y0=[2.0, 0.0], t0=0.0,
+                                          t1=6.3, q=3, N=200), 4)], ids=["logistic", "vdp"])
+def test_damped_ieks_matches_the_damped_oracle(pp, spec, k):
+    lm = 0.1
+    ref = oracle.ieks(spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"],
+                      fixed_iters=k, want_cov=False, lm_sigma=lm)
+    q = spec["q"]
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        r = pp.solve(spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], q, spec["N"], precision=prec,
+                     fixed_iters=k, lm_sigma=lm)
+        assert r["status"] == 0
+        assert relerr(e0(np_(r["mean"]), q), e0(ref["mean"], q)) < tol, prec
+
+
+def test_damping_keeps_the_scan_close_to_the_sequential_smoother(pp):
+    """FitzHugh-Nagumo from the constant start, N = 1024: at the second and
+    later iterates the undamped scan is far from the sequential smoother (the
+    method's conditioning, see test_scan_conditioning.py); with damping the
+    GPU iterates follow the damped oracle."""
+    spec = wl.fhn(N=1024)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    k, lm = 4, 0.05
+    ref = oracle.ieks(*args, fixed_iters=k, want_cov=False, lm_sigma=lm)
+    plain_ref = oracle.ieks(*args, fixed_iters=k, want_cov=False)
+    r = pp.solve(*args, precision="fp64", fixed_iters=k, lm_sigma=lm)
+    p = pp.solve(*args, precision="fp64", fixed_iters=k)
+    assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < 1e-6
+    assert relerr(e0(np_(p["mean"]), 3), e0(plain_ref["mean"], 3)) > 1e-2
+
+
+def test_damped_solve_returns_the_undamped_posterior_factors(pp):
+    ref = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 500, max_iter=30, tol=1e-11, want_cov=True)
+    r = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 500, precision="fp64", max_iter=30, tol=1e-11,
+                 want_cov=True, lm_sigma=0.05)
+    assert r["converged"]
+    assert relerr(np_(r["mean"]), ref["mean"]) < 1e-8
+    assert cov_relerr(np_(r["sqrtcov"]), ref["sqrtcov"]) < 1e-8

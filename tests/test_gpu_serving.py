@@ -190,3 +190,28 @@ def test_late_arrival_joins_and_finishes_first(pp):
     assert done[1]["t_start"] < done[0]["t_done"]
     for i, r in ((0, long_r), (1, short_r)):
         assert same(done[i]["mean"], alone(pp, r)["mean"])
+
+
+def test_damped_and_plain_requests_share_a_server(pp):
+    """Damped requests (lm_sigma > 0) run in packs of their own; every
+    request, damped or not, is bitwise the same as alone."""
+    reqs = [req("logistic", [], [0.01], 10.0, 2, 300, "fp64", k=4),
+            req("logistic", [], [0.02], 10.0, 2, 200, "fp64", k=4),
+            req("van_der_pol", [1.0], [2.0, 0.0], 6.3, 3, 150, "fp32", k=3)]
+    damped = [dict(r, lm_sigma=0.1) for r in reqs]
+    mix = [reqs[0], damped[0], reqs[1], damped[1], damped[2], reqs[2]]
+    srv = pp.Server(max_slots=16)
+    for i, r in enumerate(mix):
+        srv.submit(i, **r)
+    done = {}
+    while len(done) < len(mix):
+        srv.step()
+        done.update({c["req_id"]: c for c in srv.poll()})
+    srv.close()
+    for i, r in enumerate(mix):
+        a = pp.solve(r["field"], r["params"], r["y0"], r["t0"], r["t1"], r["q"], r["N"], precision=r["precision"],
+                     fixed_iters=r["fixed_iters"], lm_sigma=r.get("lm_sigma", 0.0))
+        assert done[i]["status"] == pp.OK
+        assert same(done[i]["mean"], a["mean"]), i
+    # the damping acts
+    assert not same(done[0]["mean"], done[1]["mean"])

@@ -226,9 +226,10 @@ def random_linear_model(D, dobs, N, rng, sigma0=True):
     return mu0, S0, Phi, sQ, H, dv
 
 
-def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None):
+def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None, rstd=None):
     """Joint Gaussian of Y_0..N (Y0 = mu0 + S0 w0, Y_n = Phi Y_{n-1} + sQ w_n),
-    conditioned on H_n Y_n = d_n for n = 1..upto (all when upto is None)."""
+    conditioned on H_n Y_n = d_n for n = 1..upto (all when upto is None);
+    rstd: optional per-row noise standard deviations of the observations."""
     N, dobs, D = H.shape
     upto = N if upto is None else upto
     nw = (N + 1) * D
@@ -246,6 +247,8 @@ def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None):
         C[(n - 1) * dobs:n * dobs, n * D:(n + 1) * D] = H[n - 1]
     dd = dv[:upto].ravel()
     S = C @ Sig @ C.T
+    if rstd is not None:
+        S = S + np.diag(np.tile(np.asarray(rstd, dtype=float) ** 2, upto))
     K = np.linalg.solve(S, C @ Sig).T
     mp = m + K @ (dd - C @ m)
     Sp = Sig - K @ C @ Sig
@@ -269,6 +272,73 @@ def test_kf_rts_equals_dense_conditioning(D, dobs, N):
         assert np.abs(sPf[n] @ sPf[n].T - Pn).max() < 1e-10 * max(1.0, np.abs(Pn).max())
         # the Dirac observation holds exactly in the filtered marginal
         assert np.abs(H[n - 1] @ mf[n] - dv[n - 1]).max() < 1e-9 * max(1.0, np.abs(mf[n]).max())
+
+
+def test_kf_rts_with_noisy_rows_equals_dense_conditioning():
+    """Observation rows with noise (the damping rows of the Levenberg-Marquardt
+    variant): sequential square-root filter/smoother vs dense conditioning."""
+    D, dobs, N = 6, 4, 6
+    rng = np.random.default_rng(17)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng)
+    rstd = np.array([0.0, 0.0, 0.7, 2.5])
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv, rstd=rstd)
+    m_all, S_all = dense_conditioning(mu0, S0, Phi, sQ, H, dv, rstd=rstd)
+    for n in range(N + 1):
+        assert rel(ms[n], m_all[n]) < 1e-10
+        Pn = S_all[n * D:(n + 1) * D, n * D:(n + 1) * D]
+        assert np.abs(sPs[n] @ sPs[n].T - Pn).max() < 1e-10 * max(1.0, np.abs(Pn).max())
+    m_3, _ = dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=3, rstd=rstd)
+    assert rel(mf[3], m_3[3]) < 1e-10
+    # zero noise is the noiseless filter
+    a = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv, rstd=np.zeros(dobs))
+    b = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_damped_iterate_equals_regularised_linear_smoother():
+    """One damped IEKS iteration = the linear smoother on the model linearised
+    at the constant trajectory mu0 with the pseudo-observations E0 Y_n = E0 mu0
+    of standard deviation lm_sigma / sqrt(h), built from the unpreconditioned
+    closed forms and dense conditioning at tiny N."""
+    field, params, y0, q, N, t1, lm = "fhn", [0.2, 0.2, 3.0], np.array([-1.0, 1.0]), 2, 5, 0.5, 0.3
+    d, S = 2, q + 1
+    D = d * S
+    h = t1 / N
+    Phi1, Q1 = oracle.iwp(q, h)
+    Phi, Q = np.kron(np.eye(d), Phi1), np.kron(np.eye(d), Q1)
+    mu0 = oracle.taylor_mu0(field, params, y0, q)
+    E0 = np.zeros((d, D))
+    E1 = np.zeros((d, D))
+    for i in range(d):
+        E0[i, i * S] = 1.0
+        E1[i, i * S + 1] = 1.0
+    y = E0 @ mu0
+    J = oracle.field_jac(field, params, y)
+    f = oracle.field_f(field, params, y)
+    Hn = np.vstack([E1 - J @ E0, E0])
+    dn = np.concatenate([f - J @ y, y])
+    H = np.repeat(Hn[None], N, axis=0)
+    dv = np.repeat(dn[None], N, axis=0)
+    rstd = np.concatenate([np.zeros(d), np.full(d, lm / np.sqrt(h))])
+    m_all, _ = dense_conditioning(mu0, np.zeros((D, D)), Phi, np.linalg.cholesky(Q), H, dv, rstd=rstd)
+    r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=1, want_cov=False, lm_sigma=lm)
+    assert rel(r["mean"], m_all) < 1e-9
+    plain = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=1, want_cov=False)
+    assert rel(plain["mean"], m_all) > 1e-6  # the damping does act
+
+
+def test_damping_keeps_the_fixed_point_and_vanishes_when_weak():
+    a = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 400, max_iter=40, tol=1e-12, want_cov=True)
+    b = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 400, max_iter=40, tol=1e-12, want_cov=True, lm_sigma=0.05)
+    assert a["status"] == 0 and b["status"] == 0
+    assert rel(b["mean"], a["mean"]) < 1e-9
+    # the factors of a damped solve come from an undamped pass: the same posterior
+    assert np.abs(b["sqrtcov"] @ b["sqrtcov"].transpose(0, 2, 1)
+                  - a["sqrtcov"] @ a["sqrtcov"].transpose(0, 2, 1)).max() < 1e-9
+    w = oracle.ieks("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 10.0, 3, 200, fixed_iters=3, want_cov=False,
+                    lm_sigma=1e9)
+    p = oracle.ieks("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 10.0, 3, 200, fixed_iters=3, want_cov=False)
+    assert rel(w["mean"], p["mean"]) < 1e-8
 
 
 # ---------------------------------------------------------------------------
