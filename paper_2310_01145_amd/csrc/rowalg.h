@@ -50,11 +50,14 @@ PARAPN_DEV int gbcast_i(int x)
 {
     static_assert(R == 8 || R == 16, "DPP broadcast needs groups of 8 or 16 lanes");
     static_assert(K >= 0 && K < R, "lane out of the group");
+    // bound_ctrl set: no old value to preserve (the source lane is always an
+    // active lane of the caller's group; a read of the inactive other half of
+    // a row with R = 8 gives 0 and is not selected)
     if constexpr (R == 16) {
-        return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, false);
+        return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, true);
     } else {
-        const int lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, x, 0x158 + K, 0xF, 0xF, false);
+        const int lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, x, 0x158 + K, 0xF, 0xF, true);
         return (threadIdx.x & 8) ? hi : lo;
     }
 }
@@ -150,12 +153,24 @@ PARAPN_DEV void tria_dpp_step(T (&v)[NC], int lane)
                 d0 += v[c] * w[c];
         }
         const T dot = (d0 + d1) * sk;
-        const bool me = lane == k;
-        v[k] = me ? nrm : v[k] - dot * uk;
+        // lane k applies its own reflector too: that maps its row to
+        // (|x|, 0, ..., 0) up to rounding; the strict upper triangle is
+        // cleared once at the end
+        (void)nrm;
+        v[k] = v[k] - dot * uk;
 #pragma unroll
-        for (int c = k + 1; c < NC; ++c) v[c] = me ? T(0) : v[c] - dot * w[c];
+        for (int c = k + 1; c < NC; ++c) v[c] = v[c] - dot * w[c];
         tria_dpp_step<T, NR, NC, R, SAFE, k + 1>(v, lane);
     }
+}
+
+// exact zeros above the diagonal (the register version leaves rounding
+// residues there)
+template <typename T, int NC>
+PARAPN_DEV void canonical_upper(T (&v)[NC], int lane)
+{
+#pragma unroll
+    for (int c = 1; c < NC; ++c) v[c] = c > lane ? T(0) : v[c];
 }
 
 // Two independent trias (NR rows each) in lock step: one reflection of each
@@ -166,7 +181,7 @@ PARAPN_DEV void tria2_dpp_step(T (&v1)[NC1], T (&v2)[NC2], int lane)
     constexpr int K1 = NR < NC1 ? NR : NC1, K2 = NR < NC2 ? NR : NC2;
     constexpr int K = K1 > K2 ? K1 : K2;
     if constexpr (k < K) {
-        const bool me = lane == k;
+        (void)lane;
         if constexpr (k < K1) {
             T u0, sc, a[NC1];
             const T nrm = reflector<T, NC1, SAFE>(v1, k, u0, sc, a);
@@ -184,9 +199,10 @@ PARAPN_DEV void tria2_dpp_step(T (&v1)[NC1], T (&v2)[NC2], int lane)
                     d0 += v1[c] * w[c];
             }
             const T dot = (d0 + d1) * sk;
-            v1[k] = me ? nrm : v1[k] - dot * uk;
+            (void)nrm;
+            v1[k] = v1[k] - dot * uk;
 #pragma unroll
-            for (int c = k + 1; c < NC1; ++c) v1[c] = me ? T(0) : v1[c] - dot * w[c];
+            for (int c = k + 1; c < NC1; ++c) v1[c] = v1[c] - dot * w[c];
         }
         if constexpr (k < K2) {
             T u0, sc, a[NC2];
@@ -205,9 +221,10 @@ PARAPN_DEV void tria2_dpp_step(T (&v1)[NC1], T (&v2)[NC2], int lane)
                     d0 += v2[c] * w[c];
             }
             const T dot = (d0 + d1) * sk;
-            v2[k] = me ? nrm : v2[k] - dot * uk;
+            (void)nrm;
+            v2[k] = v2[k] - dot * uk;
 #pragma unroll
-            for (int c = k + 1; c < NC2; ++c) v2[c] = me ? T(0) : v2[c] - dot * w[c];
+            for (int c = k + 1; c < NC2; ++c) v2[c] = v2[c] - dot * w[c];
         }
         tria2_dpp_step<T, NR, NC1, NC2, R, SAFE, k + 1>(v1, v2, lane);
     }
@@ -270,6 +287,7 @@ PARAPN_DEV void tria_rows_g(T (&v)[NC], int lane, T *tr)
     }
     if constexpr (R == 8 || R == 16) {
         tria_dpp_step<T, NR, NC, R, SAFE, 0>(v, lane);
+        canonical_upper<T, NC>(v, lane);
         wave_sync();  // callers' LDS traffic stays ordered around the call, as with the LDS version
     } else {
         tria_rows<T, NR, NC, SAFE>(v, lane, tr);
@@ -300,6 +318,8 @@ PARAPN_DEV void tria2_rows_g(T (&v1)[NC1], T (&v2)[NC2], int lane, T *tr)
             for (int c = 0; c < NC2; ++c) v2[c] = __builtin_amdgcn_ldexpf(v2[c], -e2);
         }
         tria2_dpp_step<T, NR, NC1, NC2, R, SAFE, 0>(v1, v2, lane);
+        canonical_upper<T, NC1>(v1, lane);
+        canonical_upper<T, NC2>(v2, lane);
         wave_sync();
         if constexpr (sizeof(T) == 4 && !SAFE) {
 #pragma unroll
