@@ -163,6 +163,9 @@ int parapn_filter_combine(parapn_ctx *ctx, int32_t D, int64_t count, int32_t pre
  * names receives up to max NUL-terminated names of name_len bytes each;
  * *n_out is the number of distinct kernels seen (may exceed max). */
 int parapn_profile_enable(int on);
+/* Restrict the timing to launches of one kernel (names as parapn_profile_read
+ * reports them, e.g. "fwd_reduce1"); NULL or "" times every kernel. */
+int parapn_profile_only(const char *kernel);
 int parapn_profile_read(int32_t max, char *names, int32_t name_len, double *total_ms, int64_t *launches,
                         int32_t *n_out);
 

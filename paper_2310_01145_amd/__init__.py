@@ -30,8 +30,8 @@ FIELDS = {
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_pararts",
-            "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_read", "parapn_server_create",
-            "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
+            "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
+            "parapn_server_create", "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
             "parapn_server_poll", "parapn_server_footprint", "parapn_server_stats", "parapn_last_error"]
 
 
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     L.parapn_filter_combine.restype = ctypes.c_int
     L.parapn_profile_enable.argtypes = [ctypes.c_int]
     L.parapn_profile_enable.restype = ctypes.c_int
+    L.parapn_profile_only.argtypes = [ctypes.c_char_p]
+    L.parapn_profile_only.restype = ctypes.c_int
     L.parapn_profile_read.argtypes = [i32, ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
     L.parapn_profile_read.restype = ctypes.c_int
@@ -298,6 +300,11 @@ def filter_combine(a, c, *, precision="fp64", device=0, stream=None):
 def profile_enable(on: bool = True):
     """Start (or stop) per-kernel event timing; clears previous counters."""
     _check(load_library().parapn_profile_enable(1 if on else 0))
+
+
+def profile_only(kernel=None):
+    """Time only launches of this kernel name (None: every kernel)."""
+    _check(load_library().parapn_profile_only(kernel.encode() if kernel else None))
 
 
 def profile_read(max_kernels: int = 64):

@@ -804,6 +804,12 @@ int parapn_profile_enable(int on)
     return PARAPN_OK;
 }
 
+int parapn_profile_only(const char *kernel)
+{
+    parapn::prof_only(kernel);
+    return PARAPN_OK;
+}
+
 int parapn_profile_read(int32_t max, char *names, int32_t name_len, double *total_ms, int64_t *launches,
                         int32_t *n_out)
 {

@@ -149,6 +149,8 @@ int config_supported(int d, int q);
 // events on their stream and the elapsed times are summed per kernel name.
 bool prof_on();
 void prof_enable(bool on);
+// time only launches of this kernel name (null or empty: every kernel)
+void prof_only(const char *name);
 void prof_begin(const char *name, hipStream_t s, hipEvent_t *start);
 void prof_end(const char *name, hipStream_t s, hipEvent_t start);
 // resolve pending events; fills up to max entries; returns the number of names

@@ -1734,6 +1734,7 @@ struct ProfAcc {
     int64_t n;
 };
 bool g_prof_on = false;
+std::string g_prof_only;  // empty: every kernel
 std::vector<ProfRec> g_prof_pending;
 std::vector<ProfAcc> g_prof_acc;
 std::vector<hipEvent_t> g_prof_free;  // recorded-and-read events, reused
@@ -1773,6 +1774,8 @@ void prof_resolve()
 
 bool prof_on() { return g_prof_on; }
 
+void prof_only(const char *name) { g_prof_only = name ? name : ""; }
+
 void prof_enable(bool on)
 {
     g_prof_on = on;
@@ -1782,7 +1785,10 @@ void prof_enable(bool on)
 
 void prof_begin(const char *name, hipStream_t s, hipEvent_t *start)
 {
-    (void)name;
+    if (!g_prof_only.empty() && g_prof_only != name) {
+        *start = nullptr;
+        return;
+    }
     *start = prof_event();
     if (*start) hipEventRecord(*start, s);
 }
