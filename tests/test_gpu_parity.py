@@ -323,3 +323,79 @@ def test_damped_solve_returns_the_undamped_posterior_factors(pp):
     assert r["converged"]
     assert relerr(np_(r["mean"]), ref["mean"]) < 1e-8
     assert cov_relerr(np_(r["sqrtcov"]), ref["sqrtcov"]) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# full size, in the configuration bench.py times
+# ---------------------------------------------------------------------------
+def test_fhn_full_size_matches_the_oracle(pp):
+    """FitzHugh-Nagumo at N = 2^18 from bench.py's starting trajectory
+    (device-resident, as timed), two iterations, both precisions."""
+    import torch
+
+    spec = wl.fhn(N=1 << 18)
+    start = wl.reference_start(spec)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    ref = oracle.ieks(*args, fixed_iters=2, want_cov=False, init_traj=start)
+    dev = torch.tensor(start, dtype=torch.float64, device="cuda")
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        r = pp.solve(*args, precision=prec, fixed_iters=2, init_traj=dev)
+        assert r["status"] == 0
+        # the start is converged to ~1e-10, so delta is rounding-level: it is
+        # compared on the solution's scale, with the gate of the means
+        scale = np.abs(e0(ref["mean"], 3)).max()
+        assert np.abs(r["deltas"] - ref["deltas"]).max() < tol * scale
+        assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < tol, prec
+
+
+def test_fhn_full_size_first_iteration_from_constant_start(pp):
+    """The first iterate from the constant start moves the trajectory by O(1):
+    in FP32 that whole increment is composed over 2^18 steps of a nearly
+    neutral oscillator (the linearisation at y0), and its phase error builds
+    up to a few 1e-3.  FP64 holds the 1e-9 gate; the FP32 gate of 1e-4
+    applies once the increments are small (refinement against the FP64
+    trajectory, see the two tests below and the one above)."""
+    spec = wl.fhn(N=1 << 18)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    ref = oracle.ieks(*args, fixed_iters=1, want_cov=False)
+    r64 = pp.solve(*args, precision="fp64", fixed_iters=1)
+    assert relerr(e0(np_(r64["mean"]), 3), e0(ref["mean"], 3)) < 1e-9
+    r32 = pp.solve(*args, precision="fp32", fixed_iters=1)
+    assert relerr(e0(np_(r32["mean"]), 3), e0(ref["mean"], 3)) < 1e-2
+
+
+def test_fp32_refines_to_the_fp64_solution_at_full_size(pp):
+    """Logistic at N = 2^18 from the constant start: the FP32 increments are
+    taken against the FP64 trajectory and FP64 residuals, so the converged
+    FP32 solve meets the oracle's converged solution at 1e-4 even though its
+    first increment does not."""
+    args = ("logistic", [], [0.01], 0.0, 10.0, 2, 1 << 18)
+    ref1 = oracle.ieks(*args, fixed_iters=1, want_cov=False)
+    ref = oracle.ieks(*args, max_iter=30, tol=1e-10, want_cov=False)
+    assert ref["status"] == 0
+    r1 = pp.solve(*args, precision="fp32", fixed_iters=1)
+    r = pp.solve(*args, precision="fp32", max_iter=30, tol=1e-10)
+    assert r["status"] == 0 and r["converged"]
+    first = relerr(e0(np_(r1["mean"]), 2), e0(ref1["mean"], 2))
+    final = relerr(e0(np_(r["mean"]), 2), e0(ref["mean"], 2))
+    assert final < 1e-4
+    assert final <= first
+
+
+def test_lorenz_full_size_first_iteration(pp):
+    """Lorenz-63 at N = 2^18, q = 4 (D = 15) from bench.py's start, one
+    iteration.  Chaos amplifies rounding like exp(0.9 t): FP32 is gated on
+    t <= 8, FP64 on t <= 15 (the readings of the Lorenz gates)."""
+    spec = wl.lorenz(N=1 << 18)
+    start = wl.reference_start(spec)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    ref = oracle.ieks(*args, fixed_iters=1, want_cov=False, init_traj=start)
+    ref0 = e0(ref["mean"], 4)
+    n8 = int(8.0 / 20.0 * spec["N"])
+    n15 = int(15.0 / 20.0 * spec["N"])
+    r64 = pp.solve(*args, precision="fp64", fixed_iters=1, init_traj=start)
+    assert relerr(e0(np_(r64["mean"]), 4)[: n15 + 1], ref0[: n15 + 1]) < 1e-9
+    assert relerr(e0(np_(r64["mean"]), 4), ref0) < 1e-7
+    r32 = pp.solve(*args, precision="fp32", fixed_iters=1, init_traj=start)
+    assert r32["status"] == 0
+    assert relerr(e0(np_(r32["mean"]), 4)[: n8 + 1], ref0[: n8 + 1]) < 1e-4
