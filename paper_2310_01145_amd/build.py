@@ -21,12 +21,18 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-# translation units: the kernel file is compiled once per precision so the
-# two halves build in parallel
+# translation units: the kernel file is compiled once per precision and once
+# more per precision for the damped forward scan, so the parts build in
+# parallel
 UNITS = [
     ("scan_kernels_f32.o", "scan_kernels.hip", ["-DPARAPN_BUILD_FP32=1", "-DPARAPN_BUILD_FP64=0"]),
     ("scan_kernels_f64.o", "scan_kernels.hip", ["-DPARAPN_BUILD_FP32=0", "-DPARAPN_BUILD_FP64=1",
                                                 "-DPARAPN_BUILD_HELPERS=0"]),
+    # the damped (Levenberg-Marquardt) forward scan, per precision
+    ("scan_kernels_f32_lm.o", "scan_kernels.hip", ["-DPARAPN_BUILD_FP32=1", "-DPARAPN_BUILD_FP64=0",
+                                                   "-DPARAPN_BUILD_HELPERS=0", "-DPARAPN_BUILD_LM=1"]),
+    ("scan_kernels_f64_lm.o", "scan_kernels.hip", ["-DPARAPN_BUILD_FP32=0", "-DPARAPN_BUILD_FP64=1",
+                                                   "-DPARAPN_BUILD_HELPERS=0", "-DPARAPN_BUILD_LM=1"]),
     ("parapn_api.o", "parapn_api.cpp", ["-x", "hip"]),
 ]
 

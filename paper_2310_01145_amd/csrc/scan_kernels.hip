@@ -1655,13 +1655,22 @@ static hipError_t dispatch_t(int d, int q, F &&f)
     return hipErrorInvalidValue;
 }
 
+// damped packs: instantiated in translation units of their own (they build in
+// parallel with the rest)
 template <typename T>
-hipError_t launch_forward_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
+hipError_t launch_forward_lm_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
 {
     return dispatch_t<T>(d, q, [&](auto c) {
         using C = decltype(c);
-        return pk.lm ? fwd_seq<Cfg<T, C::d, C::q, 0, true>>(pk, m, w, s) : fwd_seq<C>(pk, m, w, s);
+        return fwd_seq<Cfg<T, C::d, C::q, 0, true>>(pk, m, w, s);
     });
+}
+
+template <typename T>
+hipError_t launch_forward_t(int d, int q, const Pack &pk, const ModelDev &m, const Work &w, hipStream_t s)
+{
+    if (pk.lm) return launch_forward_lm_t<T>(d, q, pk, m, w, s);
+    return dispatch_t<T>(d, q, [&](auto c) { return fwd_seq<decltype(c)>(pk, m, w, s); });
 }
 
 template <typename T>
@@ -1706,6 +1715,10 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
 #ifndef PARAPN_BUILD_HELPERS
 #define PARAPN_BUILD_HELPERS 1
 #endif
+// 0: every launcher but the damped forward scan; 1: only the damped one
+#ifndef PARAPN_BUILD_LM
+#define PARAPN_BUILD_LM 0
+#endif
 
 #define PARAPN_INSTANTIATE(T)                                                                                       \
     template hipError_t launch_forward_t<T>(int, int, const Pack &, const ModelDev &, const Work &, hipStream_t);  \
@@ -1715,11 +1728,32 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
                                                    hipStream_t);                                                   \
     template hipError_t launch_tria_square_t<T>(int, int, const void *, void *, hipStream_t);
 
+#define PARAPN_INSTANTIATE_LM(T) \
+    template hipError_t launch_forward_lm_t<T>(int, int, const Pack &, const ModelDev &, const Work &, hipStream_t);
+
+#if PARAPN_BUILD_LM
+#if PARAPN_BUILD_FP32
+PARAPN_INSTANTIATE_LM(float)
+#endif
+#if PARAPN_BUILD_FP64
+PARAPN_INSTANTIATE_LM(double)
+#endif
+#else
+// the damped launchers come from the other translation units
+#if PARAPN_BUILD_FP32
+extern template hipError_t launch_forward_lm_t<float>(int, int, const Pack &, const ModelDev &, const Work &,
+                                                      hipStream_t);
+#endif
+#if PARAPN_BUILD_FP64
+extern template hipError_t launch_forward_lm_t<double>(int, int, const Pack &, const ModelDev &, const Work &,
+                                                       hipStream_t);
+#endif
 #if PARAPN_BUILD_FP32
 PARAPN_INSTANTIATE(float)
 #endif
 #if PARAPN_BUILD_FP64
 PARAPN_INSTANTIATE(double)
+#endif
 #endif
 
 #if PARAPN_BUILD_HELPERS
