@@ -52,19 +52,27 @@ extern "C" {
  * PARAPN_AFFINE          d    y' = L y + c                                    params L (d*d, row-major), c (d)
  * PARAPN_RIGID_BODY      d=3  y' = (-2 y2 y3, 1.25 y1 y3, -0.5 y1 y2)         no params
  * PARAPN_VAN_DER_POL     d=2  y' = (y2, mu((1-y1^2) y2 - y1))                 params mu
+ * PARAPN_MOL_HEAT_REACTION  d>=3  method of lines for u_t = nu u_xx + u(1-u) on
+ *                        d periodic grid points x_i = i/d:
+ *                        y_i' = nu d^2 (y_{i-1} - 2 y_i + y_{i+1}) + y_i (1 - y_i)  params nu
  * The first three, the rigid body and Van der Pol follow the problems of the
  * experiments section and the workload list; the affine field is the exactly
  * solvable case of Sec. 3.1. */
 #define PARAPN_LOGISTIC 0
 #define PARAPN_FHN 1
 #define PARAPN_LORENZ63 2
+#define PARAPN_MOL_HEAT_REACTION 4
 #define PARAPN_LOTKA_VOLTERRA 3
 #define PARAPN_AFFINE 5
 #define PARAPN_RIGID_BODY 6
 #define PARAPN_VAN_DER_POL 7
 
-/* limits of this build: 1 <= d <= 3, 1 <= q <= 4, D = d(q+1) <= 15 */
+/* limits of this build: 1 <= q <= 4; the fixed-size fields have 1 <= d <= 3,
+ * D = d(q+1) <= 15 (one group of lanes per scan element); the method-of-lines
+ * field has d >= 3 and D <= 256 (one workgroup per element, matrix-core
+ * products and triangularisations) */
 #define PARAPN_MAX_D 15
+#define PARAPN_MAX_DENSE_D 256
 #define PARAPN_MAX_PARAMS 16
 
 typedef struct parapn_ctx parapn_ctx;
@@ -132,6 +140,19 @@ int parapn_workspace_size(const parapn_problem *prob, size_t *bytes);
  * per iteration (8-byte read of delta_k). */
 int parapn_solve(parapn_ctx *ctx, const parapn_problem *prob, void *mean_out, void *sqrtcov_out,
                  parapn_info *info, void *stream);
+
+/* Alg. 2 for `batch` instances of one problem that differ only in their
+ * initial values: instance b starts from y0s + b*d (host, batch*d values;
+ * prob->y0 is ignored).  Outputs are stacked: mean_out [batch][N+1][D],
+ * sqrtcov_out [batch][N+1][D][D] or NULL, info [batch] (or NULL).  Each
+ * instance stops on its own test and its result is the one parapn_solve gives
+ * for it.  The method-of-lines field runs all instances in the same launches
+ * (one workgroup per element operation of any instance); other fields are
+ * solved one instance after another.  Returns PARAPN_ENONFINITE if any
+ * instance turned non-finite, else PARAPN_MAXITER if any hit max_iter, else
+ * PARAPN_OK; per-instance outcomes are in info. */
+int parapn_solve_batch(parapn_ctx *ctx, const parapn_problem *prob, int32_t batch, const double *y0s,
+                       void *mean_out, void *sqrtcov_out, parapn_info *info, void *stream);
 
 /* ParaRTS, Alg. 1, on a linear model (eq. affine-estimation) with constant
  * transition:  Y0 ~ N(mu0, S0 S0^T),  Y_n = Phi Y_{n-1} + w_n, w_n ~ N(0, sqrtQ sqrtQ^T),

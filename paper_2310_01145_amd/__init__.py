@@ -23,13 +23,15 @@ FIELDS = {
     "fhn": 1,
     "lorenz": 2,
     "lotka_volterra": 3,
+    "mol_heat_reaction": 4,
     "affine": 5,
     "rigid_body": 6,
     "van_der_pol": 7,
 }
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
-EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_pararts",
+EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
+            "parapn_pararts",
             "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
             "parapn_server_create", "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
             "parapn_server_poll", "parapn_server_footprint", "parapn_server_stats", "parapn_last_error"]
@@ -106,6 +108,9 @@ def load_library(path: str = LIB_PATH):
     L.parapn_workspace_size.restype = ctypes.c_int
     L.parapn_solve.argtypes = [vp, ctypes.POINTER(Problem), vp, vp, ctypes.POINTER(Info), vp]
     L.parapn_solve.restype = ctypes.c_int
+    L.parapn_solve_batch.argtypes = [vp, ctypes.POINTER(Problem), i32, ctypes.POINTER(ctypes.c_double), vp, vp,
+                                      ctypes.POINTER(Info), vp]
+    L.parapn_solve_batch.restype = ctypes.c_int
     L.parapn_pararts.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.parapn_pararts.restype = ctypes.c_int
     L.parapn_filter_combine.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
@@ -256,6 +261,40 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
     k = info.iterations
     return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy(),
             "converged": bool(info.converged), "tol_used": info.tol_used, "final_delta": info.final_delta}
+
+
+def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
+                want_cov=False, device=0, stream=None):
+    """Alg. 2 for a batch of initial values ``y0s`` [B, d] of one problem
+    (parapn_solve_batch).  Returns ``mean`` [B, N+1, D], ``sqrtcov``
+    [B, N+1, D, D] or None, the overall ``status`` and per-instance
+    ``iterations``, ``converged``, ``final_delta``, ``deltas``."""
+    torch = _torch()
+    L = load_library()
+    y0s = np.ascontiguousarray(np.asarray(y0s, dtype=np.float64))
+    if y0s.ndim != 2:
+        raise ValueError("y0s must be [batch, d]")
+    B, d = y0s.shape
+    pb = make_problem(field, params, y0s[0], t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
+                      fixed_iters=fixed_iters, d=d)
+    D = d * (pb.q + 1)
+    dt = _dtype(pb.precision)
+    dev = torch.device("cuda", device)
+    mean = torch.empty((B, pb.N + 1, D), dtype=dt, device=dev)
+    cov = torch.empty((B, pb.N + 1, D, D), dtype=dt, device=dev) if want_cov else None
+    cap = max(pb.max_iter, pb.fixed_iters, 1)
+    hist = np.zeros((B, cap))
+    infos = (Info * B)()
+    for b in range(B):
+        infos[b].delta_history = hist[b].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = L.parapn_solve_batch(context(device), ctypes.byref(pb), B, y0s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _dptr(mean), _dptr(cov), infos, _stream_handle(stream))
+    _check(rc, allow=(OK, MAXITER, ENONFINITE))
+    its = [infos[b].iterations for b in range(B)]
+    return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": its,
+            "converged": [bool(infos[b].converged) for b in range(B)],
+            "final_delta": [infos[b].final_delta for b in range(B)],
+            "deltas": [hist[b, :its[b]].copy() for b in range(B)]}
 
 
 def pararts(mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, *, precision="fp64", want_cov=True, want_filter=True,

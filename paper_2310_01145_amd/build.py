@@ -33,6 +33,8 @@ UNITS = [
                                                    "-DPARAPN_BUILD_HELPERS=0", "-DPARAPN_BUILD_LM=1"]),
     ("scan_kernels_f64_lm.o", "scan_kernels.hip", ["-DPARAPN_BUILD_FP32=0", "-DPARAPN_BUILD_FP64=1",
                                                    "-DPARAPN_BUILD_HELPERS=0", "-DPARAPN_BUILD_LM=1"]),
+    # the dense engine (large D)
+    ("dense_kernels.o", "dense_kernels.hip", []),
     ("parapn_api.o", "parapn_api.cpp", ["-x", "hip"]),
 ]
 

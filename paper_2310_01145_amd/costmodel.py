@@ -100,3 +100,69 @@ def per_step(d, q, esize, b1=32, bs1=8):
 
 def iteration_flops(d, q, b1=32):
     return sum(v[0] for v in per_step(d, q, 4, b1).values())
+
+
+# ---------------------------------------------------------------------------
+# dense engine (one workgroup per element operation, Blelloch sweeps)
+# ---------------------------------------------------------------------------
+def dense_element(D, d):
+    """linearised filtering element of one step (step 1 stops after b, sqrtC)"""
+    return tria(d + D, D) + trsolve(D, d) + mm(D, d, D) + trsolve(D, d) + 2 * D * d + d * d + 2 * D * d
+
+
+def dense_fcombine(D, state):
+    """filtering operator on dense D x D operands; state: the left operand is
+    a prefix state (only b and sqrtC are formed)"""
+    f = (mm(D, D, D) + tria(2 * D, 2 * D) + trsolve(D, D) + mm(D, D, D) + mm(D, D, D) + 6 * D * D
+         + mm(D, D, D) + tria(D, 2 * D))
+    if not state:
+        f += mm(D, D, D) + 8 * D * D + mm(D, D, D) + tria(D, 2 * D)
+    return f
+
+
+def dense_selement(D, q):
+    return 2 * D * D * (q + 1) + tria(2 * D, 2 * D) + trsolve(D, D) + 2 * D * D + 2 * D * (q + 1)
+
+
+def dense_bcombine(D, state, with_L=False):
+    f = 2 * D * D + (0 if state else mm(D, D, D))
+    if with_L:
+        f += mm(D, D, D) + tria(D, 2 * D)
+    return f
+
+
+def dense_sweep_pairs(N):
+    """(general, state) pair counts of the up-sweep and the state pairs of the
+    down-sweep, as the level launches enumerate them"""
+    up_g = up_s = down = 0
+    s = 1
+    smax = 0
+    while 2 * s <= N:
+        np_ = N // (2 * s)
+        up_s += 1
+        up_g += np_ - 1
+        smax = s
+        s *= 2
+    s = smax
+    while s >= 1:
+        if N >= 3 * s:
+            down += (N - 3 * s) // (2 * s) + 1
+        s //= 2
+    return up_g, up_s, down
+
+
+def dense_iteration_flops(D, d, q, N, B=1):
+    """Algorithmic flops of one dense iteration per kernel name (whole batch)."""
+    up_g, up_s, down = dense_sweep_pairs(N)
+    fc = dense_fcombine(D, False)
+    fs = dense_fcombine(D, True)
+    out = {
+        "dense_elements": B * (N * dense_element(D, d)),
+        "dense_fcombine_up": B * (up_g * fc + up_s * fs),
+        "dense_fcombine_down": B * down * fs,
+        "dense_selements": B * max(N - 1, 0) * dense_selement(D, q),
+        "dense_bcombine_up": B * (up_g * dense_bcombine(D, False) + up_s * dense_bcombine(D, True)),
+        "dense_bcombine_down": B * down * dense_bcombine(D, True),
+        "dense_update": B * N * D,
+    }
+    return out

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "dense.h"
 #include "fields.h"
 #include "parapn_internal.h"
 
@@ -102,8 +103,31 @@ bool taylor_mu0_d(int field, const double *p, const double *y0, int q, double *m
     return true;
 }
 
+// the method-of-lines field (any d >= 3): periodic second differences with
+// dx = 1/d plus the logistic reaction, on truncated series
+bool taylor_mu0_mol(int d, const double *p, const double *y0, int q, double *mu0)
+{
+    std::vector<Ser> y(d), f(d);
+    const double k = p[0] * (double)d * (double)d;
+    for (int i = 0; i < d; ++i) y[i] = ser_const(y0[i]);
+    for (int kk = 0; kk < q; ++kk) {
+        for (int i = 0; i < d; ++i)
+            f[i] = k * (y[(i + d - 1) % d] - 2.0 * y[i] + y[(i + 1) % d]) + y[i] * (1.0 - y[i]);
+        for (int i = 0; i < d; ++i) y[i].c[kk + 1] = f[i].c[kk] / (kk + 1);
+    }
+    for (int i = 0; i < d; ++i) {
+        double fact = 1.0;
+        for (int j = 0; j <= q; ++j) {
+            if (j > 0) fact *= j;
+            mu0[i * (q + 1) + j] = fact * y[i].c[j];
+        }
+    }
+    return true;
+}
+
 bool taylor_mu0(int field, int d, const double *p, const double *y0, int q, double *mu0)
 {
+    if (field == parapn::F_MOL) return d >= 3 && taylor_mu0_mol(d, p, y0, q, mu0);
     switch (d) {
     case 1: return taylor_mu0_d<1>(field, p, y0, q, mu0);
     case 2: return taylor_mu0_d<2>(field, p, y0, q, mu0);
@@ -415,13 +439,26 @@ static int ensure_host_bits(parapn_ctx *ctx, size_t n)
 static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
 {
     if (!p) return fail(PARAPN_EINVAL, "problem is NULL");
-    const int fd = parapn::field_fixed_dim(p->field);
-    if (fd < 0) return fail(PARAPN_EINVAL, "unknown field id " + std::to_string(p->field));
-    if (fd > 0 && p->d != fd) return fail(PARAPN_EINVAL, "field requires d = " + std::to_string(fd));
-    if (p->d < 1 || p->d > 3) return fail(PARAPN_EINVAL, "d must be in 1..3 in this build");
-    if (p->q < 1 || p->q > 4) return fail(PARAPN_EINVAL, "q must be in 1..4");
-    if (parapn::config_supported(p->d, p->q) < 0) return fail(PARAPN_EINVAL, "unsupported (d, q)");
-    const int np = parapn::field_n_params(p->field, p->d);
+    int np;
+    if (p->field == parapn::F_MOL) {
+        // the dense engine
+        if (p->q < 1 || p->q > 4) return fail(PARAPN_EINVAL, "q must be in 1..4");
+        if (p->d < 3 || p->d * (p->q + 1) > parapn::kDenseMaxD)
+            return fail(PARAPN_EINVAL, "the method-of-lines field needs d >= 3 and d(q+1) <= " +
+                                           std::to_string(parapn::kDenseMaxD));
+        if (p->lm_sigma != 0.0) return fail(PARAPN_EINVAL, "damping (lm_sigma > 0) is not available for this field");
+        np = 1;
+        if (p->n_params >= 1 && p->params && !(std::isfinite(p->params[0]) && p->params[0] >= 0.0))
+            return fail(PARAPN_EINVAL, "nu must be finite and >= 0");
+    } else {
+        const int fd = parapn::field_fixed_dim(p->field);
+        if (fd < 0) return fail(PARAPN_EINVAL, "unknown field id " + std::to_string(p->field));
+        if (fd > 0 && p->d != fd) return fail(PARAPN_EINVAL, "field requires d = " + std::to_string(fd));
+        if (p->d < 1 || p->d > 3) return fail(PARAPN_EINVAL, "d must be in 1..3 in this build");
+        if (p->q < 1 || p->q > 4) return fail(PARAPN_EINVAL, "q must be in 1..4");
+        if (parapn::config_supported(p->d, p->q) < 0) return fail(PARAPN_EINVAL, "unsupported (d, q)");
+        np = parapn::field_n_params(p->field, p->d);
+    }
     if (p->n_params < np || p->n_params > PARAPN_MAX_PARAMS)
         return fail(PARAPN_EINVAL, "field needs " + std::to_string(np) + " parameters");
     if (np > 0 && !p->params) return fail(PARAPN_EINVAL, "params is NULL");
@@ -576,6 +613,171 @@ static int init_resident(const Solve &sv, double *buf, const double *init_traj, 
     return PARAPN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// dense engine (method-of-lines field): B instances of one problem
+// ---------------------------------------------------------------------------
+constexpr int kDenseWorkgroups = 512;  // two per compute unit; each owns a scratch slot
+
+static int64_t dense_traj_stride(int D, int64_t N) { return ((N + 1) * D + 2 * D + 31) & ~int64_t(31); }
+
+struct DenseLayout {
+    size_t traj, dbits, active, A, b, C, e, J, E, g, L, scratch, total;
+};
+
+static DenseLayout dense_layout(bool fp64, int D, int64_t N, int B, bool cov)
+{
+    DenseLayout L{};
+    size_t off = 0;
+    const size_t esz = fp64 ? 8 : 4, el = (size_t)B * N, DD = (size_t)D * D;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.traj = take((size_t)B * dense_traj_stride(D, N) * 8);
+    L.dbits = take((size_t)2 * B * 8);
+    L.active = take((size_t)B * 4);
+    L.A = take(el * DD * esz);
+    L.C = take(el * DD * esz);
+    L.J = take(el * DD * esz);
+    L.E = take(el * DD * esz);
+    L.b = take(el * D * esz);
+    L.e = take(el * D * esz);
+    L.g = take(el * D * esz);
+    L.L = cov ? take(el * DD * esz) : 0;
+    L.scratch = take((size_t)kDenseWorkgroups * parapn::dense_scratch_elems(D) * esz);
+    L.total = off;
+    return L;
+}
+
+// Alg. 2 for instances b = 0..B-1 of problem p with initial values
+// y0s + b d.  All instances iterate together; one that has converged (or
+// turned non-finite) is frozen: its kernels skip it from then on, so its
+// result is the one it would get alone.
+static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const double *y0s, void *mean_out,
+                       void *cov_out, parapn_info *info, hipStream_t s)
+{
+    const bool fp64 = p->precision == PARAPN_FP64;
+    const int esz = fp64 ? 8 : 4;
+    std::vector<Solve> sv(B);
+    for (int b = 0; b < B; ++b) {
+        parapn_problem pb = *p;
+        pb.y0 = y0s + (size_t)b * p->d;
+        for (int i = 0; i < p->d; ++i)
+            if (!std::isfinite(pb.y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
+        const int rc = prepare(&pb, sv[b]);
+        if (rc) return rc;
+    }
+    const int D = sv[0].D;
+    const int64_t N = sv[0].N;
+    const DenseLayout L = dense_layout(fp64, D, N, B, cov_out != nullptr);
+    int rc = ensure_ws(ctx, L.total);
+    if (rc) return rc;
+    rc = ensure_host_bits(ctx, 2 * (size_t)B);
+    if (rc) return rc;
+    char *ws = (char *)ctx->ws;
+    // the dense layout overwrites what the row-per-lane packs cached there
+    ctx->consts_at = nullptr;
+    ctx->reqs_at = nullptr;
+    const int64_t ts = dense_traj_stride(D, N);
+    double *traj = (double *)(ws + L.traj);
+    for (int b = 0; b < B; ++b) {
+        rc = init_resident(sv[b], traj + (size_t)b * ts, p->init_traj, p->init_on_device != 0, s);
+        if (rc) return rc;
+    }
+    parapn::DenseModel md{};
+    md.field = p->field;
+    md.d = p->d;
+    md.q = p->q;
+    md.D = D;
+    md.B = B;
+    md.N = N;
+    md.hq = sv[0].h / p->q;
+    md.T0 = sv[0].Td[0];
+    md.T1 = sv[0].Td[1];
+    for (int i = 0; i < parapn::kMaxParams; ++i) md.p[i] = sv[0].params[i];
+    {
+        std::vector<double> Phi, sQ;
+        prior_blocks(1, p->q, Phi, sQ);
+        const int S = p->q + 1;
+        for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j) {
+                md.phib[i * 5 + j] = Phi[i * S + j];
+                md.sqb[i * 5 + j] = sQ[i * S + j];
+            }
+    }
+    parapn::DenseWork w{};
+    w.A = ws + L.A;
+    w.b = ws + L.b;
+    w.C = ws + L.C;
+    w.e = ws + L.e;
+    w.J = ws + L.J;
+    w.E = ws + L.E;
+    w.g = ws + L.g;
+    w.L = cov_out ? ws + L.L : nullptr;
+    w.scratch = ws + L.scratch;
+    w.traj = traj;
+    w.traj_stride = ts;
+    w.dbits = (unsigned long long *)(ws + L.dbits);
+    int *active_dev = (int *)(ws + L.active);
+    w.active = active_dev;
+    w.nwg = kDenseWorkgroups;
+    std::vector<Solve *> ptr(B);
+    for (int b = 0; b < B; ++b) ptr[b] = &sv[b];
+    std::vector<int> active(B, 1);
+    while (true) {
+        PARAPN_HIP(hipMemcpyAsync(active_dev, active.data(), (size_t)B * sizeof(int), hipMemcpyHostToDevice, s),
+                   "copy flags");
+        PARAPN_HIP(hipMemsetAsync(w.dbits, 0, (size_t)2 * B * sizeof(unsigned long long), s), "memset");
+        PARAPN_HIP(parapn::dense_iteration(fp64, md, w, s), "dense iteration");
+        PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, w.dbits, (size_t)2 * B * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s),
+                   "read delta");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        pack_finish(ptr, ctx->host_bits);
+        bool all = true;
+        for (int b = 0; b < B; ++b) {
+            active[b] = sv[b].done ? 0 : 1;
+            all = all && sv[b].done;
+        }
+        if (all) break;
+    }
+    for (int b = 0; b < B; ++b) {
+        const double *tb = traj + (size_t)b * ts;
+        PARAPN_HIP(parapn::launch_unscale(fp64, D, N, tb + (size_t)(N + 1) * D, tb, nullptr,
+                                          (char *)mean_out + (size_t)b * (N + 1) * D * esz, nullptr, s, true),
+                   "unscale");
+    }
+    if (cov_out) {
+        // factors at each instance's last linearisation (its filtering
+        // marginals are still in place)
+        w.active = nullptr;
+        PARAPN_HIP(parapn::dense_covariance(fp64, md, w, cov_out, s), "covariance pass");
+    }
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    int status = PARAPN_OK;
+    for (int b = 0; b < B; ++b) {
+        const Solve &v = sv[b];
+        if (info) {
+            parapn_info &f = info[b];
+            f.iterations = v.iter;
+            f.converged = v.converged ? 1 : 0;
+            f.final_delta = v.delta;
+            f.tol_used = v.tol_used;
+            if (f.delta_history) {
+                const int cap = std::max(v.max_iter, v.fixed_iters);
+                for (int k = 0; k < (int)v.deltas.size() && k < cap; ++k) f.delta_history[k] = v.deltas[k];
+            }
+        }
+        if (v.status == PARAPN_ENONFINITE)
+            status = PARAPN_ENONFINITE;
+        else if (v.status == PARAPN_MAXITER && status == PARAPN_OK)
+            status = PARAPN_MAXITER;
+    }
+    if (status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
+    return status;
+}
+
 extern "C" {
 
 const char *parapn_last_error(void) { return g_err.c_str(); }
@@ -617,6 +819,10 @@ int parapn_workspace_size(const parapn_problem *p, size_t *bytes)
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
+    if (p->field == parapn::F_MOL) {
+        *bytes = dense_layout(p->precision == PARAPN_FP64, D, p->N, 1, true).total;
+        return PARAPN_OK;
+    }
     std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
     r[0].N = p->N;
     const size_t resident = align_up(((size_t)(p->N + 1) * D + 2 * D) * 8);
@@ -639,6 +845,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     const int esz = fp64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stream;
     PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (p->field == parapn::F_MOL) return dense_solve(ctx, p, 1, p->y0, mean_out, sqrtcov_out, info, s);
     Solve sv;
     rc = prepare(p, sv);
     if (rc) return rc;
@@ -714,6 +921,40 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     }
     if (sv.status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
     return sv.status;
+}
+
+int parapn_solve_batch(parapn_ctx *ctx, const parapn_problem *p, int32_t batch, const double *y0s, void *mean_out,
+                       void *sqrtcov_out, parapn_info *info, void *stream)
+{
+    if (!ctx) return fail(PARAPN_EINVAL, "ctx is NULL");
+    int q, D;
+    int rc = check_problem(p, &q, &D);
+    if (rc) return rc;
+    if (batch < 1) return fail(PARAPN_EINVAL, "batch must be >= 1");
+    if (!y0s) return fail(PARAPN_EINVAL, "y0s is NULL");
+    if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
+    for (size_t i = 0; i < (size_t)batch * p->d; ++i)
+        if (!std::isfinite(y0s[i])) return fail(PARAPN_EINVAL, "y0s is not finite");
+    hipStream_t s = (hipStream_t)stream;
+    PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (p->field == parapn::F_MOL) return dense_solve(ctx, p, batch, y0s, mean_out, sqrtcov_out, info, s);
+    // row-per-lane fields: one solve after another
+    const size_t esz = p->precision == PARAPN_FP64 ? 8 : 4;
+    const size_t mstride = (size_t)(p->N + 1) * D * esz, cstride = mstride * D;
+    int status = PARAPN_OK;
+    for (int b = 0; b < batch; ++b) {
+        parapn_problem pb = *p;
+        pb.y0 = y0s + (size_t)b * p->d;
+        rc = parapn_solve(ctx, &pb, (char *)mean_out + b * mstride,
+                          sqrtcov_out ? (char *)sqrtcov_out + b * cstride : nullptr, info ? info + b : nullptr, stream);
+        if (rc < 0 && rc != PARAPN_ENONFINITE) return rc;
+        if (rc == PARAPN_ENONFINITE)
+            status = PARAPN_ENONFINITE;
+        else if (rc == PARAPN_MAXITER && status == PARAPN_OK)
+            status = PARAPN_MAXITER;
+    }
+    if (status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
+    return status;
 }
 
 int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
@@ -904,6 +1145,7 @@ int parapn_server_footprint(const parapn_problem *p, size_t *bytes)
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
+    if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the server does not batch the method-of-lines field");
     Solve sv;
     rc = prepare(p, sv);
     if (rc) return rc;
@@ -930,6 +1172,7 @@ int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t r
     if (rc) return rc;
     if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
     if (p->init_traj) return fail(PARAPN_EINVAL, "served requests start from the constant trajectory");
+    if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the server does not batch the method-of-lines field");
     ServedReq *r = new ServedReq{};
     r->id = req_id;
     rc = prepare(p, r->sv);

@@ -13,6 +13,11 @@ Problems:
                   (alpha, beta, gamma, delta ~ U[0.5, 1.5], y0 ~ U[0.5, 2]^2),
                   q ~ U{2, 3, 4}, N log-uniform in [256, 65536].
 
+  mol(d, ...)  -- method of lines for the heat/reaction chain u_t = nu u_xx + u(1-u)
+                  on d periodic grid points, nu = 0.01, IWP(2) (D = 3d), N = 4096,
+                  t in [0, 1]; mol_batch(B) gives B seeded initial profiles
+                  u0 = 0.5 + 0.1 sin(2 pi x_i) + N(0, 0.01^2) noise (seed = instance).
+
 reference_start(spec) gives a starting trajectory near a problem's solution
 (a classical Runge-Kutta solution from scipy, an input like any other).
 """
@@ -59,6 +64,22 @@ def served_stream(n_requests=4096, seed=0):
             p = lotka_volterra(rng, N, q)
         out.append(p)
     return out
+
+
+def mol_initial(d, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(d) / d
+    return 0.5 + 0.1 * np.sin(2 * np.pi * x) + rng.normal(0.0, 0.01, size=d)
+
+
+def mol(d=64, N=4096, q=2, nu=0.01, seed=0, t1=1.0):
+    return dict(name="mol_heat_reaction", field="mol_heat_reaction", params=[nu], y0=list(mol_initial(d, seed)),
+                t0=0.0, t1=t1, q=q, N=int(N))
+
+
+def mol_batch(B=16, d=64, N=4096, q=2, nu=0.01, t1=1.0):
+    """(spec, y0s [B, d]): instances b = 0..B-1 use seed b."""
+    return mol(d, N, q, nu, 0, t1), np.stack([mol_initial(d, b) for b in range(B)])
 
 
 def random_observations(rng, N, d, q, scale=0.3):

@@ -1,0 +1,138 @@
+"""Dense engine (method-of-lines field, D = d(q+1) up to 192): parity of the
+GPU solve with the oracle's sequential square-root filter and RTS smoother
+(Alg. 2 with the same start, the same iterations and the same stopping
+rule).
+
+Tolerances (as for the row-per-lane engine's solves): FP64 E0 means and
+covariances 1e-9 relative (to the largest entry), FP32 E0 means 1e-4
+relative.  The derivative components of an iterated solve are compared
+through the covariances and the E0 means they produce.  Covariances are
+compared as Sigma = L L^T (the factor's column signs are not unique).  Shapes
+cover one 16-wide tile and a ragged tail (D = 10, 15, 24, 48, 192), N = 1, 2, 3 and ragged N, and the
+batch entry point (every instance bitwise equal to its solve alone).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_01145_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+
+    import paper_2310_01145_amd as m
+
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+def np_(t):
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def sigma(L):
+    L = np.asarray(L, dtype=np.float64)
+    return L @ np.swapaxes(L, -1, -2)
+
+
+def same(a, b):
+    import torch
+
+    iv = {4: torch.int32, 8: torch.int64}
+    return a.shape == b.shape and torch.equal(a.view(iv[a.element_size()]), b.view(iv[b.element_size()]))
+
+
+def spec_args(sp):
+    return (sp["field"], sp["params"], sp["y0"], sp["t0"], sp["t1"], sp["q"], sp["N"])
+
+
+FP64_CASES = [
+    # d, q, N, fixed iterations
+    (8, 2, 50, 3),    # D = 24: a full tile and a ragged one
+    (3, 4, 37, 3),    # D = 15: one ragged tile
+    (5, 1, 64, 2),    # D = 10
+    (16, 2, 33, 2),   # D = 48
+    (8, 3, 1, 2),     # one step
+    (8, 2, 2, 2),
+    (6, 2, 3, 2),
+]
+
+
+@pytest.mark.parametrize("d,q,N,k", FP64_CASES)
+def test_dense_fp64_matches_oracle(pp, d, q, N, k):
+    sp = workloads.mol(d=d, N=N, q=q, seed=d + N, t1=0.25)
+    ref = oracle.ieks(*spec_args(sp), fixed_iters=k, want_cov=True)
+    print("dense fp64 d=%d q=%d N=%d k=%d" % (d, q, N, k), flush=True)
+    out = pp.solve(*spec_args(sp), precision="fp64", fixed_iters=k, want_cov=True)
+    assert out["status"] == pp.OK and out["iterations"] == k
+    S = q + 1
+    assert rel(np_(out["mean"])[:, ::S], ref["mean"][:, ::S]) < 1e-9
+    assert rel(sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+    np.testing.assert_allclose(out["deltas"], ref["deltas"], rtol=1e-6,
+                               atol=1e-9 * np.abs(ref["mean"][:, ::S]).max())
+
+
+def test_dense_fp64_converges_like_the_oracle(pp):
+    sp = workloads.mol(d=8, N=200, q=2, seed=3)
+    ref = oracle.ieks(*spec_args(sp), tol=1e-10, max_iter=20)
+    out = pp.solve(*spec_args(sp), precision="fp64", tol=1e-10, max_iter=20)
+    assert ref["status"] == 0 and out["status"] == pp.OK
+    assert out["iterations"] == ref["iterations"]
+    assert rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-9
+
+
+def test_dense_fp32_matches_oracle(pp):
+    sp = workloads.mol(d=16, N=100, q=2, seed=5)
+    ref = oracle.ieks(*spec_args(sp), tol=1e-10, max_iter=20)
+    out = pp.solve(*spec_args(sp), precision="fp32", tol=1e-10, max_iter=20)
+    assert out["status"] == pp.OK
+    assert rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_dense_d64_matches_oracle(pp, prec, tol):
+    """The benchmark's state size: d = 64 grid points, q = 2, D = 192."""
+    sp = workloads.mol(d=64, N=12, q=2, seed=7, t1=12.0 / 4096)
+    ref = oracle.ieks(*spec_args(sp), fixed_iters=2, want_cov=True)
+    print("dense d=64 %s" % prec, flush=True)
+    out = pp.solve(*spec_args(sp), precision=prec, fixed_iters=2, want_cov=True)
+    assert out["status"] == pp.OK
+    assert rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3]) < tol
+    if prec == "fp64":
+        assert rel(sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+    else:
+        S, R = sigma(np_(out["sqrtcov"]))[:, ::3, ::3], sigma(ref["sqrtcov"])[:, ::3, ::3]
+        assert rel(S, R) < 1e-2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_batch_equals_alone(pp, prec):
+    sp, y0s = workloads.mol_batch(B=3, d=8, N=40, q=2, t1=0.5)
+    out = pp.solve_batch(sp["field"], sp["params"], y0s, sp["t0"], sp["t1"], sp["q"], sp["N"], precision=prec,
+                         tol=1e-10, max_iter=20, want_cov=True)
+    for b in range(3):
+        a = pp.solve(sp["field"], sp["params"], y0s[b], sp["t0"], sp["t1"], sp["q"], sp["N"], precision=prec,
+                     tol=1e-10, max_iter=20, want_cov=True)
+        assert out["iterations"][b] == a["iterations"]
+        assert same(out["mean"][b], a["mean"]), b
+        assert same(out["sqrtcov"][b], a["sqrtcov"]), b
+
+
+def test_batch_of_row_per_lane_field(pp):
+    y0s = np.array([[0.01], [0.02], [0.05]])
+    out = pp.solve_batch("logistic", [], y0s, 0.0, 10.0, 2, 300, precision="fp64", fixed_iters=4)
+    for b in range(3):
+        a = pp.solve("logistic", [], y0s[b], 0.0, 10.0, 2, 300, precision="fp64", fixed_iters=4)
+        assert same(out["mean"][b], a["mean"])
