@@ -235,6 +235,69 @@ def cpu_baseline(wl_full, start, k=10):
                       "thread, %.1f s" % (N, r["iterations"], el)}
 
 
+def mol_batch_run(pp, torch, prec, B=16, max_iter=20):
+    """Method-of-lines batch (d=64, q=2, D=192, N=4096, B seeded instances)
+    on the dense engine: one batched solve to convergence, every kernel timed
+    by events (a few dozen launches per iteration, each milliseconds long)."""
+    from paper_2310_01145_amd import costmodel, workloads
+
+    sp, y0s = workloads.mol_batch(B=B)
+    d, q, N = len(sp["y0"]), sp["q"], sp["N"]
+    D = d * (q + 1)
+    # warm-up: a short batch loads the kernels
+    pp.solve_batch(sp["field"], sp["params"], y0s[:2], sp["t0"], sp["t1"], q, 64, precision=prec, fixed_iters=1)
+    torch.cuda.synchronize()
+    pp.profile_enable(True)
+    t = time.perf_counter()
+    r = pp.solve_batch(sp["field"], sp["params"], y0s, sp["t0"], sp["t1"], q, N, precision=prec, tol=1e-10,
+                       max_iter=max_iter)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    prof = pp.profile_read()
+    pp.profile_enable(False)
+    its = r["iterations"]
+    per = costmodel.dense_iteration_flops(D, d, q, N, 1)
+    flops = {k: v * float(sum(its)) for k, v in per.items()}
+    name = max(prof, key=lambda k: prof[k][0])
+    peak = PEAK["f32" if prec == "fp32" else "f64"]
+    kern = {}
+    for k, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        kern[k] = {"total_ms": ms, "launches": n,
+                   "TFLOPs": (flops[k] / (ms * 1e-3) / 1e12) if k in flops and ms > 0 else None}
+    achieved = flops[name] / (prof[name][0] * 1e-3)
+    total_flops = sum(flops.values())
+    return r, {
+        "value": N * float(sum(its)) / el,
+        "ms_per_solve": 1e3 * el,
+        "status": r["status"],
+        "iterations": its,
+        "roofline": {"kernel": name, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "avg_launch_us": prof[name][0] * 1e3 / prof[name][1], "launches": prof[name][1]},
+        "whole_solve_TFLOPs": total_flops / el / 1e12,
+        "whole_solve_frac": total_flops / el / peak,
+        "kernels": kern,
+    }
+
+
+def mol_cpu_baseline(steps=96):
+    """The oracle on a bounded sample of the method-of-lines workload: one
+    instance, its first `steps` steps (same h), two iterations."""
+    import oracle
+
+    from paper_2310_01145_amd import workloads
+
+    sp = workloads.mol(N=4096)
+    t1 = sp["t1"] * steps / sp["N"]
+    t = time.perf_counter()
+    r = oracle.ieks(sp["field"], sp["params"], sp["y0"], sp["t0"], t1, sp["q"], steps, fixed_iters=2,
+                    want_cov=False)
+    el = time.perf_counter() - t
+    return {"value": steps * r["iterations"] / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": "one method-of-lines instance (d=64, D=192), its first %d steps at the same h, 2 iterations, "
+                      "FP64, single thread, %.1f s" % (steps, el)}
+
+
 def copy_probe(torch, mib):
     """One plain device-to-device copy of mib MiB (read mib, write mib): the
     reference that scales the HBM byte counters of a profiling run."""
@@ -260,6 +323,8 @@ def main():
     ap.add_argument("--no-lorenz", action="store_true", help="skip the Lorenz-63 (D=15) measurement")
     ap.add_argument("--no-constant-start", action="store_true", help="skip the constant-start report")
     ap.add_argument("--no-extras", action="store_true", help="skip the logistic latency and the N sweep")
+    ap.add_argument("--no-mol", action="store_true", help="skip the method-of-lines batch (dense engine, D=192)")
+    ap.add_argument("--no-mol-fp64", action="store_true", help="method-of-lines batch in FP32 only")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -331,9 +396,10 @@ def main():
         lw = lorenz_workload(args.N, args.iters)
         cold = pp.solve(lw["field"], lw["params"], lw["y0"], lw["t0"], lw["t1"], lw["q"], lw["N"], precision="fp32",
                         max_iter=3)
-        start = torch.tensor(workloads.reference_start(lw), dtype=torch.float64, device="cuda")
-        l32 = run_gpu(pp, torch, lw, "fp32", args.steps, args.warmup, False, d=3, init_traj=start)
-        l64 = run_gpu(pp, torch, lw, "fp64", max(1, args.steps // 2), 1, False, d=3, init_traj=start)
+        lstart = torch.tensor(workloads.reference_start(lw), dtype=torch.float64, device="cuda")
+        l32 = run_gpu(pp, torch, lw, "fp32", args.steps, args.warmup, False, d=3, init_traj=lstart)
+        l64 = run_gpu(pp, torch, lw, "fp64", max(1, args.steps // 2), 1, False, d=3, init_traj=lstart)
+        del lstart
         print("bench: lorenz done %.3f / %.3f ms/solve" % (l32["ms_per_step"], l64["ms_per_step"]), file=sys.stderr,
               flush=True)
         line["lorenz"] = {
@@ -350,6 +416,26 @@ def main():
         line["logistic_c0"] = logistic_latency(pp, torch)
         line["fhn_n_sweep"] = n_sweep(pp, torch, args.iters)
         print("bench: extras done", file=sys.stderr, flush=True)
+    if not args.no_mol:
+        m32r, m32 = mol_batch_run(pp, torch, "fp32")
+        print("bench: mol fp32 done %.1f ms/solve" % m32["ms_per_solve"], file=sys.stderr, flush=True)
+        line["mol_batch"] = {
+            "workload": "method of lines u_t = 0.01 u_xx + u(1-u), d=64 periodic points, IWP(2) D=192, N=4096, "
+                        "t in [0,1], 16 seeded initial profiles in one batched solve, constant start, "
+                        "to tol 1e-10 (at most 20 iterations)",
+            "fp32": m32,
+        }
+        if not args.no_mol_fp64:
+            m64r, m64 = mol_batch_run(pp, torch, "fp64")
+            print("bench: mol fp64 done %.1f ms/solve" % m64["ms_per_solve"], file=sys.stderr, flush=True)
+            a = m32r["mean"][:, :, ::3].double()
+            b = m64r["mean"][:, :, ::3]
+            line["mol_batch"]["fp64"] = m64
+            line["mol_batch"]["fp32_vs_fp64_e0_relerr"] = float((a - b).abs().max() / b.abs().max())
+            del m64r, a, b
+        del m32r
+        if not args.no_cpu_baseline:
+            line["mol_batch"]["cpu_baseline"] = mol_cpu_baseline()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(wl, start)
         cb["cores"] = 1

@@ -107,12 +107,27 @@ __device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool 
     for (int t = wv; t < tm * tn; t += NW) {
         const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
         const int ia = i0 + li, jb = j0 + li;
+        const bool rok = ia < m, cok = jb < n;
         typename MF<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-        for (int p0 = 0; p0 < k; p0 += 4) {
+        // 16 values of k per step, all loads issued before the four MFMAs;
+        // lane group g takes k = p0 + 4g + u in MFMA u (the same k for A and B)
+        int p0 = 0;
+        for (; p0 + 16 <= k; p0 += 16) {
+            T a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int p = p0 + 4 * lg + u;
+                a[u] = rok ? (ta ? A[(size_t)p * lda + ia] : A[(size_t)ia * lda + p]) : T(0);
+                b[u] = cok ? (tb ? B[(size_t)jb * ldb + p] : B[(size_t)p * ldb + jb]) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = MF<T>::mma(a[u], b[u], acc);
+        }
+        for (; p0 < k; p0 += 4) {
             const int p = p0 + lg;
             T a = T(0), b = T(0);
-            if (ia < m && p < k) a = ta ? A[(size_t)p * lda + ia] : A[(size_t)ia * lda + p];
-            if (jb < n && p < k) b = tb ? B[(size_t)jb * ldb + p] : B[(size_t)p * ldb + jb];
+            if (rok && p < k) a = ta ? A[(size_t)p * lda + ia] : A[(size_t)ia * lda + p];
+            if (cok && p < k) b = tb ? B[(size_t)jb * ldb + p] : B[(size_t)p * ldb + jb];
             acc = MF<T>::mma(a, b, acc);
         }
 #pragma unroll
@@ -264,12 +279,18 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
             const int ra = r0 + li;
             const T *mrow = M + (size_t)ra * ld + k0;
             typename MF<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-            for (int c0 = 0; c0 < w; c0 += 4) {
-                const int c = c0 + lg;
-                const T a = (ra < m && c < w) ? mrow[c] : T(0);
-                T b = T(0);
-                if (li < nb && c < w) b = c < li ? T(0) : (c == li ? T(1) : P[li * w + c]);
-                acc = MF<T>::mma(a, b, acc);
+            const bool rok = ra < m;
+            for (int c0 = 0; c0 < w; c0 += 16) {
+                T a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + 4 * lg + u;
+                    a[u] = (rok && c < w) ? mrow[c] : T(0);
+                    b[u] = T(0);
+                    if (li < nb && c < w) b[u] = c < li ? T(0) : (c == li ? T(1) : P[li * w + c]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = MF<T>::mma(a[u], b[u], acc);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Wl[MF<T>::row(lg, v) * 16 + li] = acc[v];
@@ -286,13 +307,22 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
 #pragma unroll
             for (int v = 0; v < 4; ++v) Wl[MF<T>::row(lg, v) * 16 + li] = -wt[v];
             wave_sync();
+            typename MF<T>::v4 nx;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + MF<T>::row(lg, v);
+                nx[v] = (r < m && li < w) ? M[(size_t)r * ld + k0 + li] : T(0);
+            }
             for (int c0 = 0; c0 < w; c0 += 16) {
                 const int c = c0 + li;
-                typename MF<T>::v4 cc;
+                typename MF<T>::v4 cc = nx;
+                // the next tile's loads are in flight during this tile's MFMAs
+                if (c0 + 16 < w) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = r0 + MF<T>::row(lg, v);
-                    cc[v] = (r < m && c < w) ? M[(size_t)r * ld + k0 + c] : T(0);
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = r0 + MF<T>::row(lg, v);
+                        nx[v] = (r < m && c + 16 < w) ? M[(size_t)r * ld + k0 + c + 16] : T(0);
+                    }
                 }
 #pragma unroll
                 for (int l0 = 0; l0 < 16; l0 += 4) {
