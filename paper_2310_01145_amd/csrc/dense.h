@@ -41,6 +41,8 @@ struct DenseWork {
 };
 
 size_t dense_scratch_elems(int D);
+// workgroups per launch (and scratch slots) of the precision's kernels
+int dense_workgroups(int fp64);
 // one Gauss-Newton iteration: linearise, both scans, trajectory update, delta
 hipError_t dense_iteration(int fp64, const DenseModel &m, const DenseWork &w, hipStream_t s);
 // smoothed factors at the last linearisation (filtering marginals still in

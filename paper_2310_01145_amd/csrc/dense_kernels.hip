@@ -43,8 +43,13 @@
 namespace parapn {
 namespace dense {
 
-constexpr int NT = 256;  // threads per workgroup
-constexpr int NW = NT / 64;
+// Threads per workgroup: FP32 workgroups are two wavefronts (four fit a
+// compute unit, 30 KB of LDS each at D = 192); FP64 ones need twice the LDS,
+// so two per compute unit of four wavefronts each.  Per-element work is
+// largely sequential (panel factorisations, row solves), so the number of
+// elements in flight sets the throughput.
+template <typename T>
+__host__ __device__ constexpr int nt_of() { return sizeof(T) == 4 ? 128 : 256; }
 constexpr int NB = 16;   // reflectors per panel
 
 template <typename T>
@@ -102,6 +107,8 @@ template <typename T>
 __device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool ta, const T *B, int ldb, bool tb,
                         T beta, T *C, int ldc)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
     const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
     for (int t = wv; t < tm * tn; t += NW) {
@@ -148,6 +155,8 @@ __device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool 
 template <typename T>
 __device__ void wg_gemv(int m, int k, T alpha, const T *A, int lda, bool ta, const T *x, T beta, T *y)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     for (int i = threadIdx.x; i < m; i += NT) {
         T s = T(0);
         if (ta)
@@ -163,6 +172,8 @@ __device__ void wg_gemv(int m, int k, T alpha, const T *A, int lda, bool ta, con
 template <typename T>
 __device__ void wg_copy(T *dst, int ldd, const T *src, int ldsrc, int m, int n)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     for (int e = threadIdx.x; e < m * n; e += NT) {
         const int i = e / n, j = e - i * n;
         dst[(size_t)i * ldd + j] = src ? src[(size_t)i * ldsrc + j] : T(0);
@@ -173,6 +184,8 @@ __device__ void wg_copy(T *dst, int ldd, const T *src, int ldsrc, int m, int n)
 template <typename T>
 __device__ void wg_vcopy(T *dst, const T *src, int n)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     for (int i = threadIdx.x; i < n; i += NT) dst[i] = src ? src[i] : T(0);
     __syncthreads();
 }
@@ -247,7 +260,8 @@ __device__ void panel_factor(T *P, int nb, int w, T *Tm, T *Z, T *tau)
 }
 
 // LDS elements the workgroup primitives need for operands up to nmax columns
-__host__ __device__ constexpr int smem_elems(int nmax) { return NB * nmax + 2 * NB * NB + NB + NW * 256; }
+template <typename T>
+__host__ __device__ constexpr int smem_elems(int nmax) { return NB * nmax + 2 * NB * NB + NB + (nt_of<T>() / 64) * 256; }
 
 // tria in place: the m x n matrix M (row stride ld) becomes the lower-
 // trapezoidal L (columns >= min(m, n) zero) with L L^T = M M^T, M = L Q.
@@ -255,6 +269,8 @@ __host__ __device__ constexpr int smem_elems(int nmax) { return NB * nmax + 2 * 
 template <typename T>
 __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     T *P = sm;
     T *Tm = P + NB * n;
     T *Z = Tm + NB * NB;
@@ -355,6 +371,8 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
 template <typename T, bool TRANS>
 __device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     const int nblk = (k + 15) >> 4;
     for (int bi = 0; bi < nblk; ++bi) {
         const int jb = TRANS ? bi : nblk - 1 - bi;
@@ -393,6 +411,8 @@ __device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
 template <typename T>
 __device__ void wg_lower_solve_vec(const T *L, int ldl, int k, const T *v, T *z, T *sm)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     for (int i = threadIdx.x; i < k; i += NT) sm[i] = v[i];
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -452,8 +472,10 @@ __device__ __forceinline__ bool inactive(const DenseWork &w, int b) { return w.a
 
 // linearisation (EK1, Sec. 3.2.1) and the filtering element of every step
 template <typename T>
-__global__ __launch_bounds__(NT) void k_elements(DenseModel md, DenseWork w)
+__global__ __launch_bounds__(nt_of<T>()) void k_elements(DenseModel md, DenseWork w)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     Views<T> V(w);
@@ -564,6 +586,8 @@ template <typename T>
 __device__ void fcombine_pair(const DenseModel &md, Views<T> &V, int64_t li_, int64_t ri_, bool state, T *scr,
                               T *sm)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     const int D = md.D, D2 = 2 * D;
     const size_t DD = (size_t)D * D;
     const T *Ai = V.A + li_ * DD, *bi = V.b + li_ * D, *Ci = V.C + li_ * DD, *ei = V.e + li_ * D,
@@ -640,8 +664,10 @@ __device__ void fcombine_pair(const DenseModel &md, Views<T> &V, int64_t li_, in
 // r = 2s(p + 1) - 1 (pair 0's left operand starts at step 1: a state);
 // down: r = 2s(p + 1) + s - 1, whose left operand is a complete prefix.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_fcombine(DenseModel md, DenseWork w, int64_t s, int up, int64_t npairs)
+__global__ __launch_bounds__(nt_of<T>()) void k_fcombine(DenseModel md, DenseWork w, int64_t s, int up, int64_t npairs)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     Views<T> V(w);
@@ -660,8 +686,10 @@ __global__ __launch_bounds__(NT) void k_fcombine(DenseModel md, DenseWork w, int
 // smoothing element of every step from its filtering marginal (m, sqrtP) in
 // (b, C); with_L also stores sqrtL.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_selements(DenseModel md, DenseWork w, int with_L)
+__global__ __launch_bounds__(nt_of<T>()) void k_selements(DenseModel md, DenseWork w, int with_L)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     Views<T> V(w);
@@ -731,9 +759,11 @@ __global__ __launch_bounds__(NT) void k_selements(DenseModel md, DenseWork w, in
 // position x is step index N-1-x.  The earlier element of a pair absorbs the
 // later one; state: the later operand contains the last step (E = 0).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bcombine(DenseModel md, DenseWork w, int64_t s, int up, int64_t npairs,
+__global__ __launch_bounds__(nt_of<T>()) void k_bcombine(DenseModel md, DenseWork w, int64_t s, int up, int64_t npairs,
                                                  int with_L)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = (T *)smem_raw;
     Views<T> V(w);
@@ -775,8 +805,10 @@ __device__ __forceinline__ double nan_max(double x, double u) { return (u > x ||
 // trajectory update eta += delta (FP64) and the two maxima of the stopping
 // test, per instance: blockIdx.y = instance
 template <typename T>
-__global__ __launch_bounds__(NT) void k_update(DenseModel md, DenseWork w)
+__global__ __launch_bounds__(nt_of<T>()) void k_update(DenseModel md, DenseWork w)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     const int b = blockIdx.y;
     if (inactive(w, b)) return;
     const int D = md.D, S = md.q + 1;
@@ -842,7 +874,7 @@ __global__ void k_cov_out(DenseModel md, DenseWork w, T *cov)
 template <typename T>
 size_t smem_bytes(int D)
 {
-    return (size_t)smem_elems(2 * D) * sizeof(T);
+    return (size_t)smem_elems<T>(2 * D) * sizeof(T);
 }
 
 template <typename K>
@@ -868,6 +900,8 @@ hipError_t set_smem(int D)
 template <typename T>
 hipError_t smoother_scan(const DenseModel &md, const DenseWork &w, int with_L, hipStream_t st)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     const size_t sh = smem_bytes<T>(md.D);
     const int64_t N = md.N;
     int64_t smax = 0;
@@ -889,6 +923,8 @@ hipError_t smoother_scan(const DenseModel &md, const DenseWork &w, int with_L, h
 template <typename T>
 hipError_t iteration_t(const DenseModel &md, const DenseWork &w, hipStream_t st)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     hipError_t e = set_smem<T>(md.D);
     if (e != hipSuccess) return e;
     const size_t sh = smem_bytes<T>(md.D);
@@ -918,6 +954,8 @@ hipError_t iteration_t(const DenseModel &md, const DenseWork &w, hipStream_t st)
 template <typename T>
 hipError_t covariance_t(const DenseModel &md, const DenseWork &w, void *cov_out, hipStream_t st)
 {
+    constexpr int NT = nt_of<T>(), NW = NT / 64;
+    (void)NW;
     hipError_t e = set_smem<T>(md.D);
     if (e != hipSuccess) return e;
     const size_t sh = smem_bytes<T>(md.D);
@@ -934,6 +972,10 @@ hipError_t covariance_t(const DenseModel &md, const DenseWork &w, void *cov_out,
 }  // namespace dense
 
 size_t dense_scratch_elems(int D) { return dense::dense_scratch_elems_dev(D); }
+
+// as many as the compute units hold at once (256 CUs: four FP32 or two FP64
+// workgroups each, limited by LDS at D = 192)
+int dense_workgroups(int fp64) { return fp64 ? 512 : 1024; }
 
 hipError_t dense_iteration(int fp64, const DenseModel &m, const DenseWork &w, hipStream_t s)
 {

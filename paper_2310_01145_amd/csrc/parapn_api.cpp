@@ -616,7 +616,6 @@ static int init_resident(const Solve &sv, double *buf, const double *init_traj, 
 // ---------------------------------------------------------------------------
 // dense engine (method-of-lines field): B instances of one problem
 // ---------------------------------------------------------------------------
-constexpr int kDenseWorkgroups = 512;  // two per compute unit; each owns a scratch slot
 
 static int64_t dense_traj_stride(int D, int64_t N) { return ((N + 1) * D + 2 * D + 31) & ~int64_t(31); }
 
@@ -645,7 +644,7 @@ static DenseLayout dense_layout(bool fp64, int D, int64_t N, int B, bool cov)
     L.e = take(el * D * esz);
     L.g = take(el * D * esz);
     L.L = cov ? take(el * DD * esz) : 0;
-    L.scratch = take((size_t)kDenseWorkgroups * parapn::dense_scratch_elems(D) * esz);
+    L.scratch = take((size_t)parapn::dense_workgroups(fp64) * parapn::dense_scratch_elems(D) * esz);
     L.total = off;
     return L;
 }
@@ -721,7 +720,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     w.dbits = (unsigned long long *)(ws + L.dbits);
     int *active_dev = (int *)(ws + L.active);
     w.active = active_dev;
-    w.nwg = kDenseWorkgroups;
+    w.nwg = parapn::dense_workgroups(fp64);
     std::vector<Solve *> ptr(B);
     for (int b = 0; b < B; ++b) ptr[b] = &sv[b];
     std::vector<int> active(B, 1);
