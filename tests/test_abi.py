@@ -96,3 +96,36 @@ def test_server_host_validation():
     with pytest.raises(pp.ParapnError) as e:
         pp.server_footprint("logistic", [], [0.1], 0.0, 1.0, 2, 0)
     assert e.value.code == pp.EINVAL
+
+
+def test_dense_engine_host_checks():
+    """Method-of-lines problems (the dense engine): workspace sizing follows
+    the element layout (3 D^2 + 2 D filtering and 2 D^2 + D smoothing values
+    per step, plus the covariance factors) and the field's argument checks."""
+    import paper_2310_01145_amd as pp
+
+    pp.load_library()
+    y0 = [0.5] * 64
+    w32 = pp.workspace_size(pp.make_problem("mol_heat_reaction", [0.01], y0, 0.0, 1.0, 2, 4096, precision="fp32"))
+    w64 = pp.workspace_size(pp.make_problem("mol_heat_reaction", [0.01], y0, 0.0, 1.0, 2, 4096, precision="fp64"))
+    D, N = 192, 4096
+    per_step = 4 * (5 * D * D + 3 * D)  # FP32: A, C, J, E, L and b, e, g
+    assert per_step * N < w32 < per_step * N + (2 << 30)  # + scratch slots and the trajectory
+    # FP64 doubles the element arrays; the scratch slots take the same bytes
+    # in both precisions (half as many, twice the size) and the trajectory is
+    # FP64 in both
+    assert abs((w64 - w32) - per_step * N) < 4096
+    bad = [
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5, 0.5], 0.0, 1.0, 2, 10),              # d < 3
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 100, 0.0, 1.0, 2, 10),             # D = 300 > 256
+        pp.make_problem("mol_heat_reaction", [], [0.5] * 8, 0.0, 1.0, 2, 10),                   # no nu
+        pp.make_problem("mol_heat_reaction", [-1.0], [0.5] * 8, 0.0, 1.0, 2, 10),               # nu < 0
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, lm_sigma=0.1),  # damping
+    ]
+    for b in bad:
+        with pytest.raises(pp.ParapnError) as e:
+            pp.workspace_size(b)
+        assert e.value.code == pp.EINVAL
+    with pytest.raises(pp.ParapnError) as e:
+        pp.server_footprint("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, precision="fp32")
+    assert e.value.code == pp.EINVAL
