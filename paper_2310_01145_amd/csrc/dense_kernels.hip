@@ -51,6 +51,10 @@ namespace dense {
 template <typename T>
 __host__ __device__ constexpr int nt_of() { return sizeof(T) == 4 ? 128 : 256; }
 constexpr int NB = 16;   // reflectors per panel
+// MFMAs per batch of loads in the k loops (4 k-values each): 8 in FP32; 4 in
+// FP64, where more loads in flight would cost a wavefront per SIMD
+template <typename T>
+__host__ __device__ constexpr int kstep_of() { return sizeof(T) == 4 ? 8 : 4; }
 
 template <typename T>
 struct MF;
@@ -116,19 +120,20 @@ __device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool 
         const int ia = i0 + li, jb = j0 + li;
         const bool rok = ia < m, cok = jb < n;
         typename MF<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-        // 16 values of k per step, all loads issued before the four MFMAs;
-        // lane group g takes k = p0 + 4g + u in MFMA u (the same k for A and B)
+        // 4U values of k per step, all loads issued before the U MFMAs; lane
+        // group g takes k = p0 + U g + u in MFMA u (the same k for A and B)
+        constexpr int U = kstep_of<T>();
         int p0 = 0;
-        for (; p0 + 16 <= k; p0 += 16) {
-            T a[4], b[4];
+        for (; p0 + 4 * U <= k; p0 += 4 * U) {
+            T a[U], b[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int p = p0 + 4 * lg + u;
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + U * lg + u;
                 a[u] = rok ? (ta ? A[(size_t)p * lda + ia] : A[(size_t)ia * lda + p]) : T(0);
                 b[u] = cok ? (tb ? B[(size_t)jb * ldb + p] : B[(size_t)p * ldb + jb]) : T(0);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = MF<T>::mma(a[u], b[u], acc);
+            for (int u = 0; u < U; ++u) acc = MF<T>::mma(a[u], b[u], acc);
         }
         for (; p0 < k; p0 += 4) {
             const int p = p0 + lg;
@@ -296,17 +301,18 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
             const T *mrow = M + (size_t)ra * ld + k0;
             typename MF<T>::v4 acc = {T(0), T(0), T(0), T(0)};
             const bool rok = ra < m;
-            for (int c0 = 0; c0 < w; c0 += 16) {
-                T a[4], b[4];
+            constexpr int U = kstep_of<T>();
+            for (int c0 = 0; c0 < w; c0 += 4 * U) {
+                T a[U], b[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int c = c0 + 4 * lg + u;
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + U * lg + u;
                     a[u] = (rok && c < w) ? mrow[c] : T(0);
                     b[u] = T(0);
                     if (li < nb && c < w) b[u] = c < li ? T(0) : (c == li ? T(1) : P[li * w + c]);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc = MF<T>::mma(a[u], b[u], acc);
+                for (int u = 0; u < U; ++u) acc = MF<T>::mma(a[u], b[u], acc);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) Wl[MF<T>::row(lg, v) * 16 + li] = acc[v];
@@ -388,6 +394,23 @@ __device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
         const T *Lb = L + (size_t)j0 * ldl + j0;
         for (int r = threadIdx.x; r < m; r += NT) {
             T *xr = X + (size_t)r * ldx + j0;
+            if (sizeof(T) == 4 && TRANS && nbk == 16) {
+                // a full block of the forward solve in registers (FP32 only:
+                // in FP64 the block would push the combine kernel into spills)
+                T x[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) x[c] = xr[c];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    T s = x[j];
+#pragma unroll
+                    for (int c = 0; c < j; ++c) s -= x[c] * Lb[(size_t)j * ldl + c];
+                    x[j] = s / Lb[(size_t)j * ldl + j];
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c) xr[c] = x[c];
+                continue;
+            }
             if (TRANS) {
                 for (int j = 0; j < nbk; ++j) {
                     T s = xr[j];
