@@ -38,6 +38,10 @@ extern "C" {
 #define PARAPN_EDEVICE (-3)  /* HIP runtime error                                   */
 #define PARAPN_ENONFINITE (-4) /* NaN/Inf in the iterate; outputs hold the last one  */
 
+/* priors */
+#define PARAPN_PRIOR_IWP 0
+#define PARAPN_PRIOR_IOUP 1
+
 /* arithmetic of the path */
 #define PARAPN_FP64 0      /* every step in double                                  */
 #define PARAPN_FP32_SQRT 1 /* elements, scans and linearisation in float; the prior
@@ -108,6 +112,12 @@ typedef struct {
                               * conditioned at unstable iterates.  Factors
                               * (sqrtcov_out) then come from one more, undamped pass
                               * at the final iterate.  0: plain Alg. 2.             */
+    int32_t prior;           /* PARAPN_PRIOR_IWP (0, Sec. 2.1) or PARAPN_PRIOR_IOUP: the
+                              * q-th derivative an Ornstein-Uhlenbeck process
+                              * dX_q = -prior_theta X_q dt + dW (one of the alternative
+                              * Gauss-Markov priors of Sec. 2.1), discretised in FP64
+                              * on the host.  Served requests must use the IWP prior. */
+    double prior_theta;      /* IOUP rate, finite and >= 0 (0 gives the IWP)         */
 } parapn_problem;
 
 typedef struct {

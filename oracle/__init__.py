@@ -81,6 +81,11 @@ def lib():
         L.orc_ieks_lm.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, P, P, P,
                                   ctypes.POINTER(ctypes.c_int)]
         L.orc_ieks_lm.restype = i
+        L.orc_ieks_prior.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, i, dl, P, P, P,
+                                     ctypes.POINTER(ctypes.c_int)]
+        L.orc_ieks_prior.restype = i
+        L.orc_ioup.argtypes = [i, dl, dl, P, P]
+        L.orc_ioup.restype = None
         L.orc_filter_element.argtypes = [i, i, P, P, P, P, P, P, i, P, P, P, P, P]
         L.orc_filter_combine.argtypes = [i] + [P] * 15
         L.orc_smoother_element.argtypes = [i, P, P, P, P, i, P, P, P]
@@ -183,8 +188,19 @@ def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None):
     return mf, sPf, ms, sPs
 
 
+def ioup(q, theta, h):
+    """IOUP(q, theta) blocks Phi(h), Q(h) in original coordinates."""
+    S = q + 1
+    Phi, Q = np.zeros((S, S)), np.zeros((S, S))
+    lib().orc_ioup(q, float(theta), float(h), _p(Phi), _p(Q))
+    return Phi, Q
+
+
+PRIORS = {"iwp": 0, "ioup": 1}
+
+
 def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
-         want_cov=True, lm_sigma=0.0):
+         want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0):
     """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
     sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas.
     lm_sigma > 0: Levenberg-Marquardt damping, a pseudo-observation of each
@@ -202,9 +218,10 @@ def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fix
     hist = np.zeros(max(max_iter, fixed_iters, 1))
     iters = ctypes.c_int(0)
     init = _f64(init_traj) if init_traj is not None else None
-    rc = lib().orc_ieks_lm(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
-                           float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
-                           _p(mean), _p(cov) if cov is not None else None, _p(hist), ctypes.byref(iters))
+    rc = lib().orc_ieks_prior(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
+                              float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
+                              PRIORS[prior], float(theta), _p(mean), _p(cov) if cov is not None else None, _p(hist),
+                              ctypes.byref(iters))
     if rc == -1:
         raise ValueError("bad problem")
     k = iters.value

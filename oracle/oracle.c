@@ -416,6 +416,81 @@ void orc_iwp(int q, double h, double *Phi, double *Q)
         }
 }
 
+/* exp(A) for a small n x n matrix: scaling and squaring of the Taylor series */
+static void expm_taylor(int n, const double *A, double *E)
+{
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j) r += fabs(A[i * n + j]);
+        if (r > nrm) nrm = r;
+    }
+    int sq = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    double sc = ldexp(1.0, -sq);
+    double *term = dalloc(n * n), *tmp = dalloc(n * n);
+    for (int i = 0; i < n * n; ++i) {
+        E[i] = (i % (n + 1) == 0) ? 1.0 : 0.0;
+        term[i] = E[i];
+    }
+    for (int k = 1; k <= 24; ++k) {
+        /* term <- term * (sc A) / k */
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int l = 0; l < n; ++l) t += term[i * n + l] * A[l * n + j];
+                tmp[i * n + j] = t * sc / k;
+            }
+        for (int i = 0; i < n * n; ++i) {
+            term[i] = tmp[i];
+            E[i] += term[i];
+        }
+    }
+    for (int r = 0; r < sq; ++r) {
+        mm(n, n, n, E, 0, E, 0, tmp);
+        memcpy(E, tmp, sizeof(double) * n * n);
+    }
+    free(term);
+    free(tmp);
+}
+
+/* Integrated Ornstein-Uhlenbeck prior IOUP(q, theta) (the alternative priors
+ * of Sec. 2.1): derivatives 0..q with X_i' = X_{i+1} (i < q) and
+ * dX_q = -theta X_q dt + dW.  Drift F: F[i][i+1] = 1, F[q][q] = -theta.
+ * Phi = exp(F h); Q = int_0^h exp(F s) e_q e_q^T exp(F s)^T ds, by composite
+ * 5-point Gauss-Legendre quadrature over 64 panels (the integrand is smooth).
+ * theta = 0 is the integrated Wiener process. */
+void orc_ioup(int q, double theta, double h, double *Phi, double *Q)
+{
+    int S = q + 1;
+    double *F = dalloc(S * S), *A = dalloc(S * S), *E = dalloc(S * S);
+    memset(F, 0, sizeof(double) * S * S);
+    for (int i = 0; i < q; ++i) F[i * S + i + 1] = 1.0;
+    F[q * S + q] = -theta;
+    for (int i = 0; i < S * S; ++i) A[i] = F[i] * h;
+    expm_taylor(S, A, Phi);
+    static const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
+                                 0.9061798459386640};
+    static const double gw[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889, 0.4786286704993665,
+                                 0.2369268850561891};
+    const int panels = 64;
+    memset(Q, 0, sizeof(double) * S * S);
+    double ph = h / panels;
+    for (int p = 0; p < panels; ++p)
+        for (int g = 0; g < 5; ++g) {
+            double s = ph * (p + 0.5 + 0.5 * gx[g]);
+            for (int i = 0; i < S * S; ++i) A[i] = F[i] * s;
+            expm_taylor(S, A, E);
+            /* column q of exp(F s) */
+            for (int i = 0; i < S; ++i)
+                for (int j = 0; j < S; ++j) Q[i * S + j] += 0.5 * ph * gw[g] * E[i * S + q] * E[j * S + q];
+        }
+    free(F); free(A); free(E);
+}
+
 /* diagonal of the one-dimensional preconditioner T(h) */
 void orc_precond_diag(int q, double h, double *T)
 {
@@ -425,12 +500,16 @@ void orc_precond_diag(int q, double h, double *T)
 /* preconditioned full-state transition and process-noise square root:
  * Phibar = T^{-1} Phi T, Qbar = T^{-1} Q T^{-T}, sqrtQbar = chol(Qbar),
  * all D x D with D = d(q+1), block-diagonal (I_d (x) block). */
-static void precond_model(int d, int q, double h, double *PhiB, double *sQB, double *Tfull)
+static void precond_model_prior(int d, int q, double h, int prior, double theta, double *PhiB, double *sQB,
+                                double *Tfull)
 {
     int S = q + 1, D = d * S;
     double *Ph = dalloc(S * S), *Qh = dalloc(S * S), *T = dalloc(S);
     double *Pb = dalloc(S * S), *Qb = dalloc(S * S), *Lb = dalloc(S * S);
-    orc_iwp(q, h, Ph, Qh);
+    if (prior == 1)
+        orc_ioup(q, theta, h, Ph, Qh);
+    else
+        orc_iwp(q, h, Ph, Qh);
     orc_precond_diag(q, h, T);
     for (int i = 0; i < S; ++i)
         for (int j = 0; j < S; ++j) {
@@ -449,6 +528,11 @@ static void precond_model(int d, int q, double h, double *PhiB, double *sQB, dou
             }
         }
     free(Ph); free(Qh); free(T); free(Pb); free(Qb); free(Lb);
+}
+
+static void precond_model(int d, int q, double h, double *PhiB, double *sQB, double *Tfull)
+{
+    precond_model_prior(d, q, h, 0, 0.0, PhiB, sQB, Tfull);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -585,16 +669,18 @@ int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, con
  * damping of the Gauss-Newton step, which the paper leaves as future work;
  * the fixed point is unchanged).  When damped, the returned factors come
  * from one more, undamped linearise-and-smooth pass at the final iterate. */
-int orc_ieks_lm(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
-                int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
-                double lm_sigma, double *mean_out, double *sqrtcov_out, double *delta_hist, int *iters_out)
+/* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta). */
+int orc_ieks_prior(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+                   int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+                   double lm_sigma, int prior, double theta, double *mean_out, double *sqrtcov_out,
+                   double *delta_hist, int *iters_out)
 {
     int d = orc_field_dim(field, d_req, nparams);
     if (d < 1 || q < 1 || N < 1 || !(t1 > t0)) return -1;
     int S = q + 1, D = d * S;
     double h = (t1 - t0) / (double)N;
     double *PhiB = dalloc(D * D), *sQB = dalloc(D * D), *T = dalloc(D);
-    precond_model(d, q, h, PhiB, sQB, T);
+    precond_model_prior(d, q, h, prior, theta, PhiB, sQB, T);
     double *mu0 = dalloc(D), *mu0b = dalloc(D);
     orc_taylor_mu0(field, params, d, y0, q, mu0);
     for (int k = 0; k < D; ++k) mu0b[k] = mu0[k] / T[k];
@@ -880,6 +966,14 @@ void orc_smoother_combine(int D, const double *Ei, const double *gi, const doubl
     orc_tria(D, 2 * D, W, sL);
     free(t);
     free(W);
+}
+
+int orc_ieks_lm(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+                int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+                double lm_sigma, double *mean_out, double *sqrtcov_out, double *delta_hist, int *iters_out)
+{
+    return orc_ieks_prior(field, params, nparams, d_req, y0, t0, t1, q, N, max_iter, tol, fixed_iters, init_traj,
+                          lm_sigma, 0, 0.0, mean_out, sqrtcov_out, delta_hist, iters_out);
 }
 
 int orc_ieks(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,

@@ -30,6 +30,7 @@ FIELDS = {
 }
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
+PRIORS = {"iwp": 0, "ioup": 1}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
             "parapn_pararts",
             "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
@@ -61,6 +62,8 @@ class Problem(ctypes.Structure):
         ("init_traj", ctypes.POINTER(ctypes.c_double)),
         ("init_on_device", ctypes.c_int32),
         ("lm_sigma", ctypes.c_double),
+        ("prior", ctypes.c_int32),
+        ("prior_theta", ctypes.c_double),
     ]
 
 
@@ -187,7 +190,7 @@ def _dtype(precision):
 
 
 def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                 init_traj=None, d=None, lm_sigma=0.0):
+                 init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0):
     """Build the ctypes Problem (keeps the host arrays alive on the object)."""
     fid = FIELDS[field] if isinstance(field, str) else int(field)
     y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
@@ -206,6 +209,8 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.fixed_iters = int(fixed_iters)
     pb.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     pb.lm_sigma = float(lm_sigma)
+    pb.prior = PRIORS[prior] if isinstance(prior, str) else int(prior)
+    pb.prior_theta = float(theta)
     keep = [y0, prm]
     pb.init_on_device = 0
     if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
@@ -234,7 +239,8 @@ def workspace_size(problem: Problem) -> int:
 
 
 def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-          init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0):
+          init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0, prior="iwp",
+          theta=0.0):
     """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
     (original coordinates, torch tensor on the device), ``sqrtcov``
     [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
@@ -243,7 +249,7 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
     torch = _torch()
     L = load_library()
     pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                      fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma)
+                      fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta)
     D = pb.d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -264,7 +270,7 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
 
 
 def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                want_cov=False, device=0, stream=None):
+                want_cov=False, device=0, stream=None, prior="iwp", theta=0.0):
     """Alg. 2 for a batch of initial values ``y0s`` [B, d] of one problem
     (parapn_solve_batch).  Returns ``mean`` [B, N+1, D], ``sqrtcov``
     [B, N+1, D, D] or None, the overall ``status`` and per-instance
@@ -276,7 +282,7 @@ def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10
         raise ValueError("y0s must be [batch, d]")
     B, d = y0s.shape
     pb = make_problem(field, params, y0s[0], t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                      fixed_iters=fixed_iters, d=d)
+                      fixed_iters=fixed_iters, d=d, prior=prior, theta=theta)
     D = d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -380,10 +386,10 @@ class Server:
         self._pending = {}
 
     def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
-               fixed_iters=0, d=None, lm_sigma=0.0):
+               fixed_iters=0, d=None, lm_sigma=0.0, prior="iwp", theta=0.0):
         torch = _torch()
         pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                          fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma)
+                          fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta)
         D = pb.d * (pb.q + 1)
         mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=torch.device("cuda", self._device))
         _check(self._L.parapn_server_submit(self._h, ctypes.byref(pb), int(req_id), _dptr(mean)))

@@ -192,6 +192,95 @@ void precond_diag(int d, int q, double h, std::vector<double> &T)
         for (int i = 0; i < S; ++i) T[b * S + i] = std::sqrt(h) * std::pow(h, q - i) / fact(q - i);
 }
 
+// exp(A) for small n: scaling and squaring of the Taylor series
+void expm_small(int n, const std::vector<double> &A, std::vector<double> &E)
+{
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j) r += std::fabs(A[i * n + j]);
+        nrm = std::max(nrm, r);
+    }
+    int sq = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = std::ldexp(1.0, -sq);
+    std::vector<double> term(n * n, 0.0), nxt(n * n);
+    E.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) E[i * n + i] = term[i * n + i] = 1.0;
+    for (int k = 1; k <= 24; ++k) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int l = 0; l < n; ++l) t += term[i * n + l] * A[l * n + j];
+                nxt[i * n + j] = t * sc / k;
+            }
+        term.swap(nxt);
+        for (int i = 0; i < n * n; ++i) E[i] += term[i];
+    }
+    for (int r = 0; r < sq; ++r) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int l = 0; l < n; ++l) t += E[i * n + l] * E[l * n + j];
+                nxt[i * n + j] = t;
+            }
+        E.swap(nxt);
+    }
+}
+
+// Preconditioned IOUP(q, theta) prior (the q-th derivative an Ornstein-
+// Uhlenbeck process, dX_q = -theta X_q dt + dW).  With T as above the drift
+// becomes h T^{-1} F T = Fb, Fb[i][i+1] = q - i, Fb[q][q] = -theta h, and the
+// noise enters as e_q e_q^T over unit time, so Van Loan's block exponential
+// exp([[-Fb, e_q e_q^T], [0, Fb^T]]) = [[., E12], [0, E22]] gives
+// Phibar = E22^T and Qbar = Phibar E12 without cancellation.  theta = 0
+// reproduces the binomial / Hilbert blocks of the integrated Wiener process.
+void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double> &Phi, std::vector<double> &sQ)
+{
+    const int S = q + 1, D = d * S, M = 2 * S;
+    std::vector<double> C(M * M, 0.0), E;
+    for (int i = 0; i < q; ++i) {
+        C[i * M + i + 1] = -(double)(q - i);
+        C[(S + i + 1) * M + S + i] = (double)(q - i);
+    }
+    C[q * M + q] = theta * h;
+    C[(S + q) * M + S + q] = -theta * h;
+    C[q * M + S + q] = 1.0;
+    expm_small(M, C, E);
+    std::vector<double> Pb(S * S), Qb(S * S, 0.0), Lb(S * S, 0.0);
+    for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) Pb[i * S + j] = E[(S + j) * M + S + i];
+    for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) {
+            double t = 0.0;
+            for (int l = 0; l < S; ++l) t += Pb[i * S + l] * E[l * M + S + j];
+            Qb[i * S + j] = t;
+        }
+    for (int i = 0; i < S; ++i)
+        for (int j = 0; j < i; ++j) Qb[i * S + j] = Qb[j * S + i] = 0.5 * (Qb[i * S + j] + Qb[j * S + i]);
+    for (int j = 0; j < S; ++j) {
+        double v = Qb[j * S + j];
+        for (int k = 0; k < j; ++k) v -= Lb[j * S + k] * Lb[j * S + k];
+        Lb[j * S + j] = std::sqrt(v);
+        for (int i = j + 1; i < S; ++i) {
+            double t = Qb[i * S + j];
+            for (int k = 0; k < j; ++k) t -= Lb[i * S + k] * Lb[j * S + k];
+            Lb[i * S + j] = t / Lb[j * S + j];
+        }
+    }
+    Phi.assign(D * D, 0.0);
+    sQ.assign(D * D, 0.0);
+    for (int b = 0; b < d; ++b)
+        for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j) {
+                Phi[(b * S + i) * D + b * S + j] = Pb[i * S + j];
+                sQ[(b * S + i) * D + b * S + j] = Lb[i * S + j];
+            }
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 
@@ -282,6 +371,8 @@ struct Solve {
     int64_t N;
     double t0, t1, h, tol;
     double lm_sigma, lm_s;  // damping (0: none) and its preconditioned per-step std
+    int prior;              // PARAPN_PRIOR_IWP or PARAPN_PRIOR_IOUP
+    double theta;           // IOUP rate
     int max_iter, fixed_iters;
     double params[PARAPN_MAX_PARAMS];
     std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
@@ -308,6 +399,8 @@ int prepare(const parapn_problem *p, Solve &sv)
     sv.max_iter = p->max_iter;
     sv.fixed_iters = p->fixed_iters;
     sv.lm_sigma = p->lm_sigma;
+    sv.prior = p->prior;
+    sv.theta = p->prior_theta;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
     precond_diag(sv.d, sv.q, sv.h, sv.Td);
     sv.mu0.assign(sv.D, 0.0);
@@ -320,6 +413,15 @@ int prepare(const parapn_problem *p, Solve &sv)
         sv.mu0b[k] = sv.mu0[k] / sv.Td[k];
     }
     return PARAPN_OK;
+}
+
+// the solve's preconditioned prior blocks for d components
+void prior_blocks_of(const Solve &sv, int d, std::vector<double> &Phi, std::vector<double> &sQ)
+{
+    if (sv.prior == PARAPN_PRIOR_IOUP)
+        prior_blocks_ioup(d, sv.q, sv.h, sv.theta, Phi, sQ);
+    else
+        prior_blocks(d, sv.q, Phi, sQ);
 }
 
 void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parapn::ReqDev &r)
@@ -340,11 +442,11 @@ void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parap
 // Upload the (precision, d, q) constants: Phi | sqrtQ | initial increment
 // state (0, 0) -- the scans run on the increment over a trajectory whose
 // row 0 is mu0 itself.
-int upload_consts(int d, int q, bool fp64, char *dst, hipStream_t s)
+int upload_consts(const Solve &sv, bool fp64, char *dst, hipStream_t s)
 {
-    const int D = d * (q + 1);
+    const int D = sv.d * (sv.q + 1);
     std::vector<double> Phi, sQ;
-    prior_blocks(d, q, Phi, sQ);
+    prior_blocks_of(sv, sv.d, Phi, sQ);
     std::vector<double> cst(3 * D * D + D, 0.0);
     for (int i = 0; i < D * D; ++i) {
         cst[i] = Phi[i];
@@ -471,6 +573,9 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
         return fail(PARAPN_EINVAL, "unknown precision");
     if (p->init_on_device != 0 && p->init_on_device != 1) return fail(PARAPN_EINVAL, "init_on_device must be 0 or 1");
     if (!(p->lm_sigma >= 0.0) || !std::isfinite(p->lm_sigma)) return fail(PARAPN_EINVAL, "lm_sigma must be finite and >= 0");
+    if (p->prior != PARAPN_PRIOR_IWP && p->prior != PARAPN_PRIOR_IOUP) return fail(PARAPN_EINVAL, "unknown prior");
+    if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
+        return fail(PARAPN_EINVAL, "prior_theta must be finite and >= 0");
     for (int i = 0; i < p->d; ++i)
         if (!std::isfinite(p->y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
     *q_out = p->q;
@@ -507,11 +612,14 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
     char *ws = (char *)ctx->ws;
     bind_plan(*pl, ws);
     const PackLayout &L = pl->L;
+    // IWP constants depend on (d, q, precision) only and are cached; IOUP
+    // ones also on h and theta and are uploaded every time
     const int ckey = (s0.d * 8 + s0.q) * 2 + (fp64 ? 1 : 0);
-    if (ctx->consts_at != ws + L.consts || ctx->consts_key != ckey) {
-        rc = upload_consts(s0.d, s0.q, fp64, ws + L.consts, s);
+    const bool cacheable = s0.prior == PARAPN_PRIOR_IWP;
+    if (!cacheable || ctx->consts_at != ws + L.consts || ctx->consts_key != ckey) {
+        rc = upload_consts(s0, fp64, ws + L.consts, s);
         if (rc) return rc;
-        ctx->consts_at = ws + L.consts;
+        ctx->consts_at = cacheable ? ws + L.consts : nullptr;
         ctx->consts_key = ckey;
     }
     if (ctx->reqs_at != ws + L.reqs || ctx->reqs_key != pl->image) {
@@ -697,7 +805,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     for (int i = 0; i < parapn::kMaxParams; ++i) md.p[i] = sv[0].params[i];
     {
         std::vector<double> Phi, sQ;
-        prior_blocks(1, p->q, Phi, sQ);
+        prior_blocks_of(sv[0], 1, Phi, sQ);
         const int S = p->q + 1;
         for (int i = 0; i < S; ++i)
             for (int j = 0; j < S; ++j) {
@@ -1145,6 +1253,7 @@ int parapn_server_footprint(const parapn_problem *p, size_t *bytes)
     if (rc) return rc;
     if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
     if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the server does not batch the method-of-lines field");
+    if (p->prior != PARAPN_PRIOR_IWP) return fail(PARAPN_EINVAL, "served requests use the IWP prior");
     Solve sv;
     rc = prepare(p, sv);
     if (rc) return rc;
@@ -1172,6 +1281,7 @@ int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t r
     if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
     if (p->init_traj) return fail(PARAPN_EINVAL, "served requests start from the constant trajectory");
     if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the server does not batch the method-of-lines field");
+    if (p->prior != PARAPN_PRIOR_IWP) return fail(PARAPN_EINVAL, "served requests use the IWP prior");
     ServedReq *r = new ServedReq{};
     r->id = req_id;
     rc = prepare(p, r->sv);

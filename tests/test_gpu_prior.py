@@ -1,0 +1,103 @@
+"""IOUP prior (the q-th derivative an Ornstein-Uhlenbeck process, one of the
+Gauss-Markov priors of Sec. 2.1): the GPU solves, whose host discretises the
+preconditioned prior by Van Loan's block exponential, against the oracle,
+which integrates the process noise by quadrature in original coordinates.
+Gates as for the IWP prior: FP64 E0 means and covariances 1e-9, FP32 E0 means
+1e-4.  A zero rate must reproduce the IWP solve."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+
+    import paper_2310_01145_amd as m
+
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+def np_(t):
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def sigma(L):
+    L = np.asarray(L, dtype=np.float64)
+    return L @ np.swapaxes(L, -1, -2)
+
+
+CASES = [
+    ("logistic", [], [0.01], 10.0, 2, 300, 1.0),
+    ("van_der_pol", [1.0], [2.0, 0.0], 6.3, 3, 200, 0.5),
+    ("rigid_body", [], [1.0, 0.0, 0.9], 20.0, 2, 150, 2.0),
+]
+
+
+@pytest.mark.parametrize("field,params,y0,t1,q,N,theta", CASES, ids=[c[0] for c in CASES])
+def test_ioup_solve_matches_oracle(pp, field, params, y0, t1, q, N, theta):
+    k = 5
+    ref = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=k, want_cov=True, prior="ioup", theta=theta)
+    S = q + 1
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        r = pp.solve(field, params, y0, 0.0, t1, q, N, precision=prec, fixed_iters=k, want_cov=True, prior="ioup",
+                     theta=theta)
+        assert r["status"] == pp.OK
+        assert rel(np_(r["mean"])[:, ::S], ref["mean"][:, ::S]) < tol, prec
+        if prec == "fp64":
+            assert rel(sigma(np_(r["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+
+
+def test_ioup_converges_like_the_oracle(pp):
+    ref = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 1000, tol=1e-10, max_iter=20, prior="ioup", theta=0.7)
+    r = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 1000, precision="fp64", tol=1e-10, max_iter=20, prior="ioup",
+                 theta=0.7)
+    assert ref["status"] == 0 and r["status"] == pp.OK and r["iterations"] == ref["iterations"]
+    assert rel(np_(r["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-9
+
+
+def test_ioup_with_zero_rate_is_the_iwp_solve(pp):
+    a = pp.solve("van_der_pol", [1.0], [2.0, 0.0], 0.0, 6.3, 3, 200, precision="fp64", fixed_iters=4, want_cov=True)
+    b = pp.solve("van_der_pol", [1.0], [2.0, 0.0], 0.0, 6.3, 3, 200, precision="fp64", fixed_iters=4, want_cov=True,
+                 prior="ioup", theta=0.0)
+    # the two discretisations (block exponential vs closed forms) differ by
+    # rounding only
+    assert rel(np_(b["mean"]), np_(a["mean"])) < 1e-10
+    assert rel(sigma(np_(b["sqrtcov"])), sigma(np_(a["sqrtcov"]))) < 1e-10
+
+
+def test_ioup_changes_the_solution(pp):
+    a = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 100, precision="fp64", fixed_iters=3, want_cov=True)
+    b = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 100, precision="fp64", fixed_iters=3, want_cov=True,
+                 prior="ioup", theta=5.0)
+    assert rel(sigma(np_(b["sqrtcov"])), sigma(np_(a["sqrtcov"]))) > 1e-3
+
+
+def test_ioup_on_the_dense_engine(pp):
+    y0 = 0.5 + 0.1 * np.sin(2 * np.pi * np.arange(8) / 8)
+    ref = oracle.ieks("mol_heat_reaction", [0.01], y0, 0.0, 0.25, 2, 40, fixed_iters=3, want_cov=True, prior="ioup",
+                      theta=2.0)
+    r = pp.solve("mol_heat_reaction", [0.01], y0, 0.0, 0.25, 2, 40, precision="fp64", fixed_iters=3, want_cov=True,
+                 prior="ioup", theta=2.0)
+    assert r["status"] == pp.OK
+    assert rel(np_(r["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-9
+    assert rel(sigma(np_(r["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+
+
+def test_server_refuses_other_priors(pp):
+    srv = pp.Server(max_slots=2)
+    with pytest.raises(pp.ParapnError) as e:
+        srv.submit(0, "logistic", [], [0.01], 0.0, 1.0, 2, 10, precision="fp32", prior="ioup", theta=1.0)
+    assert e.value.code == pp.EINVAL
+    srv.close()

@@ -566,3 +566,46 @@ def test_first_element_is_initial_state_combined_with_regular_element(D, dobs):
     assert np.abs(comb[0]).max() < 1e-12 and np.abs(comb[3]).max() < 1e-12 and np.abs(comb[4]).max() < 1e-12
     assert rel(comb[1], first[1]) < 1e-10
     assert rel(comb[2] @ comb[2].T, first[2] @ first[2].T) < 1e-10
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+@pytest.mark.parametrize("theta,h", [(0.5, 0.01), (2.0, 0.3), (1.0, 1e-3)])
+def test_ioup_prior_matches_van_loan(q, theta, h):
+    """IOUP(q, theta) blocks (the q-th derivative an Ornstein-Uhlenbeck
+    process; the oracle integrates Q by quadrature) against Van Loan's block
+    exponential evaluated in 40-digit arithmetic (in double precision its
+    smallest Q entries cancel), entry by entry (Q scaled by sqrt(Q_ii Q_jj)),
+    and the OU closed forms of the last block entries."""
+    import mpmath
+
+    Phi, Q = oracle.ioup(q, theta, h)
+    S = q + 1
+    with mpmath.workdps(40):
+        C = mpmath.zeros(2 * S, 2 * S)
+        for i in range(q):
+            C[i, i + 1] = -h
+            C[S + i + 1, S + i] = h
+        C[q, q] = theta * h
+        C[2 * S - 1, 2 * S - 1] = -theta * h
+        C[q, S + q] = h
+        E = mpmath.expm(C)
+        E12 = E[:S, S:]
+        Pm = E[S:, S:].T
+        Qm = Pm * E12
+        Pr = np.array([[float(Pm[i, j]) for j in range(S)] for i in range(S)])
+        Qr = np.array([[float(Qm[i, j]) for j in range(S)] for i in range(S)])
+    assert np.abs(Phi - Pr).max() < 1e-13 * np.abs(Pr).max()
+    sc = np.sqrt(np.outer(np.diag(Qr), np.diag(Qr)))
+    assert (np.abs(Q - Qr) / sc).max() < 1e-10
+    assert abs(Phi[q, q] - np.exp(-theta * h)) < 1e-15
+    assert abs(Q[q, q] - (1 - np.exp(-2 * theta * h)) / (2 * theta)) < 1e-14 * Q[q, q]
+
+
+@pytest.mark.parametrize("q", [1, 2, 4])
+def test_ioup_with_zero_rate_is_the_integrated_wiener_process(q):
+    h = 0.05
+    Phi, Q = oracle.ioup(q, 0.0, h)
+    P0, Q0 = oracle.iwp(q, h)
+    assert np.abs(Phi - P0).max() < 1e-14
+    sc = np.sqrt(np.outer(np.diag(Q0), np.diag(Q0)))
+    assert (np.abs(Q - Q0) / sc).max() < 1e-10
