@@ -168,3 +168,21 @@ def test_dense_full_size_batch(pp):
     assert mol_residual(m64, sp["params"][0], sp["q"]) < 1e-6
     assert mol_residual(m32, sp["params"][0], sp["q"]) < 1e-3
     assert rel(m32[..., ::3], m64[..., ::3]) < 1e-4
+
+
+def test_dense_batch_isolates_a_non_finite_instance(pp):
+    """An instance whose defect overflows FP32 (start at 1e20) turns
+    non-finite in its first iteration and is frozen; the other instances of
+    the batch run on and come out bitwise as alone."""
+    sp, y0s = workloads.mol_batch(B=3, d=8, N=40, q=2, t1=0.5)
+    y0s = y0s.copy()
+    y0s[1, :] = 1e20
+    out = pp.solve_batch(sp["field"], sp["params"], y0s, sp["t0"], sp["t1"], sp["q"], sp["N"], precision="fp32",
+                         tol=1e-10, max_iter=20)
+    assert out["status"] == pp.ENONFINITE
+    assert out["iterations"][1] == 1
+    for b in (0, 2):
+        a = pp.solve(sp["field"], sp["params"], y0s[b], sp["t0"], sp["t1"], sp["q"], sp["N"], precision="fp32",
+                     tol=1e-10, max_iter=20)
+        assert a["status"] == pp.OK and out["iterations"][b] == a["iterations"]
+        assert same(out["mean"][b], a["mean"]), b
