@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 import time
 
 import numpy as np
@@ -129,6 +130,7 @@ def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1
         pp.solve("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 1.0, q, 64, precision="fp64", fixed_iters=1)
         pp.solve("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 1.0, q, 64, precision="fp32", fixed_iters=1)
     service, st_p, it_p = run_plain(pp, torch, reqs, tol=tol, max_iter=max_iter, keep=keep_ref)
+    print("serve: plain FP64 pass done (%.1f s of service)" % service.sum(), file=sys.stderr, flush=True)
     capacity = n_requests / service.sum()
     qps = load * capacity
     arr = arrival_times(n_requests, qps, seed=seed + 1)
@@ -145,6 +147,7 @@ def run(n_requests=4096, load=0.8, seed=0, max_slots=512, budget=64 << 30, tol=1
     lat_s, st_s, it_s, wait_s, span_s, steps, stats = run_served(pp, torch, reqs, arr, tol=tol, max_iter=max_iter,
                                                                  max_slots=max_slots, budget=budget,
                                                                  on_done=compare)
+    print("serve: real-time served replay done (%.1f s)" % span_s, file=sys.stderr, flush=True)
     sat = None
     if saturate:
         # every request present at time 0: the server's own throughput
