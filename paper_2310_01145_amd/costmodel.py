@@ -84,7 +84,10 @@ def per_step(d, q, esize, b1=32, bs1=8):
     rows) and the stored records with their flag word."""
     D = d * (q + 1)
     DP = D * (D + 1) // 2
-    FEF, FS, SEF, SAF = 3 * D * D + 2 * D + 1, D + D * D, D * D + D + 1, 2 * D * D + D + 1
+    FEF, FS, SAF = 3 * D * D + 2 * D + 1, D + D * D, 2 * D * D + D + 1
+    # smoothing record: E, offset, filtering mean, flag (the reverse reduce
+    # reads all but the mean)
+    SEF, SEF_R = D * D + 2 * D + 1, D * D + D + 1
     s = esize
     return {
         "fwd_reduce1": (obs_setup(D, d) + filter_element(D, d) + filter_combine(D, d, D - d) * (b1 - 1) / b1,
@@ -93,7 +96,7 @@ def per_step(d, q, esize, b1=32, bs1=8):
         "fwd_tree_down": (state_apply(D) / b1, s * (FEF + 2 * FS) / b1),
         "fwd_down1": (obs_setup(D, d) + kf_step_with_smoothing_element(D, d),
                       8 * D + s * (FS / b1 + SEF + DP)),
-        "bwd_reduce1": (smoother_combine(D) * (bs1 - 1) / bs1, s * (SEF + SAF / bs1)),
+        "bwd_reduce1": (smoother_combine(D) * (bs1 - 1) / bs1, s * (SEF_R + SAF / bs1)),
         "bwd_down1": (smoother_apply(D), s * (SEF + FS / bs1) + 16 * D),
     }
 

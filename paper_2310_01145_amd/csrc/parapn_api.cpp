@@ -300,7 +300,7 @@ PackLayout pack_scratch_layout(int D, int esz, const parapn::Pack &pk, int nreq,
         o = align_up(o + bytes);
         return r;
     };
-    L.se = take((size_t)pk.rows * (D * D + D + 1) * esz);
+    L.se = take((size_t)pk.rows * (D * D + 2 * D + 1) * esz);
     L.sL = take((size_t)pk.rows * DP * esz);
     L.sPs = cov ? take((size_t)pk.rows * DP * esz) : 0;
     L.mf = take((size_t)pk.rows * D * esz);

@@ -16,6 +16,23 @@
 // is the filtering operator with those zeros substituted -- which is exactly a
 // Kalman predict + update step.  Suffixes of the smoothing scan always contain
 // the last element (E_N = 0), so suffix states are (mean, factor) as well.
+//
+// Two representations keep FP32 from losing the dynamics at small steps.
+// In preconditioned coordinates a step's transition acts on the trajectory
+// as the identity plus O(h); a matrix entry near 1 rounded to FP32 carries
+// only eps/h of relative precision in that O(h) part, and composing the
+// rounded steps over N steps drifts by ~N eps.  So every filtering element
+// and aggregate stores A - I in place of A, and the operator is evaluated in
+// that form (below), which rounds each term relative to its own size.  On
+// the smoothing side the element offset g = m^f - E m^- is a difference of two
+// nearly equal means; instead the reverse scan runs on the smoothing
+// correction c_n = m^s_n - m^f_n:
+//   c_n = E_n c_{n+1} + E_n k_{n+1},   c_N = 0,
+// where k_{n+1} = m^f_{n+1} - m^-_{n+1} is the Kalman update of step n+1 --
+// the same recursion (and the same associative operator) with offset
+// E_n k_{n+1}; the element records carry m^f_n beside it and the smoothed
+// mean is m^f_n + c_n.  Both forms are exact rewritings of the paper's
+// element and operator equations.
 #include <hip/hip_runtime.h>
 
 #include "fields.h"
@@ -93,7 +110,7 @@ struct Cfg {
     // record sizes (T units)
     static constexpr int FE = 3 * D * D + 2 * D;  // filter element / aggregate: A, b, sqrtC, eta, sqrtJ
     static constexpr int FS = D + D * D;          // filter state: mean, factor
-    static constexpr int SE = D * D + D;          // smoothing element (E, g)
+    static constexpr int SE = D * D + 2 * D;      // smoothing element (E, g) and the filtering mean
     static constexpr int SA = 2 * D * D + D;      // smoothing aggregate: E, g, sqrtL
     static constexpr int SS = D + D * D;          // smoother state: mean, factor
     // FP32 with the IWP(4) prior: every Householder reflector is formed from
@@ -345,6 +362,7 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
 //   A = (I - K H) Phi,  b = m- - K (H m- - r),  sqrtC = Psi22,
 //   sqrtJ = Phi^T H^T Psi11^{-T} (D x d, zero padded),
 //   eta = sqrtJ Psi11^{-1} (r - H m-).
+// The returned row holds A - I (the representation the scans use).
 // The initial distribution is not folded in here: it enters the scan as the
 // exclusive prefix state of step 1.
 // ---------------------------------------------------------------------------
@@ -401,7 +419,8 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
         e.b = b;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            T a = cphi[lane * LDM + c];
+            // A - I = (Phi - I) - K H Phi; Phi - I has exact integer entries
+            T a = cphi[lane * LDM + c] - (c == lane ? T(1) : T(0));
 #pragma unroll
             for (int i = 0; i < DO; ++i) a -= K[i] * HP[i * LDM + c];
             e.A[c] = a;
@@ -430,6 +449,12 @@ PARAPN_DEV FRow<C> filter_element(int lane, typename C::T *sh, const typename C:
 //   eta_ij = A_i^T F^T (eta_j - sqrtJ_j sqrtJ_j^T b_i) + eta_i,
 //   sqrtJ_ij = tria([A_i^T Xi22, sqrtJ_i]).
 // (F^T = I - Xi21 Xi11^{-1} sqrtC_i^T, the factor of the eta formula.)
+// Evaluated on the stored differences Ai~ = A_i - I, Aj~ = A_j - I and
+// F~ = F - I = -G Xi21^T: with P = A_j F - I = Aj~ + F~ + Aj~ F~,
+//   A_ij - I = P + Ai~ + P Ai~,   b_ij = b_j + v + P v,
+//   A_j G = G + Aj~ G,   A_i^T Xi22 = Xi22 + Ai~^T Xi22,
+//   eta_ij = eta_i + y + Ai~^T y  with  y = z + F~^T z,
+// (v = b_i + sqrtC_i sqrtC_i^T eta_j, z = eta_j - sqrtJ_j sqrtJ_j^T b_i).
 // ---------------------------------------------------------------------------
 // NJ: number of leading columns of sqrtJ_j that can be nonzero (D for an
 // aggregate, d for a single step's element, whose sqrtJ is D x d).  The
@@ -466,11 +491,11 @@ PARAPN_DEV void xi_and_G_F(int lane, typename C::T *sh, const typename C::T (&sC
     T *Xi = sh + C::BIG;
     put_rows<T, D2, NC>(Xi, LDB, lane, w);
     wave_sync();
-    // G row = sqrtC_i row * Xi11^{-T}
+    // G row = sqrtC_i row * Xi11^{-T};  F~ row = -G row * Xi21^T
     solve_xLt<T, D>(G, sCi, Xi, LDB);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        T f = (c == lane) ? T(1) : T(0);
+        T f = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) f -= G[k] * Xi[(D + c) * LDB + k];
         F[c] = f;
@@ -511,8 +536,11 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     wave_sync();
     FRow<C> o;
     zero(o);
+    // P = A_j F - I = Aj~ + F~ + Aj~ F~  (M2 holds F~)
     T ajf[D];
-    row_times<T, D, D>(ajf, ej.A, M2, LDM);  // A_j F
+    row_times<T, D, D>(ajf, ej.A, M2, LDM);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ajf[c] += ej.A[c] + F[c];
     if (lane < D) {
         // v = b_i + sqrtC_i wv ;  z = eta_j - sqrtJ_j u
         T v = ei.b, z = ej.eta;
@@ -525,16 +553,20 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     }
     wave_sync();
     if (lane < D) {
-        row_times<T, D, D>(o.A, ajf, M3, LDM);  // A_j F A_i
-        T bb = ej.b;
+        // A_ij - I = P + Ai~ + P Ai~  (M3 holds Ai~)
+        row_times<T, D, D>(o.A, ajf, M3, LDM);
+#pragma unroll
+        for (int c = 0; c < D; ++c) o.A[c] += ajf[c] + ei.A[c];
+        // b_ij = b_j + v + P v,  y = z + F~^T z
+        T pv = 0;
         T y = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            bb += ajf[k] * V4[k];
-            y += M2[k * LDM + lane] * V5[k];  // (F^T z)_lane
+            pv += ajf[k] * V4[k];
+            y += M2[k * LDM + lane] * V5[k];
         }
-        o.b = bb;
-        V0[lane] = y;  // eta_j no longer needed
+        o.b = ej.b + (V4[lane] + pv);
+        V0[lane] = V5[lane] + y;  // eta_j no longer needed
     }
     wave_sync();
     // sqrtC_ij = tria([A_j G, sqrtC_j]) and sqrtJ_ij = tria([A_i^T Xi22,
@@ -542,23 +574,25 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     {
         T w[D + NCJ], wj[NJ + D];
         if (lane < D) {
+            // A_j G = G + Aj~ G
             T t[D];
             row_times<T, D, D>(t, ej.A, M4, LDM);
 #pragma unroll
-            for (int c = 0; c < D; ++c) w[c] = t[c];
+            for (int c = 0; c < D; ++c) w[c] = t[c] + G[c];
 #pragma unroll
             for (int c = 0; c < NCJ; ++c) w[D + c] = ej.sC[c];
+            // A_i^T Xi22 = Xi22 + Ai~^T Xi22
             T tj[NJ];
             rowT_times<T, D, NJ>(tj, lane, M3, LDM, Xi + D * LDB + D, LDB);
 #pragma unroll
-            for (int c = 0; c < NJ; ++c) wj[c] = tj[c];
+            for (int c = 0; c < NJ; ++c) wj[c] = tj[c] + Xi[(D + lane) * LDB + D + c];
 #pragma unroll
             for (int c = 0; c < D; ++c) wj[NJ + c] = ei.sJ[c];
-            // eta_ij = A_i^T y + eta_i
-            T et = ei.eta;
+            // eta_ij = eta_i + y + Ai~^T y
+            T et = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) et += M3[k * LDM + lane] * V0[k];
-            o.eta = et;
+            o.eta = ei.eta + (V0[lane] + et);
         } else {
 #pragma unroll
             for (int c = 0; c < D + NCJ; ++c) w[c] = 0;
@@ -576,8 +610,9 @@ PARAPN_DEV FRow<C> filter_combine(int lane, typename C::T *sh, const FRow<C> &ei
     return o;
 }
 
-// state (mean m, factor P) followed by aggregate a_j: the filtering operator
-// with A_i = 0, eta_i = 0, sqrtJ_i = 0; returns the new (b_ij, sqrtC_ij).
+// state (mean m, factor P) followed by aggregate a_j (holding A_j - I): the
+// filtering operator with A_i = 0, eta_i = 0, sqrtJ_i = 0; returns the new
+// (b_ij, sqrtC_ij).
 template <class C>
 PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, const FRow<C> &ej)
 {
@@ -598,10 +633,14 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
         V2[lane] = wv;
     }
     wave_sync();
+    // P = A_j F - I = Aj~ + F~ + Aj~ F~
     T ajf[D];
     row_times<T, D, D>(ajf, ej.A, M2, LDM);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ajf[c] += ej.A[c] + F[c];
+    T v = 0;
     if (lane < D) {
-        T v = s.m;
+        v = s.m;
 #pragma unroll
         for (int c = 0; c < D; ++c) v += s.P[c] * V2[c];
         V4[lane] = v;
@@ -610,18 +649,20 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
     SRow<C> o;
     o.m = 0;
     if (lane < D) {
-        T bb = ej.b;
+        // b = b_j + v + P v
+        T pv = 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) bb += ajf[k] * V4[k];
-        o.m = bb;
+        for (int k = 0; k < D; ++k) pv += ajf[k] * V4[k];
+        o.m = ej.b + (v + pv);
     }
     T w[D2];
     if (lane < D) {
+        // A_j G = G + Aj~ G
         T t[D];
         row_times<T, D, D>(t, ej.A, M4, LDM);
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            w[c] = t[c];
+            w[c] = t[c] + G[c];
             w[D + c] = ej.sC[c];
         }
     } else {
@@ -641,18 +682,22 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
 //   Pi = tria([[Phi sqrtP, sqrtQ], [sqrtP, 0]])   (2D x 2D)
 // gives Pi11 = tria([Phi sqrtP, sqrtQ]), the predicted factor of step n (its
 // first D reflections are the prediction's), and
-//   E_{n-1} = Pi21 Pi11^{-1},  g_{n-1} = m - E_{n-1} m-,  sqrtL_{n-1} = Pi22,
+//   E_{n-1} = Pi21 Pi11^{-1},  sqrtL_{n-1} = Pi22,
 // with the predicted mean m- = Phi m + u_n.  The update is
 //   Psi = tria([[H sqrtP-], [sqrtP-]]),  K = Psi21 Psi11^{-1},
-//   m = m- + K (r - H m-),  sqrtP = Psi22.
-// The smoothing element comes back in lanes D..2D-1 (row lane - D).
+//   k = K (r - H m-),  m = m- + k,  sqrtP = Psi22.
+// The element's offset is kept in correction form, E_{n-1} k (the paper's
+// g_{n-1} = m - E_{n-1} m- is m + E_{n-1} k minus E_{n-1} applied to the
+// smoothed mean, see the top of this file).  The smoothing element (E,
+// E k) and the filtering mean m of step n-1 come back in lanes D..2D-1 (row
+// lane - D; the mean in mf_prev).
 template <class C>
 PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
-                              const typename C::T *csq, ERow<C> &eo)
+                              const typename C::T *csq, ERow<C> &eo, typename C::T &mf_prev)
 {
     using T = typename C::T;
     constexpr int d = C::d, D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
-    T *M0 = sh + C::M0, *V0 = sh + C::V0, *V1 = sh + C::V1;
+    T *M0 = sh + C::M0, *V0 = sh + C::V0, *V1 = sh + C::V1, *V2 = sh + C::V2;
     put_rows<T, D, D>(M0, LDM, lane, s.P);
     if (lane < D) V0[lane] = s.m;
     wave_sync();
@@ -697,10 +742,6 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
             eo.L[c] = w[D + c];
         }
         solve_xL<T, D>(eo.E, p21, Pi, LDB);
-        T g = V0[lane - D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) g -= eo.E[c] * V1[c];
-        eo.g = g;
     }
     // update with the predicted factor Pi11 (rows 0..D-1 of Pi):
     // tria([[H Pi11, sqrtR], [Pi11, 0]])
@@ -745,12 +786,22 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
             p21[i] = Psi[(DO + lane) * LDB + i];
         }
         solve_xL<T, DO>(K, p21, Psi, LDB);
-        T m = mp;
+        T k = 0;
 #pragma unroll
-        for (int i = 0; i < DO; ++i) m += K[i] * res[i];
-        o.m = m;
+        for (int i = 0; i < DO; ++i) k += K[i] * res[i];
+        o.m = mp + k;
+        V2[lane] = k;
 #pragma unroll
         for (int c = 0; c < D - d; ++c) o.P[c] = Psi[(DO + lane) * LDB + DO + c];
+    }
+    wave_sync();
+    mf_prev = 0;
+    if (lane >= D && lane < D2) {
+        T g = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) g += eo.E[c] * V2[c];
+        eo.g = g;
+        mf_prev = V0[lane - D];
     }
     wave_sync();
     return o;
@@ -998,7 +1049,10 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
             zero(el);
             el.b = st.m;
 #pragma unroll
-            for (int c = 0; c < C::D; ++c) el.sC[c] = st.P[c];
+            for (int c = 0; c < C::D; ++c) {
+                el.sC[c] = st.P[c];
+                el.A[c] = (c == lane) ? T(-1) : T(0);  // A = 0
+            }
             el.flag = 1;
         }
         if (n == s)
@@ -1109,8 +1163,9 @@ __global__ __launch_bounds__(C::NT) void k_fwd_tree_down(Pack pk, const typename
 // (a request's first chunk starts from the initial state).  The smoothing
 // element of a step is formed from its filtering marginal inside the next
 // step's Kalman step, so a chunk covering steps s..e-1 writes the elements
-// (E, g) and sqrtL of steps s-1..e-2; the chunk holding step N also writes
-// the last element (E = 0, g = m^f_N, sqrtL = sqrtP^f_N, boundary flag).
+// (E, E k, m^f) and sqrtL of steps s-1..e-2; the chunk holding step N also
+// writes the last element (E = 0, offset 0, m^f_N, sqrtL = sqrtP^f_N,
+// boundary flag).
 // Filtering marginals are written only when mf is given.
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename C::T *pref, typename C::T *se,
@@ -1136,7 +1191,8 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
     for (int64_t n = s; n < e; ++n) {
         obs_setup<C>(a.pk, q, n, lane, sh, cphi);
         ERow<C> eo;
-        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo);
+        T mfp;
+        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp);
         const int64_t row = q.row + n - 1;
         if (lane >= D && lane < C::D2) {
             const int r = lane - D;
@@ -1144,6 +1200,7 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
 #pragma unroll
             for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
             rec[D * D + r] = eo.g;
+            rec[D * D + D + r] = mfp;
             if (r == 0) rec[C::SE] = 0;
             store_packed<C>(sL + row * C::DP, r, eo.L);
         }
@@ -1157,7 +1214,8 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
         T *rec = se + row * C::SEF;
 #pragma unroll
         for (int c = 0; c < D; ++c) rec[lane * D + c] = 0;
-        rec[D * D + lane] = st.m;
+        rec[D * D + lane] = 0;
+        rec[D * D + D + lane] = st.m;
         if (lane == 0) rec[C::SE] = 1;
         store_packed<C>(sL + row * C::DP, lane, st.P);
     }
@@ -1325,7 +1383,9 @@ __global__ __launch_bounds__(C::NT) void k_bwd_down(Pack pk, const typename C::T
 }
 
 // step level, smoother down-sweep over one chunk of a request's steps from
-// its suffix state.  UPDATE: add the smoothed increments to the request's
+// its suffix state.  The scan carries the smoothing correction c = m^s - m^f;
+// the smoothed mean is the stored m^f plus c.  UPDATE: add the smoothed
+// increments to the request's
 // FP64 trajectory (the next linearisation point) and accumulate, in double,
 //   delta = max |T0 E0 increment|  and  max |T0 E0 trajectory|
 // into the request's counters; otherwise write the smoothed means to mout
@@ -1358,6 +1418,10 @@ PARAPN_DEV int bwd_down1_group(const KArgs<C> &a, int64_t chunk, int lane, typen
 #pragma unroll
         for (int i = 0; i < C::B1; ++i) told[i] = (i < cnt && lane < D) ? q.traj[(s + i) * D + lane] : 0.0;
     }
+    // filtering means of the chunk's steps (the scan below yields m^s - m^f)
+    T mfv[C::B1];
+#pragma unroll
+    for (int i = 0; i < C::B1; ++i) mfv[i] = (i < cnt && lane < D) ? se[(row0 + i) * C::SEF + D * D + D + lane] : T(0);
     SRow<C> st = load_state<C>(suf + (sbase + lc) * C::SS, lane);
 #pragma unroll
     for (int i = C::B1 - 1; i >= 0; --i) {
@@ -1367,16 +1431,17 @@ PARAPN_DEV int bwd_down1_group(const KArgs<C> &a, int64_t chunk, int lane, typen
                                  PREFETCH ? els[i % NB] : load_selem<C, WITH_L>(se, sL, row0 + i, lane), st);
         if (lane < D) {
             if (UPDATE) {
-                const double nw = told[i] + (double)st.m;
+                const double inc = (double)mfv[i] + (double)st.m;
+                const double nw = told[i] + inc;
                 if (lane % C::S == 0) {
-                    const double df = fabs(q.T0 * (double)st.m);
+                    const double df = fabs(q.T0 * inc);
                     dmax = (df > dmax || df != df) ? df : dmax;
                     const double am = fabs(q.T0 * nw);
                     mmax = (am > mmax || am != am) ? am : mmax;
                 }
                 q.traj[n * D + lane] = nw;
             } else {
-                mout[(row0 + i) * D + lane] = st.m;
+                mout[(row0 + i) * D + lane] = mfv[i] + st.m;
             }
             if (WITH_L) store_packed<C>(sPs + (row0 + i) * C::DP, lane, st.P);
         }
@@ -1450,7 +1515,17 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
     if (k >= count) return;
     FRow<C> ei = load_frow<C, false>(aa + k * C::FE, lane);
     FRow<C> ej = load_frow<C, false>(cc + k * C::FE, lane);
+    // the operator works on A - I
+#pragma unroll
+    for (int c = 0; c < C::D; ++c)
+        if (c == lane) {
+            ei.A[c] -= T(1);
+            ej.A[c] -= T(1);
+        }
     FRow<C> o = filter_combine<C, C::D, C::D>(lane, sh, ei, ej);
+#pragma unroll
+    for (int c = 0; c < C::D; ++c)
+        if (c == lane) o.A[c] += T(1);
     store_frow<C, false>(out + k * C::FE, lane, o);
 }
 

@@ -348,27 +348,32 @@ def test_fhn_full_size_matches_the_oracle(pp):
         assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < tol, prec
 
 
-def test_fhn_full_size_first_iteration_from_constant_start(pp):
-    """The first iterate from the constant start moves the trajectory by O(1):
-    in FP32 that whole increment is composed over 2^18 steps of a nearly
-    neutral oscillator (the linearisation at y0), and its phase error builds
-    up to a few 1e-3.  FP64 holds the 1e-9 gate; the FP32 gate of 1e-4
-    applies once the increments are small (refinement against the FP64
-    trajectory, see the two tests below and the one above)."""
-    spec = wl.fhn(N=1 << 18)
+@pytest.mark.parametrize("logN", [12, 14, 16, 18])
+def test_fhn_first_iteration_from_constant_start_across_n(pp, logN):
+    """C1 as specified (constant start): the first linearise+smooth pass moves
+    the trajectory by O(1) -- the whole solution of the linearisation at y0,
+    composed over N steps.  Both precisions are gated at every N of the sweep
+    (FP32 at 1e-4: the scans store A - I and run the smoother on the
+    correction m^s - m^f, so the FP32 error does not grow with N)."""
+    spec = wl.fhn(N=1 << logN)
     args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
     ref = oracle.ieks(*args, fixed_iters=1, want_cov=False)
     r64 = pp.solve(*args, precision="fp64", fixed_iters=1)
-    assert relerr(e0(np_(r64["mean"]), 3), e0(ref["mean"], 3)) < 1e-9
+    e64 = relerr(e0(np_(r64["mean"]), 3), e0(ref["mean"], 3))
     r32 = pp.solve(*args, precision="fp32", fixed_iters=1)
-    assert relerr(e0(np_(r32["mean"]), 3), e0(ref["mean"], 3)) < 1e-2
+    e32 = relerr(e0(np_(r32["mean"]), 3), e0(ref["mean"], 3))
+    print("FHN first iterate N=2^%d: FP64 %.2e, FP32 %.2e" % (logN, e64, e32))
+    assert e64 < 1e-9
+    assert e32 < 1e-4
+    # delta_1 is the size of that first increment (O(1) on the solution's scale)
+    assert abs(r32["deltas"][0] - ref["deltas"][0]) < 1e-4 * ref["deltas"][0]
+    assert ref["deltas"][0] > 0.5
 
 
 def test_fp32_refines_to_the_fp64_solution_at_full_size(pp):
-    """Logistic at N = 2^18 from the constant start: the FP32 increments are
-    taken against the FP64 trajectory and FP64 residuals, so the converged
-    FP32 solve meets the oracle's converged solution at 1e-4 even though its
-    first increment does not."""
+    """Logistic at N = 2^18 from the constant start: the first FP32 iterate
+    (an O(1) increment) and the converged FP32 solve both meet the oracle at
+    1e-4."""
     args = ("logistic", [], [0.01], 0.0, 10.0, 2, 1 << 18)
     ref1 = oracle.ieks(*args, fixed_iters=1, want_cov=False)
     ref = oracle.ieks(*args, max_iter=30, tol=1e-10, want_cov=False)
@@ -378,8 +383,9 @@ def test_fp32_refines_to_the_fp64_solution_at_full_size(pp):
     assert r["status"] == 0 and r["converged"]
     first = relerr(e0(np_(r1["mean"]), 2), e0(ref1["mean"], 2))
     final = relerr(e0(np_(r["mean"]), 2), e0(ref["mean"], 2))
+    print("logistic N=2^18 FP32: first iterate %.2e, converged %.2e" % (first, final))
+    assert first < 1e-4
     assert final < 1e-4
-    assert final <= first
 
 
 def test_lorenz_full_size_first_iteration(pp):
