@@ -90,6 +90,13 @@ def lib():
         L.orc_filter_combine.argtypes = [i] + [P] * 15
         L.orc_smoother_element.argtypes = [i, P, P, P, P, i, P, P, P]
         L.orc_smoother_combine.argtypes = [i] + [P] * 9
+        LP = ctypes.POINTER(ctypes.c_long)
+        L.orc_coarse_grid.argtypes = [l, l, LP, LP]
+        L.orc_coarse_grid.restype = None
+        L.orc_iwp_bridge.argtypes = [i, dl, dl, P, P, P]
+        L.orc_iwp_bridge.restype = None
+        L.orc_coarse_start.argtypes = [i, P, i, i, P, dl, dl, i, l, l, P]
+        L.orc_coarse_start.restype = i
         _lib = L
     return _lib
 
@@ -199,12 +206,61 @@ def ioup(q, theta, h):
 PRIORS = {"iwp": 0, "ioup": 1}
 
 
+def coarse_grid(N, M_target):
+    """(s, M): fine steps per coarse step and number of coarse steps."""
+    s, M = ctypes.c_long(0), ctypes.c_long(0)
+    lib().orc_coarse_grid(int(N), int(M_target), ctypes.byref(s), ctypes.byref(M))
+    return s.value, M.value
+
+
+def default_coarse_points(N):
+    """Coarse-grid size used when none is given: max(1024, 64 ceil(log2 N)),
+    at most N (the reading adopted for the O(log N) grid of the remark on
+    other initial trajectories)."""
+    lg = max(1, int(np.ceil(np.log2(max(N, 2)))))
+    return int(min(N, max(1024, 64 * lg)))
+
+
+def iwp_bridge(q, H, tau, xk, xk1):
+    """IWP(q) prior mean at t_k + tau given the full states at t_k and t_k + H."""
+    xk, xk1 = _f64(xk), _f64(xk1)
+    out = np.zeros(q + 1)
+    lib().orc_iwp_bridge(q, float(H), float(tau), _p(xk), _p(xk1), _p(out))
+    return out
+
+
+def coarse_start(field, params, y0, t0, t1, q, N, M_target=None, d=None):
+    """Starting trajectory [N+1, D] (original coordinates) from a sequential
+    extended Kalman smoother on a coarse grid, bridged to the fine grid by the
+    prior.  Raises FloatingPointError if the coarse smoother diverged."""
+    y0 = _f64(y0).ravel()
+    params = _f64(params if len(params) else [0.0]).ravel()
+    dd = y0.size if d is None else d
+    fid = _field_id(field)
+    dim = lib().orc_field_dim(fid, dd, params.size)
+    if dim < 1:
+        raise ValueError("field/parameter mismatch")
+    M = default_coarse_points(N) if not M_target else int(M_target)
+    out = np.zeros((N + 1, dim * (q + 1)))
+    rc = lib().orc_coarse_start(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, int(N), M,
+                                _p(out))
+    if rc == -1:
+        raise ValueError("bad problem")
+    if rc != 0:
+        raise FloatingPointError("the coarse-grid smoother produced non-finite values")
+    return out
+
+
 def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
-         want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0):
+         want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0, init=None, coarse_points=0):
     """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
     sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas.
     lm_sigma > 0: Levenberg-Marquardt damping, a pseudo-observation of each
-    step's E0 at the current iterate with std lm_sigma / sqrt(h)."""
+    step's E0 at the current iterate with std lm_sigma / sqrt(h).
+    init="coarse": start from coarse_start(...) (coarse_points coarse steps,
+    0 = the default) instead of the constant mu0."""
+    if init == "coarse":
+        init_traj = coarse_start(field, params, y0, t0, t1, q, N, coarse_points or None, d=d)
     y0 = _f64(y0).ravel()
     params = _f64(params if len(params) else [0.0]).ravel()
     dd = y0.size if d is None else d

@@ -983,3 +983,177 @@ int orc_ieks(int field, const double *params, int nparams, int d_req, const doub
     return orc_ieks_lm(field, params, nparams, d_req, y0, t0, t1, q, N, max_iter, tol, fixed_iters, init_traj, 0.0,
                        mean_out, sqrtcov_out, delta_hist, iters_out);
 }
+
+/* ------------------------------------------------------------------------ */
+/* starting trajectory from a coarse grid (remark "Other choices for the     */
+/* initial state trajectory", Sec. 3.2.2)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* The coarse grid: s = ceil(N / M_target) fine steps per coarse step and
+ * M = ceil(N / s) coarse steps of length H = s h from t0 (the last coarse
+ * node may lie past t1; the vector fields are autonomous). */
+void orc_coarse_grid(long N, long M_target, long *s_out, long *M_out)
+{
+    if (M_target < 1) M_target = 1;
+    long s = (N + M_target - 1) / M_target;
+    if (s < 1) s = 1;
+    *s_out = s;
+    *M_out = (N + s - 1) / s;
+}
+
+/* Mean of the IWP(q) prior at t_k + tau conditioned on its full states x_k at
+ * t_k and x_k1 at t_k + H (one ODE component, q+1 derivatives), i.e. the
+ * Gaussian bridge
+ *   x(tau) = Phi(tau) x_k + Q(tau) Phi(H - tau)^T Q(H)^{-1} (x_k1 - Phi(H) x_k),
+ * the conditional mean of the first of the two jointly Gaussian transitions
+ * given their sum (Sec. 2.1 transition densities). */
+void orc_iwp_bridge(int q, double H, double tau, const double *xk, const double *xk1, double *out)
+{
+    int S = q + 1;
+    double *Pt = dalloc(S * S), *Qt = dalloc(S * S), *Pr = dalloc(S * S), *Qr = dalloc(S * S);
+    double *PH = dalloc(S * S), *QH = dalloc(S * S), *L = dalloc(S * S), *v = dalloc(S), *w = dalloc(S);
+    double *z = dalloc(S), *u = dalloc(S);
+    orc_iwp(q, tau, Pt, Qt);
+    orc_iwp(q, H - tau, Pr, Qr);
+    orc_iwp(q, H, PH, QH);
+    /* v = x_k1 - Phi(H) x_k ; w = Q(H)^{-1} v by Cholesky */
+    mv(S, S, PH, 0, xk, v);
+    for (int i = 0; i < S; ++i) v[i] = xk1[i] - v[i];
+    orc_chol(S, QH, L);
+    lower_solve_vec(S, L, v, z);
+    for (int i = S - 1; i >= 0; --i) { /* L^T w = z */
+        double t = z[i];
+        for (int k = i + 1; k < S; ++k) t -= L[k * S + i] * w[k];
+        w[i] = t / L[i * S + i];
+    }
+    mv(S, S, Pr, 1, w, u);   /* Phi(H - tau)^T w */
+    mv(S, S, Qt, 0, u, z);   /* Q(tau) (...) */
+    mv(S, S, Pt, 0, xk, out);
+    for (int i = 0; i < S; ++i) out[i] += z[i];
+    free(Pt); free(Qt); free(Pr); free(Qr); free(PH); free(QH); free(L); free(v); free(w); free(z); free(u);
+}
+
+/* Sequential extended Kalman smoother on the coarse grid, then the bridge to
+ * the fine grid.  Filter: at each coarse step, predict with the prior
+ * (preconditioned coordinates of step H), linearise the ODE at the predicted
+ * mean (EK1, Sec. 3.2.1: Hbar = E1 - (T0/T1) F_y E0, innovation
+ * (f(y-) - y-')/T1), update in square-root form (Psi = tria([[Hbar sqrtP-],
+ * [sqrtP-]])).  Smoother: RTS,
+ *   m^s_k = m^f_k + G_k (m^s_{k+1} - Phi m^f_k),  G_k = Pi21 Pi11^{-1},
+ *   Pi = tria([[Phi sqrtP^f_k, sqrtQ], [sqrtP^f_k, 0]]).
+ * traj_out: [N+1][D] fine-grid trajectory in original coordinates, row 0 =
+ * mu0.  Returns 0, -1 (bad arguments) or -4 (non-finite coarse values). */
+int orc_coarse_start(int field, const double *params, int nparams, int d_req, const double *y0, double t0,
+                     double t1, int q, long N, long M_target, double *traj_out)
+{
+    int d = orc_field_dim(field, d_req, nparams);
+    if (d < 1 || q < 1 || N < 1 || !(t1 > t0)) return -1;
+    long s, M;
+    orc_coarse_grid(N, M_target, &s, &M);
+    int S = q + 1, D = d * S, n2 = d + D;
+    double h = (t1 - t0) / (double)N, H = s * h;
+    double *PhiB = dalloc(D * D), *sQB = dalloc(D * D), *T = dalloc(D), *mu0 = dalloc(D);
+    precond_model(d, q, H, PhiB, sQB, T);
+    orc_taylor_mu0(field, params, d, y0, q, mu0);
+    double *mf = dalloc((M + 1) * D), *sPf = dalloc((M + 1) * D * D), *ms = dalloc((M + 1) * D);
+    double *mp = dalloc(D), *sPp = dalloc(D * D), *tmp = dalloc(D * D), *W = dalloc(4L * D * D);
+    double *Mx = dalloc((long)n2 * n2), *Psi = dalloc((long)n2 * n2), *Hn = dalloc(d * D), *res = dalloc(d);
+    double *Ps11 = dalloc(d * d), *Ps21 = dalloc(D * d), *K = dalloc(D * d), *v = dalloc(D), *v2 = dalloc(D);
+    double *y = dalloc(d), *fy = dalloc(d), *Jy = dalloc(d * d), *Pi = dalloc(4L * D * D);
+    double *P11 = dalloc(D * D), *P21 = dalloc(D * D), *G = dalloc(D * D);
+    double T0 = T[0], T1 = T[1];
+    int bad = 0;
+    for (int k = 0; k < D; ++k) mf[k] = mu0[k] / T[k];
+    for (long n = 1; n <= M; ++n) {
+        const double *m = mf + (n - 1) * D, *sP = sPf + (n - 1) * D * D;
+        mv(D, D, PhiB, 0, m, mp);
+        mm(D, D, D, PhiB, 0, sP, 0, tmp);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                W[r * 2 * D + c] = tmp[r * D + c];
+                W[r * 2 * D + D + c] = sQB[r * D + c];
+            }
+        orc_tria(D, 2 * D, W, sPp);
+        for (int i = 0; i < d; ++i) y[i] = T0 * mp[i * S];
+        orc_field_f(field, params, d, y, fy);
+        orc_field_jac(field, params, d, y, Jy);
+        memset(Hn, 0, sizeof(double) * d * D);
+        for (int i = 0; i < d; ++i) {
+            Hn[i * D + i * S + 1] = 1.0;
+            for (int j = 0; j < d; ++j) Hn[i * D + j * S] -= Jy[i * d + j] * T0 / T1;
+            res[i] = (fy[i] - T1 * mp[i * S + 1]) / T1;
+        }
+        memset(Mx, 0, sizeof(double) * n2 * n2);
+        mm(d, D, D, Hn, 0, sPp, 0, tmp);
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < D; ++c) Mx[r * n2 + c] = tmp[r * D + c];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) Mx[(d + r) * n2 + c] = sPp[r * D + c];
+        orc_tria(n2, n2, Mx, Psi);
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) Ps11[r * d + c] = Psi[r * n2 + c];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < d; ++c) Ps21[r * d + c] = Psi[(d + r) * n2 + c];
+        right_solve_lower(D, d, Ps11, Ps21, K);
+        mv(D, d, K, 0, res, v);
+        double *mo = mf + n * D, *so = sPf + n * D * D;
+        for (int r = 0; r < D; ++r) {
+            mo[r] = mp[r] + v[r];
+            if (!isfinite(mo[r])) bad = 1;
+            for (int c = 0; c < D; ++c) so[r * D + c] = Psi[(d + r) * n2 + d + c];
+        }
+        if (bad) break;
+    }
+    if (!bad) {
+        memcpy(ms + M * D, mf + M * D, sizeof(double) * D);
+        for (long n = M - 1; n >= 0; --n) {
+            const double *m = mf + n * D, *sP = sPf + n * D * D;
+            memset(W, 0, sizeof(double) * 4 * D * D);
+            mm(D, D, D, PhiB, 0, sP, 0, tmp);
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    W[r * 2 * D + c] = tmp[r * D + c];
+                    W[r * 2 * D + D + c] = sQB[r * D + c];
+                    W[(D + r) * 2 * D + c] = sP[r * D + c];
+                }
+            orc_tria(2 * D, 2 * D, W, Pi);
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    P11[r * D + c] = Pi[r * 2 * D + c];
+                    P21[r * D + c] = Pi[(D + r) * 2 * D + c];
+                }
+            right_solve_lower(D, D, P11, P21, G);
+            mv(D, D, PhiB, 0, m, v);
+            for (int r = 0; r < D; ++r) v[r] = ms[(n + 1) * D + r] - v[r];
+            mv(D, D, G, 0, v, v2);
+            for (int r = 0; r < D; ++r) {
+                ms[n * D + r] = m[r] + v2[r];
+                if (!isfinite(ms[n * D + r])) bad = 1;
+            }
+        }
+    }
+    if (!bad) {
+        /* bridge every fine point between its two coarse nodes, original coordinates */
+        double *xa = dalloc(S), *xb = dalloc(S), *xo = dalloc(S);
+        for (long j = 0; j <= N; ++j) {
+            long k = j / s, o = j % s;
+            for (int i = 0; i < d; ++i) {
+                for (int c = 0; c < S; ++c) {
+                    xa[c] = T[i * S + c] * ms[k * D + i * S + c];
+                    xb[c] = o ? T[i * S + c] * ms[(k + 1) * D + i * S + c] : 0.0;
+                }
+                if (o == 0)
+                    memcpy(xo, xa, sizeof(double) * S);
+                else
+                    orc_iwp_bridge(q, H, o * h, xa, xb, xo);
+                for (int c = 0; c < S; ++c) traj_out[j * D + i * S + c] = xo[c];
+            }
+        }
+        for (int k = 0; k < D; ++k) traj_out[k] = mu0[k];
+        free(xa); free(xb); free(xo);
+    }
+    free(PhiB); free(sQB); free(T); free(mu0); free(mf); free(sPf); free(ms); free(mp); free(sPp); free(tmp);
+    free(W); free(Mx); free(Psi); free(Hn); free(res); free(Ps11); free(Ps21); free(K); free(v); free(v2);
+    free(y); free(fy); free(Jy); free(Pi); free(P11); free(P21); free(G);
+    return bad ? -4 : 0;
+}

@@ -609,3 +609,161 @@ def test_ioup_with_zero_rate_is_the_integrated_wiener_process(q):
     assert np.abs(Phi - P0).max() < 1e-14
     sc = np.sqrt(np.outer(np.diag(Q0), np.diag(Q0)))
     assert (np.abs(Q - Q0) / sc).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Stopping quantity (Sec. 3.2.2): delta_k from the returned iterates
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("field,params,y0,t1,q,N", [
+    ("logistic", [], [0.01], 10.0, 2, 200),
+    ("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 20.0, 3, 300),
+    ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 0.5, 4, 100),
+])
+def test_delta_is_the_e0_change_between_returned_iterates(field, params, y0, t1, q, N):
+    """delta_k = max_n max_i |E0 (mu_n^(k) - mu_n^(k-1))| in original
+    coordinates, recomputed here from the means the oracle returns after k-1
+    and k iterations (the iterate before the first is the constant mu0, whose
+    E0 part is y0).  A delta taken in preconditioned coordinates, over all
+    derivatives, or against the wrong iterate fails this."""
+    K = 4
+    means = [np.tile(np.asarray(y0, float), (N + 1, 1))]
+    hist = None
+    for k in range(1, K + 1):
+        r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=k, want_cov=False)
+        means.append(r["mean"][:, :: q + 1])
+        hist = r["deltas"]
+    assert len(hist) == K
+    for k in range(1, K + 1):
+        ref = np.abs(means[k] - means[k - 1]).max()
+        assert abs(hist[k - 1] - ref) <= 1e-12 * max(ref, 1e-300) + 1e-15, (k, hist[k - 1], ref)
+    # an earlier fixed count gives the same leading history (the iteration
+    # does not depend on how many passes are requested)
+    assert np.array_equal(oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=2, want_cov=False)["deltas"],
+                          hist[:2])
+
+
+@pytest.mark.parametrize("logN", [12, 18])
+def test_gauss_newton_from_the_constant_start_diverges_on_fitzhugh_nagumo(logN):
+    """FitzHugh-Nagumo on [0, 100] from Alg. 2's constant start, sequential
+    smoother: the first Gauss-Newton increment is O(1) (the solution of the
+    linearisation at y0 over the whole span), and the second is already far
+    larger -- the iteration is only locally convergent (remark on the
+    convergence of the time-parallel IEKS), so the start, not the parallel
+    scan, is what fails on this workload.  The increments are recomputed from
+    the returned iterates, as in the test above."""
+    N = 1 << logN
+    args = ("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, N)
+    it1 = oracle.ieks(*args, fixed_iters=1, want_cov=False)
+    it2 = oracle.ieks(*args, fixed_iters=2, want_cov=False)
+    d1 = np.abs(it1["mean"][:, ::4] - np.array([-1.0, 1.0])).max()
+    d2 = np.abs(it2["mean"][:, ::4] - it1["mean"][:, ::4]).max()
+    assert 0.5 < d1 < 10.0
+    assert abs(it2["deltas"][1] - d2) <= 1e-12 * d2
+    assert d2 > 10.0 * d1
+    if logN == 18:
+        assert d2 > 1e9
+
+
+# ---------------------------------------------------------------------------
+# Starting trajectory from a coarse grid (remark on other initial
+# trajectories, Sec. 3.2.2): coarse sequential EKS + prior bridge
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_iwp_bridge_is_the_hermite_interpolant(q):
+    """Conditioned on the full states (q derivatives) at both ends, the IWP(q)
+    mean between them minimises the integral of the squared (q+1)-th
+    derivative, i.e. it is the Hermite interpolant of degree 2q+1 (scipy's
+    BPoly.from_derivatives, an independent route)."""
+    from scipy.interpolate import BPoly
+
+    rng = np.random.default_rng(q)
+    H = 0.37
+    xa, xb = rng.normal(size=q + 1), rng.normal(size=q + 1)
+    bp = BPoly.from_derivatives([0.0, H], [xa, xb])
+    for tau in (0.0, 0.05, 0.2, 0.31, H):
+        out = oracle.iwp_bridge(q, H, tau, xa, xb)
+        ref = np.array([bp.derivative(j)(tau) if j else bp(tau) for j in range(q + 1)])
+        # the bridge solves with Q(H), whose condition number grows steeply
+        # with q (about 8e10 at q = 4 and H = 0.37)
+        assert rel(out, ref) < 1e-8, (tau, out, ref)
+
+
+def test_coarse_grid_rule():
+    """s = ceil(N / M_target) fine steps per coarse step, M = ceil(N / s)."""
+    assert oracle.coarse_grid(1000, 1024) == (1, 1000)
+    assert oracle.coarse_grid(1 << 18, 1152) == (228, 1150)
+    assert oracle.coarse_grid(4096, 1024) == (4, 1024)
+    assert oracle.coarse_grid(4097, 1024) == (5, 820)
+    for N in (1, 7, 1000, 4097, 65535):
+        for Mt in (1, 3, 64, 1024):
+            s, M = oracle.coarse_grid(N, Mt)
+            assert M * s >= N > (M - 1) * s and M <= max(Mt, 1)
+    assert oracle.default_coarse_points(1 << 18) == 1152 and oracle.default_coarse_points(300) == 300
+
+
+def test_coarse_smoother_is_the_linear_smoother_for_an_affine_field():
+    """For an affine field the EK1 linearisation is exact wherever it is taken,
+    so the coarse extended smoother on the full grid (s = 1) is the plain
+    Kalman/RTS smoother of the model, which one IEKS pass also computes."""
+    L = np.array([[-0.5, 1.0], [-1.0, -0.3]])
+    c = np.array([0.2, -0.1])
+    p = list(L.ravel()) + list(c)
+    st = oracle.coarse_start("affine", p, [1.0, 0.0], 0.0, 5.0, 2, 200, M_target=200)
+    r = oracle.ieks("affine", p, [1.0, 0.0], 0.0, 5.0, 2, 200, fixed_iters=1, want_cov=False)
+    assert rel(st, r["mean"]) < 1e-10
+
+
+@pytest.mark.parametrize("field,params,y0,q", [("logistic", [], [0.3], 2), ("van_der_pol", [1.0], [2.0, 0.0], 3),
+                                               ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 2)])
+def test_coarse_smoother_single_step_by_hand(field, params, y0, q):
+    """One coarse step (M = 1), written out in covariance form with numpy: the
+    prediction from (mu0, 0) is (Phi mu0, Q); the ODE is linearised at the
+    predicted mean; the update conditions on Hbar x = Hbar m- + innovation;
+    with Sigma0 = 0 the smoothed node 0 is mu0 and node 1 the filtered mean;
+    fine points are the prior bridge between them."""
+    from scipy.interpolate import BPoly
+
+    t1, N = 0.05, 8
+    d, S = len(y0), q + 1
+    D = d * S
+    Phi1, Q1 = oracle.iwp(q, t1)
+    Phi, Q = np.kron(np.eye(d), Phi1), np.kron(np.eye(d), Q1)
+    mu0 = oracle.taylor_mu0(field, params, y0, q)
+    mp, Pp = Phi @ mu0, Q
+    y = mp[::S]
+    f = oracle.field_f(field, params, y)
+    J = oracle.field_jac(field, params, y)
+    E0 = np.zeros((d, D))
+    E1 = np.zeros((d, D))
+    for i in range(d):
+        E0[i, i * S] = 1.0
+        E1[i, i * S + 1] = 1.0
+    Hm = E1 - J @ E0
+    innov = f - E1 @ mp
+    K = Pp @ Hm.T @ np.linalg.inv(Hm @ Pp @ Hm.T)
+    m1 = mp + K @ innov
+    st = oracle.coarse_start(field, params, y0, 0.0, t1, q, N, M_target=1)
+    assert rel(st[0], mu0) < 1e-14
+    assert rel(st[N], m1) < 1e-9
+    ts = np.linspace(0.0, t1, N + 1)
+    for i in range(d):
+        bp = BPoly.from_derivatives([0.0, t1], [mu0[i * S:(i + 1) * S], m1[i * S:(i + 1) * S]])
+        ref = bp(ts)
+        assert np.abs(st[:, i * S] - ref).max() <= 1e-9 * max(np.abs(ref).max(), 1e-12)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_coarse_start_converges_to_the_logistic_solution(q):
+    """Logistic ODE (closed form): the coarse-grid start approaches the exact
+    solution as the coarse grid is refined, at a rate of order q or better
+    (a filter at coarse step H is a method of order ~q)."""
+    N, t1, y0 = 4096, 10.0, 0.01
+    t = np.linspace(0.0, t1, N + 1)
+    exact = 1.0 / (1.0 + (1.0 / y0 - 1.0) * np.exp(-t))
+    errs = []
+    for M in (64, 128, 256):
+        st = oracle.coarse_start("logistic", [], [y0], 0.0, t1, q, N, M_target=M)
+        errs.append(np.abs(st[:, 0] - exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > q - 0.5), (errs, rates)
+    assert errs[-1] < 1e-4
