@@ -42,6 +42,19 @@ extern "C" {
 #define PARAPN_PRIOR_IWP 0
 #define PARAPN_PRIOR_IOUP 1
 
+/* starting trajectory (parapn_problem.init_mode; a given init_traj overrides it) */
+#define PARAPN_INIT_CONSTANT 0 /* eta_n = mu0 for every n (Alg. 2)                         */
+#define PARAPN_INIT_COARSE 1   /* sequential extended Kalman smoother on a coarse grid,
+                                * bridged to the fine grid by the prior (the alternative
+                                * start of the remark on initial trajectories, Sec. 3.2.2) */
+
+/* which start a solve used (parapn_info.start) */
+#define PARAPN_START_CONSTANT 0
+#define PARAPN_START_COARSE 1
+#define PARAPN_START_GIVEN 2
+#define PARAPN_START_COARSE_FAILED 3 /* the coarse smoother produced a non-finite value; the
+                                      * solve ran from the constant start instead          */
+
 /* arithmetic of the path */
 #define PARAPN_FP64 0      /* every step in double                                  */
 #define PARAPN_FP32_SQRT 1 /* elements, scans and linearisation in float; the prior
@@ -118,6 +131,19 @@ typedef struct {
                               * Gauss-Markov priors of Sec. 2.1), discretised in FP64
                               * on the host.  Served requests must use the IWP prior. */
     double prior_theta;      /* IOUP rate, finite and >= 0 (0 gives the IWP)         */
+    int32_t init_mode;       /* PARAPN_INIT_CONSTANT or PARAPN_INIT_COARSE; used only
+                              * when init_traj is NULL.  COARSE: a sequential EK1
+                              * filter (linearised at each predicted mean) and RTS
+                              * smoother on a grid of M coarse steps of s fine steps
+                              * each, s = ceil(N / coarse_points), M = ceil(N / s)
+                              * (the last coarse node may lie past t1), with the
+                              * IWP(q) prior whatever `prior` says; every fine row is
+                              * the prior's mean between its two smoothed coarse
+                              * nodes.  Runs on the device in the path's precision
+                              * (means in FP64).                                     */
+    int32_t coarse_points;   /* target M of the coarse grid; 0 = max(1024, 64
+                              * ceil(log2 N)); values above N mean N (s = 1: the
+                              * sequential smoother on the fine grid itself)         */
 } parapn_problem;
 
 typedef struct {
@@ -126,6 +152,7 @@ typedef struct {
     double final_delta;     /* delta of the last pass                                 */
     double tol_used;        /* the threshold actually applied                         */
     double *delta_history;  /* host, max_iter entries, may be NULL                    */
+    int32_t start;          /* PARAPN_START_*: the starting trajectory used           */
 } parapn_info;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
@@ -150,6 +177,14 @@ int parapn_workspace_size(const parapn_problem *prob, size_t *bytes);
  * per iteration (8-byte read of delta_k). */
 int parapn_solve(parapn_ctx *ctx, const parapn_problem *prob, void *mean_out, void *sqrtcov_out,
                  parapn_info *info, void *stream);
+
+/* The starting trajectory a solve of this problem would use (init_traj,
+ * init_mode, coarse_points), without iterating: traj_out is device
+ * [N+1][D] FP64 in original coordinates (row 0 = mu0); *start (may be NULL)
+ * receives the PARAPN_START_* code.  Fixed-size fields only.  Waits for the
+ * stream before returning. */
+int parapn_start_trajectory(parapn_ctx *ctx, const parapn_problem *prob, double *traj_out, int32_t *start,
+                            void *stream);
 
 /* Alg. 2 for `batch` instances of one problem that differ only in their
  * initial values: instance b starts from y0s + b*d (host, batch*d values;

@@ -31,7 +31,10 @@ FIELDS = {
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
 PRIORS = {"iwp": 0, "ioup": 1}
+INITS = {"constant": 0, "coarse": 1}
+STARTS = {0: "constant", 1: "coarse", 2: "given", 3: "coarse_failed"}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
+            "parapn_start_trajectory",
             "parapn_pararts",
             "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
             "parapn_server_create", "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
@@ -64,6 +67,8 @@ class Problem(ctypes.Structure):
         ("lm_sigma", ctypes.c_double),
         ("prior", ctypes.c_int32),
         ("prior_theta", ctypes.c_double),
+        ("init_mode", ctypes.c_int32),
+        ("coarse_points", ctypes.c_int32),
     ]
 
 
@@ -74,6 +79,7 @@ class Info(ctypes.Structure):
         ("final_delta", ctypes.c_double),
         ("tol_used", ctypes.c_double),
         ("delta_history", ctypes.POINTER(ctypes.c_double)),
+        ("start", ctypes.c_int32),
     ]
 
 
@@ -111,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     L.parapn_workspace_size.restype = ctypes.c_int
     L.parapn_solve.argtypes = [vp, ctypes.POINTER(Problem), vp, vp, ctypes.POINTER(Info), vp]
     L.parapn_solve.restype = ctypes.c_int
+    L.parapn_start_trajectory.argtypes = [vp, ctypes.POINTER(Problem), vp, ctypes.POINTER(i32), vp]
+    L.parapn_start_trajectory.restype = ctypes.c_int
     L.parapn_solve_batch.argtypes = [vp, ctypes.POINTER(Problem), i32, ctypes.POINTER(ctypes.c_double), vp, vp,
                                       ctypes.POINTER(Info), vp]
     L.parapn_solve_batch.restype = ctypes.c_int
@@ -190,7 +198,7 @@ def _dtype(precision):
 
 
 def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                 init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0):
+                 init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0):
     """Build the ctypes Problem (keeps the host arrays alive on the object)."""
     fid = FIELDS[field] if isinstance(field, str) else int(field)
     y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
@@ -211,6 +219,8 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.lm_sigma = float(lm_sigma)
     pb.prior = PRIORS[prior] if isinstance(prior, str) else int(prior)
     pb.prior_theta = float(theta)
+    pb.init_mode = INITS[init] if isinstance(init, str) else int(init)
+    pb.coarse_points = int(coarse_points)
     keep = [y0, prm]
     pb.init_on_device = 0
     if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
@@ -240,16 +250,20 @@ def workspace_size(problem: Problem) -> int:
 
 def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
           init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0, prior="iwp",
-          theta=0.0):
+          theta=0.0, init="constant", coarse_points=0):
     """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
     (original coordinates, torch tensor on the device), ``sqrtcov``
     [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
-    ``converged``, ``tol_used``.  ``lm_sigma`` > 0 damps each Gauss-Newton
-    step (Levenberg-Marquardt, see parapn_problem.lm_sigma)."""
+    ``converged``, ``tol_used``, ``start``.  ``lm_sigma`` > 0 damps each
+    Gauss-Newton step (Levenberg-Marquardt, see parapn_problem.lm_sigma);
+    ``init="coarse"`` starts from the coarse-grid smoother
+    (parapn_problem.init_mode) with ``coarse_points`` coarse steps (0: the
+    library's default)."""
     torch = _torch()
     L = load_library()
     pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                      fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta)
+                      fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta,
+                      init=init, coarse_points=coarse_points)
     D = pb.d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -266,7 +280,24 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
     _check(rc, allow=(OK, MAXITER, ENONFINITE))
     k = info.iterations
     return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy(),
-            "converged": bool(info.converged), "tol_used": info.tol_used, "final_delta": info.final_delta}
+            "converged": bool(info.converged), "tol_used": info.tol_used, "final_delta": info.final_delta,
+            "start": STARTS.get(info.start, info.start)}
+
+
+def start_trajectory(field, params, y0, t0, t1, q, N, *, precision="fp64", init="coarse", coarse_points=0,
+                     init_traj=None, d=None, device=0, stream=None):
+    """The starting trajectory a solve would use: (float64 device tensor
+    [N+1, D] in original coordinates, start name)."""
+    torch = _torch()
+    L = load_library()
+    pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, init_traj=init_traj, d=d, init=init,
+                      coarse_points=coarse_points)
+    D = pb.d * (pb.q + 1)
+    out = torch.empty((pb.N + 1, D), dtype=torch.float64, device=torch.device("cuda", device))
+    st = ctypes.c_int32()
+    _check(L.parapn_start_trajectory(context(device), ctypes.byref(pb), _dptr(out), ctypes.byref(st),
+                                     _stream_handle(stream)))
+    return out, STARTS.get(st.value, st.value)
 
 
 def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,

@@ -283,6 +283,92 @@ void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double>
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------------------
+// coarse-grid starting trajectory (remark on other initial state
+// trajectories, Sec. 3.2.2): grid rule, bridge weights, device layout
+// ---------------------------------------------------------------------------
+// default coarse-grid size: max(1024, 64 ceil(log2 N)), at most N
+int64_t default_coarse_points(int64_t N)
+{
+    int lg = 1;
+    while ((int64_t(1) << lg) < N) ++lg;
+    return std::min<int64_t>(N, std::max<int64_t>(1024, 64 * (int64_t)lg));
+}
+
+// s = ceil(N / target) fine steps per coarse step, M = ceil(N / s) coarse steps
+void coarse_grid(int64_t N, int64_t target, int64_t &s, int64_t &M)
+{
+    if (target < 1) target = 1;
+    s = std::max<int64_t>(1, (N + target - 1) / target);
+    M = (N + s - 1) / s;
+}
+
+// Bridge weights.  Given the full states (q derivatives) at both ends of a
+// coarse step, the IWP(q) prior's mean in between is the Hermite interpolant
+// of degree 2q+1 (it minimises the integral of the squared (q+1)-th
+// derivative).  With tau = o/s in [0, 1] and the Hermite basis b_beta on
+// [0, 1] for the data p^(j)(0) (beta = j) and p^(j)(1) (beta = S + j):
+//   x^(r)(t_k + tau H) = H^-r sum_beta b_beta^(r)(tau) H^j x^(j)_node(beta).
+// In preconditioned coordinates (coarse T_c of H on the nodes, fine T_f of
+// h on the row) the weight of beta = (node, j) for derivative r is
+//   W[o][r][beta] = sqrt(s) s^(q-r) (q-r)!/(q-j)! b_beta^(r)(o/s),
+// independent of h.  Layout W[o][r][2S] for o = 0..s-1.
+void bridge_weights(int q, int64_t s, std::vector<double> &W)
+{
+    const int S = q + 1, n = 2 * S;
+    // V[beta][a] = d^j/dtau^j tau^a at the node of beta; basis coefficients = V^-1
+    std::vector<double> V(n * n, 0.0), X(n * n, 0.0);
+    for (int j = 0; j < S; ++j)
+        for (int a = 0; a < n; ++a) {
+            if (a == j) V[j * n + a] = fact(j);
+            if (a >= j) V[(S + j) * n + a] = fact(a) / fact(a - j);
+        }
+    for (int i = 0; i < n; ++i) X[i * n + i] = 1.0;
+    // Gauss-Jordan with partial pivoting: V X = I
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(V[r * n + c]) > std::fabs(V[piv * n + c])) piv = r;
+        for (int k = 0; k < n; ++k) {
+            std::swap(V[c * n + k], V[piv * n + k]);
+            std::swap(X[c * n + k], X[piv * n + k]);
+        }
+        const double dv = V[c * n + c];
+        for (int k = 0; k < n; ++k) {
+            V[c * n + k] /= dv;
+            X[c * n + k] /= dv;
+        }
+        for (int r = 0; r < n; ++r)
+            if (r != c) {
+                const double f = V[r * n + c];
+                if (f == 0.0) continue;
+                for (int k = 0; k < n; ++k) {
+                    V[r * n + k] -= f * V[c * n + k];
+                    X[r * n + k] -= f * X[c * n + k];
+                }
+            }
+    }
+    // X[a][beta]: coefficient of tau^a in b_beta
+    W.assign((size_t)s * S * n, 0.0);
+    for (int64_t o = 0; o < s; ++o) {
+        double *Wo = W.data() + (size_t)o * S * n;
+        const double tau = (double)o / (double)s;
+        for (int r = 0; r < S; ++r) {
+            const double sc_r = std::sqrt((double)s) * std::pow((double)s, q - r) * fact(q - r);
+            if (o == 0) {  // the coarse node itself
+                Wo[r * n + r] = sc_r / fact(q - r);
+                continue;
+            }
+            for (int beta = 0; beta < n; ++beta) {
+                const int j = beta % S;
+                double bv = 0.0;
+                for (int a = n - 1; a >= r; --a) bv = bv * tau + X[a * n + beta] * fact(a) / fact(a - r);
+                Wo[r * n + beta] = sc_r / fact(q - j) * bv;
+            }
+        }
+    }
+}
+
 
 // Byte offsets of one pack's scratch inside the context workspace.
 struct PackLayout {
@@ -374,6 +460,9 @@ struct Solve {
     int prior;              // PARAPN_PRIOR_IWP or PARAPN_PRIOR_IOUP
     double theta;           // IOUP rate
     int max_iter, fixed_iters;
+    int init_mode;          // PARAPN_INIT_*
+    int64_t coarse_target;  // coarse-grid size target (init_mode COARSE)
+    int start = PARAPN_START_CONSTANT;
     double params[PARAPN_MAX_PARAMS];
     std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
     // iteration state
@@ -401,6 +490,8 @@ int prepare(const parapn_problem *p, Solve &sv)
     sv.lm_sigma = p->lm_sigma;
     sv.prior = p->prior;
     sv.theta = p->prior_theta;
+    sv.init_mode = p->init_mode;
+    sv.coarse_target = p->coarse_points > 0 ? p->coarse_points : default_coarse_points(p->N);
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
     precond_diag(sv.d, sv.q, sv.h, sv.Td);
     sv.mu0.assign(sv.D, 0.0);
@@ -485,6 +576,89 @@ parapn::Work work_from(char *ws, const PackLayout &L, bool cov)
     w.sagg = ws + L.sagg;
     w.spref = ws + L.spref;
     return w;
+}
+
+// Device scratch of one request's coarse-grid start (byte offsets from its
+// base): smoothed coarse nodes, RTS gains, bridge weights, mu0 in coarse
+// coordinates, the status word, the request's tables and the IWP constants.
+struct CoarseLayout {
+    int64_t s, M;
+    size_t node, gain, W, mu0c, status, cd, req, consts, total;
+};
+
+CoarseLayout coarse_layout(const Solve &sv, int esz)
+{
+    CoarseLayout c{};
+    coarse_grid(sv.N, sv.coarse_target, c.s, c.M);
+    const size_t D = sv.D, S = sv.q + 1;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = align_up(o + b);
+        return r;
+    };
+    c.node = take((size_t)(c.M + 1) * D * 8);
+    c.gain = take((size_t)c.M * (D * D + D) * esz);
+    c.W = take((size_t)c.s * S * 2 * S * 8);
+    c.mu0c = take(D * 8);
+    c.status = take(sizeof(int));
+    c.cd = take(sizeof(parapn::CoarseDev));
+    c.req = take(sizeof(parapn::ReqDev));
+    c.consts = take(2 * D * D * esz);
+    c.total = o;
+    return c;
+}
+
+// Run the coarse-grid start of one solve into its resident trajectory (whose
+// tail already holds T and mu0/T) and record which start the solve uses.
+// Waits for the stream (the host tables are locals; the verdict is read back).
+int coarse_start(Solve &sv, bool fp64, char *base, const CoarseLayout &cl, double *traj, hipStream_t s)
+{
+    const int D = sv.D, esz = fp64 ? 8 : 4;
+    std::vector<double> Tc, W, Phi, sQ;
+    precond_diag(sv.d, sv.q, (double)cl.s * sv.h, Tc);
+    bridge_weights(sv.q, cl.s, W);
+    prior_blocks(sv.d, sv.q, Phi, sQ);  // the IWP prior, whatever the solve's prior
+    std::vector<double> mu0c(D);
+    for (int k = 0; k < D; ++k) mu0c[k] = sv.mu0[k] / Tc[k];
+    parapn::CoarseDev cd{};
+    cd.M = cl.M;
+    cd.s = cl.s;
+    cd.T0 = Tc[0];
+    cd.T1 = Tc[1];
+    cd.invT1 = 1.0 / Tc[1];
+    cd.hq = (double)cl.s * sv.h / sv.q;
+    cd.node = (double *)(base + cl.node);
+    cd.gain = base + cl.gain;
+    cd.W = (const double *)(base + cl.W);
+    cd.mu0c = (const double *)(base + cl.mu0c);
+    cd.status = (int *)(base + cl.status);
+    parapn::ReqDev rq;
+    fill_reqdev(sv, traj, nullptr, rq);
+    std::vector<unsigned char> cst((size_t)2 * D * D * esz);
+    for (int i = 0; i < D * D; ++i) {
+        if (fp64) {
+            ((double *)cst.data())[i] = Phi[i];
+            ((double *)cst.data())[D * D + i] = sQ[i];
+        } else {
+            ((float *)cst.data())[i] = (float)Phi[i];
+            ((float *)cst.data())[D * D + i] = (float)sQ[i];
+        }
+    }
+    PARAPN_HIP(hipMemcpyAsync(base + cl.W, W.data(), W.size() * 8, hipMemcpyHostToDevice, s), "copy bridge weights");
+    PARAPN_HIP(hipMemcpyAsync(base + cl.mu0c, mu0c.data(), D * 8, hipMemcpyHostToDevice, s), "copy mu0");
+    PARAPN_HIP(hipMemcpyAsync(base + cl.cd, &cd, sizeof(cd), hipMemcpyHostToDevice, s), "copy coarse table");
+    PARAPN_HIP(hipMemcpyAsync(base + cl.req, &rq, sizeof(rq), hipMemcpyHostToDevice, s), "copy request table");
+    PARAPN_HIP(hipMemcpyAsync(base + cl.consts, cst.data(), cst.size(), hipMemcpyHostToDevice, s), "copy constants");
+    PARAPN_HIP(parapn::launch_coarse(fp64, sv.d, sv.q, (const parapn::ReqDev *)(base + cl.req),
+                                     (const parapn::CoarseDev *)(base + cl.cd), 1, sv.N, base + cl.consts,
+                                     base + cl.consts + (size_t)D * D * esz, s),
+               "coarse start");
+    int status = 0;
+    PARAPN_HIP(hipMemcpyAsync(&status, base + cl.status, sizeof(int), hipMemcpyDeviceToHost, s), "read status");
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    sv.start = status == 0 ? PARAPN_START_COARSE : PARAPN_START_COARSE_FAILED;
+    return PARAPN_OK;
 }
 
 }  // namespace
@@ -574,6 +748,11 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (p->init_on_device != 0 && p->init_on_device != 1) return fail(PARAPN_EINVAL, "init_on_device must be 0 or 1");
     if (!(p->lm_sigma >= 0.0) || !std::isfinite(p->lm_sigma)) return fail(PARAPN_EINVAL, "lm_sigma must be finite and >= 0");
     if (p->prior != PARAPN_PRIOR_IWP && p->prior != PARAPN_PRIOR_IOUP) return fail(PARAPN_EINVAL, "unknown prior");
+    if (p->init_mode != PARAPN_INIT_CONSTANT && p->init_mode != PARAPN_INIT_COARSE)
+        return fail(PARAPN_EINVAL, "unknown init_mode");
+    if (p->coarse_points < 0) return fail(PARAPN_EINVAL, "coarse_points must be >= 0");
+    if (p->field == parapn::F_MOL && p->init_mode == PARAPN_INIT_COARSE && !p->init_traj)
+        return fail(PARAPN_EINVAL, "the coarse-grid start is available for the fixed-size fields");
     if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
         return fail(PARAPN_EINVAL, "prior_theta must be finite and >= 0");
     for (int i = 0; i < p->d; ++i)
@@ -871,6 +1050,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
             f.converged = v.converged ? 1 : 0;
             f.final_delta = v.delta;
             f.tol_used = v.tol_used;
+            f.start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
             if (f.delta_history) {
                 const int cap = std::max(v.max_iter, v.fixed_iters);
                 for (int k = 0; k < (int)v.deltas.size() && k < cap; ++k) f.delta_history[k] = v.deltas[k];
@@ -932,7 +1112,13 @@ int parapn_workspace_size(const parapn_problem *p, size_t *bytes)
     }
     std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
     r[0].N = p->N;
-    const size_t resident = align_up(((size_t)(p->N + 1) * D + 2 * D) * 8);
+    size_t resident = align_up(((size_t)(p->N + 1) * D + 2 * D) * 8);
+    if (!p->init_traj && p->init_mode == PARAPN_INIT_COARSE) {
+        Solve sv;
+        rc = prepare(p, sv);
+        if (rc) return rc;
+        resident += coarse_layout(sv, p->precision == PARAPN_FP64 ? 8 : 4).total;
+    }
     PackPlan pl;
     rc = plan_pack(p->precision == PARAPN_FP64, p->d, q, r, true, resident, pl);
     if (rc) return rc;
@@ -963,7 +1149,9 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     PackPlan pl;
     std::vector<parapn::ReqDev> r(1);
     fill_reqdev(sv, nullptr, nullptr, r[0]);
-    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv), pl, sv.lm_sigma > 0.0);
+    const bool coarse = !p->init_traj && sv.init_mode == PARAPN_INIT_COARSE;
+    const CoarseLayout cl = coarse ? coarse_layout(sv, esz) : CoarseLayout{};
+    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv) + cl.total, pl, sv.lm_sigma > 0.0);
     if (rc) return rc;
     const PackLayout &L = pl.L;
     rc = ensure_ws(ctx, L.total);
@@ -973,6 +1161,11 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     pl.reqs[0].traj = traj;
     rc = init_resident(sv, traj, p->init_traj, p->init_on_device != 0, s);
     if (rc) return rc;
+    sv.start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
+    if (coarse) {
+        rc = coarse_start(sv, fp64, ws + L.extra + resident_bytes(sv), cl, traj, s);
+        if (rc) return rc;
+    }
 
     std::vector<Solve *> one{&sv};
     std::vector<double *> trajs{traj};
@@ -1021,6 +1214,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         info->converged = sv.converged ? 1 : 0;
         info->final_delta = sv.delta;
         info->tol_used = sv.tol_used;
+        info->start = sv.start;
         if (info->delta_history) {
             const int cap = std::max(sv.max_iter, sv.fixed_iters);
             for (int k = 0; k < (int)sv.deltas.size() && k < cap; ++k) info->delta_history[k] = sv.deltas[k];
@@ -1028,6 +1222,41 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     }
     if (sv.status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
     return sv.status;
+}
+
+int parapn_start_trajectory(parapn_ctx *ctx, const parapn_problem *p, double *traj_out, int32_t *start,
+                            void *stream)
+{
+    if (!ctx) return fail(PARAPN_EINVAL, "ctx is NULL");
+    int q, D;
+    int rc = check_problem(p, &q, &D);
+    if (rc) return rc;
+    if (!traj_out) return fail(PARAPN_EINVAL, "traj_out is NULL");
+    if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the start is reported for the fixed-size fields");
+    hipStream_t s = (hipStream_t)stream;
+    PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    Solve sv;
+    rc = prepare(p, sv);
+    if (rc) return rc;
+    const bool coarse = !p->init_traj && sv.init_mode == PARAPN_INIT_COARSE;
+    const CoarseLayout cl = coarse ? coarse_layout(sv, p->precision == PARAPN_FP64 ? 8 : 4) : CoarseLayout{};
+    rc = ensure_ws(ctx, resident_bytes(sv) + cl.total);
+    if (rc) return rc;
+    char *ws = (char *)ctx->ws;
+    double *traj = (double *)ws;
+    rc = init_resident(sv, traj, p->init_traj, p->init_on_device != 0, s);
+    if (rc) return rc;
+    sv.start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
+    if (coarse) {
+        rc = coarse_start(sv, p->precision == PARAPN_FP64, ws + resident_bytes(sv), cl, traj, s);
+        if (rc) return rc;
+    }
+    PARAPN_HIP(parapn::launch_unscale(1, D, sv.N, traj + (size_t)(sv.N + 1) * D, traj, nullptr, traj_out, nullptr,
+                                      s, true),
+               "unscale");
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    if (start) *start = sv.start;
+    return PARAPN_OK;
 }
 
 int parapn_solve_batch(parapn_ctx *ctx, const parapn_problem *p, int32_t batch, const double *y0s, void *mean_out,

@@ -1531,6 +1531,151 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
 
 
 // ---------------------------------------------------------------------------
+// starting trajectory from a coarse grid (remark on other initial state
+// trajectories, Sec. 3.2.2)
+// ---------------------------------------------------------------------------
+// One group of lanes per request runs the sequential extended Kalman
+// smoother on the request's coarse grid: M steps of H = s h, in the
+// coordinates of H, with the IWP prior's h-independent Phi and sqrtQ.  Each
+// step predicts, linearises the vector field at the predicted mean (EK1,
+// Sec. 3.2.1) and updates.  The Kalman step is kf_step_se run on the
+// correction relative to the predicted mean: its prior mean is 0 and the
+// observation residual is the ODE defect at the predicted mean,
+//   r = (f(T0 E0 m-) - T1 E1 m-) / T1,
+// so it returns the correction k = K r, the next factor, and the RTS gain
+// E_{n-1} with E_{n-1} k_n.  Means are carried in FP64.  The backward pass
+// runs the RTS recursion on the correction c_n = m^s_n - m^f_n,
+//   c_{n-1} = E_{n-1} c_n + E_{n-1} k_n,   c_M = 0,
+// and overwrites each coarse node's filtering mean with its smoothed mean.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_coarse_eks(const ReqDev *reqs, const CoarseDev *cds, int nreq,
+                                                      const typename C::T *Phi, const typename C::T *sQ)
+{
+    PARAPN_GROUP_SETUP(C);
+    load_consts<C>(cphi, csq, Phi, sQ);
+    constexpr int d = C::d, D = C::D, S = C::S, LDM = C::LDM, GR = D * D + D;
+    __shared__ double dsh[C::GPB][2 * LDM];
+    const int ri = blockIdx.x * C::GPB + grp;
+    if (ri >= nreq) return;  // no block-wide barrier follows
+    const CoarseDev cd = cds[ri];
+    const int field = reqs[ri].field;
+    const double *prm = reqs[ri].p;
+    double *dm = dsh[grp], *dp = dsh[grp] + LDM;
+    T *gain = (T *)cd.gain;
+    double m = lane < D ? cd.mu0c[lane] : 0.0;
+    SRow<C> st;
+    st.m = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) st.P[c] = 0;
+    bool bad = false;
+    for (int64_t n = 1; n <= cd.M; ++n) {
+        if (lane < D) {
+            dm[lane] = m;
+            cd.node[(n - 1) * D + lane] = m;
+        }
+        wave_sync();
+        double mp = 0.0;
+        if (lane < D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) mp += (double)cphi[lane * LDM + k] * dm[k];
+            dp[lane] = mp;
+        }
+        wave_sync();
+        // EK1 observation at the predicted mean
+        Dual<double, d> yd[d], fd[d];
+#pragma unroll
+        for (int i = 0; i < d; ++i) {
+            yd[i].v = cd.T0 * dp[i * S];
+#pragma unroll
+            for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
+        }
+        field_eval<d>(field, prm, yd, fd);
+#pragma unroll
+        for (int i = 0; i < d; ++i)
+            if (lane == i) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) sh[C::HO + i * LDM + c] = 0;
+#pragma unroll
+                for (int j = 0; j < d; ++j) sh[C::HO + i * LDM + j * S] = (T)(-cd.hq * fd[i].g[j]);
+                sh[C::HO + i * LDM + i * S + 1] += T(1);
+                sh[C::DVO + i] = (T)((fd[i].v - cd.T1 * dp[i * S + 1]) * cd.invT1);
+            }
+        if (lane < D) sh[C::UO + lane] = 0;
+        wave_sync();
+        ERow<C> eo;
+        T mfp;
+        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp);
+        if (lane >= D && lane < C::D2) {
+            T *g = gain + (n - 1) * GR;
+#pragma unroll
+            for (int c = 0; c < D; ++c) g[(lane - D) * D + c] = eo.E[c];
+            g[D * D + lane - D] = eo.g;
+        }
+        if (lane < D) {
+            m = mp + (double)st.m;
+            bad |= !__builtin_isfinite(m);
+        }
+        st.m = 0;
+    }
+    if (lane < D) cd.node[cd.M * D + lane] = m;
+    double c = 0.0;
+    for (int64_t n = cd.M - 1; n >= 0; --n) {
+        if (lane < D) dm[lane] = c;
+        wave_sync();
+        if (lane < D) {
+            const T *g = gain + n * GR;
+            double cn = (double)g[D * D + lane];
+#pragma unroll
+            for (int k = 0; k < D; ++k) cn += (double)g[lane * D + k] * dm[k];
+            c = cn;
+            const double ms = cd.node[n * D + lane] + c;
+            cd.node[n * D + lane] = ms;
+            bad |= !__builtin_isfinite(ms);
+        }
+        wave_sync();
+    }
+    // the group's verdict (lanes of a group share one wavefront)
+    const unsigned long long ballot = __ballot(bad ? 1 : 0);
+    const int first = (threadIdx.x & 63) & ~(C::R - 1);
+    const unsigned long long gmask = (C::R == 64 ? ~0ull : ((1ull << C::R) - 1ull)) << first;
+    if (lane == 0) *cd.status = (ballot & gmask) ? 1 : 0;
+}
+
+// Fine row j of request blockIdx.y lies o = j mod s steps after coarse node
+// k = j / s; its preconditioned state is, per ODE component, the bridge
+// W_o [m_k; m_{k+1}] of the two smoothed coarse means (the prior's mean
+// between them; W folds the coordinate changes of H and h).  Row 0 is mu0.
+// A request whose coarse smoother produced a non-finite value gets the
+// constant start mu0 instead.
+static __global__ void k_coarse_bridge(const ReqDev *reqs, const CoarseDev *cds, int d, int q)
+{
+    const int ri = blockIdx.y;
+    const int64_t N = reqs[ri].N;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > N) return;
+    const int S = q + 1, D = d * S;
+    double *traj = reqs[ri].traj;
+    double *row = traj + j * D;
+    const double *mu0b = traj + (N + 1) * D + D;  // the resident tail: T, then mu0 / T
+    const CoarseDev cd = cds[ri];
+    if (j == 0 || *cd.status != 0) {
+        for (int k = 0; k < D; ++k) row[k] = mu0b[k];
+        return;
+    }
+    const int64_t k = j / cd.s;
+    const int64_t o = j - k * cd.s;
+    const double *a = cd.node + k * D;
+    const double *b = cd.node + (o ? (k + 1) * D : k * D);
+    const double *W = cd.W + o * (int64_t)(2 * S * S);
+    for (int i = 0; i < d; ++i)
+        for (int r = 0; r < S; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < S; ++c) acc += W[r * 2 * S + c] * a[i * S + c] + W[r * 2 * S + S + c] * b[i * S + c];
+            row[i * S + r] = acc;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch sequences
 // ---------------------------------------------------------------------------
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -1781,6 +1926,23 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
     });
 }
 
+template <typename T>
+hipError_t launch_coarse_t(int d, int q, const ReqDev *reqs, const CoarseDev *cds, int nreq, int64_t maxN,
+                           const void *Phi, const void *sQ, hipStream_t s)
+{
+    if (nreq < 1 || nreq > 65535 || maxN < 1) return hipErrorInvalidValue;
+    hipError_t e = dispatch_t<T>(d, q, [&](auto cfg) {
+        using C = decltype(cfg);
+        PARAPN_LAUNCH("coarse_eks", s, k_coarse_eks<C>, dim3((unsigned)cdiv(nreq, C::GPB)), dim3(C::NT), 0, s, reqs,
+                      cds, nreq, (const T *)Phi, (const T *)sQ);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    PARAPN_LAUNCH("coarse_bridge", s, k_coarse_bridge, dim3((unsigned)cdiv(maxN + 1, 256), (unsigned)nreq), dim3(256),
+                  0, s, reqs, cds, d, q);
+    return hipGetLastError();
+}
+
 #ifndef PARAPN_BUILD_FP32
 #define PARAPN_BUILD_FP32 1
 #endif
@@ -1801,7 +1963,9 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
                                              void *, hipStream_t);                                                 \
     template hipError_t launch_filter_combine_t<T>(int, int, int64_t, const void *, const void *, void *,          \
                                                    hipStream_t);                                                   \
-    template hipError_t launch_tria_square_t<T>(int, int, const void *, void *, hipStream_t);
+    template hipError_t launch_tria_square_t<T>(int, int, const void *, void *, hipStream_t);                     \
+    template hipError_t launch_coarse_t<T>(int, int, const ReqDev *, const CoarseDev *, int, int64_t, const void *, \
+                                           const void *, hipStream_t);
 
 #define PARAPN_INSTANTIATE_LM(T) \
     template hipError_t launch_forward_lm_t<T>(int, int, const Pack &, const ModelDev &, const Work &, hipStream_t);

@@ -43,6 +43,10 @@ def test_workspace_size_and_validation_on_host():
     # footprint grows linearly in N
     pb2 = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 13, precision="fp32")
     assert 1.9 * n32 < pp.workspace_size(pb2) < 2.1 * n32
+    # the coarse-grid start adds its scratch (nodes, gains, bridge weights)
+    pbc = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp32",
+                          init="coarse")
+    assert pp.workspace_size(pbc) > n32
     bad = [
         pp.make_problem("fhn", [0.2, 0.2], [-1.0, 1.0], 0.0, 1.0, 3, 100),         # too few params
         pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0], 0.0, 1.0, 3, 100),          # d mismatch
@@ -51,6 +55,9 @@ def test_workspace_size_and_validation_on_host():
         pp.make_problem("logistic", [], [0.1], 1.0, 1.0, 2, 10),                    # empty span
         pp.make_problem(42, [], [0.1], 0.0, 1.0, 2, 10, d=1),                       # unknown field
         pp.make_problem("logistic", [], [float("nan")], 0.0, 1.0, 2, 10),           # non-finite y0
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, init=7),            # unknown start
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, init="coarse", coarse_points=-1),
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, init="coarse"),
     ]
     for b in bad:
         with pytest.raises(pp.ParapnError) as e:
