@@ -212,6 +212,22 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
                    const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
                    void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream);
 
+/* ParaRTS as parapn_pararts, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, and no hipMalloc, hipFree or other allocating call.
+ * Its scratch is one static device array per GPU of 64 MiB (held by the
+ * library until the process ends), shared by every call on that GPU and
+ * left holding the last call's contents (nothing in it needs to start at
+ * zero).  Calls that overlap on one GPU race on that array.  Runs on the
+ * current HIP device; the arguments and outputs are those of
+ * parapn_pararts.  PARAPN_ENOMEM when the problem needs more scratch than
+ * the array holds (N above 46 667 at D = 8 in FP32, 22 495 in FP64, 13 700
+ * at D = 15 in FP32). */
+int parapn_pararts_noalloc(int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                           const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H,
+                           const void *dvec, void *mean_out, void *sqrtcov_out, void *filt_mean_out,
+                           void *filt_sqrtcov_out, void *stream);
+
 /* Batched square-root filtering operator (eq. sqrt-associative-filtering):
  * out_k = a_k (x)_f c_k for k < count, a earlier than c.  Each element is the
  * tuple (A [D][D], b [D], sqrtC [D][D], eta [D], sqrtJ [D][D]) stored

@@ -34,7 +34,7 @@ PRIORS = {"iwp": 0, "ioup": 1}
 INITS = {"constant": 0, "coarse": 1}
 STARTS = {0: "constant", 1: "coarse", 2: "given", 3: "coarse_failed"}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
-            "parapn_start_trajectory",
+            "parapn_start_trajectory", "parapn_pararts_noalloc",
             "parapn_pararts",
             "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
             "parapn_server_create", "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1065,6 +1066,10 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     return status;
 }
 
+namespace {
+int scratch_address(int device, void **out);
+}  // namespace
+
 extern "C" {
 
 const char *parapn_last_error(void) { return g_err.c_str(); }
@@ -1076,6 +1081,9 @@ int parapn_create(parapn_ctx **out, int device, size_t budget)
     PARAPN_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n) return fail(PARAPN_EINVAL, "no such device");
     PARAPN_HIP(hipSetDevice(device), "hipSetDevice");
+    void *scr = nullptr;  // the allocation-free entry point's scratch on this device
+    int src = scratch_address(device, &scr);
+    if (src) return src;
     parapn_ctx *c = new parapn_ctx{};
     c->device = device;
     c->budget = budget;
@@ -1293,35 +1301,35 @@ int parapn_solve_batch(parapn_ctx *ctx, const parapn_problem *p, int32_t batch, 
     return status;
 }
 
-int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
-                   const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
-                   void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks of ParaRTS (shared by both entry points); q_out = D/dobs - 1.
+int pararts_check(int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0, const void *sqrt_sigma0,
+                  const void *Phi, const void *sqrtQ, const void *H, const void *dvec, const void *mean_out, int *q_out)
 {
-    if (!ctx) return fail(PARAPN_EINVAL, "ctx is NULL");
     if (precision != PARAPN_FP64 && precision != PARAPN_FP32_SQRT) return fail(PARAPN_EINVAL, "unknown precision");
     if (dobs < 1 || D <= dobs || D > PARAPN_MAX_D || D % dobs != 0)
         return fail(PARAPN_EINVAL, "this build needs D = dobs*(q+1) with 1 <= q <= 4 and D <= 15");
-    const int d = dobs, q = D / dobs - 1;
-    if (parapn::config_supported(d, q) < 0) return fail(PARAPN_EINVAL, "unsupported (D, dobs)");
+    const int q = D / dobs - 1;
+    if (parapn::config_supported(dobs, q) < 0) return fail(PARAPN_EINVAL, "unsupported (D, dobs)");
     if (N < 1) return fail(PARAPN_EINVAL, "N must be >= 1");
     if (!mu0 || !sqrt_sigma0 || !Phi || !sqrtQ || !H || !dvec || !mean_out)
         return fail(PARAPN_EINVAL, "NULL input or mean_out");
-    const bool fp64 = precision == PARAPN_FP64;
-    const int esz = fp64 ? 8 : 4;
-    hipStream_t s = (hipStream_t)stream;
-    PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    PackPlan pl;
-    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
-    r[0].N = N;
-    int rc = plan_pack(fp64, d, q, r, true, 0, pl);
-    if (rc) return rc;
+    *q_out = q;
+    return PARAPN_OK;
+}
+
+// ParaRTS on a planned pack whose scratch starts at ws (device memory of at
+// least pl.L.total bytes).  Allocates nothing; waits for the stream.
+int pararts_run(char *ws, PackPlan &pl, int32_t D, int32_t dobs, int q, int64_t N, bool fp64, const void *mu0,
+                const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
+                void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, hipStream_t s)
+{
+    const int d = dobs, esz = fp64 ? 8 : 4;
     const PackLayout &L = pl.L;
-    rc = ensure_ws(ctx, L.total);
-    if (rc) return rc;
-    char *ws = (char *)ctx->ws;
     bind_plan(pl, ws);
-    ctx->consts_at = nullptr;  // both regions are overwritten below
-    ctx->reqs_at = nullptr;
     // initial-state record: mu0 followed by the canonical lower factor of Sigma0
     char *init = ws + L.consts;
     PARAPN_HIP(hipMemcpyAsync(init, mu0, (size_t)D * esz, hipMemcpyDeviceToDevice, s), "copy mu0");
@@ -1348,8 +1356,92 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     if (sqrtcov_out)
         PARAPN_HIP(parapn::launch_unscale(fp64, D, N, nullptr, nullptr, w.sPs, nullptr, sqrtcov_out, s),
                    "smoothed factors");
+    // the host table image must outlive its copy
     PARAPN_HIP(hipStreamSynchronize(s), "sync");
     return PARAPN_OK;
+}
+
+// Scratch of the allocation-free ParaRTS entry point: one array per device,
+// in the library's own device data, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (resolved once per
+// device, with that device current).
+int scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(PARAPN_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return PARAPN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                   const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
+                   void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream)
+{
+    if (!ctx) return fail(PARAPN_EINVAL, "ctx is NULL");
+    int q;
+    int rc = pararts_check(D, dobs, N, precision, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out, &q);
+    if (rc) return rc;
+    const bool fp64 = precision == PARAPN_FP64;
+    hipStream_t s = (hipStream_t)stream;
+    PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PackPlan pl;
+    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
+    r[0].N = N;
+    rc = plan_pack(fp64, dobs, q, r, true, 0, pl);
+    if (rc) return rc;
+    rc = ensure_ws(ctx, pl.L.total);
+    if (rc) return rc;
+    ctx->consts_at = nullptr;  // both regions are overwritten
+    ctx->reqs_at = nullptr;
+    return pararts_run((char *)ctx->ws, pl, D, dobs, q, N, fp64, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out,
+                       sqrtcov_out, filt_mean_out, filt_sqrtcov_out, s);
+}
+
+int parapn_pararts_noalloc(int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                           const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H,
+                           const void *dvec, void *mean_out, void *sqrtcov_out, void *filt_mean_out,
+                           void *filt_sqrtcov_out, void *stream)
+{
+    int q;
+    int rc = pararts_check(D, dobs, N, precision, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out, &q);
+    if (rc) return rc;
+    const bool fp64 = precision == PARAPN_FP64;
+    hipStream_t s = (hipStream_t)stream;
+    PackPlan pl;
+    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
+    r[0].N = N;
+    rc = plan_pack(fp64, dobs, q, r, true, 0, pl);
+    if (rc) return rc;
+    if (pl.L.total > kNoAllocScratchBytes)
+        return fail(PARAPN_ENOMEM, "parapn_pararts_noalloc: this problem needs " + std::to_string(pl.L.total) +
+                                       " bytes of scratch; the static scratch holds " +
+                                       std::to_string(kNoAllocScratchBytes) + " (use parapn_pararts)");
+    int device = 0;
+    PARAPN_HIP(hipGetDevice(&device), "hipGetDevice");
+    void *ws = nullptr;
+    rc = scratch_address(device, &ws);
+    if (rc) return rc;
+    return pararts_run((char *)ws, pl, D, dobs, q, N, fp64, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out,
+                       sqrtcov_out, filt_mean_out, filt_sqrtcov_out, s);
 }
 
 int parapn_filter_combine(parapn_ctx *ctx, int32_t D, int64_t count, int32_t precision, const void *a, const void *c,

@@ -136,3 +136,20 @@ def test_dense_engine_host_checks():
     with pytest.raises(pp.ParapnError) as e:
         pp.server_footprint("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, precision="fp32")
     assert e.value.code == pp.EINVAL
+
+
+def test_noalloc_entry_point_refuses_problems_beyond_its_scratch():
+    """parapn_pararts_noalloc checks the size against its static scratch
+    before touching the device (PARAPN_ENOMEM with a message)."""
+    import paper_2310_01145_amd as pp
+
+    L = pp.load_library()
+    L.parapn_pararts_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32] + \
+        [ctypes.c_void_p] * 11
+    L.parapn_pararts_noalloc.restype = ctypes.c_int
+    fake = [ctypes.c_void_p(256)] * 6 + [ctypes.c_void_p(256), None, None, None, None]
+    rc = L.parapn_pararts_noalloc(8, 2, 10_000_000, pp.FP32_SQRT, *fake)
+    assert rc == pp.ENOMEM
+    assert "static scratch" in pp.last_error()
+    rc = L.parapn_pararts_noalloc(8, 2, 100, 7, *fake)
+    assert rc == pp.EINVAL
