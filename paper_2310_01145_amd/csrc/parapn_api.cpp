@@ -587,7 +587,7 @@ struct CoarseLayout {
     size_t node, gain, W, mu0c, status, cd, req, consts, total;
 };
 
-CoarseLayout coarse_layout(const Solve &sv, int esz)
+CoarseLayout coarse_layout(const Solve &sv)
 {
     CoarseLayout c{};
     coarse_grid(sv.N, sv.coarse_target, c.s, c.M);
@@ -598,14 +598,15 @@ CoarseLayout coarse_layout(const Solve &sv, int esz)
         o = align_up(o + b);
         return r;
     };
+    const size_t d = sv.d;
     c.node = take((size_t)(c.M + 1) * D * 8);
-    c.gain = take((size_t)c.M * (D * D + D) * esz);
+    c.gain = take((size_t)(c.M + 1) * (D + D * D + 2 * d * D + d) * 8);
     c.W = take((size_t)c.s * S * 2 * S * 8);
     c.mu0c = take(D * 8);
     c.status = take(sizeof(int));
     c.cd = take(sizeof(parapn::CoarseDev));
     c.req = take(sizeof(parapn::ReqDev));
-    c.consts = take(2 * D * D * esz);
+    c.consts = take(2 * D * D * 8);
     c.total = o;
     return c;
 }
@@ -615,11 +616,18 @@ CoarseLayout coarse_layout(const Solve &sv, int esz)
 // Waits for the stream (the host tables are locals; the verdict is read back).
 int coarse_start(Solve &sv, bool fp64, char *base, const CoarseLayout &cl, double *traj, hipStream_t s)
 {
-    const int D = sv.D, esz = fp64 ? 8 : 4;
+    const int D = sv.D, S = sv.q + 1;
     std::vector<double> Tc, W, Phi, sQ;
     precond_diag(sv.d, sv.q, (double)cl.s * sv.h, Tc);
     bridge_weights(sv.q, cl.s, W);
     prior_blocks(sv.d, sv.q, Phi, sQ);  // the IWP prior, whatever the solve's prior
+    // [Phi | Q]: the preconditioned process-noise covariance has the entries
+    // 1/(2q+1-i-j) per component block
+    std::vector<double> cst((size_t)2 * D * D, 0.0);
+    for (int i = 0; i < D * D; ++i) cst[i] = Phi[i];
+    for (int b = 0; b < sv.d; ++b)
+        for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j) cst[D * D + (b * S + i) * D + b * S + j] = 1.0 / (2 * sv.q + 1 - i - j);
     std::vector<double> mu0c(D);
     for (int k = 0; k < D; ++k) mu0c[k] = sv.mu0[k] / Tc[k];
     parapn::CoarseDev cd{};
@@ -636,24 +644,15 @@ int coarse_start(Solve &sv, bool fp64, char *base, const CoarseLayout &cl, doubl
     cd.status = (int *)(base + cl.status);
     parapn::ReqDev rq;
     fill_reqdev(sv, traj, nullptr, rq);
-    std::vector<unsigned char> cst((size_t)2 * D * D * esz);
-    for (int i = 0; i < D * D; ++i) {
-        if (fp64) {
-            ((double *)cst.data())[i] = Phi[i];
-            ((double *)cst.data())[D * D + i] = sQ[i];
-        } else {
-            ((float *)cst.data())[i] = (float)Phi[i];
-            ((float *)cst.data())[D * D + i] = (float)sQ[i];
-        }
-    }
     PARAPN_HIP(hipMemcpyAsync(base + cl.W, W.data(), W.size() * 8, hipMemcpyHostToDevice, s), "copy bridge weights");
     PARAPN_HIP(hipMemcpyAsync(base + cl.mu0c, mu0c.data(), D * 8, hipMemcpyHostToDevice, s), "copy mu0");
     PARAPN_HIP(hipMemcpyAsync(base + cl.cd, &cd, sizeof(cd), hipMemcpyHostToDevice, s), "copy coarse table");
     PARAPN_HIP(hipMemcpyAsync(base + cl.req, &rq, sizeof(rq), hipMemcpyHostToDevice, s), "copy request table");
-    PARAPN_HIP(hipMemcpyAsync(base + cl.consts, cst.data(), cst.size(), hipMemcpyHostToDevice, s), "copy constants");
+    PARAPN_HIP(hipMemcpyAsync(base + cl.consts, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, s),
+               "copy constants");
     PARAPN_HIP(parapn::launch_coarse(fp64, sv.d, sv.q, (const parapn::ReqDev *)(base + cl.req),
                                      (const parapn::CoarseDev *)(base + cl.cd), 1, sv.N, base + cl.consts,
-                                     base + cl.consts + (size_t)D * D * esz, s),
+                                     base + cl.consts + (size_t)D * D * 8, s),
                "coarse start");
     int status = 0;
     PARAPN_HIP(hipMemcpyAsync(&status, base + cl.status, sizeof(int), hipMemcpyDeviceToHost, s), "read status");
@@ -1125,7 +1124,7 @@ int parapn_workspace_size(const parapn_problem *p, size_t *bytes)
         Solve sv;
         rc = prepare(p, sv);
         if (rc) return rc;
-        resident += coarse_layout(sv, p->precision == PARAPN_FP64 ? 8 : 4).total;
+        resident += coarse_layout(sv).total;
     }
     PackPlan pl;
     rc = plan_pack(p->precision == PARAPN_FP64, p->d, q, r, true, resident, pl);
@@ -1158,7 +1157,7 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     std::vector<parapn::ReqDev> r(1);
     fill_reqdev(sv, nullptr, nullptr, r[0]);
     const bool coarse = !p->init_traj && sv.init_mode == PARAPN_INIT_COARSE;
-    const CoarseLayout cl = coarse ? coarse_layout(sv, esz) : CoarseLayout{};
+    const CoarseLayout cl = coarse ? coarse_layout(sv) : CoarseLayout{};
     rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv) + cl.total, pl, sv.lm_sigma > 0.0);
     if (rc) return rc;
     const PackLayout &L = pl.L;
@@ -1247,7 +1246,7 @@ int parapn_start_trajectory(parapn_ctx *ctx, const parapn_problem *p, double *tr
     rc = prepare(p, sv);
     if (rc) return rc;
     const bool coarse = !p->init_traj && sv.init_mode == PARAPN_INIT_COARSE;
-    const CoarseLayout cl = coarse ? coarse_layout(sv, p->precision == PARAPN_FP64 ? 8 : 4) : CoarseLayout{};
+    const CoarseLayout cl = coarse ? coarse_layout(sv) : CoarseLayout{};
     rc = ensure_ws(ctx, resident_bytes(sv) + cl.total);
     if (rc) return rc;
     char *ws = (char *)ctx->ws;

@@ -52,7 +52,8 @@ struct CoarseDev {
     int64_t M, s;                // coarse steps; fine steps per coarse step
     double T0, T1, invT1, hq;    // scales of E0 / E1 in the coordinates of the coarse step H, and H/q
     double *node;                // [M+1][D] FP64: filtering means, then (in place) smoothed means
-    void *gain;                  // [M][D*D + D], path precision: RTS gain E_k and E_k k_{k+1}
+    void *gain;                  // [M+1] FP64 records: m^f_k, P_k (D x D), then for k >= 1 Hbar_k (d x D),
+                                 // K_k (D x d) and S_k^-1 r_k (d)
     const double *mu0c;          // [D] mu0 in the coordinates of H
     const double *W;             // [s][q+1][2(q+1)] bridge weights per fine offset o = 0..s-1
     int *status;                 // written by the smoother: 0, or 1 when a coarse value is not finite
@@ -156,19 +157,19 @@ hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, c
                           bool src_fp64 = false);
 // Coarse-grid start for nreq requests of one (precision, d, q): the
 // sequential extended Kalman smoother on each request's coarse grid
-// (k_coarse_eks, one group of lanes per request), then the bridge of the
-// smoothed coarse means to every fine row of the request's resident
-// trajectory (k_coarse_bridge).  Phi, sQ: the IWP prior's preconditioned
-// constants in the path precision.  reqs and cds are device arrays; maxN is
-// the largest N among the requests.
+// (k_coarse_eks, one wavefront per request, FP64 for either precision),
+// then the bridge of the smoothed coarse means to every fine row of the
+// request's resident trajectory (k_coarse_bridge).  Phi, Q: the IWP prior's
+// preconditioned transition and process-noise covariance, FP64 [D][D].
+// reqs and cds are device arrays; maxN is the largest N among the requests.
 template <typename T>
 hipError_t launch_coarse_t(int d, int q, const ReqDev *reqs, const CoarseDev *cds, int nreq, int64_t maxN,
-                           const void *Phi, const void *sQ, hipStream_t s);
+                           const void *Phi, const void *Q, hipStream_t s);
 inline hipError_t launch_coarse(int fp64, int d, int q, const ReqDev *reqs, const CoarseDev *cds, int nreq,
-                                int64_t maxN, const void *Phi, const void *sQ, hipStream_t s)
+                                int64_t maxN, const void *Phi, const void *Q, hipStream_t s)
 {
-    return fp64 ? launch_coarse_t<double>(d, q, reqs, cds, nreq, maxN, Phi, sQ, s)
-                : launch_coarse_t<float>(d, q, reqs, cds, nreq, maxN, Phi, sQ, s);
+    return fp64 ? launch_coarse_t<double>(d, q, reqs, cds, nreq, maxN, Phi, Q, s)
+                : launch_coarse_t<float>(d, q, reqs, cds, nreq, maxN, Phi, Q, s);
 }
 // traj [N+1][D] = preconditioned starting trajectory (k_init_traj)
 hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s);

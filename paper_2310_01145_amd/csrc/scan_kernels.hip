@@ -1534,111 +1534,294 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
 // starting trajectory from a coarse grid (remark on other initial state
 // trajectories, Sec. 3.2.2)
 // ---------------------------------------------------------------------------
-// One group of lanes per request runs the sequential extended Kalman
-// smoother on the request's coarse grid: M steps of H = s h, in the
-// coordinates of H, with the IWP prior's h-independent Phi and sqrtQ.  Each
-// step predicts, linearises the vector field at the predicted mean (EK1,
-// Sec. 3.2.1) and updates.  The Kalman step is kf_step_se run on the
-// correction relative to the predicted mean: its prior mean is 0 and the
-// observation residual is the ODE defect at the predicted mean,
-//   r = (f(T0 E0 m-) - T1 E1 m-) / T1,
-// so it returns the correction k = K r, the next factor, and the RTS gain
-// E_{n-1} with E_{n-1} k_n.  Means are carried in FP64.  The backward pass
-// runs the RTS recursion on the correction c_n = m^s_n - m^f_n,
-//   c_{n-1} = E_{n-1} c_n + E_{n-1} k_n,   c_M = 0,
-// and overwrites each coarse node's filtering mean with its smoothed mean.
-template <class C>
-__global__ __launch_bounds__(C::NT) void k_coarse_eks(const ReqDev *reqs, const CoarseDev *cds, int nreq,
-                                                      const typename C::T *Phi, const typename C::T *sQ)
+// One wavefront per request runs the sequential extended Kalman smoother on
+// the request's coarse grid: M steps of H = s h, in the coordinates of H
+// with the IWP prior's h-independent Phi, Q, in FP64 and covariance form
+// (the sequential recursion is latency-bound: every lane owns entries of the
+// D x D covariance, so a step is a few short dot products, not a chain of
+// reflections).  Filter step n: predict m- = Phi m, P- = Phi P Phi^T + Q;
+// linearise the vector field at the predicted mean (EK1, Sec. 3.2.1):
+//   Hbar = E1 - (H/q) F_y E0,  r = (f(T0 E0 m-) - T1 E1 m-) / T1;
+// update with U = P- Hbar^T, S = Hbar U = L_S L_S^T:
+//   K = U S^-1,  z = S^-1 r,  m = m- + K r,  P = (I - K Hbar) P- (I - K Hbar)^T
+// (the Joseph form: the plain P- - K S K^T loses the small eigenvalues of the
+// rank-deficient noiseless-data covariance to cancellation).
+// Smoother (the RTS means, written without inverting P-): with
+// nu_{M+1} = 0 and t_n = Phi^T nu_{n+1},
+//   m^s_n = m^f_n + P_n t_n,   nu_n = Hbar_n^T (z_n - K_n^T t_n) + t_n,
+// which is m^s_n = m^f_n + G_n (m^s_{n+1} - m-_{n+1}) with the RTS gain
+// G_n = P_n Phi^T (P-_{n+1})^-1 and nu_{n+1} = (P-_{n+1})^-1 (m^s_{n+1} -
+// m-_{n+1}).  Per coarse node the records hold m^f_n, P_n, and for n >= 1
+// Hbar_n, K_n and z_n; the smoothed means go to the node array.
+template <int d, int q>
+__global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const CoarseDev *cds, const double *Phi,
+                                                   const double *Q)
 {
-    PARAPN_GROUP_SETUP(C);
-    load_consts<C>(cphi, csq, Phi, sQ);
-    constexpr int d = C::d, D = C::D, S = C::S, LDM = C::LDM, GR = D * D + D;
-    __shared__ double dsh[C::GPB][2 * LDM];
-    const int ri = blockIdx.x * C::GPB + grp;
-    if (ri >= nreq) return;  // no block-wide barrier follows
-    const CoarseDev cd = cds[ri];
-    const int field = reqs[ri].field;
-    const double *prm = reqs[ri].p;
-    double *dm = dsh[grp], *dp = dsh[grp] + LDM;
-    T *gain = (T *)cd.gain;
-    double m = lane < D ? cd.mu0c[lane] : 0.0;
-    SRow<C> st;
-    st.m = 0;
+    constexpr int S = q + 1, D = d * S, DD = D * D, EPL = (DD + 63) / 64;
+    constexpr int REC = D + DD + 2 * d * D + d;
+    __shared__ double sPhi[DD], sQ[DD], sP[DD], sA[DD], sB[DD], sPp[DD], sm[D], smp[D], sH[d * D], sU[D * d],
+        sK[D * d], st[D], snu[D], su[d];
+    const int lane = threadIdx.x;
+    const ReqDev &rq = reqs[blockIdx.x];
+    const CoarseDev cd = cds[blockIdx.x];
+    const int field = rq.field;
+    // the parameters in registers: the loop stores to global memory, so
+    // values read through the request table would be reloaded every step
+    double prm[kMaxParams];
 #pragma unroll
-    for (int c = 0; c < D; ++c) st.P[c] = 0;
+    for (int i = 0; i < kMaxParams; ++i) prm[i] = rq.p[i];
+    double *rec = (double *)cd.gain;
+    for (int e = lane; e < DD; e += 64) {
+        sPhi[e] = Phi[e];
+        sQ[e] = Q[e];
+        sP[e] = 0.0;
+    }
+    if (lane < D) sm[lane] = cd.mu0c[lane];
+    wave_sync();
     bool bad = false;
     for (int64_t n = 1; n <= cd.M; ++n) {
-        if (lane < D) {
-            dm[lane] = m;
-            cd.node[(n - 1) * D + lane] = m;
-        }
-        wave_sync();
-        double mp = 0.0;
-        if (lane < D) {
+        double *rp = rec + (n - 1) * REC;  // node n-1: m^f, P
+        if (lane < D) rp[lane] = sm[lane];
+        for (int e = lane; e < DD; e += 64) rp[D + e] = sP[e];
+        // A = Phi P, m- = Phi m
 #pragma unroll
-            for (int k = 0; k < D; ++k) mp += (double)cphi[lane * LDM + k] * dm[k];
-            dp[lane] = mp;
+        for (int k = 0; k < EPL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < DD) {
+                const int i = e / D, j = e % D;
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += sPhi[i * D + l] * sP[l * D + j];
+                sA[e] = acc;
+            }
+        }
+        if (lane < D) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += sPhi[lane * D + l] * sm[l];
+            smp[lane] = acc;
         }
         wave_sync();
-        // EK1 observation at the predicted mean
+        // P- = A Phi^T + Q
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < DD) {
+                const int i = e / D, j = e % D;
+                double acc = sQ[e];
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += sA[i * D + l] * sPhi[j * D + l];
+                sPp[e] = acc;
+            }
+        }
+        // EK1 observation at the predicted mean (every lane evaluates it)
         Dual<double, d> yd[d], fd[d];
 #pragma unroll
         for (int i = 0; i < d; ++i) {
-            yd[i].v = cd.T0 * dp[i * S];
+            yd[i].v = cd.T0 * smp[i * S];
 #pragma unroll
             for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
         }
         field_eval<d>(field, prm, yd, fd);
+        double r[d];
 #pragma unroll
-        for (int i = 0; i < d; ++i)
-            if (lane == i) {
+        for (int a = 0; a < d; ++a) r[a] = (fd[a].v - cd.T1 * smp[a * S + 1]) * cd.invT1;
+        for (int e = lane; e < d * D; e += 64) {
+            const int a = e / D, c = e % D;
+            double h = (c == a * S + 1) ? 1.0 : 0.0;
+            if (c % S == 0) h -= cd.hq * fd[a].g[c / S];
+            sH[e] = h;
+        }
+        wave_sync();
+        // U = P- Hbar^T (D x d)
+        for (int e = lane; e < D * d; e += 64) {
+            const int i = e / d, a = e % d;
+            double acc = 0.0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) sh[C::HO + i * LDM + c] = 0;
+            for (int l = 0; l < D; ++l) acc += sPp[i * D + l] * sH[a * D + l];
+            sU[e] = acc;
+        }
+        wave_sync();
+        // S = Hbar U and its Cholesky factor (d <= 3: every lane)
+        double L[d][d];
 #pragma unroll
-                for (int j = 0; j < d; ++j) sh[C::HO + i * LDM + j * S] = (T)(-cd.hq * fd[i].g[j]);
-                sh[C::HO + i * LDM + i * S + 1] += T(1);
-                sh[C::DVO + i] = (T)((fd[i].v - cd.T1 * dp[i * S + 1]) * cd.invT1);
+        for (int a = 0; a < d; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += sH[a * D + l] * sU[l * d + b];
+                L[a][b] = acc;
             }
-        if (lane < D) sh[C::UO + lane] = 0;
-        wave_sync();
-        ERow<C> eo;
-        T mfp;
-        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp);
-        if (lane >= D && lane < C::D2) {
-            T *g = gain + (n - 1) * GR;
+        // (one FP64 division per diagonal entry; the substitutions multiply
+        // by the reciprocals)
+        double inv[d];
 #pragma unroll
-            for (int c = 0; c < D; ++c) g[(lane - D) * D + c] = eo.E[c];
-            g[D * D + lane - D] = eo.g;
-        }
-        if (lane < D) {
-            m = mp + (double)st.m;
-            bad |= !__builtin_isfinite(m);
-        }
-        st.m = 0;
-    }
-    if (lane < D) cd.node[cd.M * D + lane] = m;
-    double c = 0.0;
-    for (int64_t n = cd.M - 1; n >= 0; --n) {
-        if (lane < D) dm[lane] = c;
-        wave_sync();
-        if (lane < D) {
-            const T *g = gain + n * GR;
-            double cn = (double)g[D * D + lane];
+        for (int b = 0; b < d; ++b) {
+            double dg = L[b][b];
 #pragma unroll
-            for (int k = 0; k < D; ++k) cn += (double)g[lane * D + k] * dm[k];
-            c = cn;
-            const double ms = cd.node[n * D + lane] + c;
-            cd.node[n * D + lane] = ms;
-            bad |= !__builtin_isfinite(ms);
+            for (int c = 0; c < b; ++c) dg -= L[b][c] * L[b][c];
+            dg = __builtin_sqrt(dg);
+            L[b][b] = dg;
+            inv[b] = 1.0 / dg;
+#pragma unroll
+            for (int a = b + 1; a < d; ++a) {
+                double v = L[a][b];
+#pragma unroll
+                for (int c = 0; c < b; ++c) v -= L[a][c] * L[b][c];
+                L[a][b] = v * inv[b];
+            }
+        }
+        // z = S^-1 r (forward then backward substitution)
+        double z[d];
+#pragma unroll
+        for (int a = 0; a < d; ++a) {
+            double v = r[a];
+#pragma unroll
+            for (int c = 0; c < a; ++c) v -= L[a][c] * z[c];
+            z[a] = v * inv[a];
+        }
+#pragma unroll
+        for (int a = d - 1; a >= 0; --a) {
+            double v = z[a];
+#pragma unroll
+            for (int c = a + 1; c < d; ++c) v -= L[c][a] * z[c];
+            z[a] = v * inv[a];
+        }
+        // K = U S^-1 (row i: W_i L_S^T = U_i, then K_i L_S = W_i)
+        double *rn = rec + n * REC;  // step n: Hbar, K, z after node n's m^f, P
+        if (lane < D) {
+            double w[d], kk[d];
+#pragma unroll
+            for (int a = 0; a < d; ++a) {
+                double v = sU[lane * d + a];
+#pragma unroll
+                for (int c = 0; c < a; ++c) v -= w[c] * L[a][c];
+                w[a] = v * inv[a];
+            }
+#pragma unroll
+            for (int a = d - 1; a >= 0; --a) {
+                double v = w[a];
+#pragma unroll
+                for (int c = a + 1; c < d; ++c) v -= kk[c] * L[c][a];
+                kk[a] = v * inv[a];
+            }
+            double mn = smp[lane];
+#pragma unroll
+            for (int a = 0; a < d; ++a) {
+                sK[lane * d + a] = kk[a];
+                rn[D + DD + d * D + lane * d + a] = kk[a];
+                mn += kk[a] * r[a];
+            }
+            sm[lane] = mn;
+            bad |= !__builtin_isfinite(mn);
+        }
+        for (int e = lane; e < d * D; e += 64) rn[D + DD + e] = sH[e];
+        if (lane < d) rn[D + DD + 2 * d * D + lane] = z[lane];
+        wave_sync();
+        // P = A P- A^T with A = I - K Hbar (into sA; the old A is consumed)
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < DD) {
+                const int i = e / D, j = e % D;
+                double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                for (int a = 0; a < d; ++a) acc -= sK[i * d + a] * sH[a * D + j];
+                sA[e] = acc;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < DD) {
+                const int i = e / D, j = e % D;
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += sA[i * D + l] * sPp[l * D + j];
+                sB[e] = acc;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < DD) {
+                const int i = e / D, j = e % D;
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc += sB[i * D + l] * sA[j * D + l];
+                sP[e] = acc;
+            }
         }
         wave_sync();
     }
-    // the group's verdict (lanes of a group share one wavefront)
+    {
+        double *rp = rec + cd.M * REC;
+        if (lane < D) rp[lane] = sm[lane];
+        for (int e = lane; e < DD; e += 64) rp[D + e] = sP[e];
+    }
+    // smoother.  Each lane's share of a record (its row of P and m^f, its
+    // column of Hbar; lanes < d their column of K and entry of z) is loaded
+    // one step ahead, so the global-memory latency overlaps the previous
+    // step's arithmetic.
+    if (lane < D) snu[lane] = 0.0;
+    struct Share {
+        double mf, P[D], H[d], K[D], z;
+    };
+    auto load_share = [&](int64_t n, Share &sh) {
+        const double *rp = rec + n * REC;
+        const int r = lane < D ? lane : 0, a = lane < d ? lane : 0;
+        sh.mf = rp[r];
+#pragma unroll
+        for (int l = 0; l < D; ++l) sh.P[l] = rp[D + r * D + l];
+        if (n >= 1) {
+#pragma unroll
+            for (int b = 0; b < d; ++b) sh.H[b] = rp[D + DD + b * D + r];
+#pragma unroll
+            for (int l = 0; l < D; ++l) sh.K[l] = rp[D + DD + d * D + l * d + a];
+            sh.z = rp[D + DD + 2 * d * D + a];
+        }
+    };
+    Share cur, nxt;
+    load_share(cd.M, cur);
+    wave_sync();
+    for (int64_t n = cd.M; n >= 0; --n) {
+        if (n >= 1) load_share(n - 1, nxt);
+        // t = Phi^T nu_{n+1}
+        if (lane < D) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += sPhi[l * D + lane] * snu[l];
+            st[lane] = acc;
+        }
+        wave_sync();
+        if (lane < D) {
+            double acc = cur.mf;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += cur.P[l] * st[l];
+            cd.node[n * D + lane] = acc;
+            bad |= !__builtin_isfinite(acc);
+        }
+        if (n >= 1 && lane < d) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc += cur.K[l] * st[l];
+            su[lane] = cur.z - acc;
+        }
+        wave_sync();
+        if (n >= 1 && lane < D) {
+            double acc = st[lane];
+#pragma unroll
+            for (int a = 0; a < d; ++a) acc += cur.H[a] * su[a];
+            snu[lane] = acc;
+        }
+        wave_sync();
+        cur = nxt;
+    }
     const unsigned long long ballot = __ballot(bad ? 1 : 0);
-    const int first = (threadIdx.x & 63) & ~(C::R - 1);
-    const unsigned long long gmask = (C::R == 64 ? ~0ull : ((1ull << C::R) - 1ull)) << first;
-    if (lane == 0) *cd.status = (ballot & gmask) ? 1 : 0;
+    if (lane == 0) *cd.status = ballot ? 1 : 0;
 }
 
 // Fine row j of request blockIdx.y lies o = j mod s steps after coarse node
@@ -1928,13 +2111,14 @@ hipError_t launch_tria_square_t(int d, int q, const void *full, void *out, hipSt
 
 template <typename T>
 hipError_t launch_coarse_t(int d, int q, const ReqDev *reqs, const CoarseDev *cds, int nreq, int64_t maxN,
-                           const void *Phi, const void *sQ, hipStream_t s)
+                           const void *Phi, const void *Q, hipStream_t s)
 {
     if (nreq < 1 || nreq > 65535 || maxN < 1) return hipErrorInvalidValue;
-    hipError_t e = dispatch_t<T>(d, q, [&](auto cfg) {
+    // the coarse smoother runs in FP64 for either path precision
+    hipError_t e = dispatch_t<double>(d, q, [&](auto cfg) {
         using C = decltype(cfg);
-        PARAPN_LAUNCH("coarse_eks", s, k_coarse_eks<C>, dim3((unsigned)cdiv(nreq, C::GPB)), dim3(C::NT), 0, s, reqs,
-                      cds, nreq, (const T *)Phi, (const T *)sQ);
+        PARAPN_LAUNCH("coarse_eks", s, (k_coarse_eks<C::d, C::q>), dim3((unsigned)nreq), dim3(64), 0, s, reqs, cds,
+                      (const double *)Phi, (const double *)Q);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
