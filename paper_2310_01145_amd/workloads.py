@@ -19,7 +19,8 @@ Problems:
                   u0 = 0.5 + 0.1 sin(2 pi x_i) + N(0, 0.01^2) noise (seed = instance).
 
 reference_start(spec) gives a starting trajectory near a problem's solution
-(a classical Runge-Kutta solution from scipy, an input like any other).
+(the values of a classical Runge-Kutta solution from scipy, an input like any
+other).
 """
 from __future__ import annotations
 
@@ -99,60 +100,11 @@ _FIELDS = {
 }
 
 
-class _Series:
-    """Truncated Taylor series in t, vectorised over grid points: c[k] is the
-    k-th coefficient (arrays).  Supports what the polynomial fields use."""
-
-    def __init__(self, c):
-        self.c = c
-
-    @staticmethod
-    def _lift(x, like):
-        if isinstance(x, _Series):
-            return x
-        c = [np.zeros_like(like.c[0]) for _ in like.c]
-        c[0] = c[0] + x
-        return _Series(c)
-
-    def __add__(self, o):
-        o = _Series._lift(o, self)
-        return _Series([a + b for a, b in zip(self.c, o.c)])
-
-    __radd__ = __add__
-
-    def __neg__(self):
-        return _Series([-a for a in self.c])
-
-    def __sub__(self, o):
-        return self + (-_Series._lift(o, self))
-
-    def __rsub__(self, o):
-        return _Series._lift(o, self) - self
-
-    def __mul__(self, o):
-        if not isinstance(o, _Series):
-            return _Series([a * o for a in self.c])
-        K = len(self.c)
-        return _Series([sum(self.c[j] * o.c[k - j] for j in range(k + 1)) for k in range(K)])
-
-    __rmul__ = __mul__
-
-    def __truediv__(self, x):
-        return _Series([a / x for a in self.c])
-
-    def __pow__(self, n):
-        out = self
-        for _ in range(n - 1):
-            out = out * self
-        return out
-
-
 def reference_start(spec):
-    """[N+1, d(q+1)] starting trajectory near the solution: the values from
-    scipy's DOP853 (rtol 1e-12) on the grid, and at every grid point the
-    derivatives 1..q of the solution through that value, from the Taylor
-    recursion of the (polynomial) vector field.  For problems whose
-    Gauss-Newton iteration from the constant start breaks down."""
+    """[N+1, d(q+1)] starting trajectory near a problem's solution: the
+    values of scipy's DOP853 solution (rtol 1e-12) on the grid, derivative
+    rows zero (Alg. 2 reads only E0 of a start).  An input like any other,
+    for tests that need a start other than the solver's own."""
     from scipy.integrate import solve_ivp
 
     f = _FIELDS[spec["field"]]
@@ -162,16 +114,7 @@ def reference_start(spec):
     sol = solve_ivp(lambda t, y: f(p, y), (spec["t0"], spec["t1"]), spec["y0"], method="DOP853", rtol=1e-12,
                     atol=1e-12, t_eval=ts)
     d = len(spec["y0"])
-    # Taylor coefficients y_k of y(t + s) at every grid point: y_{k+1} = [f(y)]_k / (k + 1)
-    ys = [_Series([sol.y[i].copy()] + [np.zeros(N + 1) for _ in range(q)]) for i in range(d)]
-    for k in range(q):
-        fy = f(p, ys)
-        for i in range(d):
-            ys[i].c[k + 1] = fy[i].c[k] / (k + 1)
     tr = np.zeros((N + 1, d * (q + 1)))
-    fact = 1.0
-    for k in range(q + 1):
-        fact = fact * k if k > 0 else 1.0
-        for i in range(d):
-            tr[:, i * (q + 1) + k] = fact * ys[i].c[k]
+    for i in range(d):
+        tr[:, i * (q + 1)] = sol.y[i]
     return tr

@@ -300,20 +300,32 @@ def test_damped_ieks_matches_the_damped_oracle(pp, spec, k):
         assert relerr(e0(np_(r["mean"]), q), e0(ref["mean"], q)) < tol, prec
 
 
-def test_damping_keeps_the_scan_close_to_the_sequential_smoother(pp):
-    """FitzHugh-Nagumo from the constant start, N = 1024: at the second and
-    later iterates the undamped scan is far from the sequential smoother (the
-    method's conditioning, see test_scan_conditioning.py); with damping the
-    GPU iterates follow the damped oracle."""
+def test_damped_iterates_follow_the_damped_oracle_from_the_constant_start(pp):
+    """FitzHugh-Nagumo from the constant start, N = 1024: Gauss-Newton
+    diverges here in the sequential smoother too (its second increment is
+    larger than the first); damped, the GPU iterates follow the damped oracle.
+    The gate is 1e-6: along these unstable iterates the log-depth composition
+    of the scan amplifies rounding (test_scan_conditioning.py)."""
     spec = wl.fhn(N=1024)
     args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
     k, lm = 4, 0.05
     ref = oracle.ieks(*args, fixed_iters=k, want_cov=False, lm_sigma=lm)
-    plain_ref = oracle.ieks(*args, fixed_iters=k, want_cov=False)
     r = pp.solve(*args, precision="fp64", fixed_iters=k, lm_sigma=lm)
-    p = pp.solve(*args, precision="fp64", fixed_iters=k)
     assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < 1e-6
-    assert relerr(e0(np_(p["mean"]), 3), e0(plain_ref["mean"], 3)) > 1e-2
+
+
+@pytest.mark.parametrize("lm", [0.0, 0.05])
+def test_iterates_from_a_start_in_the_basin_match_the_oracle(pp, lm):
+    """The same problem from the oracle's coarse-grid start (passed to both
+    sides as the starting trajectory), where Gauss-Newton converges: undamped
+    and damped iterates match the sequential smoother at 1e-9."""
+    spec = wl.fhn(N=1024)
+    args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+    start = oracle.coarse_start(*args)
+    ref = oracle.ieks(*args, fixed_iters=4, want_cov=False, lm_sigma=lm, init_traj=start)
+    r = pp.solve(*args, precision="fp64", fixed_iters=4, lm_sigma=lm, init_traj=start)
+    assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < 1e-9
+    assert np.allclose(r["deltas"], ref["deltas"], rtol=1e-6)
 
 
 def test_damped_solve_returns_the_undamped_posterior_factors(pp):
@@ -329,8 +341,10 @@ def test_damped_solve_returns_the_undamped_posterior_factors(pp):
 # full size, in the configuration bench.py times
 # ---------------------------------------------------------------------------
 def test_fhn_full_size_matches_the_oracle(pp):
-    """FitzHugh-Nagumo at N = 2^18 from bench.py's starting trajectory
-    (device-resident, as timed), two iterations, both precisions."""
+    """FitzHugh-Nagumo at N = 2^18 from a device-resident starting trajectory
+    (the DOP853 values on the grid, derivative rows zero), two iterations,
+    both precisions.  (bench.py's configuration -- the solver's own
+    coarse-grid start -- is tested in test_gpu_start.py.)"""
     import torch
 
     spec = wl.fhn(N=1 << 18)
@@ -341,8 +355,9 @@ def test_fhn_full_size_matches_the_oracle(pp):
     for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
         r = pp.solve(*args, precision=prec, fixed_iters=2, init_traj=dev)
         assert r["status"] == 0
-        # the start is converged to ~1e-10, so delta is rounding-level: it is
-        # compared on the solution's scale, with the gate of the means
+        # the start's E0 values are within ~1e-10 of the fixed point, so delta
+        # is rounding-level: it is compared on the solution's scale, with the
+        # gate of the means
         scale = np.abs(e0(ref["mean"], 3)).max()
         assert np.abs(r["deltas"] - ref["deltas"]).max() < tol * scale
         assert relerr(e0(np_(r["mean"]), 3), e0(ref["mean"], 3)) < tol, prec
@@ -389,11 +404,13 @@ def test_fp32_refines_to_the_fp64_solution_at_full_size(pp):
 
 
 def test_lorenz_full_size_first_iteration(pp):
-    """Lorenz-63 at N = 2^18, q = 4 (D = 15) from bench.py's start, one
+    """Lorenz-63 at N = 2^18, q = 4 (D = 15) from the coarse-grid start that
+    bench.py's solves compute (here the oracle's, passed to both sides), one
     iteration.  Chaos amplifies rounding like exp(0.9 t): FP32 is gated on
     t <= 8, FP64 on t <= 15 (the readings of the Lorenz gates)."""
     spec = wl.lorenz(N=1 << 18)
-    start = wl.reference_start(spec)
+    start = oracle.coarse_start(spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"],
+                                spec["N"])
     args = (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
     ref = oracle.ieks(*args, fixed_iters=1, want_cov=False, init_traj=start)
     ref0 = e0(ref["mean"], 4)
