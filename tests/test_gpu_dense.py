@@ -186,3 +186,50 @@ def test_dense_batch_isolates_a_non_finite_instance(pp):
                      tol=1e-10, max_iter=20)
         assert a["status"] == pp.OK and out["iterations"][b] == a["iterations"]
         assert same(out["mean"][b], a["mean"]), b
+
+
+_REF_CACHE = {}
+
+
+def _ref(key, sp, k, want_cov):
+    if key not in _REF_CACHE:
+        _REF_CACHE[key] = oracle.ieks(*spec_args(sp), fixed_iters=k, want_cov=want_cov)
+    return _REF_CACHE[key]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_dense_d64_at_128_steps_matches_oracle(pp, prec, tol):
+    """d = 64 (D = 192) at the benchmark's step size and N = 128 steps: seven
+    sweep levels each way, with a 2D x 2D = 384 x 384 triangularisation per
+    general combine."""
+    sp = workloads.mol(d=64, N=128, q=2, seed=7, t1=128.0 / 4096)
+    ref = _ref("d64n128", sp, 2, True)
+    print("dense d=64 N=128 %s" % prec, flush=True)
+    out = pp.solve(*spec_args(sp), precision=prec, fixed_iters=2, want_cov=True)
+    assert out["status"] == pp.OK
+    e = rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3])
+    S, R = sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])
+    c = rel(S, R) if prec == "fp64" else rel(S[:, ::3, ::3], R[:, ::3, ::3])
+    print("  E0 mean rel err %.2e, covariance rel err %.2e" % (e, c))
+    assert e < tol
+    # FP32: the E0 block of the covariances (measured 1.2e-5)
+    assert c < (1e-9 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_dense_workgroup_stride_loop_matches_oracle(pp, prec, tol):
+    """d = 8, q = 2 (D = 24), N = 4096 over [0, 1] (the benchmark's N and h):
+    the first sweep level has 2048 pairs, more than the resident workgroups
+    (1024 in FP32, 512 in FP64), so each workgroup strides over several
+    pairs; twelve levels each way."""
+    sp = workloads.mol(d=8, N=4096, q=2, seed=11, t1=1.0)
+    ref = _ref("d8n4096", sp, 2, True)
+    print("dense d=8 N=4096 %s" % prec, flush=True)
+    out = pp.solve(*spec_args(sp), precision=prec, fixed_iters=2, want_cov=True)
+    assert out["status"] == pp.OK
+    e = rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3])
+    print("  E0 mean rel err %.2e" % e)
+    assert e < tol
+    np.testing.assert_allclose(out["deltas"], ref["deltas"], rtol=(1e-6 if prec == "fp64" else 1e-2))
+    if prec == "fp64":
+        assert rel(sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
