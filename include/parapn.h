@@ -257,22 +257,33 @@ int parapn_profile_read(int32_t max, char *names, int32_t name_len, double *tota
  * parapn_server_step performs one Gauss-Newton iteration (linearisation, the
  * forward filtering scan, the reverse smoothing scan, the trajectory update;
  * Alg. 1 inside Alg. 2) for all active requests, packing requests that share
- * (precision, d, q) into one pair of scans.  Requests never mix: the first
+ * (precision, d, q, damping) into one pair of scans.  The packs of a step are
+ * queued back to back on the server's stream and the step waits once, so
+ * their device work overlaps.  A pack whose composition did not change since
+ * the previous step replays a HIP graph of its iteration (captured once the
+ * composition has lasted a step; not on the legacy default stream, and not
+ * while parapn_profile_enable is on).  Requests never mix: the first
  * filtering element of each request resets the forward prefix and its last
  * smoothing element cuts the reverse suffix, so one request's NaN or
  * divergence cannot reach another (each converges on its own Delta, Alg. 2's
  * stopping rule).  A finished request's smoothed means are written to its
- * mean_out (device, [N+1][d(q+1)], its precision's element type) and a
- * completion record is queued.  Requests start from the constant trajectory
- * (init_traj must be NULL); covariances are not produced.
+ * mean_out (device, [N+1][d(q+1)], its precision's element type), and its
+ * square-root covariances (the factors of the last linearisation, [N+1][D][D]
+ * lower-triangular) to sqrtcov_out when one was given; a completion record
+ * is queued.  Requests start from mu0 or, with init_mode = PARAPN_INIT_COARSE,
+ * from their coarse-grid start, computed at admission for all requests
+ * admitted in a step in one launch per (d, q) (init_traj must be NULL).
  *
  * Admission is in submission order, limited by max_slots active requests and
  * by hbm_budget_bytes (0 = unlimited) summed over the admitted requests'
- * footprints (resident FP64 trajectory plus their share of the scan scratch);
- * a request waits in the queue until both allow it.  The scan scratch lives
- * in the context's workspace (shared by all packs of a step).  mean_out must
- * stay valid until the request's completion is polled.  One server per
- * context; a server is not thread-safe. */
+ * footprints (resident FP64 trajectory, their share of the scan scratch, and
+ * their coarse start); a request waits in the queue until both allow it.
+ * Resident trajectories come from a pool of device chunks that the server
+ * keeps until it is destroyed, and every pack keeps its own scratch between
+ * steps, so once a stream's working set has been reached a step allocates
+ * nothing.  mean_out and sqrtcov_out must stay valid until the request's
+ * completion is polled.  One server per context; a server is not
+ * thread-safe. */
 typedef struct parapn_server parapn_server;
 
 typedef struct {
@@ -281,6 +292,7 @@ typedef struct {
     int32_t iterations;  /* Gauss-Newton iterations performed */
     double final_delta;  /* Delta of the last iteration */
     double t_submit, t_start, t_done; /* parapn_server_clock() at submission, admission, completion */
+    int32_t start;       /* PARAPN_START_*: the starting trajectory used */
 } parapn_completion;
 
 /* stream: HIP stream for all of the server's work (NULL = default stream).
@@ -288,21 +300,24 @@ typedef struct {
 int parapn_server_create(parapn_server **srv, parapn_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes,
                          void *stream);
 /* Waits for the server's stream, frees every request (queued or active)
- * without writing their outputs. */
+ * without writing their outputs, and releases the server's device memory. */
 void parapn_server_destroy(parapn_server *srv);
 /* Seconds on a monotonic clock (the one completion times use). */
 double parapn_server_clock(void);
 /* Queue one request (validated as for parapn_solve; init_traj must be NULL).
- * PARAPN_ENOMEM if its footprint alone exceeds the server budget. */
-int parapn_server_submit(parapn_server *srv, const parapn_problem *prob, uint64_t req_id, void *mean_out);
+ * sqrtcov_out: device [N+1][D][D] for the request's square-root covariances,
+ * or NULL.  PARAPN_ENOMEM if its footprint alone exceeds the server budget. */
+int parapn_server_submit(parapn_server *srv, const parapn_problem *prob, uint64_t req_id, void *mean_out,
+                         void *sqrtcov_out);
 /* Admit what fits, run one iteration for all active requests, retire the
  * finished ones.  Returns after the device work of the step is complete.
  * *n_active / *n_queued (either may be NULL): requests still active / waiting. */
 int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued);
 /* Move up to max completion records into out (oldest first); *n_out = count. */
 int parapn_server_poll(parapn_server *srv, parapn_completion *out, int32_t max, int32_t *n_out);
-/* Footprint (bytes) that admission charges for a request: its resident FP64
- * trajectory plus its share of the scan scratch.  Errors as for submit. */
+/* Footprint (bytes) that admission charges for a request without covariances:
+ * its resident FP64 trajectory, its share of the scan scratch and its coarse
+ * start.  Errors as for submit. */
 int parapn_server_footprint(const parapn_problem *prob, size_t *bytes);
 /* Admitted bytes now and at most so far; requests admitted and completed.
  * Any output pointer may be NULL. */

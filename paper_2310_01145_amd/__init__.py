@@ -92,6 +92,7 @@ class Completion(ctypes.Structure):
         ("t_submit", ctypes.c_double),
         ("t_start", ctypes.c_double),
         ("t_done", ctypes.c_double),
+        ("start", ctypes.c_int32),
     ]
 
 
@@ -139,7 +140,7 @@ def load_library(path: str = LIB_PATH):
     L.parapn_server_destroy.restype = None
     L.parapn_server_clock.argtypes = []
     L.parapn_server_clock.restype = ctypes.c_double
-    L.parapn_server_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_uint64, vp]
+    L.parapn_server_submit.argtypes = [vp, ctypes.POINTER(Problem), ctypes.c_uint64, vp, vp]
     L.parapn_server_submit.restype = ctypes.c_int
     L.parapn_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.parapn_server_step.restype = ctypes.c_int
@@ -406,10 +407,14 @@ class Server:
     allocated at submission and kept until the completion is polled."""
 
     def __init__(self, max_slots=64, budget=0, device=0, stream=None, ctx_budget=0):
+        """stream: the HIP stream of all the server's work; by default a
+        stream of its own (default priority), on which an unchanged pack
+        replays a captured graph of its iteration (the legacy default stream
+        cannot be captured: on it every launch is issued anew)."""
         torch = _torch()
         self._L = load_library()
         self._device = device
-        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = ctypes.c_void_p()
         _check(self._L.parapn_server_create(ctypes.byref(h), context(device, ctx_budget), int(max_slots), int(budget),
                                             ctypes.c_void_p(self._stream.cuda_stream)))
@@ -417,14 +422,18 @@ class Server:
         self._pending = {}
 
     def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
-               fixed_iters=0, d=None, lm_sigma=0.0, prior="iwp", theta=0.0):
+               fixed_iters=0, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0,
+               want_cov=False):
         torch = _torch()
         pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                          fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta)
+                          fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta, init=init,
+                          coarse_points=coarse_points)
         D = pb.d * (pb.q + 1)
-        mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=torch.device("cuda", self._device))
-        _check(self._L.parapn_server_submit(self._h, ctypes.byref(pb), int(req_id), _dptr(mean)))
-        self._pending[int(req_id)] = mean
+        dev = torch.device("cuda", self._device)
+        mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=dev)
+        cov = torch.empty((pb.N + 1, D, D), dtype=_dtype(pb.precision), device=dev) if want_cov else None
+        _check(self._L.parapn_server_submit(self._h, ctypes.byref(pb), int(req_id), _dptr(mean), _dptr(cov)))
+        self._pending[int(req_id)] = (mean, cov)
         return mean
 
     def step(self):
@@ -435,16 +444,17 @@ class Server:
 
     def poll(self, max_records=1024):
         """List of completion dicts (req_id, status, iterations, final_delta,
-        t_submit, t_start, t_done, mean)."""
+        t_submit, t_start, t_done, start, mean, sqrtcov)."""
         buf = (Completion * max_records)()
         n = ctypes.c_int32()
         _check(self._L.parapn_server_poll(self._h, buf, max_records, ctypes.byref(n)))
         out = []
         for k in range(n.value):
             c = buf[k]
+            mean, cov = self._pending.pop(c.req_id, (None, None))
             out.append({"req_id": c.req_id, "status": c.status, "iterations": c.iterations,
                         "final_delta": c.final_delta, "t_submit": c.t_submit, "t_start": c.t_start,
-                        "t_done": c.t_done, "mean": self._pending.pop(c.req_id, None)})
+                        "t_done": c.t_done, "start": STARTS.get(c.start, c.start), "mean": mean, "sqrtcov": cov})
         return out
 
     def clock(self):

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -809,7 +810,7 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
         ctx->reqs_key = pl->image;
     }
     unsigned long long *dbits = (unsigned long long *)(ws + L.dbits);
-    PARAPN_HIP(hipMemsetAsync(dbits, 0, 2 * nreq * sizeof(unsigned long long), s), "memset");
+    PARAPN_HIP(parapn::launch_zero_u64(dbits, 2 * nreq, s), "reset delta slots");
     parapn::Pack pk = pl->pk;
     pk.mode = 0;
     pk.lm = s0.lm_sigma > 0.0 ? 1 : 0;
@@ -1014,7 +1015,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     while (true) {
         PARAPN_HIP(hipMemcpyAsync(active_dev, active.data(), (size_t)B * sizeof(int), hipMemcpyHostToDevice, s),
                    "copy flags");
-        PARAPN_HIP(hipMemsetAsync(w.dbits, 0, (size_t)2 * B * sizeof(unsigned long long), s), "memset");
+        PARAPN_HIP(parapn::launch_zero_u64(w.dbits, 2 * (int64_t)B, s), "reset delta slots");
         PARAPN_HIP(parapn::dense_iteration(fp64, md, w, s), "dense iteration");
         PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, w.dbits, (size_t)2 * B * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, s),
@@ -1501,14 +1502,167 @@ double now_seconds()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Device chunks (hipMalloc'd when the pool first needs them) carved first-fit
+// for resident trajectories and returned with coalescing; chunks live until
+// the server is destroyed, so a stream whose working set has been reached
+// allocates nothing.
+struct Pool {
+    struct Chunk {
+        char *base;
+        size_t size;
+        std::map<size_t, size_t> free;  // offset -> length
+    };
+    std::vector<Chunk> chunks;
+
+    int alloc(size_t bytes, char **out)
+    {
+        bytes = align_up(bytes);
+        for (auto &c : chunks)
+            for (auto it = c.free.begin(); it != c.free.end(); ++it)
+                if (it->second >= bytes) {
+                    const size_t off = it->first, len = it->second;
+                    c.free.erase(it);
+                    if (len > bytes) c.free[off + bytes] = len - bytes;
+                    *out = c.base + off;
+                    return PARAPN_OK;
+                }
+        const size_t sz = std::max(bytes, size_t(256) << 20);
+        char *p = nullptr;
+        if (hipMalloc((void **)&p, sz) != hipSuccess) return fail(PARAPN_ENOMEM, "server pool: hipMalloc failed");
+        Chunk c{p, sz, {}};
+        if (sz > bytes) c.free[bytes] = sz - bytes;
+        chunks.push_back(std::move(c));
+        *out = p;
+        return PARAPN_OK;
+    }
+    void release(char *p, size_t bytes)
+    {
+        bytes = align_up(bytes);
+        for (auto &c : chunks)
+            if (p >= c.base && p < c.base + c.size) {
+                auto it = c.free.emplace((size_t)(p - c.base), bytes).first;
+                auto nx = std::next(it);
+                if (nx != c.free.end() && it->first + it->second == nx->first) {
+                    it->second += nx->second;
+                    c.free.erase(nx);
+                }
+                if (it != c.free.begin()) {
+                    auto pv = std::prev(it);
+                    if (pv->first + pv->second == it->first) {
+                        pv->second += it->second;
+                        c.free.erase(it);
+                    }
+                }
+                return;
+            }
+    }
+    void destroy()
+    {
+        for (auto &c : chunks) hipFree(c.base);
+        chunks.clear();
+    }
+};
+
+// Device buffer that only grows (call between steps: nothing may be in flight).
+struct DevBuf {
+    char *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n, bool *moved = nullptr)
+    {
+        if (n <= cap) return PARAPN_OK;
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = std::max(n, n / 2 * 3);
+        if (hipMalloc((void **)&p, want) != hipSuccess) return fail(PARAPN_ENOMEM, "server scratch: hipMalloc failed");
+        cap = want;
+        if (moved) *moved = true;
+        return PARAPN_OK;
+    }
+    void destroy()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Pinned host buffer that only grows.
+struct HostBuf {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n)
+    {
+        if (n <= cap) return PARAPN_OK;
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = std::max(n, n / 2 * 3);
+        if (hipHostMalloc((void **)&p, want, hipHostMallocDefault) != hipSuccess)
+            return fail(PARAPN_ENOMEM, "server staging: hipHostMalloc failed");
+        cap = want;
+        return PARAPN_OK;
+    }
+    void destroy()
+    {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
 struct ServedReq {
     uint64_t id;
     Solve sv;
-    void *mean_out;
-    double *resident;  // device: trajectory, T, mu0/T
-    size_t bytes;      // admitted footprint (resident + pack scratch share)
+    void *mean_out, *cov_out;
+    char *resident;
+    size_t res_bytes, bytes;  // resident trajectory; admitted footprint
     double t_submit, t_start;
+    int adm_slot;             // this step's coarse-start status word, or -1
 };
+
+// One pack per (precision, d, q, damped): its own scratch (tables, elements,
+// scan levels, delta slots), pinned staging, and the graph of one iteration
+// of its current composition.  The tables are rebuilt only when the
+// composition changes; a graph is captured once a composition has lasted one
+// step and replayed while it lasts.
+struct PackState {
+    DevBuf dev;
+    HostBuf img, bits;
+    std::vector<const ServedReq *> sig;
+    bool cov = false;
+    PackPlan plan;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int stable = 0;
+    std::vector<ServedReq *> members;
+    std::vector<Solve *> solves;
+
+    void drop_graph()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+// scratch of a request's coarse-grid start (transient: its admission step)
+size_t coarse_bytes(const Solve &sv) { return sv.init_mode == PARAPN_INIT_COARSE ? coarse_layout(sv).total : 0; }
+
+// admitted footprint of a request: its resident trajectory, its scan scratch
+// (in a pack, the same region it would use alone) and its coarse start
+size_t footprint(const Solve &sv, bool cov)
+{
+    std::vector<parapn::ReqDev> r(1);
+    fill_reqdev(sv, nullptr, nullptr, r[0]);
+    PackPlan pl;
+    if (plan_pack(sv.precision == PARAPN_FP64, sv.d, sv.q, r, cov, 0, pl, sv.lm_sigma > 0.0) != PARAPN_OK)
+        return SIZE_MAX;
+    return resident_bytes(sv) + pl.L.total + coarse_bytes(sv);
+}
+
+int pack_key(const Solve &v) { return (((v.precision == PARAPN_FP64 ? 1 : 0) * 4 + v.d) * 8 + v.q) * 2 + (v.lm_sigma > 0.0); }
 
 }  // namespace
 
@@ -1521,18 +1675,215 @@ struct parapn_server {
     std::deque<ServedReq *> queue;
     std::vector<ServedReq *> active;
     std::deque<parapn_completion> done;
+    Pool pool;
+    std::map<int, PackState> packs;
+    DevBuf adm_dev;  // coarse starts of one step's admissions
+    HostBuf stage;   // pinned staging of one step's admissions
 };
 
-// admitted footprint of a request: its resident trajectory plus its scan
-// scratch, which in a pack is the same region it would use alone
-static size_t footprint(const Solve &sv)
+namespace {
+
+// Queue one iteration of a pack (delta slots reset, forward scan, reverse
+// scan with the trajectory update, delta read-back into the pack's pinned
+// bits).  Only launches and a device-to-host copy: capturable.
+int pack_iteration_enqueue(PackState &pk, bool fp64, int d, int q, hipStream_t s)
 {
-    std::vector<parapn::ReqDev> r(1);
-    fill_reqdev(sv, nullptr, nullptr, r[0]);
-    PackPlan pl;
-    if (plan_pack(sv.precision == PARAPN_FP64, sv.d, sv.q, r, false, 0, pl) != PARAPN_OK) return SIZE_MAX;
-    return resident_bytes(sv) + pl.L.total;
+    const int nreq = (int)pk.members.size();
+    const int D = d * (q + 1), esz = fp64 ? 8 : 4;
+    const PackLayout &L = pk.plan.L;
+    char *ws = pk.dev.p;
+    unsigned long long *dbits = (unsigned long long *)(ws + L.dbits);
+    PARAPN_HIP(parapn::launch_zero_u64(dbits, 2 * (int64_t)nreq, s), "reset delta slots");
+    parapn::Pack p = pk.plan.pk;
+    p.mode = 0;
+    const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
+    const parapn::Work w = work_from(ws, L, false);
+    PARAPN_HIP(parapn::launch_forward(fp64, d, q, p, m, w, s), "forward scan");
+    PARAPN_HIP(parapn::launch_smoother(fp64, d, q, p, m, w, false, true, nullptr, s), "reverse scan");
+    PARAPN_HIP(hipMemcpyAsync(pk.bits.p, dbits, 2 * (size_t)nreq * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              s),
+               "read delta");
+    return PARAPN_OK;
 }
+
+// (Re)build a pack's tables for its members, upload them and its constants.
+int pack_replan(PackState &pk, bool fp64, int d, int q, bool lm, hipStream_t s)
+{
+    const int nreq = (int)pk.members.size();
+    const int D = d * (q + 1);
+    std::vector<parapn::ReqDev> reqs(nreq);
+    for (int i = 0; i < nreq; ++i) fill_reqdev(pk.members[i]->sv, (double *)pk.members[i]->resident, nullptr, reqs[i]);
+    int rc = plan_pack(fp64, d, q, reqs, pk.cov, 0, pk.plan, lm);
+    if (rc) return rc;
+    bool moved = false;
+    rc = pk.dev.ensure(pk.plan.L.total, &moved);
+    if (rc) return rc;
+    if (moved) pk.drop_graph();
+    bind_plan(pk.plan, pk.dev.p);
+    // staging: constants [Phi | sqrtQ | initial increment state (0, 0)], then the table image
+    std::vector<double> Phi, sQ;
+    prior_blocks(d, q, Phi, sQ);
+    const size_t cbytes = (size_t)(3 * D * D + D) * (fp64 ? 8 : 4);
+    rc = pk.img.ensure(cbytes + pk.plan.image.size());
+    if (rc) return rc;
+    std::memset(pk.img.p, 0, cbytes);
+    for (int i = 0; i < D * D; ++i) {
+        if (fp64) {
+            ((double *)pk.img.p)[i] = Phi[i];
+            ((double *)pk.img.p)[D * D + i] = sQ[i];
+        } else {
+            ((float *)pk.img.p)[i] = (float)Phi[i];
+            ((float *)pk.img.p)[D * D + i] = (float)sQ[i];
+        }
+    }
+    std::memcpy(pk.img.p + cbytes, pk.plan.image.data(), pk.plan.image.size());
+    PARAPN_HIP(hipMemcpyAsync(pk.dev.p + pk.plan.L.consts, pk.img.p, cbytes, hipMemcpyHostToDevice, s),
+               "copy constants");
+    PARAPN_HIP(hipMemcpyAsync(pk.dev.p + pk.plan.L.reqs, pk.img.p + cbytes, pk.plan.image.size(),
+                              hipMemcpyHostToDevice, s),
+               "copy request tables");
+    rc = pk.bits.ensure(2 * (size_t)nreq * sizeof(unsigned long long));
+    return rc;
+}
+
+// Admission work of one step on the stream: every admitted request's resident
+// tail (T, mu0/T) and constant trajectory, then the coarse-grid starts of
+// those that asked for one, one launch per (d, q).  Host tables are staged
+// in pinned memory that stays untouched until the step's wait.
+int admit_enqueue(parapn_server *srv, std::vector<ServedReq *> &adm, hipStream_t s)
+{
+    if (adm.empty()) return PARAPN_OK;
+    // staging layout: tails, then per coarse group [reqs | cds | consts], then per
+    // coarse request [W | mu0c], then the status words (read back)
+    struct Item {
+        ServedReq *r;
+        CoarseLayout cl;
+        size_t w_off, mu_off;  // in the upload region
+        size_t node_off, gain_off;  // in the scratch region
+    };
+    std::map<int, std::vector<Item>> groups;  // by d * 8 + q
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t r = off;
+        off = align_up(off + b);
+        return r;
+    };
+    std::vector<size_t> tail_off(adm.size());
+    for (size_t i = 0; i < adm.size(); ++i) tail_off[i] = take((size_t)2 * adm[i]->sv.D * 8);
+    for (ServedReq *r : adm)
+        if (r->sv.init_mode == PARAPN_INIT_COARSE) groups[r->sv.d * 8 + r->sv.q].push_back(Item{r, coarse_layout(r->sv)});
+    struct Group {
+        int d, q;
+        size_t reqs_off, cds_off, consts_off;
+        std::vector<Item> *items;
+    };
+    std::vector<Group> gl;
+    int nstat = 0;
+    for (auto &kv : groups) {
+        Group g;
+        g.d = kv.first / 8;
+        g.q = kv.first % 8;
+        g.items = &kv.second;
+        const int n = (int)kv.second.size();
+        g.reqs_off = take((size_t)n * sizeof(parapn::ReqDev));
+        g.cds_off = take((size_t)n * sizeof(parapn::CoarseDev));
+        const int D = g.d * (g.q + 1);
+        g.consts_off = take((size_t)2 * D * D * 8);
+        for (Item &it : kv.second) {
+            it.w_off = take((size_t)it.cl.s * (g.q + 1) * 2 * (g.q + 1) * 8);
+            it.mu_off = take((size_t)D * 8);
+            it.r->adm_slot = nstat++;
+        }
+        gl.push_back(g);
+    }
+    const size_t status_off = take((size_t)std::max(nstat, 1) * sizeof(int));
+    const size_t upload = off;
+    // device scratch of the coarse smoothers after the upload region
+    for (auto &kv : groups)
+        for (Item &it : kv.second) {
+            it.node_off = take((size_t)(it.cl.M + 1) * it.r->sv.D * 8);
+            const size_t D = it.r->sv.D, d = it.r->sv.d;
+            it.gain_off = take((size_t)(it.cl.M + 1) * (D + D * D + 2 * d * D + d) * 8);
+        }
+    int rc = srv->stage.ensure(upload);
+    if (rc) return rc;
+    rc = srv->adm_dev.ensure(off);
+    if (rc) return rc;
+    unsigned char *h = srv->stage.p;
+    char *dv = srv->adm_dev.p;
+    // resident tails and the constant start
+    for (size_t i = 0; i < adm.size(); ++i) {
+        const Solve &v = adm[i]->sv;
+        double *t = (double *)(h + tail_off[i]);
+        for (int k = 0; k < v.D; ++k) {
+            t[k] = v.Td[k];
+            t[v.D + k] = v.mu0b[k];
+        }
+        double *traj = (double *)adm[i]->resident;
+        double *tail = traj + (size_t)(v.N + 1) * v.D;
+        PARAPN_HIP(hipMemcpyAsync(tail, t, (size_t)2 * v.D * 8, hipMemcpyHostToDevice, s), "copy T");
+        PARAPN_HIP(parapn::launch_init_traj(v.D, v.N, nullptr, tail, traj, s), "initial trajectory");
+    }
+    if (gl.empty()) return PARAPN_OK;
+    for (Group &g : gl) {
+        const int D = g.d * (g.q + 1), S = g.q + 1;
+        std::vector<double> Phi, sQ;
+        prior_blocks(g.d, g.q, Phi, sQ);
+        double *cst = (double *)(h + g.consts_off);
+        for (int i = 0; i < 2 * D * D; ++i) cst[i] = 0.0;
+        for (int i = 0; i < D * D; ++i) cst[i] = Phi[i];
+        for (int b = 0; b < g.d; ++b)
+            for (int i = 0; i < S; ++i)
+                for (int j = 0; j < S; ++j) cst[D * D + (b * S + i) * D + b * S + j] = 1.0 / (2 * g.q + 1 - i - j);
+        parapn::ReqDev *rq = (parapn::ReqDev *)(h + g.reqs_off);
+        parapn::CoarseDev *cd = (parapn::CoarseDev *)(h + g.cds_off);
+        int64_t maxN = 1;
+        for (size_t k = 0; k < g.items->size(); ++k) {
+            Item &it = (*g.items)[k];
+            Solve &v = it.r->sv;
+            std::vector<double> Tc, W;
+            precond_diag(v.d, v.q, (double)it.cl.s * v.h, Tc);
+            bridge_weights(v.q, it.cl.s, W);
+            std::memcpy(h + it.w_off, W.data(), W.size() * 8);
+            double *mu = (double *)(h + it.mu_off);
+            for (int j = 0; j < D; ++j) mu[j] = v.mu0[j] / Tc[j];
+            fill_reqdev(v, (double *)it.r->resident, nullptr, rq[k]);
+            parapn::CoarseDev c{};
+            c.M = it.cl.M;
+            c.s = it.cl.s;
+            c.T0 = Tc[0];
+            c.T1 = Tc[1];
+            c.invT1 = 1.0 / Tc[1];
+            c.hq = (double)it.cl.s * v.h / v.q;
+            c.node = (double *)(dv + it.node_off);
+            c.gain = dv + it.gain_off;
+            c.W = (const double *)(dv + it.w_off);
+            c.mu0c = (const double *)(dv + it.mu_off);
+            c.status = (int *)(dv + status_off) + it.r->adm_slot;
+            cd[k] = c;
+            maxN = std::max<int64_t>(maxN, v.N);
+        }
+        (void)maxN;
+    }
+    PARAPN_HIP(hipMemcpyAsync(dv, h, status_off, hipMemcpyHostToDevice, s), "copy coarse tables");
+    for (Group &g : gl) {
+        int64_t maxN = 1;
+        for (Item &it : *g.items) maxN = std::max<int64_t>(maxN, it.r->sv.N);
+        const int D = g.d * (g.q + 1);
+        PARAPN_HIP(parapn::launch_coarse(1, g.d, g.q, (const parapn::ReqDev *)(dv + g.reqs_off),
+                                         (const parapn::CoarseDev *)(dv + g.cds_off), (int)g.items->size(), maxN,
+                                         dv + g.consts_off, dv + g.consts_off + (size_t)D * D * 8, s),
+                   "coarse start");
+    }
+    PARAPN_HIP(hipMemcpyAsync(h + status_off, dv + status_off, (size_t)nstat * sizeof(int), hipMemcpyDeviceToHost, s),
+               "read coarse status");
+    // after the step's wait, each coarse request reads its word from here
+    for (auto &kv : groups)
+        for (Item &it : kv.second) it.r->adm_slot = (int)(status_off / sizeof(int)) + it.r->adm_slot;
+    return PARAPN_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1556,11 +1907,17 @@ void parapn_server_destroy(parapn_server *srv)
     if (!srv) return;
     hipSetDevice(srv->ctx->device);
     hipStreamSynchronize(srv->stream);
-    for (ServedReq *r : srv->active) {
-        if (r->resident) hipFree(r->resident);
-        delete r;
-    }
+    for (ServedReq *r : srv->active) delete r;
     for (ServedReq *r : srv->queue) delete r;
+    for (auto &kv : srv->packs) {
+        kv.second.drop_graph();
+        kv.second.dev.destroy();
+        kv.second.img.destroy();
+        kv.second.bits.destroy();
+    }
+    srv->adm_dev.destroy();
+    srv->stage.destroy();
+    srv->pool.destroy();
     delete srv;
 }
 
@@ -1577,7 +1934,7 @@ int parapn_server_footprint(const parapn_problem *p, size_t *bytes)
     Solve sv;
     rc = prepare(p, sv);
     if (rc) return rc;
-    *bytes = footprint(sv);
+    *bytes = footprint(sv, false);
     return *bytes == SIZE_MAX ? PARAPN_EINVAL : PARAPN_OK;
 }
 
@@ -1592,14 +1949,15 @@ int parapn_server_stats(parapn_server *srv, size_t *used_bytes, size_t *peak_byt
     return PARAPN_OK;
 }
 
-int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t req_id, void *mean_out)
+int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t req_id, void *mean_out,
+                         void *sqrtcov_out)
 {
     if (!srv) return fail(PARAPN_EINVAL, "server is NULL");
     int q, D;
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!mean_out) return fail(PARAPN_EINVAL, "mean_out is NULL");
-    if (p->init_traj) return fail(PARAPN_EINVAL, "served requests start from the constant trajectory");
+    if (p->init_traj) return fail(PARAPN_EINVAL, "served requests start from mu0 or their coarse-grid start");
     if (p->field == parapn::F_MOL) return fail(PARAPN_EINVAL, "the server does not batch the method-of-lines field");
     if (p->prior != PARAPN_PRIOR_IWP) return fail(PARAPN_EINVAL, "served requests use the IWP prior");
     ServedReq *r = new ServedReq{};
@@ -1610,7 +1968,10 @@ int parapn_server_submit(parapn_server *srv, const parapn_problem *p, uint64_t r
         return rc;
     }
     r->mean_out = mean_out;
-    r->bytes = footprint(r->sv);
+    r->cov_out = sqrtcov_out;
+    r->res_bytes = resident_bytes(r->sv);
+    r->bytes = footprint(r->sv, sqrtcov_out != nullptr);
+    r->adm_slot = -1;
     if (r->bytes == SIZE_MAX) {  // the reason is already recorded
         delete r;
         return PARAPN_EINVAL;
@@ -1629,73 +1990,153 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
     if (!srv) return fail(PARAPN_EINVAL, "server is NULL");
     hipStream_t s = srv->stream;
     PARAPN_HIP(hipSetDevice(srv->ctx->device), "hipSetDevice");
-    // admission in arrival order, by slots and HBM footprint
+    // 1. admission in arrival order, by slots and HBM footprint
+    std::vector<ServedReq *> adm;
     while (!srv->queue.empty() && (int)srv->active.size() < srv->max_slots) {
         ServedReq *r = srv->queue.front();
         if (srv->budget && srv->used + r->bytes > srv->budget) break;
-        hipError_t e = hipMalloc((void **)&r->resident, resident_bytes(r->sv));
-        if (e != hipSuccess) {
-            r->resident = nullptr;
-            break;  // wait for memory to free up
-        }
-        int rc = init_resident(r->sv, r->resident, nullptr, false, s);
-        if (rc) return rc;
+        if (srv->pool.alloc(r->res_bytes, &r->resident) != PARAPN_OK) break;  // wait for memory to free up
         r->t_start = now_seconds();
+        r->adm_slot = -1;
+        r->sv.start = PARAPN_START_CONSTANT;
         srv->used += r->bytes;
         srv->peak = std::max(srv->peak, srv->used);
         srv->admitted += 1;
         srv->queue.pop_front();
         srv->active.push_back(r);
+        adm.push_back(r);
     }
-    // one IEKS iteration for every active request, one pack per (precision, d, q, damped or not)
-    std::vector<int> order(srv->active.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::vector<bool> taken(order.size(), false);
-    for (size_t i = 0; i < order.size(); ++i) {
-        if (taken[i]) continue;
-        const Solve &k = srv->active[i]->sv;
-        std::vector<Solve *> pack;
-        std::vector<double *> trajs;
-        for (size_t j = i; j < order.size(); ++j) {
-            const Solve &o = srv->active[j]->sv;
-            if (!taken[j] && o.precision == k.precision && o.d == k.d && o.q == k.q &&
-                (o.lm_sigma > 0.0) == (k.lm_sigma > 0.0)) {
-                taken[j] = true;
-                pack.push_back(&srv->active[j]->sv);
-                trajs.push_back(srv->active[j]->resident);
-            }
-        }
-        int rc = pack_iteration(srv->ctx, pack, trajs, s);
-        if (rc) return rc;
+    int rc = admit_enqueue(srv, adm, s);
+    if (rc) return rc;
+    // 2. one IEKS iteration for every active request: the packs are queued
+    // back to back and their work overlaps on the device; one wait
+    for (auto &kv : srv->packs) {
+        kv.second.members.clear();
+        kv.second.solves.clear();
     }
-    // retire finished requests: write their means, free their memory
-    std::vector<ServedReq *> still;
     for (ServedReq *r : srv->active) {
-        if (!r->sv.done) {
-            still.push_back(r);
+        PackState &pk = srv->packs[pack_key(r->sv)];
+        pk.members.push_back(r);
+        pk.solves.push_back(&r->sv);
+    }
+    // graphs need a stream that can be captured (not the legacy default
+    // stream) and no per-launch timing events
+    const bool graphs = s != nullptr && !parapn::prof_on();
+    for (auto &kv : srv->packs) {
+        PackState &pk = kv.second;
+        if (pk.members.empty()) {
+            pk.sig.clear();
+            pk.drop_graph();
             continue;
         }
-        const Solve &v = r->sv;
-        const double *Tdev = r->resident + (size_t)(v.N + 1) * v.D;
-        PARAPN_HIP(parapn::launch_unscale(v.precision == PARAPN_FP64, v.D, v.N, Tdev, r->resident, nullptr,
-                                          r->mean_out, nullptr, s, true),
-                   "unscale");
-        PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        PARAPN_HIP(hipFree(r->resident), "hipFree");
-        srv->used -= r->bytes;
-        parapn_completion c{};
-        c.req_id = r->id;
-        c.status = v.status;
-        c.iterations = v.iter;
-        c.final_delta = v.delta;
-        c.t_submit = r->t_submit;
-        c.t_start = r->t_start;
-        c.t_done = now_seconds();
-        srv->done.push_back(c);
-        srv->completed += 1;
-        delete r;
+        const Solve &v0 = *pk.solves[0];
+        const bool fp64 = v0.precision == PARAPN_FP64, lm = v0.lm_sigma > 0.0;
+        bool cov = false;
+        for (ServedReq *r : pk.members) cov |= r->cov_out != nullptr;
+        std::vector<const ServedReq *> sig(pk.members.begin(), pk.members.end());
+        if (sig != pk.sig || cov != pk.cov) {
+            pk.drop_graph();
+            pk.sig = sig;
+            pk.cov = cov;
+            pk.stable = 0;
+            rc = pack_replan(pk, fp64, v0.d, v0.q, lm, s);
+            if (rc) return rc;
+        } else {
+            pk.stable += 1;
+        }
+        if (graphs && pk.stable >= 1) {
+            if (!pk.exec) {
+                PARAPN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+                rc = pack_iteration_enqueue(pk, fp64, v0.d, v0.q, s);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(s, &g);
+                if (rc) {
+                    if (g) hipGraphDestroy(g);
+                    return rc;
+                }
+                PARAPN_HIP(e, "end capture");
+                pk.graph = g;
+                PARAPN_HIP(hipGraphInstantiate(&pk.exec, pk.graph, nullptr, nullptr, 0), "graph instantiate");
+            }
+            PARAPN_HIP(hipGraphLaunch(pk.exec, s), "graph launch");
+        } else {
+            rc = pack_iteration_enqueue(pk, fp64, v0.d, v0.q, s);
+            if (rc) return rc;
+        }
     }
-    srv->active.swap(still);
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    for (ServedReq *r : adm)
+        if (r->adm_slot >= 0)
+            r->sv.start = ((const int *)srv->stage.p)[r->adm_slot] == 0 ? PARAPN_START_COARSE
+                                                                       : PARAPN_START_COARSE_FAILED;
+    for (auto &kv : srv->packs)
+        if (!kv.second.members.empty())
+            pack_finish(kv.second.solves, (const unsigned long long *)kv.second.bits.p);
+    // 3. retire the finished requests: their means (and factors) in original
+    // coordinates, then their memory back to the pool
+    bool any = false;
+    for (auto &kv : srv->packs) {
+        PackState &pk = kv.second;
+        if (pk.members.empty()) continue;
+        bool cov_done = false;
+        for (ServedReq *r : pk.members) cov_done |= r->sv.done && r->cov_out && r->sv.status != PARAPN_ENONFINITE;
+        const Solve &v0 = *pk.solves[0];
+        const bool fp64 = v0.precision == PARAPN_FP64;
+        const int D = v0.D, esz = fp64 ? 8 : 4;
+        const PackLayout &L = pk.plan.L;
+        if (cov_done) {
+            // smoothed factors of the last linearisation: the reverse scan with
+            // factors over the pack's smoothing elements (means to scratch)
+            parapn::Pack p = pk.plan.pk;
+            p.mode = 0;
+            const parapn::ModelDev m = model_from(pk.dev.p + L.consts, D, esz);
+            const parapn::Work w = work_from(pk.dev.p, L, true);
+            if (p.lm) {
+                p.lm = 0;
+                PARAPN_HIP(parapn::launch_forward(fp64, v0.d, v0.q, p, m, w, s), "undamped forward scan");
+            }
+            PARAPN_HIP(parapn::launch_smoother(fp64, v0.d, v0.q, p, m, w, true, false, w.mf, s), "covariance pass");
+        }
+        for (size_t i = 0; i < pk.members.size(); ++i) {
+            ServedReq *r = pk.members[i];
+            if (!r->sv.done) continue;
+            any = true;
+            const Solve &v = r->sv;
+            const double *traj = (const double *)r->resident;
+            const double *Tdev = traj + (size_t)(v.N + 1) * v.D;
+            const bool want = r->cov_out && v.status != PARAPN_ENONFINITE;
+            const char *sPs = want ? pk.dev.p + L.sPs + (size_t)pk.plan.reqs[i].row * (D * (D + 1) / 2) * esz : nullptr;
+            PARAPN_HIP(parapn::launch_unscale(fp64, v.D, v.N, Tdev, traj, sPs, r->mean_out, want ? r->cov_out : nullptr,
+                                              s, true),
+                       "unscale");
+        }
+    }
+    if (any) {
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        std::vector<ServedReq *> still;
+        for (ServedReq *r : srv->active) {
+            if (!r->sv.done) {
+                still.push_back(r);
+                continue;
+            }
+            srv->pool.release(r->resident, r->res_bytes);
+            srv->used -= r->bytes;
+            const Solve &v = r->sv;
+            parapn_completion c{};
+            c.req_id = r->id;
+            c.status = v.status;
+            c.iterations = v.iter;
+            c.final_delta = v.delta;
+            c.t_submit = r->t_submit;
+            c.t_start = r->t_start;
+            c.t_done = now_seconds();
+            c.start = v.start;
+            srv->done.push_back(c);
+            srv->completed += 1;
+            delete r;
+        }
+        srv->active.swap(still);
+    }
     if (n_active) *n_active = (int32_t)srv->active.size();
     if (n_queued) *n_queued = (int32_t)srv->queue.size();
     return PARAPN_OK;

@@ -171,6 +171,8 @@ inline hipError_t launch_coarse(int fp64, int d, int q, const ReqDev *reqs, cons
     return fp64 ? launch_coarse_t<double>(d, q, reqs, cds, nreq, maxN, Phi, Q, s)
                 : launch_coarse_t<float>(d, q, reqs, cds, nreq, maxN, Phi, Q, s);
 }
+// p[0..n) = 0 by a kernel (graph-capturable, unlike a memset node)
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 // traj [N+1][D] = preconditioned starting trajectory (k_init_traj)
 hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s);
 // index of an instantiated (d, q) configuration, or -1

@@ -2019,6 +2019,13 @@ __global__ void k_init_traj(int D, int64_t N, const T *init, const T *Td, T *tra
     traj[i] = (i < D || !init) ? Td[D + k] : init[i] / Td[k];
 }
 
+// zero n 64-bit words (a kernel, so that it may be captured in a graph)
+static __global__ void k_zero_u64(unsigned long long *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // canonical lower-triangular factor of a D x D square root (one group)
 template <class C>
 __global__ __launch_bounds__(C::R) void k_tria_square(const typename C::T *full, typename C::T *out)
@@ -2389,6 +2396,13 @@ hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, c
     else
         hipLaunchKernelGGL((k_unscale<float, float>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
                            (const float *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)
+{
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ def test_server_host_validation():
     L = pp.load_library()
     h = ctypes.c_void_p()
     assert L.parapn_server_create(ctypes.byref(h), None, 4, 0, None) == pp.EINVAL
-    assert L.parapn_server_submit(None, None, 0, None) == pp.EINVAL
+    assert L.parapn_server_submit(None, None, 0, None, None) == pp.EINVAL
     assert L.parapn_server_step(None, None, None) == pp.EINVAL
     assert L.parapn_server_poll(None, None, 0, None) == pp.EINVAL
     assert L.parapn_server_stats(None, None, None, None, None) == pp.EINVAL

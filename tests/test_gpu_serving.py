@@ -215,3 +215,81 @@ def test_damped_and_plain_requests_share_a_server(pp):
         assert same(done[i]["mean"], a["mean"]), i
     # the damping acts
     assert not same(done[0]["mean"], done[1]["mean"])
+
+
+def serve_on(pp, reqs, stream=None, max_slots=64):
+    srv = pp.Server(max_slots=max_slots, stream=stream)
+    for i, r in enumerate(reqs):
+        srv.submit(i, **r)
+    done = {}
+    steps = 0
+    while len(done) < len(reqs):
+        srv.step()
+        done.update({c["req_id"]: c for c in srv.poll()})
+        steps += 1
+        assert steps < 2000
+    srv.close()
+    return done
+
+
+COARSE_MIX = [
+    dict(req("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 100.0, 3, 6000, "fp64"), init="coarse"),
+    dict(req("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 100.0, 3, 3001, "fp32"), init="coarse"),
+    dict(req("lotka_volterra", [0.7, 1.2, 0.9, 1.1], [1.3, 0.8], 15.0, 2, 2500, "fp64"), init="coarse"),
+    dict(req("lotka_volterra", [1.3, 0.6, 1.1, 0.8], [0.9, 1.7], 15.0, 4, 777, "fp64"), init="coarse",
+         coarse_points=200),
+    dict(req("lotka_volterra", [0.7, 1.2, 0.9, 1.1], [1.3, 0.8], 15.0, 3, 1500, "fp32"), init="coarse"),
+    req("logistic", [], [0.01], 10.0, 2, 1000, "fp64"),
+]
+
+
+def test_coarse_start_requests_equal_their_solves(pp):
+    """Requests that start from their coarse-grid start (computed at
+    admission, one launch for all admitted requests of a (d, q)) converge and
+    are bitwise the solve of each alone (parapn_solve with the same start)."""
+    done = serve_on(pp, COARSE_MIX)
+    for i, r in enumerate(COARSE_MIX):
+        a = pp.solve(r["field"], r["params"], r["y0"], r["t0"], r["t1"], r["q"], r["N"], precision=r["precision"],
+                     tol=r["tol"], max_iter=r["max_iter"], init=r.get("init", "constant"),
+                     coarse_points=r.get("coarse_points", 0))
+        c = done[i]
+        assert c["start"] == a["start"] == ("coarse" if r.get("init") else "constant")
+        assert c["status"] == a["status"] == pp.OK, (i, c["status"], a["status"])
+        assert c["iterations"] == a["iterations"]
+        assert same(c["mean"], a["mean"]), i
+
+
+def test_graph_replays_equal_direct_launches(pp):
+    """The same stream of requests served on the legacy default stream
+    (every launch issued directly) and on the server's own stream (packs
+    whose composition lasts replay a captured graph): bitwise the same, at
+    every request -- every replay of every graph fed the next iteration."""
+    import torch
+
+    mix = MIX + COARSE_MIX
+    a = serve_on(pp, mix, stream=torch.cuda.default_stream())
+    b = serve_on(pp, mix)
+    for i in range(len(mix)):
+        assert a[i]["iterations"] == b[i]["iterations"]
+        assert same(a[i]["mean"], b[i]["mean"]), i
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_served_covariances_equal_the_solve(pp, prec):
+    """Requests that ask for covariances get the factors of their last
+    linearisation, bitwise those of parapn_solve with want_cov; a neighbour
+    without covariances shares the pack."""
+    mix = [dict(req("logistic", [], [0.01], 10.0, 2, 700, prec, k=5), want_cov=True),
+           req("logistic", [], [0.03], 10.0, 2, 300, prec, k=3),
+           dict(req("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 50.0, 3, 2000, prec), init="coarse", want_cov=True)]
+    done = serve_on(pp, mix)
+    for i, r in enumerate(mix):
+        a = pp.solve(r["field"], r["params"], r["y0"], r["t0"], r["t1"], r["q"], r["N"], precision=prec,
+                     fixed_iters=r["fixed_iters"], tol=r["tol"], max_iter=r["max_iter"],
+                     init=r.get("init", "constant"), want_cov=r.get("want_cov", False))
+        c = done[i]
+        assert same(c["mean"], a["mean"]), i
+        if r.get("want_cov"):
+            assert same(c["sqrtcov"], a["sqrtcov"]), i
+        else:
+            assert c["sqrtcov"] is None
