@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the logistic latency and the N sweep")
     ap.add_argument("--no-mol", action="store_true", help="skip the method-of-lines batch (dense engine, D=192)")
     ap.add_argument("--no-mol-fp64", action="store_true", help="method-of-lines batch in FP32 only")
+    ap.add_argument("--no-stream", action="store_true", help="skip the served stream (4096 requests)")
+    ap.add_argument("--stream-requests", type=int, default=4096)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -471,6 +473,12 @@ def main():
         del m32r
         if not args.no_cpu_baseline:
             line["mol_batch"]["cpu_baseline"] = mol_cpu_baseline()
+    if not args.no_stream:
+        from paper_2310_01145_amd import serve
+
+        st = serve.run(n_requests=args.stream_requests, load=0.8)
+        print("bench: served stream done", file=sys.stderr, flush=True)
+        line["served_stream"] = st
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line))

@@ -1570,10 +1570,12 @@ struct DevBuf {
     int ensure(size_t n, bool *moved = nullptr)
     {
         if (n <= cap) return PARAPN_OK;
+        // doubling from 64 MiB: a stream's packs reach their size in few steps
+        size_t want = std::max<size_t>(size_t(64) << 20, 2 * cap);
+        while (want < n) want *= 2;
         if (p) hipFree(p);
         p = nullptr;
         cap = 0;
-        const size_t want = std::max(n, n / 2 * 3);
         if (hipMalloc((void **)&p, want) != hipSuccess) return fail(PARAPN_ENOMEM, "server scratch: hipMalloc failed");
         cap = want;
         if (moved) *moved = true;
@@ -1597,7 +1599,8 @@ struct HostBuf {
         if (p) hipHostFree(p);
         p = nullptr;
         cap = 0;
-        const size_t want = std::max(n, n / 2 * 3);
+        size_t want = size_t(1) << 20;
+        while (want < n) want *= 2;
         if (hipHostMalloc((void **)&p, want, hipHostMallocDefault) != hipSuccess)
             return fail(PARAPN_ENOMEM, "server staging: hipHostMalloc failed");
         cap = want;
