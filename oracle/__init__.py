@@ -97,6 +97,13 @@ def lib():
         L.orc_iwp_bridge.restype = None
         L.orc_coarse_start.argtypes = [i, P, i, i, P, dl, dl, i, l, l, P]
         L.orc_coarse_start.restype = i
+        L.orc_kf_rts_qf.argtypes = [i, i, l, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_kf_rts_qf.restype = i
+        L.orc_objective.argtypes = [i, i, dl, l, P, i, dl]
+        L.orc_objective.restype = dl
+        L.orc_ieks_ext.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, i, dl, i, dl, dl, P, P, P, P, P,
+                                   P, ctypes.POINTER(ctypes.c_int)]
+        L.orc_ieks_ext.restype = i
         _lib = L
     return _lib
 
@@ -174,14 +181,23 @@ def precond_model(d, q, h):
     return PhiB, sQB, T
 
 
-def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None):
+def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None, return_qf=False):
     """Sequential square-root KF + RTS.  H is [N, dobs, D], dv [N, dobs];
     rstd (dobs) optional per-row observation noise standard deviations.
-    Returns (mf, sPf, ms, sPs), stacks over n = 0..N."""
+    Returns (mf, sPf, ms, sPs), stacks over n = 0..N; with return_qf (noiseless
+    rows only) also the sum of the innovations' quadratic forms."""
     mu0, S0, Phi, sqrtQ, H, dv = map(_f64, (mu0, S0, Phi, sqrtQ, H, dv))
     N, dobs, D = H.shape
     mf, ms = np.zeros((N + 1, D)), np.zeros((N + 1, D))
     sPf, sPs = np.zeros((N + 1, D, D)), np.zeros((N + 1, D, D))
+    if return_qf:
+        assert rstd is None
+        qf = ctypes.c_double(0.0)
+        rc = lib().orc_kf_rts_qf(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
+                                 _p(ms), _p(sPs), ctypes.byref(qf))
+        if rc != 0:
+            raise FloatingPointError("non-finite values in the sequential smoother")
+        return mf, sPf, ms, sPs, qf.value
     if rstd is None:
         rc = lib().orc_kf_rts(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
                               _p(ms), _p(sPs))
@@ -251,14 +267,31 @@ def coarse_start(field, params, y0, t0, t1, q, N, M_target=None, d=None):
     return out
 
 
+def objective(traj, q, h, d=None, prior="iwp", theta=0.0):
+    """V(eta) = 1/2 sum_n |eta_n - Phi eta_{n-1}|^2_{Q^-1} (eq. objective-value)
+    of a trajectory [N+1, D] in original coordinates."""
+    traj = _f64(traj)
+    Np1, D = traj.shape
+    dd = D // (q + 1) if d is None else d
+    return lib().orc_objective(dd, q, float(h), Np1 - 1, _p(traj), PRIORS[prior], float(theta))
+
+
+STOP_TRAJECTORY, STOP_OBJECTIVE = 1, 2
+
+
 def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
-         want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0, init=None, coarse_points=0):
+         want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0, init=None, coarse_points=0, stop_rule=1,
+         obj_atol=1e-9, obj_rtol=1e-6):
     """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
     sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas.
     lm_sigma > 0: Levenberg-Marquardt damping, a pseudo-observation of each
     step's E0 at the current iterate with std lm_sigma / sqrt(h).
     init="coarse": start from coarse_start(...) (coarse_points coarse steps,
-    0 = the default) instead of the constant mu0."""
+    0 = the default) instead of the constant mu0.  stop_rule: bit 0 the
+    trajectory change, bit 1 the objective change (|V_k - V_{k-1}| <=
+    obj_atol + obj_rtol |V_k|), either stops.  The result also carries
+    objectives (V after each iteration), objective0 (of the start) and sigma2
+    (the quasi-MLE diffusion of the last undamped filter pass)."""
     if init == "coarse":
         init_traj = coarse_start(field, params, y0, t0, t1, q, N, coarse_points or None, d=d)
     y0 = _f64(y0).ravel()
@@ -274,14 +307,18 @@ def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fix
     hist = np.zeros(max(max_iter, fixed_iters, 1))
     iters = ctypes.c_int(0)
     init = _f64(init_traj) if init_traj is not None else None
-    rc = lib().orc_ieks_prior(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
-                              float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
-                              PRIORS[prior], float(theta), _p(mean), _p(cov) if cov is not None else None, _p(hist),
-                              ctypes.byref(iters))
+    ohist = np.zeros_like(hist)
+    obj0, s2 = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().orc_ieks_ext(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
+                            float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
+                            PRIORS[prior], float(theta), int(stop_rule), float(obj_atol), float(obj_rtol), _p(mean),
+                            _p(cov) if cov is not None else None, _p(hist), _p(ohist), ctypes.byref(obj0),
+                            ctypes.byref(s2), ctypes.byref(iters))
     if rc == -1:
         raise ValueError("bad problem")
     k = iters.value
-    return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy()}
+    return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy(),
+            "objectives": ohist[:k].copy(), "objective0": obj0.value, "sigma2": s2.value}
 
 
 def filter_element(Phi, sqrtQ, H, dv, m_prev, sP_prev, first):

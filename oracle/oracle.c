@@ -548,9 +548,14 @@ static void precond_model(int d, int q, double h, double *PhiB, double *sQB, dou
 /* Observation rows may carry independent noise: rstd[r] is the standard
  * deviation of row r (NULL or 0: noiseless).  The update factor then comes
  * from tria([[H sqrtP-, diag(rstd)], [sqrtP-, 0]]). */
-int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
-                     const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
-                     double *sPf, double *ms, double *sPs)
+/* qf (may be NULL) receives the sum over n of the innovations' quadratic
+ * forms r_n^T S_n^-1 r_n, r_n = d_n - H_n m-_n, S_n = Psi11 Psi11^T: the
+ * prediction-error decomposition of the data's log-likelihood, whose
+ * maximiser over the diffusion sigma^2 is qf / (N dobs) (the quasi-maximum-
+ * likelihood calibration of Sec. 2.4; every covariance scales with sigma^2). */
+static int kf_rts_core(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+                       const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
+                       double *sPf, double *ms, double *sPs, double *qf)
 {
     int n2 = dobs + D;
     double *mp = dalloc(D), *sPp = dalloc(D * D), *M = dalloc((long)n2 * n2), *Psi = dalloc((long)n2 * n2);
@@ -589,6 +594,12 @@ int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S
         right_solve_lower(D, dobs, Ps11, Ps21, K); /* K = Psi21 Psi11^{-1} */
         mv(dobs, D, Hn, 0, mp, res);
         for (int r = 0; r < dobs; ++r) res[r] = dn[r] - res[r];
+        if (qf) {
+            double *x = dalloc(dobs);
+            lower_solve_vec(dobs, Ps11, res, x);
+            for (int r = 0; r < dobs; ++r) *qf += x[r] * x[r];
+            free(x);
+        }
         double *mo = mf + n * D, *so = sPf + n * D * D;
         mv(D, dobs, K, 0, res, v);
         for (int r = 0; r < D; ++r) mo[r] = mp[r] + v[r];
@@ -643,11 +654,67 @@ int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S
     return bad ? -4 : 0;
 }
 
+int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+                     const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
+                     double *sPf, double *ms, double *sPs)
+{
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, rstd, mf, sPf, ms, sPs, NULL);
+}
+
 int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
                const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf,
                double *ms, double *sPs)
 {
-    return orc_kf_rts_noise(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs);
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs, NULL);
+}
+
+/* the noiseless filter/smoother and the innovations' quadratic-form sum */
+int orc_kf_rts_qf(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+                  const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf, double *ms,
+                  double *sPs, double *qf)
+{
+    *qf = 0.0;
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs, qf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* objective value (eq. objective-value)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* V(eta) = 1/2 sum_{n=1}^N |eta_n - Phi eta_{n-1}|^2_{Q^-1} for a trajectory
+ * traj [N+1][D] in original coordinates (the negative log-density of the
+ * trajectory under the prior, up to a constant), Phi = Phi(h), Q = Q(h) of the
+ * IWP(q) or IOUP(q, theta) prior per ODE component.  The residual is formed in
+ * original coordinates; the weighted norm is taken as |L^-1 T^-1 r|^2 with
+ * T = T(h) and L = chol(T^-1 Q T^-T) (Q(h) itself spans too many orders of
+ * magnitude for a plain Cholesky at small h). */
+double orc_objective(int d, int q, double h, long N, const double *traj, int prior, double theta)
+{
+    int S = q + 1, D = d * S;
+    double *Ph = dalloc(S * S), *Qh = dalloc(S * S), *T = dalloc(S), *Qb = dalloc(S * S), *L = dalloc(S * S);
+    double *r = dalloc(S), *w = dalloc(S);
+    if (prior == 1)
+        orc_ioup(q, theta, h, Ph, Qh);
+    else
+        orc_iwp(q, h, Ph, Qh);
+    orc_precond_diag(q, h, T);
+    for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) Qb[i * S + j] = Qh[i * S + j] / (T[i] * T[j]);
+    orc_chol(S, Qb, L);
+    double V = 0.0;
+    for (long n = 1; n <= N; ++n)
+        for (int c = 0; c < d; ++c) {
+            const double *a = traj + (n - 1) * D + c * S, *b = traj + n * D + c * S;
+            for (int i = 0; i < S; ++i) {
+                double t = b[i];
+                for (int j = 0; j < S; ++j) t -= Ph[i * S + j] * a[j];
+                r[i] = t / T[i];
+            }
+            lower_solve_vec(S, L, r, w);
+            for (int i = 0; i < S; ++i) V += 0.5 * w[i] * w[i];
+        }
+    free(Ph); free(Qh); free(T); free(Qb); free(L); free(r); free(w);
+    return V;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -669,11 +736,20 @@ int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, con
  * damping of the Gauss-Newton step, which the paper leaves as future work;
  * the fixed point is unchanged).  When damped, the returned factors come
  * from one more, undamped linearise-and-smooth pass at the final iterate. */
-/* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta). */
-int orc_ieks_prior(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
-                   int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
-                   double lm_sigma, int prior, double theta, double *mean_out, double *sqrtcov_out,
-                   double *delta_hist, int *iters_out)
+/* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta), and
+ * the paper's stopping criteria (Sec. 3.2.2): stop_rule bit 0 -- the
+ * trajectory change delta_k < tol; bit 1 -- the change of the objective value
+ * (eq. objective-value) |V_k - V_{k-1}| <= obj_atol + obj_rtol |V_k|, with V_0
+ * the objective of the starting trajectory; either met stops the loop.
+ * obj_hist[k-1] receives V_k (may be NULL), *obj0 V_0 (may be NULL).
+ * *sigma2 (may be NULL) receives the quasi-maximum-likelihood diffusion of
+ * the last undamped filter pass (its innovations' quadratic forms over N d;
+ * NaN when every pass was damped). */
+int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+                 int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+                 double lm_sigma, int prior, double theta, int stop_rule, double obj_atol, double obj_rtol,
+                 double *mean_out, double *sqrtcov_out, double *delta_hist, double *obj_hist, double *obj0,
+                 double *sigma2, int *iters_out)
 {
     int d = orc_field_dim(field, d_req, nparams);
     if (d < 1 || q < 1 || N < 1 || !(t1 > t0)) return -1;
@@ -698,6 +774,11 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
     for (int r = 0; r < dobs; ++r) rstd[r] = r < d ? 0.0 : lm_sigma / (sqrt(h) * T0);
     int status = 0, k = 0;
     int limit = fixed_iters > 0 ? fixed_iters : max_iter;
+    double *traj_o = dalloc((N + 1) * D), qf = 0.0, s2 = NAN;
+    for (long n = 0; n <= N; ++n)
+        for (int r = 0; r < D; ++r) traj_o[n * D + r] = T[r] * eta[n * D + r];
+    double Vprev = orc_objective(d, q, h, N, traj_o, prior, theta);
+    if (obj0) *obj0 = Vprev;
     for (k = 1; k <= limit; ++k) {
         /* EK1 linearisation at every grid point (Sec. 3.2.1), then the
          * preconditioned observation  (H T) Ybar = d  with rows divided by T1:
@@ -720,7 +801,9 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
                 dn[d + i] = eta[n * D + i * S];
             }
         }
-        int rc = orc_kf_rts_noise(D, dobs, N, mu0b, S0, PhiB, sQB, H, dv, rstd, mf, sPf, ms, sPs);
+        qf = 0.0;
+        int rc = kf_rts_core(D, dobs, N, mu0b, S0, PhiB, sQB, H, dv, rstd, mf, sPf, ms, sPs, lm ? NULL : &qf);
+        if (!lm) s2 = qf / ((double)N * d);
         double delta = 0.0;
         for (long n = 0; n <= N; ++n)
             for (int i = 0; i < d; ++i) {
@@ -729,10 +812,18 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
             }
         if (delta_hist) delta_hist[k - 1] = delta;
         memcpy(eta, ms, sizeof(double) * (N + 1) * D);
+        for (long n = 0; n <= N; ++n)
+            for (int r = 0; r < D; ++r) traj_o[n * D + r] = T[r] * eta[n * D + r];
+        double V = orc_objective(d, q, h, N, traj_o, prior, theta);
+        if (obj_hist) obj_hist[k - 1] = V;
         if (rc != 0 || !isfinite(delta)) { status = -4; break; }
-        if (fixed_iters <= 0 && delta < tol) { status = 0; break; }
+        int stop_traj = (stop_rule & 1) && delta < tol;
+        int stop_obj = (stop_rule & 2) && fabs(V - Vprev) <= obj_atol + obj_rtol * fabs(V);
+        Vprev = V;
+        if (fixed_iters <= 0 && (stop_traj || stop_obj)) { status = 0; break; }
         if (fixed_iters <= 0 && k == max_iter) { status = 1; break; }
     }
+    free(traj_o);
     if (k > limit) k = limit;
     if (iters_out) *iters_out = k;
     if (lm && sqrtcov_out && status != -4) {
@@ -753,7 +844,9 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
                 for (int j = 0; j < d; ++j) Hn[i * D + j * S] -= Jy[i * d + j] * T0 / T1;
             }
         }
-        orc_kf_rts(D, d, N, mu0b, S0, PhiB, sQB, H, dv, mf, sPf, ms, sPs);
+        qf = 0.0;
+        kf_rts_core(D, d, N, mu0b, S0, PhiB, sQB, H, dv, NULL, mf, sPf, ms, sPs, &qf);
+        s2 = qf / ((double)N * d);
         memcpy(ms, msk, sizeof(double) * (N + 1) * D);
         free(msk);
     }
@@ -763,9 +856,20 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
             if (sqrtcov_out)
                 for (int c = 0; c < D; ++c) sqrtcov_out[(n * D + r) * D + c] = T[r] * sPs[(n * D + r) * D + c];
         }
+    if (sigma2) *sigma2 = s2;
     free(PhiB); free(sQB); free(T); free(mu0); free(mu0b); free(eta); free(H); free(dv); free(rstd);
     free(mf); free(sPf); free(ms); free(sPs); free(S0); free(y); free(fy); free(Jy);
     return status;
+}
+
+int orc_ieks_prior(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
+                   int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
+                   double lm_sigma, int prior, double theta, double *mean_out, double *sqrtcov_out,
+                   double *delta_hist, int *iters_out)
+{
+    return orc_ieks_ext(field, params, nparams, d_req, y0, t0, t1, q, N, max_iter, tol, fixed_iters, init_traj,
+                        lm_sigma, prior, theta, 1, 0.0, 0.0, mean_out, sqrtcov_out, delta_hist, NULL, NULL, NULL,
+                        iters_out);
 }
 
 /* preconditioned model constants, exposed for pins: PhiB, sqrtQB (D x D), T (D) */

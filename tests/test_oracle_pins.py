@@ -767,3 +767,124 @@ def test_coarse_start_converges_to_the_logistic_solution(q):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > q - 0.5), (errs, rates)
     assert errs[-1] < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.4 uncertainty calibration (quasi-MLE diffusion) and the objective
+# value (eq. objective-value) of the stopping rule
+# ---------------------------------------------------------------------------
+def dense_quadratic_form(mu0, S0, Phi, sQ, H, dv):
+    """(d - C m)^T (C Sigma C^T)^-1 (d - C m) for the stacked observations
+    C Y = d of the joint Gaussian of Y_0..N -- the data's log-likelihood is
+    -qf / (2 sigma^2) - (N dobs / 2) log sigma^2 + const when every covariance
+    carries the diffusion sigma^2, so sigma-hat^2 = qf / (N dobs)."""
+    N, dobs, D = H.shape
+    G = np.zeros(((N + 1) * D, (N + 1) * D))
+    m = np.zeros((N + 1) * D)
+    G[:D, :D] = S0
+    m[:D] = mu0
+    for n in range(1, N + 1):
+        G[n * D:(n + 1) * D] = Phi @ G[(n - 1) * D:n * D]
+        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += sQ
+        m[n * D:(n + 1) * D] = Phi @ m[(n - 1) * D:n * D]
+    C = np.zeros((N * dobs, (N + 1) * D))
+    for n in range(1, N + 1):
+        C[(n - 1) * dobs:n * dobs, n * D:(n + 1) * D] = H[n - 1]
+    r = dv.ravel() - C @ m
+    S = C @ G @ G.T @ C.T
+    return float(r @ np.linalg.solve(S, r))
+
+
+@pytest.mark.parametrize("D,dobs,N,sigma0", [(3, 1, 6, True), (8, 2, 7, False), (6, 3, 5, True)])
+def test_innovation_quadratic_forms_equal_the_joint_quadratic_form(D, dobs, N, sigma0):
+    """The sequential filter's innovations (prediction-error decomposition)
+    against the dense joint Gaussian of all observations."""
+    rng = np.random.default_rng(D * 31 + N)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng, sigma0)
+    qf = oracle.kf_rts(mu0, S0, Phi, sQ, H, dv, return_qf=True)[4]
+    ref = dense_quadratic_form(mu0, S0, Phi, sQ, H, dv)
+    assert abs(qf - ref) <= 1e-9 * abs(ref)
+
+
+def test_sigma_hat_of_an_affine_solve_is_the_quasi_mle_of_its_linear_model():
+    """For an affine field every linearisation is exact, so the IEKS's
+    quasi-MLE is that of one linear model: sigma-hat^2 = qf / (N d) with qf
+    the dense joint quadratic form of the preconditioned model (IWP(q) closed
+    forms, observation rows E1 - (h/q) L E0 and offsets c / T1, built here)."""
+    L = np.array([[-0.5, 1.0], [-1.0, -0.3]])
+    c = np.array([0.2, -0.1])
+    d, q, N, t1 = 2, 2, 7, 0.7
+    h = t1 / N
+    r = oracle.ieks("affine", list(L.ravel()) + list(c), [1.0, 0.0], 0.0, t1, q, N, fixed_iters=2, want_cov=False)
+    S = q + 1
+    T = np.array([math.sqrt(h) * h ** (q - i) / math.factorial(q - i) for i in range(S)])
+    Phib = np.array([[math.comb(q - i, j - i) if j >= i else 0 for j in range(S)] for i in range(S)], float)
+    Qb = np.array([[1.0 / (2 * q + 1 - i - j) for j in range(S)] for i in range(S)])
+    Phi, sQ = np.kron(np.eye(d), Phib), np.kron(np.eye(d), np.linalg.cholesky(Qb))
+    Tf = np.tile(T, d)
+    mu0 = oracle.taylor_mu0("affine", list(L.ravel()) + list(c), [1.0, 0.0], q) / Tf
+    H = np.zeros((N, d, d * S))
+    dv = np.zeros((N, d))
+    for n in range(N):
+        for a in range(d):
+            H[n, a, a * S + 1] = 1.0
+            for b in range(d):
+                H[n, a, b * S] -= (h / q) * L[a, b]
+            dv[n, a] = c[a] / T[1]
+    qf = dense_quadratic_form(mu0, np.zeros((d * S, d * S)), Phi, sQ, H, dv)
+    assert abs(r["sigma2"] - qf / (N * d)) <= 1e-9 * qf / (N * d)
+
+
+@pytest.mark.parametrize("q,prior,theta", [(1, "iwp", 0.0), (2, "iwp", 0.0), (3, "ioup", 0.7)])
+def test_objective_is_the_negative_log_density_under_the_prior(q, prior, theta):
+    """V = sum_n -log N(eta_n; Phi eta_{n-1}, Q) minus the normalising
+    constants, with Phi, Q from the Van Loan exponential of the prior's SDE and
+    scipy's Gaussian log-density; and V = 0 on a path that follows the prior
+    mean."""
+    from scipy.stats import multivariate_normal
+
+    S, d, N, h = q + 1, 2, 6, 0.3
+    F = np.diag(np.ones(q), 1)
+    F[q, q] = -theta
+    M = np.zeros((2 * S, 2 * S))
+    M[:S, :S] = F
+    M[q, S + q] = 1.0
+    M[S:, S:] = -F.T
+    E = scipy.linalg.expm(M * h)
+    Phi1, Q1 = E[:S, :S], E[:S, S:] @ E[:S, :S].T
+    rng = np.random.default_rng(q)
+    tr = rng.normal(size=(N + 1, d * S))
+    ref = 0.0
+    for n in range(1, N + 1):
+        for i in range(d):
+            a, b = tr[n - 1, i * S:(i + 1) * S], tr[n, i * S:(i + 1) * S]
+            mvn = multivariate_normal(mean=Phi1 @ a, cov=Q1)
+            ref -= mvn.logpdf(b) + 0.5 * np.linalg.slogdet(2 * np.pi * Q1)[1]
+    V = oracle.objective(tr, q, h, prior=prior, theta=theta)
+    assert abs(V - ref) <= 1e-8 * abs(ref)
+    path = np.zeros((N + 1, d * S))
+    path[0] = rng.normal(size=d * S)
+    for n in range(1, N + 1):
+        for i in range(d):
+            path[n, i * S:(i + 1) * S] = Phi1 @ path[n - 1, i * S:(i + 1) * S]
+    assert abs(oracle.objective(path, q, h, prior=prior, theta=theta)) <= 1e-10 * np.abs(path).max() ** 2
+
+
+def test_objective_history_and_the_objective_stopping_rule():
+    """The oracle's objective after each iteration is V of the iterate it
+    returns, and with the objective rule (Sec. 3.2.2; atol 1e-9, rtol 1e-6)
+    the loop stops at the first iteration whose change meets it."""
+    args = ("logistic", [], [0.01], 0.0, 10.0, 2, 400)
+    full = oracle.ieks(*args, max_iter=30, tol=1e-12, want_cov=False, stop_rule=1)
+    assert full["status"] == 0
+    h = 10.0 / 400
+    for k in (1, 3, 6):
+        rk = oracle.ieks(*args, fixed_iters=k, want_cov=False)
+        assert abs(full["objectives"][k - 1] - oracle.objective(rk["mean"], 2, h)) <= 1e-10 * abs(full["objectives"][k - 1])
+    V = np.concatenate([[full["objective0"]], full["objectives"]])
+    ok = np.abs(np.diff(V)) <= 1e-9 + 1e-6 * np.abs(V[1:])
+    first = int(np.argmax(ok)) + 1
+    r = oracle.ieks(*args, max_iter=30, tol=1e-12, want_cov=False, stop_rule=2)
+    assert r["status"] == 0 and r["iterations"] == first < full["iterations"]
+    both = oracle.ieks(*args, max_iter=30, tol=1e-12, want_cov=False, stop_rule=3)
+    assert both["iterations"] == min(first, full["iterations"])
