@@ -55,6 +55,10 @@ extern "C" {
 #define PARAPN_START_COARSE_FAILED 3 /* the coarse smoother produced a non-finite value; the
                                       * solve ran from the constant start instead          */
 
+/* stopping criteria (parapn_problem.stop_rule) */
+#define PARAPN_STOP_TRAJECTORY 1
+#define PARAPN_STOP_OBJECTIVE 2
+
 /* arithmetic of the path */
 #define PARAPN_FP64 0      /* every step in double                                  */
 #define PARAPN_FP32_SQRT 1 /* elements, scans and linearisation in float; the prior
@@ -144,6 +148,17 @@ typedef struct {
     int32_t coarse_points;   /* target M of the coarse grid; 0 = max(1024, 64
                               * ceil(log2 N)); values above N mean N (s = 1: the
                               * sequential smoother on the fine grid itself)         */
+    int32_t stop_rule;       /* stopping criteria of Sec. 3.2.2 (not with fixed_iters):
+                              * PARAPN_STOP_TRAJECTORY (bit 0): delta_k below the
+                              * threshold of parapn_solve; PARAPN_STOP_OBJECTIVE
+                              * (bit 1): the change of the objective value
+                              * V (eq. objective-value) since the previous iterate
+                              * (the start for k = 1) at most obj_atol + obj_rtol |V_k|;
+                              * with both bits either criterion stops.  0 = bit 0. */
+    double obj_atol, obj_rtol; /* >= 0; the paper's experiments use 1e-9 and 1e-6  */
+    int32_t calibrate;       /* 1: scale the returned factors (sqrtcov_out) by the
+                              * quasi-maximum-likelihood diffusion sigma-hat of the
+                              * final linearisation (Sec. 2.4); 0: sigma = 1        */
 } parapn_problem;
 
 typedef struct {
@@ -153,6 +168,20 @@ typedef struct {
     double tol_used;        /* the threshold actually applied                         */
     double *delta_history;  /* host, max_iter entries, may be NULL                    */
     int32_t start;          /* PARAPN_START_*: the starting trajectory used           */
+    double sigma_hat;       /* quasi-maximum-likelihood diffusion (Sec. 2.4) of the final
+                             * linearisation: sqrt(sum_n r_n^T S_n^-1 r_n / (N d)) over
+                             * the filter's innovations r_n (S_n their covariance at
+                             * sigma = 1), accumulated in FP64 (not bitwise reproducible:
+                             * atomic sums).  FP64 path: from the last filter pass (for
+                             * damped solves from the undamped pass that sqrtcov_out
+                             * triggers, else NaN).  FP32 path: from one FP64 filter pass
+                             * at the final iterate that calibrate with sqrtcov_out
+                             * triggers, else NaN (the FP32 innovations cancel at a
+                             * converged iterate).  NaN for the method-of-lines field. */
+    double objective;       /* V (eq. objective-value) of the returned trajectory, FP64 (in
+                             * the FP32 path V of a trajectory carrying FP32 increments);
+                             * NaN for the method-of-lines field                      */
+    double *objective_history; /* host, max_iter entries (V after each iteration), may be NULL */
 } parapn_info;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
@@ -293,6 +322,8 @@ typedef struct {
     double final_delta;  /* Delta of the last iteration */
     double t_submit, t_start, t_done; /* parapn_server_clock() at submission, admission, completion */
     int32_t start;       /* PARAPN_START_*: the starting trajectory used */
+    double sigma_hat;    /* as parapn_info.sigma_hat (NaN for damped requests) */
+    double objective;    /* as parapn_info.objective */
 } parapn_completion;
 
 /* stream: HIP stream for all of the server's work (NULL = default stream).

@@ -33,6 +33,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
 PRIORS = {"iwp": 0, "ioup": 1}
 INITS = {"constant": 0, "coarse": 1}
 STARTS = {0: "constant", 1: "coarse", 2: "given", 3: "coarse_failed"}
+STOP_RULES = {"trajectory": 1, "objective": 2, "either": 3}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
             "parapn_start_trajectory", "parapn_pararts_noalloc",
             "parapn_pararts",
@@ -69,6 +70,10 @@ class Problem(ctypes.Structure):
         ("prior_theta", ctypes.c_double),
         ("init_mode", ctypes.c_int32),
         ("coarse_points", ctypes.c_int32),
+        ("stop_rule", ctypes.c_int32),
+        ("obj_atol", ctypes.c_double),
+        ("obj_rtol", ctypes.c_double),
+        ("calibrate", ctypes.c_int32),
     ]
 
 
@@ -80,6 +85,9 @@ class Info(ctypes.Structure):
         ("tol_used", ctypes.c_double),
         ("delta_history", ctypes.POINTER(ctypes.c_double)),
         ("start", ctypes.c_int32),
+        ("sigma_hat", ctypes.c_double),
+        ("objective", ctypes.c_double),
+        ("objective_history", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -93,6 +101,8 @@ class Completion(ctypes.Structure):
         ("t_start", ctypes.c_double),
         ("t_done", ctypes.c_double),
         ("start", ctypes.c_int32),
+        ("sigma_hat", ctypes.c_double),
+        ("objective", ctypes.c_double),
     ]
 
 
@@ -199,7 +209,8 @@ def _dtype(precision):
 
 
 def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                 init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0):
+                 init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0,
+                 stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False):
     """Build the ctypes Problem (keeps the host arrays alive on the object)."""
     fid = FIELDS[field] if isinstance(field, str) else int(field)
     y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
@@ -222,6 +233,10 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.prior_theta = float(theta)
     pb.init_mode = INITS[init] if isinstance(init, str) else int(init)
     pb.coarse_points = int(coarse_points)
+    pb.stop_rule = STOP_RULES[stop_rule] if isinstance(stop_rule, str) else int(stop_rule)
+    pb.obj_atol = float(obj_atol)
+    pb.obj_rtol = float(obj_rtol)
+    pb.calibrate = 1 if calibrate else 0
     keep = [y0, prm]
     pb.init_on_device = 0
     if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
@@ -251,11 +266,15 @@ def workspace_size(problem: Problem) -> int:
 
 def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
           init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0, prior="iwp",
-          theta=0.0, init="constant", coarse_points=0):
+          theta=0.0, init="constant", coarse_points=0, stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6,
+          calibrate=False):
     """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
     (original coordinates, torch tensor on the device), ``sqrtcov``
     [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
-    ``converged``, ``tol_used``, ``start``.  ``lm_sigma`` > 0 damps each
+    ``converged``, ``tol_used``, ``start``, ``sigma_hat`` (quasi-MLE
+    diffusion), ``objective`` and ``objectives`` (V after each iteration).
+    ``stop_rule``: "trajectory", "objective" or "either" (Sec. 3.2.2);
+    ``calibrate`` scales the returned factors by sigma_hat.  ``lm_sigma`` > 0 damps each
     Gauss-Newton step (Levenberg-Marquardt, see parapn_problem.lm_sigma);
     ``init="coarse"`` starts from the coarse-grid smoother
     (parapn_problem.init_mode) with ``coarse_points`` coarse steps (0: the
@@ -264,7 +283,8 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
     L = load_library()
     pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
                       fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta,
-                      init=init, coarse_points=coarse_points)
+                      init=init, coarse_points=coarse_points, stop_rule=stop_rule, obj_atol=obj_atol,
+                      obj_rtol=obj_rtol, calibrate=calibrate)
     D = pb.d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -274,15 +294,18 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
         mean = torch.empty((pb.N + 1, D), dtype=dt, device=dev)
         cov = torch.empty((pb.N + 1, D, D), dtype=dt, device=dev) if want_cov else None
     hist = np.zeros(max(pb.max_iter, pb.fixed_iters, 1))
+    ohist = np.zeros_like(hist)
     info = Info()
     info.delta_history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    info.objective_history = ohist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     rc = L.parapn_solve(context(device), ctypes.byref(pb), _dptr(mean), _dptr(cov), ctypes.byref(info),
                         _stream_handle(stream))
     _check(rc, allow=(OK, MAXITER, ENONFINITE))
     k = info.iterations
     return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": k, "deltas": hist[:k].copy(),
             "converged": bool(info.converged), "tol_used": info.tol_used, "final_delta": info.final_delta,
-            "start": STARTS.get(info.start, info.start)}
+            "start": STARTS.get(info.start, info.start), "sigma_hat": info.sigma_hat, "objective": info.objective,
+            "objectives": ohist[:k].copy()}
 
 
 def start_trajectory(field, params, y0, t0, t1, q, N, *, precision="fp64", init="coarse", coarse_points=0,
@@ -423,11 +446,12 @@ class Server:
 
     def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
                fixed_iters=0, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0,
-               want_cov=False):
+               want_cov=False, stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False):
         torch = _torch()
         pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
                           fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta, init=init,
-                          coarse_points=coarse_points)
+                          coarse_points=coarse_points, stop_rule=stop_rule, obj_atol=obj_atol, obj_rtol=obj_rtol,
+                          calibrate=calibrate)
         D = pb.d * (pb.q + 1)
         dev = torch.device("cuda", self._device)
         mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=dev)
@@ -454,7 +478,8 @@ class Server:
             mean, cov = self._pending.pop(c.req_id, (None, None))
             out.append({"req_id": c.req_id, "status": c.status, "iterations": c.iterations,
                         "final_delta": c.final_delta, "t_submit": c.t_submit, "t_start": c.t_start,
-                        "t_done": c.t_done, "start": STARTS.get(c.start, c.start), "mean": mean, "sqrtcov": cov})
+                        "t_done": c.t_done, "start": STARTS.get(c.start, c.start), "sigma_hat": c.sigma_hat,
+                        "objective": c.objective, "mean": mean, "sqrtcov": cov})
         return out
 
     def clock(self):

@@ -374,7 +374,8 @@ void bridge_weights(int q, int64_t s, std::vector<double> &W)
 
 // Byte offsets of one pack's scratch inside the context workspace.
 struct PackLayout {
-    size_t se, sL, sPs, mf, sPf, fagg, fpart, fpref, sagg, spref, consts, reqs, ftab, stab, dbits, extra, total;
+    size_t se, sL, sPs, mf, sPf, fagg, fpart, fpref, sagg, spref, consts, consts64, reqs, ftab, stab, dbits, extra,
+        total;
 };
 
 PackLayout pack_scratch_layout(int D, int esz, const parapn::Pack &pk, int nreq, bool cov, size_t extra_bytes)
@@ -399,10 +400,11 @@ PackLayout pack_scratch_layout(int D, int esz, const parapn::Pack &pk, int nreq,
     L.sagg = take((size_t)pk.srecs * SAF * esz);
     L.spref = take((size_t)pk.srecs * FS * esz);
     L.consts = take((size_t)(3 * D * D + D) * esz);
+    L.consts64 = take((size_t)2 * D * D * 8);  // FP64 Phi, sqrtQ (the objective value)
     L.reqs = take((size_t)nreq * sizeof(parapn::ReqDev));
     L.ftab = take((size_t)nreq * sizeof(parapn::ScanTab));
     L.stab = take((size_t)nreq * sizeof(parapn::ScanTab));
-    L.dbits = take((size_t)nreq * 2 * sizeof(unsigned long long));
+    L.dbits = take((size_t)nreq * parapn::kCounters * sizeof(unsigned long long));
     L.extra = take(extra_bytes);
     L.total = o;
     return L;
@@ -443,7 +445,7 @@ void bind_plan(PackPlan &pl, char *ws)
 {
     const int nreq = (int)pl.reqs.size();
     unsigned long long *dbits = (unsigned long long *)(ws + pl.L.dbits);
-    for (int i = 0; i < nreq; ++i) pl.reqs[i].dbits = dbits + 2 * i;
+    for (int i = 0; i < nreq; ++i) pl.reqs[i].dbits = dbits + parapn::kCounters * i;
     pl.pk.reqs = (const parapn::ReqDev *)(ws + pl.L.reqs);
     pl.pk.ftab = (const parapn::ScanTab *)(ws + pl.L.ftab);
     pl.pk.stab = (const parapn::ScanTab *)(ws + pl.L.stab);
@@ -465,6 +467,9 @@ struct Solve {
     int init_mode;          // PARAPN_INIT_*
     int64_t coarse_target;  // coarse-grid size target (init_mode COARSE)
     int start = PARAPN_START_CONSTANT;
+    int stop_rule;          // bit 0 trajectory change, bit 1 objective change
+    double obj_atol, obj_rtol;
+    int calibrate;
     double params[PARAPN_MAX_PARAMS];
     std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
     // iteration state
@@ -473,6 +478,10 @@ struct Solve {
     bool done = false, converged = false;
     double delta = 0.0, tol_used = 0.0;
     std::vector<double> deltas;
+    double sigma2 = NAN;     // quasi-MLE diffusion of the last undamped filter pass
+    double objective = NAN;  // V of the current trajectory
+    double obj_prev = NAN;   // V before the last pass (the objective rule)
+    std::vector<double> objectives;
 };
 
 int prepare(const parapn_problem *p, Solve &sv)
@@ -494,6 +503,10 @@ int prepare(const parapn_problem *p, Solve &sv)
     sv.theta = p->prior_theta;
     sv.init_mode = p->init_mode;
     sv.coarse_target = p->coarse_points > 0 ? p->coarse_points : default_coarse_points(p->N);
+    sv.stop_rule = p->stop_rule == 0 ? 1 : p->stop_rule;
+    sv.obj_atol = p->obj_atol;
+    sv.obj_rtol = p->obj_rtol;
+    sv.calibrate = p->calibrate;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
     precond_diag(sv.d, sv.q, sv.h, sv.Td);
     sv.mu0.assign(sv.D, 0.0);
@@ -535,11 +548,17 @@ void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parap
 // Upload the (precision, d, q) constants: Phi | sqrtQ | initial increment
 // state (0, 0) -- the scans run on the increment over a trajectory whose
 // row 0 is mu0 itself.
-int upload_consts(const Solve &sv, bool fp64, char *dst, hipStream_t s)
+int upload_consts(const Solve &sv, bool fp64, char *dst, char *dst64, hipStream_t s)
 {
     const int D = sv.d * (sv.q + 1);
     std::vector<double> Phi, sQ;
     prior_blocks_of(sv, sv.d, Phi, sQ);
+    std::vector<double> c64(2 * D * D);
+    for (int i = 0; i < D * D; ++i) {
+        c64[i] = Phi[i];
+        c64[D * D + i] = sQ[i];
+    }
+    PARAPN_HIP(hipMemcpyAsync(dst64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice, s), "copy FP64 constants");
     std::vector<double> cst(3 * D * D + D, 0.0);
     for (int i = 0; i < D * D; ++i) {
         cst[i] = Phi[i];
@@ -752,6 +771,10 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (p->init_mode != PARAPN_INIT_CONSTANT && p->init_mode != PARAPN_INIT_COARSE)
         return fail(PARAPN_EINVAL, "unknown init_mode");
     if (p->coarse_points < 0) return fail(PARAPN_EINVAL, "coarse_points must be >= 0");
+    if (p->stop_rule < 0 || p->stop_rule > 3) return fail(PARAPN_EINVAL, "stop_rule must be 0..3");
+    if (!(p->obj_atol >= 0.0) || !(p->obj_rtol >= 0.0)) return fail(PARAPN_EINVAL, "objective tolerances must be >= 0");
+    if (p->field == parapn::F_MOL && (p->stop_rule & 2))
+        return fail(PARAPN_EINVAL, "the objective stopping rule is available for the fixed-size fields");
     if (p->field == parapn::F_MOL && p->init_mode == PARAPN_INIT_COARSE && !p->init_traj)
         return fail(PARAPN_EINVAL, "the coarse-grid start is available for the fixed-size fields");
     if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
@@ -770,7 +793,7 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
 // caller has sized.  fixed: a plan the caller already sized the workspace
 // for (else the pack is planned here and the workspace grown to fit it).
 static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
-                        PackPlan *fixed, size_t slot)
+                        PackPlan *fixed, size_t slot, bool obj_start = false)
 {
     const int nreq = (int)sv.size();
     const Solve &s0 = *sv[0];
@@ -788,7 +811,7 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
         if (rc) return rc;
         pl = &local;
     }
-    if (slot + 2 * (size_t)nreq > ctx->host_bits_n) return fail(PARAPN_EINVAL, "internal: delta slots");
+    if (slot + parapn::kCounters * (size_t)nreq > ctx->host_bits_n) return fail(PARAPN_EINVAL, "internal: delta slots");
     char *ws = (char *)ctx->ws;
     bind_plan(*pl, ws);
     const PackLayout &L = pl->L;
@@ -797,7 +820,7 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
     const int ckey = (s0.d * 8 + s0.q) * 2 + (fp64 ? 1 : 0);
     const bool cacheable = s0.prior == PARAPN_PRIOR_IWP;
     if (!cacheable || ctx->consts_at != ws + L.consts || ctx->consts_key != ckey) {
-        rc = upload_consts(s0, fp64, ws + L.consts, s);
+        rc = upload_consts(s0, fp64, ws + L.consts, ws + L.consts64, s);
         if (rc) return rc;
         ctx->consts_at = cacheable ? ws + L.consts : nullptr;
         ctx->consts_key = ckey;
@@ -810,15 +833,19 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
         ctx->reqs_key = pl->image;
     }
     unsigned long long *dbits = (unsigned long long *)(ws + L.dbits);
-    PARAPN_HIP(parapn::launch_zero_u64(dbits, 2 * nreq, s), "reset delta slots");
+    PARAPN_HIP(parapn::launch_zero_u64(dbits, parapn::kCounters * (int64_t)nreq, s), "reset delta slots");
     parapn::Pack pk = pl->pk;
     pk.mode = 0;
     pk.lm = s0.lm_sigma > 0.0 ? 1 : 0;
     const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
     const parapn::Work w = work_from(ws, L, false);
+    const double *c64 = (const double *)(ws + L.consts64);
+    if (obj_start)
+        PARAPN_HIP(parapn::launch_objective(s0.d, s0.q, pk, c64, c64 + D * D, 4, s), "objective of the start");
     PARAPN_HIP(parapn::launch_forward(fp64, s0.d, s0.q, pk, m, w, s), "forward scan");
     PARAPN_HIP(parapn::launch_smoother(fp64, s0.d, s0.q, pk, m, w, false, true, nullptr, s), "reverse scan");
-    PARAPN_HIP(hipMemcpyAsync(ctx->host_bits + slot, dbits, 2 * nreq * sizeof(unsigned long long),
+    PARAPN_HIP(parapn::launch_objective(s0.d, s0.q, pk, c64, c64 + D * D, 3, s), "objective");
+    PARAPN_HIP(hipMemcpyAsync(ctx->host_bits + slot, dbits, parapn::kCounters * nreq * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s),
                "read delta");
     return PARAPN_OK;
@@ -826,17 +853,35 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
 
 // Advance each solve's state from its iteration's counters (bits: 2 per
 // request, delta and max |E0 trajectory|, as doubles).
-static void pack_finish(std::vector<Solve *> &sv, const unsigned long long *bits)
+// Advance each solve's state from its iteration's counters (stride words per
+// request: delta and max |E0 trajectory| as bit patterns; with the row
+// engine's kCounters also the innovations' quadratic-form sum, the objective
+// after and before the pass, as doubles).  The stopping rule of Sec. 3.2.2:
+// the trajectory change below tol, or the objective change below
+// obj_atol + obj_rtol |V|, as the solve's stop_rule selects.
+static void pack_finish(std::vector<Solve *> &sv, const unsigned long long *bits, int stride = parapn::kCounters)
 {
     for (size_t i = 0; i < sv.size(); ++i) {
         Solve &v = *sv[i];
         if (v.done) continue;
-        double delta, mmax;
-        std::memcpy(&delta, bits + 2 * i, 8);
-        std::memcpy(&mmax, bits + 2 * i + 1, 8);
+        double delta, mmax, qf = NAN, Vend = NAN, Vstart = NAN;
+        std::memcpy(&delta, bits + stride * i, 8);
+        std::memcpy(&mmax, bits + stride * i + 1, 8);
+        if (stride >= 5) {
+            std::memcpy(&qf, bits + stride * i + 2, 8);
+            std::memcpy(&Vend, bits + stride * i + 3, 8);
+            std::memcpy(&Vstart, bits + stride * i + 4, 8);
+        }
+        if (v.iter == 0) v.obj_prev = Vstart;
         v.iter += 1;
         v.delta = delta;
         v.deltas.push_back(delta);
+        // the FP32 filter's quadratic forms are not reported (see the FP64 pass)
+        v.sigma2 = (v.lm_sigma > 0.0 || v.precision != PARAPN_FP64) ? NAN : qf / ((double)v.N * v.d);
+        v.objective = Vend;
+        v.objectives.push_back(Vend);
+        const bool obj_stop = (v.stop_rule & 2) && std::fabs(Vend - v.obj_prev) <= v.obj_atol + v.obj_rtol * std::fabs(Vend);
+        v.obj_prev = Vend;
         const int limit = v.fixed_iters > 0 ? v.fixed_iters : v.max_iter;
         if (!std::isfinite(delta)) {
             v.status = PARAPN_ENONFINITE;
@@ -849,7 +894,7 @@ static void pack_finish(std::vector<Solve *> &sv, const unsigned long long *bits
                 v.status = PARAPN_OK;
                 v.done = true;
             }
-        } else if (delta < v.tol_used) {
+        } else if (((v.stop_rule & 1) && delta < v.tol_used) || obj_stop) {
             v.status = PARAPN_OK;
             v.converged = true;
             v.done = true;
@@ -864,9 +909,11 @@ static void pack_finish(std::vector<Solve *> &sv, const unsigned long long *bits
 static int pack_iteration(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<double *> &trajs, hipStream_t s,
                           PackPlan *fixed = nullptr)
 {
-    int rc = ensure_host_bits(ctx, 2 * sv.size());
+    int rc = ensure_host_bits(ctx, parapn::kCounters * sv.size());
     if (rc) return rc;
-    rc = pack_enqueue(ctx, sv, trajs, s, fixed, 0);
+    bool obj_start = false;
+    for (Solve *v : sv) obj_start |= v->iter == 0 && (v->stop_rule & 2);
+    rc = pack_enqueue(ctx, sv, trajs, s, fixed, 0, obj_start);
     if (rc) return rc;
     PARAPN_HIP(hipStreamSynchronize(s), "sync");
     pack_finish(sv, ctx->host_bits);
@@ -1021,7 +1068,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
                                   hipMemcpyDeviceToHost, s),
                    "read delta");
         PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        pack_finish(ptr, ctx->host_bits);
+        pack_finish(ptr, ctx->host_bits, 2);
         bool all = true;
         for (int b = 0; b < B; ++b) {
             active[b] = sv[b].done ? 0 : 1;
@@ -1052,6 +1099,8 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
             f.final_delta = v.delta;
             f.tol_used = v.tol_used;
             f.start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
+            f.sigma_hat = NAN;  // not computed by the dense engine
+            f.objective = NAN;
             if (f.delta_history) {
                 const int cap = std::max(v.max_iter, v.fixed_iters);
                 for (int k = 0; k < (int)v.deltas.size() && k < cap; ++k) f.delta_history[k] = v.deltas[k];
@@ -1159,7 +1208,17 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     fill_reqdev(sv, nullptr, nullptr, r[0]);
     const bool coarse = !p->init_traj && sv.init_mode == PARAPN_INIT_COARSE;
     const CoarseLayout cl = coarse ? coarse_layout(sv) : CoarseLayout{};
-    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv) + cl.total, pl, sv.lm_sigma > 0.0);
+    // a calibrated FP32 solve takes sigma-hat from one FP64 filter pass at the
+    // final iterate (in FP32 the innovations' quadratic forms cancel: each is
+    // tiny against the terms it is formed from at a converged iterate)
+    const bool pass64 = !fp64 && sv.calibrate;
+    PackPlan pl64;
+    if (pass64) {
+        rc = plan_pack(true, sv.d, sv.q, r, false, 0, pl64, false);
+        if (rc) return rc;
+    }
+    const size_t extra64 = pass64 ? pl64.L.total : 0;
+    rc = plan_pack(fp64, sv.d, sv.q, r, true, resident_bytes(sv) + cl.total + extra64, pl, sv.lm_sigma > 0.0);
     if (rc) return rc;
     const PackLayout &L = pl.L;
     rc = ensure_ws(ctx, L.total);
@@ -1181,14 +1240,15 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         // the iteration count is known: queue every iteration, each copying
         // its counters to its own slot, and read them all after one wait
         // (iterations after a non-finite one change nothing that is returned)
-        rc = ensure_host_bits(ctx, 2 * (size_t)sv.fixed_iters);
+        rc = ensure_host_bits(ctx, parapn::kCounters * (size_t)sv.fixed_iters);
         if (rc) return rc;
         for (int it = 0; it < sv.fixed_iters; ++it) {
-            rc = pack_enqueue(ctx, one, trajs, s, &pl, 2 * (size_t)it);
+            rc = pack_enqueue(ctx, one, trajs, s, &pl, parapn::kCounters * (size_t)it);
             if (rc) return rc;
         }
         PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        for (int it = 0; it < sv.fixed_iters && !sv.done; ++it) pack_finish(one, ctx->host_bits + 2 * it);
+        for (int it = 0; it < sv.fixed_iters && !sv.done; ++it)
+            pack_finish(one, ctx->host_bits + parapn::kCounters * it);
     }
     while (!sv.done) {
         rc = pack_iteration(ctx, one, trajs, s, &pl);
@@ -1204,13 +1264,51 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
         const parapn::Work w = work_from(ws, L, true);
         if (pk.lm && sv.status != PARAPN_ENONFINITE) {
-            // damped iterations: the factors come from an undamped
-            // linearise-and-filter pass at the final iterate
+            // damped iterations: the factors (and the quasi-MLE diffusion)
+            // come from an undamped linearise-and-filter pass at the final
+            // iterate
             pk.lm = 0;
+            unsigned long long *db = (unsigned long long *)(ws + L.dbits);
+            PARAPN_HIP(parapn::launch_zero_u64(db, parapn::kCounters, s), "reset counters");
             PARAPN_HIP(parapn::launch_forward(fp64, sv.d, sv.q, pk, m, w, s), "undamped forward scan");
+            PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, db, parapn::kCounters * sizeof(unsigned long long),
+                                      hipMemcpyDeviceToHost, s),
+                       "read counters");
+            PARAPN_HIP(hipStreamSynchronize(s), "sync");
+            double qf;
+            std::memcpy(&qf, ctx->host_bits + 2, 8);
+            if (fp64) sv.sigma2 = qf / ((double)sv.N * sv.d);
         }
+        if (pass64 && sv.status != PARAPN_ENONFINITE) {
+            // FP64 linearise-and-filter pass at the final iterate for sigma-hat
+            char *w64 = ws + L.extra + resident_bytes(sv) + cl.total;
+            pl64.reqs[0].traj = traj;
+            bind_plan(pl64, w64);
+            const PackLayout &L64 = pl64.L;
+            rc = upload_consts(sv, true, w64 + L64.consts, w64 + L64.consts64, s);  // waits for the stream
+            if (rc) return rc;
+            PARAPN_HIP(hipMemcpyAsync(w64 + L64.reqs, pl64.image.data(), pl64.image.size(), hipMemcpyHostToDevice, s),
+                       "copy request tables");
+            unsigned long long *db = (unsigned long long *)(w64 + L64.dbits);
+            PARAPN_HIP(parapn::launch_zero_u64(db, parapn::kCounters, s), "reset counters");
+            parapn::Pack p64 = pl64.pk;
+            p64.mode = 0;
+            p64.lm = 0;
+            PARAPN_HIP(parapn::launch_forward(1, sv.d, sv.q, p64, model_from(w64 + L64.consts, D, 8),
+                                              work_from(w64, L64, false), s),
+                       "FP64 forward scan");
+            PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, db, parapn::kCounters * sizeof(unsigned long long),
+                                      hipMemcpyDeviceToHost, s),
+                       "read counters");
+            PARAPN_HIP(hipStreamSynchronize(s), "sync");
+            double qf;
+            std::memcpy(&qf, ctx->host_bits + 2, 8);
+            sv.sigma2 = qf / ((double)sv.N * sv.d);
+        }
+        // calibrate: Sigma scales with the diffusion, so the factors with sigma-hat
+        const double cs = sv.calibrate ? std::sqrt(sv.sigma2) : 1.0;
         PARAPN_HIP(parapn::launch_smoother(fp64, sv.d, sv.q, pk, m, w, true, false, w.mf, s), "covariance pass");
-        PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, w.sPs, mean_out, sqrtcov_out, s, true),
+        PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, w.sPs, mean_out, sqrtcov_out, s, true, cs),
                    "unscale");
     } else {
         PARAPN_HIP(parapn::launch_unscale(fp64, D, sv.N, Tdev, traj, nullptr, mean_out, nullptr, s, true),
@@ -1223,10 +1321,13 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
         info->final_delta = sv.delta;
         info->tol_used = sv.tol_used;
         info->start = sv.start;
-        if (info->delta_history) {
-            const int cap = std::max(sv.max_iter, sv.fixed_iters);
+        info->sigma_hat = std::sqrt(sv.sigma2);
+        info->objective = sv.objective;
+        const int cap = std::max(sv.max_iter, sv.fixed_iters);
+        if (info->delta_history)
             for (int k = 0; k < (int)sv.deltas.size() && k < cap; ++k) info->delta_history[k] = sv.deltas[k];
-        }
+        if (info->objective_history)
+            for (int k = 0; k < (int)sv.objectives.size() && k < cap; ++k) info->objective_history[k] = sv.objectives[k];
     }
     if (sv.status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
     return sv.status;
@@ -1634,6 +1735,7 @@ struct PackState {
     HostBuf img, bits;
     std::vector<const ServedReq *> sig;
     bool cov = false;
+    bool obj_start = false;  // the objective of the start is wanted (a member at its first iteration)
     PackPlan plan;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1696,15 +1798,19 @@ int pack_iteration_enqueue(PackState &pk, bool fp64, int d, int q, hipStream_t s
     const PackLayout &L = pk.plan.L;
     char *ws = pk.dev.p;
     unsigned long long *dbits = (unsigned long long *)(ws + L.dbits);
-    PARAPN_HIP(parapn::launch_zero_u64(dbits, 2 * (int64_t)nreq, s), "reset delta slots");
+    PARAPN_HIP(parapn::launch_zero_u64(dbits, parapn::kCounters * (int64_t)nreq, s), "reset delta slots");
     parapn::Pack p = pk.plan.pk;
     p.mode = 0;
     const parapn::ModelDev m = model_from(ws + L.consts, D, esz);
     const parapn::Work w = work_from(ws, L, false);
+    const double *c64 = (const double *)(ws + L.consts64);
+    if (pk.obj_start)
+        PARAPN_HIP(parapn::launch_objective(d, q, p, c64, c64 + D * D, 4, s), "objective of the start");
     PARAPN_HIP(parapn::launch_forward(fp64, d, q, p, m, w, s), "forward scan");
     PARAPN_HIP(parapn::launch_smoother(fp64, d, q, p, m, w, false, true, nullptr, s), "reverse scan");
-    PARAPN_HIP(hipMemcpyAsync(pk.bits.p, dbits, 2 * (size_t)nreq * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                              s),
+    PARAPN_HIP(parapn::launch_objective(d, q, p, c64, c64 + D * D, 3, s), "objective");
+    PARAPN_HIP(hipMemcpyAsync(pk.bits.p, dbits, parapn::kCounters * (size_t)nreq * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s),
                "read delta");
     return PARAPN_OK;
 }
@@ -1742,10 +1848,21 @@ int pack_replan(PackState &pk, bool fp64, int d, int q, bool lm, hipStream_t s)
     std::memcpy(pk.img.p + cbytes, pk.plan.image.data(), pk.plan.image.size());
     PARAPN_HIP(hipMemcpyAsync(pk.dev.p + pk.plan.L.consts, pk.img.p, cbytes, hipMemcpyHostToDevice, s),
                "copy constants");
+    // FP64 Phi, sqrtQ for the objective value, after the table image
+    const size_t c64off = align_up(cbytes + pk.plan.image.size());
+    rc = pk.img.ensure(c64off + (size_t)2 * D * D * 8);
+    if (rc) return rc;
+    double *c64 = (double *)(pk.img.p + c64off);
+    for (int i = 0; i < D * D; ++i) {
+        c64[i] = Phi[i];
+        c64[D * D + i] = sQ[i];
+    }
+    PARAPN_HIP(hipMemcpyAsync(pk.dev.p + pk.plan.L.consts64, c64, (size_t)2 * D * D * 8, hipMemcpyHostToDevice, s),
+               "copy FP64 constants");
     PARAPN_HIP(hipMemcpyAsync(pk.dev.p + pk.plan.L.reqs, pk.img.p + cbytes, pk.plan.image.size(),
                               hipMemcpyHostToDevice, s),
                "copy request tables");
-    rc = pk.bits.ensure(2 * (size_t)nreq * sizeof(unsigned long long));
+    rc = pk.bits.ensure(parapn::kCounters * (size_t)nreq * sizeof(unsigned long long));
     return rc;
 }
 
@@ -2034,8 +2151,13 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
         }
         const Solve &v0 = *pk.solves[0];
         const bool fp64 = v0.precision == PARAPN_FP64, lm = v0.lm_sigma > 0.0;
-        bool cov = false;
-        for (ServedReq *r : pk.members) cov |= r->cov_out != nullptr;
+        bool cov = false, obj_start = false;
+        for (ServedReq *r : pk.members) {
+            cov |= r->cov_out != nullptr;
+            obj_start |= r->sv.iter == 0 && (r->sv.stop_rule & 2);
+        }
+        if (obj_start != pk.obj_start) pk.drop_graph();  // another launch sequence
+        pk.obj_start = obj_start;
         std::vector<const ServedReq *> sig(pk.members.begin(), pk.members.end());
         if (sig != pk.sig || cov != pk.cov) {
             pk.drop_graph();
@@ -2109,8 +2231,9 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
             const double *Tdev = traj + (size_t)(v.N + 1) * v.D;
             const bool want = r->cov_out && v.status != PARAPN_ENONFINITE;
             const char *sPs = want ? pk.dev.p + L.sPs + (size_t)pk.plan.reqs[i].row * (D * (D + 1) / 2) * esz : nullptr;
+            const double cs = v.calibrate ? std::sqrt(v.sigma2) : 1.0;
             PARAPN_HIP(parapn::launch_unscale(fp64, v.D, v.N, Tdev, traj, sPs, r->mean_out, want ? r->cov_out : nullptr,
-                                              s, true),
+                                              s, true, cs),
                        "unscale");
         }
     }
@@ -2134,6 +2257,8 @@ int parapn_server_step(parapn_server *srv, int32_t *n_active, int32_t *n_queued)
             c.t_start = r->t_start;
             c.t_done = now_seconds();
             c.start = v.start;
+            c.sigma_hat = std::sqrt(v.sigma2);
+            c.objective = v.objective;
             srv->done.push_back(c);
             srv->completed += 1;
             delete r;

@@ -10,6 +10,7 @@ namespace parapn {
 
 constexpr int kMaxParams = 16;
 constexpr int kMaxLevels = 24;  // scan levels per request (tree width >= 2, <= 2^24 chunks)
+constexpr int kCounters = 5;    // per-request counter words (ReqDev::dbits)
 
 // One request of a pack (device-side table, filled by the host).
 struct ReqDev {
@@ -19,7 +20,9 @@ struct ReqDev {
     double T0, T1, invT1, hq;   // scales of the E0 / E1 coordinates and h/q
     double lm_s;                // damping: std of the E0 pseudo-observations (preconditioned), packs with lm only
     double *traj;               // FP64 preconditioned trajectory [N+1][D]; null for a given linear model
-    unsigned long long *dbits;  // 2 entries: bit patterns of delta and max |E0 mu| (doubles)
+    unsigned long long *dbits;  // kCounters words: delta and max |E0 mu| (bit patterns of doubles, atomic
+                                // max), then as doubles the innovations' quadratic-form sum, the objective of
+                                // the updated trajectory and the objective of the trajectory before the pass
     int64_t N;                  // steps of this request
     int64_t row;                // packed row of its step 0 in the per-step scratch arrays
     int64_t fchunk;             // index of its first forward step-level chunk
@@ -151,10 +154,10 @@ inline hipError_t launch_tria_square(int fp64, int d, int q, const void *full, v
     return fp64 ? launch_tria_square_t<double>(d, q, full, out, s) : launch_tria_square_t<float>(d, q, full, out, s);
 }
 // mean_out [N+1][D] = Tdiag * src (src FP64 when src_fp64); cov_out [N+1][D][D]
-// = Tdiag * unpack(srcP); either output may be null; Tdiag_dev null means 1
+// = cov_scale * Tdiag * unpack(srcP); either output may be null; Tdiag_dev null means 1
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
                           const void *src_packed, void *mean_out, void *cov_out, hipStream_t s,
-                          bool src_fp64 = false);
+                          bool src_fp64 = false, double cov_scale = 1.0);
 // Coarse-grid start for nreq requests of one (precision, d, q): the
 // sequential extended Kalman smoother on each request's coarse grid
 // (k_coarse_eks, one wavefront per request, FP64 for either precision),
@@ -171,6 +174,11 @@ inline hipError_t launch_coarse(int fp64, int d, int q, const ReqDev *reqs, cons
     return fp64 ? launch_coarse_t<double>(d, q, reqs, cds, nreq, maxN, Phi, Q, s)
                 : launch_coarse_t<float>(d, q, reqs, cds, nreq, maxN, Phi, Q, s);
 }
+// Objective value (eq. objective-value) of every request's resident
+// trajectory under the prior (Phi, sQ: the preconditioned transition and the
+// process-noise factor, FP64 [D][D]), added to counter word `slot` of each
+// request (its dbits, FP64).
+hipError_t launch_objective(int d, int q, const Pack &pk, const double *Phi, const double *sQ, int slot, hipStream_t s);
 // p[0..n) = 0 by a kernel (graph-capturable, unlike a memset node)
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 // traj [N+1][D] = preconditioned starting trajectory (k_init_traj)

@@ -691,9 +691,12 @@ PARAPN_DEV SRow<C> state_apply(int lane, typename C::T *sh, const SRow<C> &s, co
 // smoothed mean, see the top of this file).  The smoothing element (E,
 // E k) and the filtering mean m of step n-1 come back in lanes D..2D-1 (row
 // lane - D; the mean in mf_prev).
+// qf (lane 0; 0 elsewhere): the quadratic form r^T S^-1 r of the step's
+// innovation r over the d ODE rows, S = Psi11 Psi11^T (the prediction-error
+// term of the quasi-maximum-likelihood diffusion, Sec. 2.4).
 template <class C>
 PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, const typename C::T *cphi,
-                              const typename C::T *csq, ERow<C> &eo, typename C::T &mf_prev)
+                              const typename C::T *csq, ERow<C> &eo, typename C::T &mf_prev, typename C::T &qf)
 {
     using T = typename C::T;
     constexpr int d = C::d, D = C::D, D2 = C::D2, LDM = C::LDM, LDB = C::LDB;
@@ -773,6 +776,7 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
     wave_sync();
     SRow<C> o;
     o.m = 0;
+    qf = 0;
 #pragma unroll
     for (int c = 0; c < D; ++c) o.P[c] = 0;
     if (lane < D) {
@@ -791,6 +795,20 @@ PARAPN_DEV SRow<C> kf_step_se(int lane, typename C::T *sh, const SRow<C> &s, con
         for (int i = 0; i < DO; ++i) k += K[i] * res[i];
         o.m = mp + k;
         V2[lane] = k;
+        if (lane == 0) {
+            // Psi11^-1 r over the leading d rows (their block of the factor is
+            // the factor of their block of S)
+            T x[d], acc = 0;
+#pragma unroll
+            for (int i = 0; i < d; ++i) {
+                T v = res[i];
+#pragma unroll
+                for (int j = 0; j < i; ++j) v -= Psi[i * LDB + j] * x[j];
+                x[i] = v / Psi[i * LDB + i];
+                acc += x[i] * x[i];
+            }
+            qf = acc;
+        }
 #pragma unroll
         for (int c = 0; c < D - d; ++c) o.P[c] = Psi[(DO + lane) * LDB + DO + c];
     }
@@ -1188,11 +1206,13 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
         mf[q.row * D + lane] = st.m;
         store_packed<C>(sPf + q.row * C::DP, lane, st.P);
     }
+    double qsum = 0.0;  // lane 0: the chunk's innovation quadratic forms
     for (int64_t n = s; n < e; ++n) {
         obs_setup<C>(a.pk, q, n, lane, sh, cphi);
         ERow<C> eo;
-        T mfp;
-        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp);
+        T mfp, qf;
+        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp, qf);
+        qsum += (double)qf;
         const int64_t row = q.row + n - 1;
         if (lane >= D && lane < C::D2) {
             const int r = lane - D;
@@ -1209,6 +1229,7 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
             store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
         }
     }
+    if (lane == 0 && q.dbits) atomicAdd((double *)q.dbits + 2, qsum);
     if (e == q.N + 1 && lane < D) {
         const int64_t row = q.row + q.N;
         T *rec = se + row * C::SEF;
@@ -1991,7 +2012,7 @@ static hipError_t bwd_seq(const Pack &pk, const ModelDev &m, const Work &w, bool
 // small helpers
 // ---------------------------------------------------------------------------
 template <typename T, typename TS>
-__global__ void k_unscale(int D, int64_t N, const double *Td, const TS *src, const T *srcP, T *mo, T *co)
+__global__ void k_unscale(int D, int64_t N, const double *Td, const TS *src, const T *srcP, T *mo, T *co, double cs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t rows = (N + 1) * D;
@@ -2003,7 +2024,7 @@ __global__ void k_unscale(int D, int64_t N, const double *Td, const TS *src, con
     if (co) {
         const T *pr = srcP + n * (int64_t)(D * (D + 1) / 2) + r * (r + 1) / 2;
         T *out = co + i * D;
-        for (int c = 0; c < D; ++c) out[c] = c <= r ? (T)(t * (double)pr[c]) : T(0);
+        for (int c = 0; c < D; ++c) out[c] = c <= r ? (T)(cs * t * (double)pr[c]) : T(0);
     }
 }
 
@@ -2017,6 +2038,64 @@ __global__ void k_init_traj(int D, int64_t N, const T *init, const T *Td, T *tra
     if (i >= (N + 1) * D) return;
     const int k = (int)(i % D);
     traj[i] = (i < D || !init) ? Td[D + k] : init[i] / Td[k];
+}
+
+// Objective value (eq. objective-value) of every request's resident
+// trajectory, in the preconditioned coordinates it is kept in, where the
+// weighted norm needs no scaling:
+//   |eta_n - Phi eta_{n-1}|^2_{Q^-1} = |sqrtQbar^-1 (etabar_n - Phibar etabar_{n-1})|^2,
+// halved and summed over n = 1..N into counter word `slot` of the request
+// (FP64).  One thread per pack row; a wavefront whose rows all belong to one
+// request adds its sum with one atomic.
+template <int D>
+__global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, const double *sQ, int slot)
+{
+    __shared__ double sPhi[D * D], sL[D * D];
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
+        sPhi[i] = Phi[i];
+        sL[i] = sQ[i];
+    }
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    int ri = -1;
+    if (r < pk.rows) {
+        int lo = 0, hi = pk.nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pk.reqs[mid].row <= r)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        ri = lo;
+        const ReqDev &q = pk.reqs[ri];
+        const int64_t n = r - q.row;
+        if (n >= 1 && q.traj) {
+            const double *a = q.traj + (n - 1) * D, *b = q.traj + n * D;
+            double w[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double u = b[i];
+#pragma unroll
+                for (int k = 0; k < D; ++k) u -= sPhi[i * D + k] * a[k];
+#pragma unroll
+                for (int j = 0; j < i; ++j) u -= sL[i * D + j] * w[j];
+                w[i] = u / sL[i * D + i];
+                v += w[i] * w[i];
+            }
+            v *= 0.5;
+        }
+    }
+    const int r0 = __shfl(ri, 0);
+    if (__all(ri == r0)) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0 && r0 >= 0 && pk.reqs[r0].dbits)
+            atomicAdd((double *)pk.reqs[r0].dbits + slot, v);
+    } else if (ri >= 0 && pk.reqs[ri].dbits) {
+        atomicAdd((double *)pk.reqs[ri].dbits + slot, v);
+    }
 }
 
 // zero n 64-bit words (a kernel, so that it may be captured in a graph)
@@ -2382,21 +2461,33 @@ int pack_layout(int fp64, int d, int q, ReqDev *reqs, ScanTab *ftab, ScanTab *st
 }
 
 hipError_t launch_unscale(int fp64, int D, int64_t N, const double *Tdiag_dev, const void *src_mean,
-                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s, bool src_fp64)
+                          const void *src_packed, void *mean_out, void *cov_out, hipStream_t s, bool src_fp64,
+                          double cov_scale)
 {
     const int64_t rows = (N + 1) * D;
     const unsigned blocks = (unsigned)cdiv(rows, 256);
     if (fp64)
         hipLaunchKernelGGL((k_unscale<double, double>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
                            (const double *)src_mean, (const double *)src_packed, (double *)mean_out,
-                           (double *)cov_out);
+                           (double *)cov_out, cov_scale);
     else if (src_fp64)
         hipLaunchKernelGGL((k_unscale<float, double>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
-                           (const double *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out);
+                           (const double *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out, cov_scale);
     else
         hipLaunchKernelGGL((k_unscale<float, float>), dim3(blocks), dim3(256), 0, s, D, N, Tdiag_dev,
-                           (const float *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out);
+                           (const float *)src_mean, (const float *)src_packed, (float *)mean_out, (float *)cov_out, cov_scale);
     return hipGetLastError();
+}
+
+hipError_t launch_objective(int d, int q, const Pack &pk, const double *Phi, const double *sQ, int slot, hipStream_t s)
+{
+    if (pk.rows < 1) return hipSuccess;
+    return dispatch_t<double>(d, q, [&](auto cfg) {
+        using C = decltype(cfg);
+        PARAPN_LAUNCH("objective", s, k_objective<C::D>, dim3((unsigned)cdiv(pk.rows, 256)), dim3(256), 0, s, pk, Phi,
+                      sQ, slot);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)

@@ -1,0 +1,168 @@
+"""GPU parity of the quasi-maximum-likelihood diffusion (Sec. 2.4), the
+objective value (eq. objective-value) and the stopping rule built on it
+(Sec. 3.2.2), against the oracle.
+
+sigma-hat^2 is accumulated inside the Kalman-step kernel of the forward scan
+(each step's innovation quadratic form over the d ODE rows) and the objective
+by a kernel over the updated FP64 trajectory; the oracle sums the sequential
+filter's innovation quadratic forms and evaluates V in original coordinates.
+FP64 gates 1e-9 relative; the FP32 path computes the innovations in FP32 and
+V of a trajectory carrying FP32 increments (gates stated per test)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_01145_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+
+    import paper_2310_01145_amd as m
+
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+def args_of(spec):
+    return (spec["field"], spec["params"], spec["y0"], spec["t0"], spec["t1"], spec["q"], spec["N"])
+
+
+CASES = [
+    (dict(field="logistic", params=[], y0=[0.01], t0=0.0, t1=10.0, q=2, N=1000), False),
+    (wl.fhn(N=4096), True),
+    (dict(field="lotka_volterra", params=[0.7, 1.2, 0.9, 1.1], y0=[1.3, 0.8], t0=0.0, t1=15.0, q=4, N=2001), True),
+    (dict(field="van_der_pol", params=[1.0], y0=[2.0, 0.0], t0=0.0, t1=6.3, q=3, N=500), False),
+]
+
+
+def objective_rounding_bound(traj, q, h):
+    """Relative rounding bound of V at a trajectory (original coordinates):
+    each residual eta_n - Phi eta_{n-1} is a difference of terms up to
+    |eta_n| + |Phi| |eta_{n-1}| (in the weighted norm), so rounding the
+    trajectory's entries perturbs V by about eps sum_n |w_n| |L^-1| (|etabar_n| +
+    |Phibar| |etabar_{n-1}|) -- large at a smooth, nearly converged trajectory,
+    where the residuals are small against the states."""
+    d = traj.shape[1] // (q + 1)
+    Phi, sQ, T = oracle.precond_model(d, q, h)
+    eb = traj / T
+    Linv = np.linalg.inv(sQ)
+    u = eb[1:] - eb[:-1] @ Phi.T
+    w = u @ Linv.T
+    mag = (np.abs(eb[1:]) + np.abs(eb[:-1]) @ np.abs(Phi).T) @ np.abs(Linv).T
+    V = 0.5 * (w * w).sum()
+    return float(np.finfo(float).eps * (np.abs(w) * mag).sum() / max(V, 1e-300))
+
+
+@pytest.mark.parametrize("spec,coarse", CASES, ids=[c[0]["field"] for c in CASES])
+def test_sigma_hat_and_objective_match_the_oracle(pp, spec, coarse):
+    """FP64: sigma-hat at 1e-9; the objective after every iteration within
+    64 times its rounding bound (at least 1e-9)."""
+    a = args_of(spec)
+    start = oracle.coarse_start(*a) if coarse else None
+    ref = oracle.ieks(*a, fixed_iters=3, want_cov=False, init_traj=start)
+    r = pp.solve(*a, precision="fp64", fixed_iters=3, init_traj=start)
+    s_ref = np.sqrt(ref["sigma2"])
+    es = abs(r["sigma_hat"] - s_ref) / s_ref
+    h = (spec["t1"] - spec["t0"]) / spec["N"]
+    bounds = []
+    for k in range(1, 4):
+        rk = oracle.ieks(*a, fixed_iters=k, want_cov=False, init_traj=start)
+        bounds.append(objective_rounding_bound(rk["mean"], spec["q"], h))
+    eo = np.abs(r["objectives"] - ref["objectives"]) / np.abs(ref["objectives"])
+    print("%s: sigma-hat %.6e (rel err %.1e), objective rel err %s, rounding bounds %s"
+          % (spec["field"], r["sigma_hat"], es, np.array2string(eo, precision=1),
+             np.array2string(np.array(bounds), formatter={"float_kind": lambda x: "%.1e" % x})))
+    assert es < 1e-9
+    assert np.all(eo <= np.maximum(64 * np.array(bounds), 1e-9))
+    assert np.isfinite(r["objective"]) and r["objective"] == r["objectives"][-1]
+
+
+@pytest.mark.parametrize("spec,coarse", CASES, ids=[c[0]["field"] for c in CASES])
+def test_fp32_sigma_hat_comes_from_an_fp64_pass(pp, spec, coarse):
+    """FP32 solves report sigma-hat from one FP64 filter pass at their final
+    iterate (calibrate with covariances): at convergence it matches the
+    oracle's converged sigma-hat (1e-4, the FP32 iterate's own accuracy); it
+    is NaN otherwise."""
+    a = args_of(spec)
+    start = oracle.coarse_start(*a) if coarse else None
+    ref = oracle.ieks(*a, max_iter=20, tol=1e-10, want_cov=False, init_traj=start)
+    r = pp.solve(*a, precision="fp32", max_iter=20, tol=1e-10, init_traj=start, want_cov=True, calibrate=True)
+    assert ref["status"] == 0 and r["status"] == 0
+    es = abs(r["sigma_hat"] - np.sqrt(ref["sigma2"])) / np.sqrt(ref["sigma2"])
+    print("%s fp32: sigma-hat %.6e, rel err %.1e" % (spec["field"], r["sigma_hat"], es))
+    assert es < 1e-4
+    assert np.isnan(pp.solve(*a, precision="fp32", max_iter=20, tol=1e-10, init_traj=start)["sigma_hat"])
+
+
+@pytest.mark.parametrize("rule", ["objective", "either"])
+def test_objective_stopping_rule_matches_the_oracle(pp, rule):
+    """Alg. 2 stopped by the objective change (atol 1e-9, rtol 1e-6), alone or
+    with the trajectory criterion: the same iteration count as the oracle and
+    the same iterate."""
+    code = {"objective": 2, "either": 3}[rule]
+    for spec, coarse in CASES[:3]:
+        a = args_of(spec)
+        start = oracle.coarse_start(*a) if coarse else None
+        ref = oracle.ieks(*a, max_iter=20, tol=1e-10, want_cov=False, init_traj=start, stop_rule=code)
+        r = pp.solve(*a, precision="fp64", max_iter=20, tol=1e-10, init_traj=start, stop_rule=rule)
+        assert r["status"] == ref["status"] == 0
+        assert r["iterations"] == ref["iterations"], spec["field"]
+        q = spec["q"]
+        m = r["mean"].double().cpu().numpy()[:, :: q + 1]
+        e = np.abs(m - ref["mean"][:, :: q + 1]).max() / np.abs(ref["mean"][:, :: q + 1]).max()
+        assert e < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_calibrated_factors_are_scaled_by_sigma_hat(pp, prec):
+    a = ("logistic", [], [0.01], 0.0, 10.0, 2, 800)
+    u = pp.solve(*a, precision=prec, max_iter=20, tol=1e-10, want_cov=True)
+    c = pp.solve(*a, precision=prec, max_iter=20, tol=1e-10, want_cov=True, calibrate=True)
+    sh = c["sigma_hat"]
+    if prec == "fp64":  # the atomic sums are not bitwise reproducible
+        assert abs(sh - u["sigma_hat"]) <= 1e-13 * sh
+    x, y = c["sqrtcov"].double(), u["sqrtcov"].double() * sh
+    assert float((x - y).abs().max() / y.abs().max()) < (1e-12 if prec == "fp64" else 1e-6)
+    ref = oracle.ieks(*a, max_iter=20, tol=1e-10, want_cov=True)
+    assert abs(sh ** 2 - ref["sigma2"]) < (1e-9 if prec == "fp64" else 1e-4) * ref["sigma2"]
+    if prec == "fp64":
+        P = np.einsum("nij,nkj->nik", x.cpu().numpy(), x.cpu().numpy())
+        Pr = np.einsum("nij,nkj->nik", ref["sqrtcov"], ref["sqrtcov"]) * ref["sigma2"]
+        assert np.abs(P - Pr).max() / np.abs(Pr).max() < 1e-9
+
+
+def test_damped_solve_reports_the_undamped_sigma_hat(pp):
+    a = ("logistic", [], [0.01], 0.0, 10.0, 2, 500)
+    ref = oracle.ieks(*a, max_iter=30, tol=1e-11, want_cov=True, lm_sigma=0.05)
+    r = pp.solve(*a, precision="fp64", max_iter=30, tol=1e-11, want_cov=True, lm_sigma=0.05)
+    assert r["iterations"] == ref["iterations"]
+    assert abs(r["sigma_hat"] ** 2 - ref["sigma2"]) < 1e-9 * ref["sigma2"]
+    # without the covariance pass a damped solve has no undamped filter pass
+    assert np.isnan(pp.solve(*a, precision="fp64", max_iter=30, tol=1e-11, lm_sigma=0.05)["sigma_hat"])
+
+
+def test_served_requests_report_sigma_hat_and_objective(pp):
+    reqs = [dict(field="logistic", params=[], y0=[0.01], t0=0.0, t1=10.0, q=2, N=900, precision="fp64",
+                 stop_rule="either"),
+            dict(field="fhn", params=[0.2, 0.2, 3.0], y0=[-1.0, 1.0], t0=0.0, t1=100.0, q=3, N=5000,
+                 precision="fp32", init="coarse", stop_rule="objective")]
+    srv = pp.Server(max_slots=8)
+    for i, r in enumerate(reqs):
+        srv.submit(i, **r)
+    done = {}
+    while len(done) < len(reqs):
+        srv.step()
+        done.update({c["req_id"]: c for c in srv.poll()})
+    srv.close()
+    for i, r in enumerate(reqs):
+        a = pp.solve(r["field"], r["params"], r["y0"], r["t0"], r["t1"], r["q"], r["N"], precision=r["precision"],
+                     init=r.get("init", "constant"), stop_rule=r["stop_rule"])
+        assert done[i]["iterations"] == a["iterations"]
+        # FP64 sums by atomics: equal to rounding; FP32 requests report no sigma-hat
+        assert np.isclose(done[i]["sigma_hat"], a["sigma_hat"], rtol=1e-13, atol=0, equal_nan=True)
+        assert np.isclose(done[i]["objective"], a["objective"], rtol=1e-13, atol=0)
