@@ -101,8 +101,8 @@ def lib():
         L.orc_kf_rts_qf.restype = i
         L.orc_objective.argtypes = [i, i, dl, l, P, i, dl]
         L.orc_objective.restype = dl
-        L.orc_ieks_ext.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, i, dl, i, dl, dl, P, P, P, P, P,
-                                   P, ctypes.POINTER(ctypes.c_int)]
+        L.orc_ieks_ext.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, i, dl, i, dl, dl, i, P, P, P, P,
+                                   P, P, ctypes.POINTER(ctypes.c_int)]
         L.orc_ieks_ext.restype = i
         _lib = L
     return _lib
@@ -277,11 +277,12 @@ def objective(traj, q, h, d=None, prior="iwp", theta=0.0):
 
 
 STOP_TRAJECTORY, STOP_OBJECTIVE = 1, 2
+LINEARIZATIONS = {"ek1": 0, "ek0": 1, "diag_ek1": 2}
 
 
 def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fixed_iters=0, init_traj=None,
          want_cov=True, lm_sigma=0.0, prior="iwp", theta=0.0, init=None, coarse_points=0, stop_rule=1,
-         obj_atol=1e-9, obj_rtol=1e-6):
+         obj_atol=1e-9, obj_rtol=1e-6, linearization="ek1"):
     """Alg. 2 with the sequential smoother.  Returns a dict with mean [N+1, D],
     sqrtcov [N+1, D, D] (original coordinates), status, iterations, deltas.
     lm_sigma > 0: Levenberg-Marquardt damping, a pseudo-observation of each
@@ -291,7 +292,9 @@ def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fix
     trajectory change, bit 1 the objective change (|V_k - V_{k-1}| <=
     obj_atol + obj_rtol |V_k|), either stops.  The result also carries
     objectives (V after each iteration), objective0 (of the start) and sigma2
-    (the quasi-MLE diffusion of the last undamped filter pass)."""
+    (the quasi-MLE diffusion of the last undamped filter pass).
+    linearization: "ek1" (exact Jacobian), "ek0" (F_y ~ 0) or "diag_ek1"
+    (its diagonal) in every iteration (the coarse start uses EK1)."""
     if init == "coarse":
         init_traj = coarse_start(field, params, y0, t0, t1, q, N, coarse_points or None, d=d)
     y0 = _f64(y0).ravel()
@@ -311,7 +314,8 @@ def ieks(field, params, y0, t0, t1, q, N, *, d=None, max_iter=20, tol=1e-10, fix
     obj0, s2 = ctypes.c_double(0.0), ctypes.c_double(0.0)
     rc = lib().orc_ieks_ext(fid, _p(params), params.size, dd, _p(y0), float(t0), float(t1), q, N, max_iter,
                             float(tol), fixed_iters, _p(init) if init is not None else None, float(lm_sigma),
-                            PRIORS[prior], float(theta), int(stop_rule), float(obj_atol), float(obj_rtol), _p(mean),
+                            PRIORS[prior], float(theta), int(stop_rule), float(obj_atol), float(obj_rtol),
+                            LINEARIZATIONS[linearization], _p(mean),
                             _p(cov) if cov is not None else None, _p(hist), _p(ohist), ctypes.byref(obj0),
                             ctypes.byref(s2), ctypes.byref(iters))
     if rc == -1:

@@ -736,6 +736,16 @@ double orc_objective(int d, int q, double h, long N, const double *traj, int pri
  * damping of the Gauss-Newton step, which the paper leaves as future work;
  * the fixed point is unchanged).  When damped, the returned factors come
  * from one more, undamped linearise-and-smooth pass at the final iterate. */
+/* Approximate Jacobians (remark on linearizing with approximate Jacobians,
+ * Sec. 3.2.1): lin 1 = EK0, F_y ~ 0; lin 2 = DiagonalEK1, F_y ~ diag(F_y);
+ * lin 0 = EK1 (the exact Jacobian, unchanged). */
+static void approx_jacobian(int lin, int d, double *J)
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            if (lin == 1 || (lin == 2 && i != j)) J[i * d + j] = 0.0;
+}
+
 /* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta), and
  * the paper's stopping criteria (Sec. 3.2.2): stop_rule bit 0 -- the
  * trajectory change delta_k < tol; bit 1 -- the change of the objective value
@@ -748,7 +758,7 @@ double orc_objective(int d, int q, double h, long N, const double *traj, int pri
 int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const double *y0, double t0, double t1,
                  int q, long N, int max_iter, double tol, int fixed_iters, const double *init_traj,
                  double lm_sigma, int prior, double theta, int stop_rule, double obj_atol, double obj_rtol,
-                 double *mean_out, double *sqrtcov_out, double *delta_hist, double *obj_hist, double *obj0,
+                 int lin, double *mean_out, double *sqrtcov_out, double *delta_hist, double *obj_hist, double *obj0,
                  double *sigma2, int *iters_out)
 {
     int d = orc_field_dim(field, d_req, nparams);
@@ -788,6 +798,7 @@ int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const 
             for (int i = 0; i < d; ++i) y[i] = T0 * eta[n * D + i * S];
             orc_field_f(field, params, d, y, fy);
             orc_field_jac(field, params, d, y, Jy);
+            approx_jacobian(lin, d, Jy);
             double *Hn = H + (n - 1) * dobs * D, *dn = dv + (n - 1) * dobs;
             for (int i = 0; i < d; ++i) {
                 double s = fy[i];
@@ -835,6 +846,7 @@ int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const 
             for (int i = 0; i < d; ++i) y[i] = T0 * eta[n * D + i * S];
             orc_field_f(field, params, d, y, fy);
             orc_field_jac(field, params, d, y, Jy);
+            approx_jacobian(lin, d, Jy);
             double *Hn = H + (n - 1) * d * D, *dn = dv + (n - 1) * d;
             for (int i = 0; i < d; ++i) {
                 double s = fy[i];
@@ -868,7 +880,7 @@ int orc_ieks_prior(int field, const double *params, int nparams, int d_req, cons
                    double *delta_hist, int *iters_out)
 {
     return orc_ieks_ext(field, params, nparams, d_req, y0, t0, t1, q, N, max_iter, tol, fixed_iters, init_traj,
-                        lm_sigma, prior, theta, 1, 0.0, 0.0, mean_out, sqrtcov_out, delta_hist, NULL, NULL, NULL,
+                        lm_sigma, prior, theta, 1, 0.0, 0.0, 0, mean_out, sqrtcov_out, delta_hist, NULL, NULL, NULL,
                         iters_out);
 }
 

@@ -522,10 +522,22 @@ def test_fixed_point_satisfies_ode_at_grid_points():
         assert abs(h @ P @ h) <= 1e-10 * max(np.abs(P).max(), 1e-30) + 1e-30
 
 
-def test_ieks_iterate_equals_linear_smoother():
-    """One IEKS iteration = the linear smoother on the model linearised at the
-    constant trajectory mu0 (Alg. 2); built here independently from the
-    unpreconditioned closed forms and dense conditioning at tiny N."""
+def approx_jac(J, lin):
+    """The Jacobian the linearisation uses (remark on approximate Jacobians,
+    Sec. 3.2.1): EK1 keeps F_y, EK0 takes 0, DiagonalEK1 its diagonal."""
+    if lin == "ek0":
+        return np.zeros_like(J)
+    if lin == "diag_ek1":
+        return np.diag(np.diag(J))
+    return J
+
+
+@pytest.mark.parametrize("lin", ["ek1", "ek0", "diag_ek1"])
+def test_ieks_iterate_equals_linear_smoother(lin):
+    """Two IEKS iterations = the linear smoother on the model linearised at the
+    constant trajectory mu0 (Alg. 2), then at that smoother's E0 means; built
+    here independently from the unpreconditioned closed forms and dense
+    conditioning at tiny N, with the Jacobian each linearisation uses."""
     field, params, y0, q, N, t1 = "fhn", [0.2, 0.2, 3.0], np.array([-1.0, 1.0]), 2, 5, 0.5
     d, S = 2, q + 1
     D = d * S
@@ -538,16 +550,57 @@ def test_ieks_iterate_equals_linear_smoother():
     for i in range(d):
         E0[i, i * S] = 1.0
         E1[i, i * S + 1] = 1.0
-    y = E0 @ mu0
-    J = oracle.field_jac(field, params, y)
-    f = oracle.field_f(field, params, y)
-    Hn = E1 - J @ E0
-    dn = f - J @ y
-    H = np.repeat(Hn[None], N, axis=0)
-    dv = np.repeat(dn[None], N, axis=0)
-    m_all, _ = dense_conditioning(mu0, np.zeros((D, D)), Phi, np.linalg.cholesky(Q), H, dv)
-    r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=1, want_cov=False)
-    assert rel(r["mean"], m_all) < 1e-9
+    traj = np.repeat(mu0[None], N + 1, axis=0)
+    for it in (1, 2):
+        H = np.zeros((N, d, D))
+        dv = np.zeros((N, d))
+        for n in range(1, N + 1):
+            y = E0 @ traj[n]
+            J = approx_jac(oracle.field_jac(field, params, y), lin)
+            H[n - 1] = E1 - J @ E0
+            dv[n - 1] = oracle.field_f(field, params, y) - J @ y
+        traj, _ = dense_conditioning(mu0, np.zeros((D, D)), Phi, np.linalg.cholesky(Q), H, dv)
+        r = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=it, want_cov=False, linearization=lin)
+        assert rel(r["mean"], traj) < 1e-9
+
+
+def test_diagonal_ek1_is_ek1_for_a_decoupled_field():
+    """With no diffusion the method-of-lines chain is d uncoupled logistic
+    equations: F_y is diagonal, so DiagonalEK1 takes exactly EK1's steps,
+    while EK0 (F_y ~ 0) does not."""
+    y0 = [0.3, 0.5, 0.7, 0.45]
+    kw = dict(fixed_iters=3, want_cov=False)
+    r1 = oracle.ieks("mol_heat_reaction", [0.0], y0, 0.0, 1.0, 2, 40, linearization="ek1", **kw)
+    r2 = oracle.ieks("mol_heat_reaction", [0.0], y0, 0.0, 1.0, 2, 40, linearization="diag_ek1", **kw)
+    r0 = oracle.ieks("mol_heat_reaction", [0.0], y0, 0.0, 1.0, 2, 40, linearization="ek0", **kw)
+    assert rel(r2["mean"], r1["mean"]) < 1e-14
+    assert rel(r0["mean"], r1["mean"]) > 1e-6
+
+
+@pytest.mark.parametrize("field,params,y0,t1,lin", [
+    ("logistic", [], [0.01], 10.0, "ek0"),
+    ("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 5.0, "diag_ek1"),
+])
+def test_approximate_jacobian_fixed_point_solves_the_ode(field, params, y0, t1, lin):
+    """An approximate Jacobian changes the iteration, not what a fixed point
+    satisfies: the noiseless constraints E1 mu_n = f(E0 mu_n) hold at every
+    grid point, and the E0 means approximate the ODE solution as closely as
+    EK1's fixed point does."""
+    from scipy.integrate import solve_ivp
+    q, N = 3, 200
+    r = oracle.ieks(field, params, y0, 0.0, t1, q, N, max_iter=200, tol=1e-12, want_cov=False, linearization=lin)
+    assert r["status"] == 0
+    d, S = len(y0), q + 1
+    m = r["mean"]
+    for n in (1, N // 2, N):
+        f = oracle.field_f(field, params, m[n, ::S])
+        assert np.abs(m[n, 1::S] - f).max() < 1e-9
+    t = np.linspace(0.0, t1, N + 1)
+    fun = (lambda _t, y: oracle.field_f(field, params, np.asarray(y)))
+    ref = solve_ivp(fun, (0.0, t1), y0, t_eval=t, rtol=1e-12, atol=1e-12, method="DOP853").y.T
+    r1 = oracle.ieks(field, params, y0, 0.0, t1, q, N, max_iter=50, tol=1e-12, want_cov=False)
+    e_lin, e_ek1 = np.abs(m[:, ::S] - ref).max(), np.abs(r1["mean"][:, ::S] - ref).max()
+    assert e_lin < 3 * e_ek1 + 1e-10
 
 
 @pytest.mark.parametrize("D,dobs", [(3, 1), (8, 2)])
