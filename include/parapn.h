@@ -55,6 +55,12 @@ extern "C" {
 #define PARAPN_START_COARSE_FAILED 3 /* the coarse smoother produced a non-finite value; the
                                       * solve ran from the constant start instead          */
 
+/* Jacobian used by the linearisation (parapn_problem.linearization; the
+ * remark on linearizing with approximate Jacobians, Sec. 3.2.1) */
+#define PARAPN_LIN_EK1 0      /* the exact Jacobian F_y (first-order Taylor)           */
+#define PARAPN_LIN_EK0 1      /* F_y ~ 0                                               */
+#define PARAPN_LIN_DIAG_EK1 2 /* F_y ~ diag(F_y)                                       */
+
 /* stopping criteria (parapn_problem.stop_rule) */
 #define PARAPN_STOP_TRAJECTORY 1
 #define PARAPN_STOP_OBJECTIVE 2
@@ -159,6 +165,18 @@ typedef struct {
     int32_t calibrate;       /* 1: scale the returned factors (sqrtcov_out) by the
                               * quasi-maximum-likelihood diffusion sigma-hat of the
                               * final linearisation (Sec. 2.4); 0: sigma = 1        */
+    int32_t linearization;   /* PARAPN_LIN_*: the Jacobian of every Gauss-Newton
+                              * linearisation (the coarse-grid start always uses
+                              * EK1).  A fixed point still satisfies the ODE at the
+                              * grid points; the iteration converges more slowly
+                              * (or not at all) when the dropped entries matter.
+                              * For PARAPN_MOL_HEAT_REACTION with EK0 or DiagonalEK1
+                              * the linearised model is block diagonal over the d
+                              * grid points and the solve runs as d independent
+                              * problems of state size q+1 (cost linear in d); its
+                              * factors (sqrtcov_out) are block diagonal, and the
+                              * objective stopping rule and sigma-hat are available
+                              * there as for the fixed-size fields.                */
 } parapn_problem;
 
 typedef struct {

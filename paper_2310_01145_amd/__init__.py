@@ -34,6 +34,7 @@ PRIORS = {"iwp": 0, "ioup": 1}
 INITS = {"constant": 0, "coarse": 1}
 STARTS = {0: "constant", 1: "coarse", 2: "given", 3: "coarse_failed"}
 STOP_RULES = {"trajectory": 1, "objective": 2, "either": 3}
+LINEARIZATIONS = {"ek1": 0, "ek0": 1, "diag_ek1": 2}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
             "parapn_start_trajectory", "parapn_pararts_noalloc",
             "parapn_pararts",
@@ -74,6 +75,7 @@ class Problem(ctypes.Structure):
         ("obj_atol", ctypes.c_double),
         ("obj_rtol", ctypes.c_double),
         ("calibrate", ctypes.c_int32),
+        ("linearization", ctypes.c_int32),
     ]
 
 
@@ -210,7 +212,7 @@ def _dtype(precision):
 
 def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
                  init_traj=None, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0,
-                 stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False):
+                 stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False, linearization="ek1"):
     """Build the ctypes Problem (keeps the host arrays alive on the object)."""
     fid = FIELDS[field] if isinstance(field, str) else int(field)
     y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).ravel())
@@ -237,6 +239,7 @@ def make_problem(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10
     pb.obj_atol = float(obj_atol)
     pb.obj_rtol = float(obj_rtol)
     pb.calibrate = 1 if calibrate else 0
+    pb.linearization = LINEARIZATIONS[linearization] if isinstance(linearization, str) else int(linearization)
     keep = [y0, prm]
     pb.init_on_device = 0
     if init_traj is not None and hasattr(init_traj, "is_cuda") and init_traj.is_cuda:
@@ -267,7 +270,7 @@ def workspace_size(problem: Problem) -> int:
 def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
           init_traj=None, want_cov=False, device=0, stream=None, out=None, d=None, lm_sigma=0.0, prior="iwp",
           theta=0.0, init="constant", coarse_points=0, stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6,
-          calibrate=False):
+          calibrate=False, linearization="ek1"):
     """ParaIEKS (Alg. 2) on the GPU.  Returns a dict with ``mean`` [N+1, D]
     (original coordinates, torch tensor on the device), ``sqrtcov``
     [N+1, D, D] or None, ``status``, ``iterations``, ``deltas``,
@@ -278,13 +281,14 @@ def solve(field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_i
     Gauss-Newton step (Levenberg-Marquardt, see parapn_problem.lm_sigma);
     ``init="coarse"`` starts from the coarse-grid smoother
     (parapn_problem.init_mode) with ``coarse_points`` coarse steps (0: the
-    library's default)."""
+    library's default).  ``linearization``: "ek1", "ek0" or "diag_ek1"
+    (parapn_problem.linearization)."""
     torch = _torch()
     L = load_library()
     pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
                       fixed_iters=fixed_iters, init_traj=init_traj, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta,
                       init=init, coarse_points=coarse_points, stop_rule=stop_rule, obj_atol=obj_atol,
-                      obj_rtol=obj_rtol, calibrate=calibrate)
+                      obj_rtol=obj_rtol, calibrate=calibrate, linearization=linearization)
     D = pb.d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -325,11 +329,13 @@ def start_trajectory(field, params, y0, t0, t1, q, N, *, precision="fp64", init=
 
 
 def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20, fixed_iters=0,
-                want_cov=False, device=0, stream=None, prior="iwp", theta=0.0):
+                want_cov=False, device=0, stream=None, prior="iwp", theta=0.0, linearization="ek1",
+                stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False, init_traj=None):
     """Alg. 2 for a batch of initial values ``y0s`` [B, d] of one problem
     (parapn_solve_batch).  Returns ``mean`` [B, N+1, D], ``sqrtcov``
     [B, N+1, D, D] or None, the overall ``status`` and per-instance
-    ``iterations``, ``converged``, ``final_delta``, ``deltas``."""
+    ``iterations``, ``converged``, ``final_delta``, ``deltas``,
+    ``sigma_hat``, ``objective`` and ``objectives``."""
     torch = _torch()
     L = load_library()
     y0s = np.ascontiguousarray(np.asarray(y0s, dtype=np.float64))
@@ -337,7 +343,9 @@ def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10
         raise ValueError("y0s must be [batch, d]")
     B, d = y0s.shape
     pb = make_problem(field, params, y0s[0], t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
-                      fixed_iters=fixed_iters, d=d, prior=prior, theta=theta)
+                      fixed_iters=fixed_iters, d=d, prior=prior, theta=theta, linearization=linearization,
+                      stop_rule=stop_rule, obj_atol=obj_atol, obj_rtol=obj_rtol, calibrate=calibrate,
+                      init_traj=init_traj)
     D = d * (pb.q + 1)
     dt = _dtype(pb.precision)
     dev = torch.device("cuda", device)
@@ -345,9 +353,11 @@ def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10
     cov = torch.empty((B, pb.N + 1, D, D), dtype=dt, device=dev) if want_cov else None
     cap = max(pb.max_iter, pb.fixed_iters, 1)
     hist = np.zeros((B, cap))
+    ohist = np.zeros((B, cap))
     infos = (Info * B)()
     for b in range(B):
         infos[b].delta_history = hist[b].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        infos[b].objective_history = ohist[b].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     rc = L.parapn_solve_batch(context(device), ctypes.byref(pb), B, y0s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               _dptr(mean), _dptr(cov), infos, _stream_handle(stream))
     _check(rc, allow=(OK, MAXITER, ENONFINITE))
@@ -355,7 +365,10 @@ def solve_batch(field, params, y0s, t0, t1, q, N, *, precision="fp64", tol=1e-10
     return {"mean": mean, "sqrtcov": cov, "status": rc, "iterations": its,
             "converged": [bool(infos[b].converged) for b in range(B)],
             "final_delta": [infos[b].final_delta for b in range(B)],
-            "deltas": [hist[b, :its[b]].copy() for b in range(B)]}
+            "deltas": [hist[b, :its[b]].copy() for b in range(B)],
+            "sigma_hat": [infos[b].sigma_hat for b in range(B)],
+            "objective": [infos[b].objective for b in range(B)],
+            "objectives": [ohist[b, :its[b]].copy() for b in range(B)]}
 
 
 def pararts(mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, *, precision="fp64", want_cov=True, want_filter=True,
@@ -446,12 +459,13 @@ class Server:
 
     def submit(self, req_id, field, params, y0, t0, t1, q, N, *, precision="fp64", tol=1e-10, max_iter=20,
                fixed_iters=0, d=None, lm_sigma=0.0, prior="iwp", theta=0.0, init="constant", coarse_points=0,
-               want_cov=False, stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False):
+               want_cov=False, stop_rule="trajectory", obj_atol=1e-9, obj_rtol=1e-6, calibrate=False,
+               linearization="ek1"):
         torch = _torch()
         pb = make_problem(field, params, y0, t0, t1, q, N, precision=precision, tol=tol, max_iter=max_iter,
                           fixed_iters=fixed_iters, d=d, lm_sigma=lm_sigma, prior=prior, theta=theta, init=init,
                           coarse_points=coarse_points, stop_rule=stop_rule, obj_atol=obj_atol, obj_rtol=obj_rtol,
-                          calibrate=calibrate)
+                          calibrate=calibrate, linearization=linearization)
         D = pb.d * (pb.q + 1)
         dev = torch.device("cuda", self._device)
         mean = torch.empty((pb.N + 1, D), dtype=_dtype(pb.precision), device=dev)

@@ -20,6 +20,10 @@ enum FieldId : int {
     F_AFFINE = 5,
     F_RIGID = 6,
     F_VDP = 7,
+    // one grid point of the method-of-lines chain solved as its own d = 1
+    // problem (approximate Jacobians decouple the chain's state-space model;
+    // the linearisation reads the neighbours' trajectories)
+    F_MOL_COMPONENT = 8,
 };
 
 // ODE dimension a field requires (0 = any d, checked against params elsewhere)

@@ -441,11 +441,12 @@ int plan_pack(int fp64, int d, int q, const std::vector<parapn::ReqDev> &reqs, b
 
 // Fill the device pointers of the plan for a workspace at ws and build the
 // image of its tables.
-void bind_plan(PackPlan &pl, char *ws)
+// group > 1: requests i share the counter slot i / group.
+void bind_plan(PackPlan &pl, char *ws, int group = 1)
 {
     const int nreq = (int)pl.reqs.size();
     unsigned long long *dbits = (unsigned long long *)(ws + pl.L.dbits);
-    for (int i = 0; i < nreq; ++i) pl.reqs[i].dbits = dbits + parapn::kCounters * i;
+    for (int i = 0; i < nreq; ++i) pl.reqs[i].dbits = dbits + parapn::kCounters * (i / group);
     pl.pk.reqs = (const parapn::ReqDev *)(ws + pl.L.reqs);
     pl.pk.ftab = (const parapn::ScanTab *)(ws + pl.L.ftab);
     pl.pk.stab = (const parapn::ScanTab *)(ws + pl.L.stab);
@@ -470,6 +471,7 @@ struct Solve {
     int stop_rule;          // bit 0 trajectory change, bit 1 objective change
     double obj_atol, obj_rtol;
     int calibrate;
+    int lin;                // PARAPN_LIN_*
     double params[PARAPN_MAX_PARAMS];
     std::vector<double> Td, mu0, mu0b;  // preconditioner, mu0, mu0 / T
     // iteration state
@@ -507,6 +509,7 @@ int prepare(const parapn_problem *p, Solve &sv)
     sv.obj_atol = p->obj_atol;
     sv.obj_rtol = p->obj_rtol;
     sv.calibrate = p->calibrate;
+    sv.lin = p->linearization;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) sv.params[i] = i < p->n_params ? p->params[i] : 0.0;
     precond_diag(sv.d, sv.q, sv.h, sv.Td);
     sv.mu0.assign(sv.D, 0.0);
@@ -534,6 +537,7 @@ void fill_reqdev(const Solve &sv, double *traj, unsigned long long *dbits, parap
 {
     std::memset(&r, 0, sizeof(r));
     r.field = sv.field;
+    r.lin = sv.lin;
     for (int i = 0; i < PARAPN_MAX_PARAMS; ++i) r.p[i] = sv.params[i];
     r.T0 = sv.Td[0];
     r.T1 = sv.Td[1];
@@ -773,8 +777,11 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (p->coarse_points < 0) return fail(PARAPN_EINVAL, "coarse_points must be >= 0");
     if (p->stop_rule < 0 || p->stop_rule > 3) return fail(PARAPN_EINVAL, "stop_rule must be 0..3");
     if (!(p->obj_atol >= 0.0) || !(p->obj_rtol >= 0.0)) return fail(PARAPN_EINVAL, "objective tolerances must be >= 0");
-    if (p->field == parapn::F_MOL && (p->stop_rule & 2))
-        return fail(PARAPN_EINVAL, "the objective stopping rule is available for the fixed-size fields");
+    if (p->linearization < PARAPN_LIN_EK1 || p->linearization > PARAPN_LIN_DIAG_EK1)
+        return fail(PARAPN_EINVAL, "unknown linearization");
+    if (p->field == parapn::F_MOL && p->linearization == PARAPN_LIN_EK1 && (p->stop_rule & 2))
+        return fail(PARAPN_EINVAL, "the objective stopping rule is available for the fixed-size fields and for the "
+                                   "method-of-lines field under an approximate Jacobian");
     if (p->field == parapn::F_MOL && p->init_mode == PARAPN_INIT_COARSE && !p->init_traj)
         return fail(PARAPN_EINVAL, "the coarse-grid start is available for the fixed-size fields");
     if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
@@ -1115,6 +1122,252 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     return status;
 }
 
+// Workspace of the decoupled chains (below): trajectories [B][d][N+1][S],
+// T (S values), mu0/T ([B][D]), a staging copy of a host init_traj, the pack
+// scratch for all instances and (calibrated FP32 with factors) an FP64
+// pack's.
+struct DecoupledLayout {
+    size_t T, mu, stage, pack, pack64, total;
+};
+
+static int decoupled_layout(const parapn_problem *p, int B, bool want_cov, DecoupledLayout &DL)
+{
+    const bool fp64 = p->precision == PARAPN_FP64;
+    const int d = p->d, S = p->q + 1, D = d * S;
+    const int64_t N = p->N;
+    DL.T = align_up((size_t)B * d * (N + 1) * S * 8);
+    DL.mu = DL.T + align_up((size_t)S * 8);
+    DL.stage = DL.mu + align_up((size_t)B * D * 8);
+    DL.pack = DL.stage + (p->init_traj && !p->init_on_device ? align_up((size_t)(N + 1) * D * 8) : 0);
+    std::vector<parapn::ReqDev> r((size_t)B * d, parapn::ReqDev{});
+    for (auto &x : r) x.N = N;
+    PackPlan pl;
+    int rc = plan_pack(fp64, 1, p->q, r, want_cov, 0, pl);
+    if (rc) return rc;
+    DL.pack64 = DL.pack + pl.L.total;
+    DL.total = DL.pack64;
+    if (!fp64 && want_cov && p->calibrate) {
+        rc = plan_pack(true, 1, p->q, r, false, 0, pl);
+        if (rc) return rc;
+        DL.total += pl.L.total;
+    }
+    return PARAPN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// method-of-lines field under an approximate Jacobian: decoupled chains
+// ---------------------------------------------------------------------------
+// With F_y ~ 0 or diag(F_y) (remark on approximate Jacobians, Sec. 3.2.1),
+// Sigma0 = 0 and the prior I_d (x) (one-dimensional prior), every matrix of
+// the linearised state-space model is block diagonal over the d grid points:
+// the filter and smoother factor into d independent problems of state size
+// S = q+1 with one scalar observation per step.  They run as d = 1 requests
+// of the row-per-lane engine (field F_MOL_COMPONENT, whose linearisation
+// reads the neighbours' trajectories).  Instance b's grid point i keeps its
+// preconditioned trajectory at traj + (b d + i)(N+1) S; the d requests of an
+// instance share one counter slot, so delta and max |E0| are maxima over the
+// chain and the quadratic forms and objective values its sums.  An instance
+// that stops leaves the pack with its outputs written (its factors from the
+// covariance pass over the last linearisation), so its result is the one it
+// gets alone.
+static int decoupled_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const double *y0s, void *mean_out,
+                           void *cov_out, parapn_info *info, hipStream_t s)
+{
+    const bool fp64 = p->precision == PARAPN_FP64;
+    const int esz = fp64 ? 8 : 4, d = p->d, q = p->q, S = q + 1, D = d * S;
+    const int64_t N = p->N, ts = (N + 1) * S;
+    std::vector<Solve> sv(B);
+    for (int b = 0; b < B; ++b) {
+        parapn_problem pb = *p;
+        pb.y0 = y0s + (size_t)b * d;
+        for (int i = 0; i < d; ++i)
+            if (!std::isfinite(pb.y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
+        const int rc = prepare(&pb, sv[b]);
+        if (rc) return rc;
+        sv[b].start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
+    }
+    const bool want_cov = cov_out != nullptr;
+    const bool pass64 = !fp64 && want_cov && p->calibrate;
+    const double k = (p->n_params >= 1 ? p->params[0] : 0.0) * (double)d * (double)d;
+    double *trajs = nullptr;  // set once the workspace is in place
+    auto requests = [&](const std::vector<int> &act) {
+        std::vector<parapn::ReqDev> reqs(act.size() * d);
+        for (size_t a = 0; a < act.size(); ++a)
+            for (int i = 0; i < d; ++i) {
+                parapn::ReqDev &r = reqs[a * d + i];
+                fill_reqdev(sv[act[a]], trajs ? trajs + ((size_t)act[a] * d + i) * ts : nullptr, nullptr, r);
+                r.field = parapn::F_MOL_COMPONENT;
+                std::memset(r.p, 0, sizeof(r.p));
+                r.p[0] = k;
+                r.p[1] = (double)((((i + d - 1) % d) - i) * ts);
+                r.p[2] = (double)((((i + 1) % d) - i) * ts);
+            }
+        return reqs;
+    };
+    std::vector<int> act(B);
+    for (int b = 0; b < B; ++b) act[b] = b;
+    const bool stage = p->init_traj && !p->init_on_device;
+    DecoupledLayout DL;
+    int rc = decoupled_layout(p, B, want_cov, DL);
+    if (rc) return rc;
+    const size_t o_T = DL.T, o_mu = DL.mu, o_stage = DL.stage, o_pack = DL.pack, o_64 = DL.pack64;
+    PackPlan pl, pl64;
+    rc = ensure_ws(ctx, DL.total);
+    if (rc) return rc;
+    rc = ensure_host_bits(ctx, parapn::kCounters * (size_t)B);
+    if (rc) return rc;
+    char *ws = (char *)ctx->ws;
+    ctx->consts_at = nullptr;  // this layout overwrites what the packs cached
+    ctx->reqs_at = nullptr;
+    trajs = (double *)ws;
+    double *Tdev = (double *)(ws + o_T), *mudev = (double *)(ws + o_mu);
+    {
+        std::vector<double> host((size_t)S + (size_t)B * D);
+        for (int j = 0; j < S; ++j) host[j] = sv[0].Td[j];
+        for (int b = 0; b < B; ++b)
+            for (int j = 0; j < D; ++j) host[S + (size_t)b * D + j] = sv[b].mu0b[j];
+        PARAPN_HIP(hipMemcpyAsync(Tdev, host.data(), S * 8, hipMemcpyHostToDevice, s), "copy T");
+        PARAPN_HIP(hipMemcpyAsync(mudev, host.data() + S, (size_t)B * D * 8, hipMemcpyHostToDevice, s), "copy mu0");
+        const double *init = p->init_traj;
+        if (stage) {
+            PARAPN_HIP(hipMemcpyAsync(ws + o_stage, p->init_traj, (size_t)(N + 1) * D * 8, hipMemcpyHostToDevice, s),
+                       "copy traj");
+            init = (const double *)(ws + o_stage);
+        }
+        PARAPN_HIP(parapn::launch_blocks_in(B, d, S, N, init, Tdev, mudev, trajs, s), "starting trajectories");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");  // host is a local
+    }
+    Solve one = sv[0];  // the constants of one grid point
+    one.d = 1;
+    one.D = S;
+    char *wp = ws + o_pack;
+    const double *c64 = nullptr;
+    parapn::ModelDev m{};
+    bool need_plan = true;
+    while (!act.empty()) {
+        if (need_plan) {
+            // the constants sit after the per-row arrays, so they move with the plan
+            rc = plan_pack(fp64, 1, q, requests(act), want_cov, 0, pl);
+            if (rc) return rc;
+            bind_plan(pl, wp, d);
+            rc = upload_consts(one, fp64, wp + pl.L.consts, wp + pl.L.consts64, s);
+            if (rc) return rc;
+            c64 = (const double *)(wp + pl.L.consts64);
+            m = model_from(wp + pl.L.consts, S, esz);
+            PARAPN_HIP(hipMemcpyAsync(wp + pl.L.reqs, pl.image.data(), pl.image.size(), hipMemcpyHostToDevice, s),
+                       "copy request tables");
+            PARAPN_HIP(hipStreamSynchronize(s), "sync");  // the image is host memory of the plan
+            need_plan = false;
+        }
+        const int na = (int)act.size();
+        std::vector<Solve *> ptr(na);
+        bool obj_start = false;
+        for (int a = 0; a < na; ++a) {
+            ptr[a] = &sv[act[a]];
+            obj_start |= ptr[a]->iter == 0 && (ptr[a]->stop_rule & 2);
+        }
+        unsigned long long *dbits = (unsigned long long *)(wp + pl.L.dbits);
+        parapn::Pack pk = pl.pk;
+        pk.mode = 0;
+        pk.lm = 0;
+        const parapn::Work w = work_from(wp, pl.L, false);
+        PARAPN_HIP(parapn::launch_zero_u64(dbits, parapn::kCounters * (int64_t)na, s), "reset counters");
+        if (obj_start) PARAPN_HIP(parapn::launch_objective(1, q, pk, c64, c64 + S * S, 4, s), "objective of the start");
+        PARAPN_HIP(parapn::launch_forward(fp64, 1, q, pk, m, w, s), "forward scan");
+        PARAPN_HIP(parapn::launch_smoother(fp64, 1, q, pk, m, w, false, true, nullptr, s), "reverse scan");
+        PARAPN_HIP(parapn::launch_objective(1, q, pk, c64, c64 + S * S, 3, s), "objective");
+        PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, dbits, parapn::kCounters * na * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s),
+                   "read counters");
+        PARAPN_HIP(hipStreamSynchronize(s), "sync");
+        pack_finish(ptr, ctx->host_bits);
+        std::vector<int> fin;  // positions in act of the instances that stopped
+        for (int a = 0; a < na; ++a)
+            if (ptr[a]->done) fin.push_back(a);
+        if (fin.empty()) continue;
+        if (pass64) {
+            // sigma-hat of each stopping instance from one FP64 linearise-and-
+            // filter pass at its final iterate (see parapn_solve)
+            std::vector<int> sub;
+            for (int a : fin)
+                if (ptr[a]->status != PARAPN_ENONFINITE) sub.push_back(act[a]);
+            if (!sub.empty()) {
+                char *w64 = ws + o_64;
+                rc = plan_pack(true, 1, q, requests(sub), false, 0, pl64);
+                if (rc) return rc;
+                bind_plan(pl64, w64, d);
+                rc = upload_consts(one, true, w64 + pl64.L.consts, w64 + pl64.L.consts64, s);
+                if (rc) return rc;
+                PARAPN_HIP(hipMemcpyAsync(w64 + pl64.L.reqs, pl64.image.data(), pl64.image.size(),
+                                          hipMemcpyHostToDevice, s),
+                           "copy request tables");
+                unsigned long long *db = (unsigned long long *)(w64 + pl64.L.dbits);
+                PARAPN_HIP(parapn::launch_zero_u64(db, parapn::kCounters * (int64_t)sub.size(), s), "reset counters");
+                parapn::Pack p64 = pl64.pk;
+                p64.mode = 0;
+                p64.lm = 0;
+                PARAPN_HIP(parapn::launch_forward(1, 1, q, p64, model_from(w64 + pl64.L.consts, S, 8),
+                                                  work_from(w64, pl64.L, false), s),
+                           "FP64 forward scan");
+                PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, db, parapn::kCounters * sub.size() * 8,
+                                          hipMemcpyDeviceToHost, s),
+                           "read counters");
+                PARAPN_HIP(hipStreamSynchronize(s), "sync");
+                for (size_t j = 0; j < sub.size(); ++j) {
+                    double qf;
+                    std::memcpy(&qf, ctx->host_bits + parapn::kCounters * j + 2, 8);
+                    sv[sub[j]].sigma2 = qf / ((double)N * d);
+                }
+            }
+        }
+        parapn::Work wc = work_from(wp, pl.L, want_cov);
+        if (want_cov)
+            PARAPN_HIP(parapn::launch_smoother(fp64, 1, q, pk, m, wc, true, false, wc.mf, s), "covariance pass");
+        for (int a : fin) {
+            const int b = act[a];
+            const double cs = p->calibrate ? std::sqrt(sv[b].sigma2) : 1.0;
+            PARAPN_HIP(parapn::launch_blocks_out(fp64, d, S, N, Tdev, trajs + (size_t)b * d * ts, wc.sPs,
+                                                 (int64_t)a * d * (N + 1),
+                                                 (char *)mean_out + (size_t)b * (N + 1) * D * esz,
+                                                 want_cov ? (char *)cov_out + (size_t)b * (N + 1) * D * D * esz
+                                                          : nullptr,
+                                                 cs, s),
+                       "outputs");
+        }
+        std::vector<int> keep;
+        for (int a = 0; a < na; ++a)
+            if (!ptr[a]->done) keep.push_back(act[a]);
+        act.swap(keep);
+        need_plan = true;
+    }
+    PARAPN_HIP(hipStreamSynchronize(s), "sync");
+    int status = PARAPN_OK;
+    for (int b = 0; b < B; ++b) {
+        const Solve &v = sv[b];
+        if (info) {
+            parapn_info &f = info[b];
+            f.iterations = v.iter;
+            f.converged = v.converged ? 1 : 0;
+            f.final_delta = v.delta;
+            f.tol_used = v.tol_used;
+            f.start = v.start;
+            f.sigma_hat = std::sqrt(v.sigma2);
+            f.objective = v.objective;
+            const int cap = std::max(v.max_iter, v.fixed_iters);
+            if (f.delta_history)
+                for (int j = 0; j < (int)v.deltas.size() && j < cap; ++j) f.delta_history[j] = v.deltas[j];
+            if (f.objective_history)
+                for (int j = 0; j < (int)v.objectives.size() && j < cap; ++j) f.objective_history[j] = v.objectives[j];
+        }
+        if (v.status == PARAPN_ENONFINITE)
+            status = PARAPN_ENONFINITE;
+        else if (v.status == PARAPN_MAXITER && status == PARAPN_OK)
+            status = PARAPN_MAXITER;
+    }
+    if (status == PARAPN_ENONFINITE) g_err = "non-finite values in the iterate";
+    return status;
+}
+
 namespace {
 int scratch_address(int device, void **out);
 }  // namespace
@@ -1163,6 +1416,13 @@ int parapn_workspace_size(const parapn_problem *p, size_t *bytes)
     int rc = check_problem(p, &q, &D);
     if (rc) return rc;
     if (!bytes) return fail(PARAPN_EINVAL, "bytes is NULL");
+    if (p->field == parapn::F_MOL && p->linearization != PARAPN_LIN_EK1) {
+        DecoupledLayout DL;
+        rc = decoupled_layout(p, 1, true, DL);
+        if (rc) return rc;
+        *bytes = DL.total;
+        return PARAPN_OK;
+    }
     if (p->field == parapn::F_MOL) {
         *bytes = dense_layout(p->precision == PARAPN_FP64, D, p->N, 1, true).total;
         return PARAPN_OK;
@@ -1195,6 +1455,8 @@ int parapn_solve(parapn_ctx *ctx, const parapn_problem *p, void *mean_out, void 
     const int esz = fp64 ? 8 : 4;
     hipStream_t s = (hipStream_t)stream;
     PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (p->field == parapn::F_MOL && p->linearization != PARAPN_LIN_EK1)
+        return decoupled_solve(ctx, p, 1, p->y0, mean_out, sqrtcov_out, info, s);
     if (p->field == parapn::F_MOL) return dense_solve(ctx, p, 1, p->y0, mean_out, sqrtcov_out, info, s);
     Solve sv;
     rc = prepare(p, sv);
@@ -1382,6 +1644,8 @@ int parapn_solve_batch(parapn_ctx *ctx, const parapn_problem *p, int32_t batch, 
         if (!std::isfinite(y0s[i])) return fail(PARAPN_EINVAL, "y0s is not finite");
     hipStream_t s = (hipStream_t)stream;
     PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (p->field == parapn::F_MOL && p->linearization != PARAPN_LIN_EK1)
+        return decoupled_solve(ctx, p, batch, y0s, mean_out, sqrtcov_out, info, s);
     if (p->field == parapn::F_MOL) return dense_solve(ctx, p, batch, y0s, mean_out, sqrtcov_out, info, s);
     // row-per-lane fields: one solve after another
     const size_t esz = p->precision == PARAPN_FP64 ? 8 : 4;

@@ -15,8 +15,10 @@ constexpr int kCounters = 5;    // per-request counter words (ReqDev::dbits)
 // One request of a pack (device-side table, filled by the host).
 struct ReqDev {
     int field;
-    int pad_;
-    double p[kMaxParams];
+    int lin;                    // Jacobian used by the linearisation: 0 exact (EK1), 1 zero (EK0), 2 its diagonal
+                                // (DiagonalEK1)
+    double p[kMaxParams];       // field parameters; for F_MOL_COMPONENT: nu d^2, then the element offsets from
+                                // this trajectory to its left and right neighbours' trajectories
     double T0, T1, invT1, hq;   // scales of the E0 / E1 coordinates and h/q
     double lm_s;                // damping: std of the E0 pseudo-observations (preconditioned), packs with lm only
     double *traj;               // FP64 preconditioned trajectory [N+1][D]; null for a given linear model
@@ -183,6 +185,20 @@ hipError_t launch_objective(int d, int q, const Pack &pk, const double *Phi, con
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 // traj [N+1][D] = preconditioned starting trajectory (k_init_traj)
 hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s);
+
+// Decoupled chains (d grid points of state size S = q+1 each, trajectories
+// [B][d][N+1][S]): blocks_in writes every instance's preconditioned starting
+// trajectories from mu0/T ([B][d S]) and, unless init is null, a starting
+// trajectory init [N+1][d S] in original coordinates shared by all instances
+// (rows n >= 1; row 0 is mu0).  blocks_out writes instance b's mean
+// [N+1][d S] and, when cov_out is set, its block-diagonal square-root factors
+// [N+1][d S][d S] in original coordinates (scaled by cov_scale) from the
+// packed lower factors of the pack rows row0 + i (N+1) + n.
+hipError_t launch_blocks_in(int B, int d, int S, int64_t N, const double *init, const double *Td, const double *mu0b,
+                            double *traj, hipStream_t s);
+hipError_t launch_blocks_out(int fp64, int d, int S, int64_t N, const double *Td, const double *traj,
+                             const void *packed, int64_t row0, void *mean_out, void *cov_out, double cov_scale,
+                             hipStream_t s);
 // index of an instantiated (d, q) configuration, or -1
 int config_supported(int d, int q);
 

@@ -272,7 +272,7 @@ struct ReqView {
     unsigned long long *dbits;
     double T0, T1, invT1, hq, lm_s;
     int64_t N, row;
-    int field;
+    int field, lin;
 };
 
 PARAPN_DEV ReqView view_of(const ReqDev &q)
@@ -289,6 +289,7 @@ PARAPN_DEV ReqView view_of(const ReqDev &q)
     v.N = q.N;
     v.row = q.row;
     v.field = q.field;
+    v.lin = q.lin;
     return v;
 }
 
@@ -305,22 +306,45 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
     if (pk.mode == 0) {
         const double *tn = o.traj + n * D;
         const double *tp = tn - D;
-        Dual<double, d> yd[d], fd[d];
-#pragma unroll
-        for (int i = 0; i < d; ++i) {
-            yd[i].v = o.T0 * tn[i * S];
-#pragma unroll
-            for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
-        }
-        field_eval<d>(o.field, o.p, yd, fd);
-#pragma unroll
-        for (int i = 0; i < d; ++i)
-            if (lane == i) {
-#pragma unroll
-                for (int j = 0; j < d; ++j) hrow[j * S] -= (T)(o.hq * fd[i].g[j]);
-                hrow[i * S + 1] += T(1);
-                rval = (T)((fd[i].v - o.T1 * tn[i * S + 1]) * o.invT1);
+        bool component = false;
+        if constexpr (d == 1) {
+            if (o.field == F_MOL_COMPONENT) {
+                // f_i = nu (y_{i-1} - 2 y_i + y_{i+1}) / dx^2 + y_i (1 - y_i), its
+                // diagonal Jacobian entry -2 nu / dx^2 + 1 - 2 y_i
+                component = true;
+                const double k = o.p[0];
+                const double y = o.T0 * tn[0], ym = o.T0 * tn[(int64_t)o.p[1]], yp = o.T0 * tn[(int64_t)o.p[2]];
+                const double fv = k * (ym - 2.0 * y + yp) + y * (1.0 - y);
+                const double jv = o.lin == 2 ? 1.0 - 2.0 * k - 2.0 * y : 0.0;
+                if (lane == 0) {
+                    hrow[0] -= (T)(o.hq * jv);
+                    hrow[1] += T(1);
+                    rval = (T)((fv - o.T1 * tn[1]) * o.invT1);
+                }
             }
+        }
+        if (!component) {
+            Dual<double, d> yd[d], fd[d];
+#pragma unroll
+            for (int i = 0; i < d; ++i) {
+                yd[i].v = o.T0 * tn[i * S];
+#pragma unroll
+                for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
+            }
+            field_eval<d>(o.field, o.p, yd, fd);
+#pragma unroll
+            for (int i = 0; i < d; ++i)
+                if (lane == i) {
+#pragma unroll
+                    for (int j = 0; j < d; ++j) {
+                        // EK0 drops F_y, DiagonalEK1 its off-diagonal entries
+                        const bool keep = o.lin == 0 || (o.lin == 2 && j == i);
+                        hrow[j * S] -= keep ? (T)(o.hq * fd[i].g[j]) : T(0);
+                    }
+                    hrow[i * S + 1] += T(1);
+                    rval = (T)((fd[i].v - o.T1 * tn[i * S + 1]) * o.invT1);
+                }
+        }
         if constexpr (C::LM) {
             // damping rows: E0 of the increment is observed as 0
 #pragma unroll
@@ -2040,6 +2064,44 @@ __global__ void k_init_traj(int D, int64_t N, const T *init, const T *Td, T *tra
     traj[i] = (i < D || !init) ? Td[D + k] : init[i] / Td[k];
 }
 
+// starting trajectories of decoupled chains: one thread per element of
+// [B][d][N+1][S]
+static __global__ void k_blocks_in(int B, int d, int S, int64_t N, const double *init, const double *Td, const double *mu0b,
+                            double *traj)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (N + 1) * S, total = (int64_t)B * d * per;
+    if (e >= total) return;
+    const int64_t bi = e / per, r = e - bi * per, n = r / S;
+    const int k = (int)(r - n * S);
+    const int b = (int)(bi / d), i = (int)(bi - (int64_t)b * d);
+    const int D = d * S, col = i * S + k;
+    traj[e] = (n == 0 || !init) ? mu0b[(int64_t)b * D + col] : init[n * D + col] / Td[k];
+}
+
+// one instance's outputs from its decoupled chains: one thread per (n, row)
+// of the [N+1][d S] mean; the same thread writes that row of the factor
+template <typename T>
+__global__ void k_blocks_out(int d, int S, int64_t N, const double *Td, const double *traj, const T *packed,
+                             int64_t row0, T *mo, T *co, double cs)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int D = d * S;
+    if (e >= (N + 1) * D) return;
+    const int64_t n = e / D;
+    const int col = (int)(e - n * D), i = col / S, r = col - i * S;
+    const double t = Td[r];
+    mo[e] = (T)(t * traj[((int64_t)i * (N + 1) + n) * S + r]);
+    if (co) {
+        const T *pr = packed + (row0 + (int64_t)i * (N + 1) + n) * (S * (S + 1) / 2) + r * (r + 1) / 2;
+        T *out = co + e * D;
+        for (int c = 0; c < D; ++c) {
+            const int j = c / S, cc = c - j * S;
+            out[c] = (j == i && cc <= r) ? (T)(cs * t * (double)pr[cc]) : T(0);
+        }
+    }
+}
+
 // Objective value (eq. objective-value) of every request's resident
 // trajectory, in the preconditioned coordinates it is kept in, where the
 // weighted norm needs no scaling:
@@ -2494,6 +2556,29 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)
 {
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks_in(int B, int d, int S, int64_t N, const double *init, const double *Td, const double *mu0b,
+                            double *traj, hipStream_t s)
+{
+    const int64_t total = (int64_t)B * d * (N + 1) * S;
+    hipLaunchKernelGGL(k_blocks_in, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, B, d, S, N, init, Td, mu0b,
+                       traj);
+    return hipGetLastError();
+}
+
+hipError_t launch_blocks_out(int fp64, int d, int S, int64_t N, const double *Td, const double *traj,
+                             const void *packed, int64_t row0, void *mean_out, void *cov_out, double cov_scale,
+                             hipStream_t s)
+{
+    const unsigned blocks = (unsigned)cdiv((N + 1) * d * S, 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_blocks_out<double>, dim3(blocks), dim3(256), 0, s, d, S, N, Td, traj,
+                           (const double *)packed, row0, (double *)mean_out, (double *)cov_out, cov_scale);
+    else
+        hipLaunchKernelGGL(k_blocks_out<float>, dim3(blocks), dim3(256), 0, s, d, S, N, Td, traj,
+                           (const float *)packed, row0, (float *)mean_out, (float *)cov_out, cov_scale);
     return hipGetLastError();
 }
 
