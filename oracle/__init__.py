@@ -86,6 +86,8 @@ def lib():
         L.orc_ieks_prior.restype = i
         L.orc_ioup.argtypes = [i, dl, dl, P, P]
         L.orc_ioup.restype = None
+        L.orc_matern.argtypes = [i, dl, dl, P, P]
+        L.orc_matern.restype = None
         L.orc_filter_element.argtypes = [i, i, P, P, P, P, P, P, i, P, P, P, P, P]
         L.orc_filter_combine.argtypes = [i] + [P] * 15
         L.orc_smoother_element.argtypes = [i, P, P, P, P, i, P, P, P]
@@ -219,7 +221,16 @@ def ioup(q, theta, h):
     return Phi, Q
 
 
-PRIORS = {"iwp": 0, "ioup": 1}
+def matern(q, ell, h):
+    """Matern(q + 1/2, length scale ell) blocks Phi(h), Q(h) in original
+    coordinates (unit diffusion)."""
+    S = q + 1
+    Phi, Q = np.zeros((S, S)), np.zeros((S, S))
+    lib().orc_matern(q, float(ell), float(h), _p(Phi), _p(Q))
+    return Phi, Q
+
+
+PRIORS = {"iwp": 0, "ioup": 1, "matern": 2}
 
 
 def coarse_grid(N, M_target):

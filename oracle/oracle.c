@@ -457,19 +457,18 @@ static void expm_taylor(int n, const double *A, double *E)
     free(tmp);
 }
 
-/* Integrated Ornstein-Uhlenbeck prior IOUP(q, theta) (the alternative priors
- * of Sec. 2.1): derivatives 0..q with X_i' = X_{i+1} (i < q) and
- * dX_q = -theta X_q dt + dW.  Drift F: F[i][i+1] = 1, F[q][q] = -theta.
- * Phi = exp(F h); Q = int_0^h exp(F s) e_q e_q^T exp(F s)^T ds, by composite
- * 5-point Gauss-Legendre quadrature over 64 panels (the integrand is smooth).
- * theta = 0 is the integrated Wiener process. */
-void orc_ioup(int q, double theta, double h, double *Phi, double *Q)
+/* Blocks of a prior whose derivatives 0..q follow X_i' = X_{i+1} (i < q) and
+ * dX_q = sum_k c_k X_k dt + dW (the alternative Gauss-Markov priors of
+ * Sec. 2.1).  Drift F: F[i][i+1] = 1, F[q][k] = c_k.  Phi = exp(F h);
+ * Q = int_0^h exp(F s) e_q e_q^T exp(F s)^T ds, by composite 5-point
+ * Gauss-Legendre quadrature over 64 panels (the integrand is smooth). */
+static void lti_prior(int q, const double *c, double h, double *Phi, double *Q)
 {
     int S = q + 1;
     double *F = dalloc(S * S), *A = dalloc(S * S), *E = dalloc(S * S);
     memset(F, 0, sizeof(double) * S * S);
     for (int i = 0; i < q; ++i) F[i * S + i + 1] = 1.0;
-    F[q * S + q] = -theta;
+    for (int k = 0; k <= q; ++k) F[q * S + k] = c[k];
     for (int i = 0; i < S * S; ++i) A[i] = F[i] * h;
     expm_taylor(S, A, Phi);
     static const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
@@ -491,6 +490,43 @@ void orc_ioup(int q, double theta, double h, double *Phi, double *Q)
     free(F); free(A); free(E);
 }
 
+/* Integrated Ornstein-Uhlenbeck prior IOUP(q, theta): dX_q = -theta X_q dt + dW.
+ * theta = 0 is the integrated Wiener process. */
+void orc_ioup(int q, double theta, double h, double *Phi, double *Q)
+{
+    double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    c[q] = -theta;
+    lti_prior(q, c, h, Phi, Q);
+}
+
+/* Matern prior of smoothness nu = q + 1/2 and length scale ell: the
+ * stationary process whose spectral density is proportional to
+ * (lambda^2 + w^2)^-(q+1), lambda = sqrt(2 nu) / ell, i.e. the drift's
+ * characteristic polynomial is (s + lambda)^(q+1):
+ * c_k = -binom(q+1, k) lambda^(q+1-k).  Unit diffusion, as for the IWP. */
+void orc_matern(int q, double ell, double h, double *Phi, double *Q)
+{
+    double lam = sqrt(2.0 * q + 1.0) / ell, c[5];
+    for (int k = 0; k <= q; ++k) {
+        double b = 1.0;
+        for (int j = 1; j <= k; ++j) b = b * (q + 2 - j) / j;  /* binom(q+1, k) */
+        c[k] = -b * pow(lam, q + 1 - k);
+    }
+    lti_prior(q, c, h, Phi, Q);
+}
+
+/* one-dimensional prior blocks: 0 IWP(q), 1 IOUP(q, theta), 2 Matern(q + 1/2,
+ * length scale theta) */
+static void prior_blocks_1d(int q, double h, int prior, double theta, double *Ph, double *Qh)
+{
+    if (prior == 1)
+        orc_ioup(q, theta, h, Ph, Qh);
+    else if (prior == 2)
+        orc_matern(q, theta, h, Ph, Qh);
+    else
+        orc_iwp(q, h, Ph, Qh);
+}
+
 /* diagonal of the one-dimensional preconditioner T(h) */
 void orc_precond_diag(int q, double h, double *T)
 {
@@ -506,10 +542,7 @@ static void precond_model_prior(int d, int q, double h, int prior, double theta,
     int S = q + 1, D = d * S;
     double *Ph = dalloc(S * S), *Qh = dalloc(S * S), *T = dalloc(S);
     double *Pb = dalloc(S * S), *Qb = dalloc(S * S), *Lb = dalloc(S * S);
-    if (prior == 1)
-        orc_ioup(q, theta, h, Ph, Qh);
-    else
-        orc_iwp(q, h, Ph, Qh);
+    prior_blocks_1d(q, h, prior, theta, Ph, Qh);
     orc_precond_diag(q, h, T);
     for (int i = 0; i < S; ++i)
         for (int j = 0; j < S; ++j) {
@@ -684,7 +717,8 @@ int orc_kf_rts_qf(int D, int dobs, long N, const double *mu0, const double *S0, 
 /* V(eta) = 1/2 sum_{n=1}^N |eta_n - Phi eta_{n-1}|^2_{Q^-1} for a trajectory
  * traj [N+1][D] in original coordinates (the negative log-density of the
  * trajectory under the prior, up to a constant), Phi = Phi(h), Q = Q(h) of the
- * IWP(q) or IOUP(q, theta) prior per ODE component.  The residual is formed in
+ * IWP(q), IOUP(q, theta) or Matern(q + 1/2, length scale theta) prior per ODE
+ * component.  The residual is formed in
  * original coordinates; the weighted norm is taken as |L^-1 T^-1 r|^2 with
  * T = T(h) and L = chol(T^-1 Q T^-T) (Q(h) itself spans too many orders of
  * magnitude for a plain Cholesky at small h). */
@@ -693,10 +727,7 @@ double orc_objective(int d, int q, double h, long N, const double *traj, int pri
     int S = q + 1, D = d * S;
     double *Ph = dalloc(S * S), *Qh = dalloc(S * S), *T = dalloc(S), *Qb = dalloc(S * S), *L = dalloc(S * S);
     double *r = dalloc(S), *w = dalloc(S);
-    if (prior == 1)
-        orc_ioup(q, theta, h, Ph, Qh);
-    else
-        orc_iwp(q, h, Ph, Qh);
+    prior_blocks_1d(q, h, prior, theta, Ph, Qh);
     orc_precond_diag(q, h, T);
     for (int i = 0; i < S; ++i)
         for (int j = 0; j < S; ++j) Qb[i * S + j] = Qh[i * S + j] / (T[i] * T[j]);
@@ -746,7 +777,8 @@ static void approx_jacobian(int lin, int d, double *J)
             if (lin == 1 || (lin == 2 && i != j)) J[i * d + j] = 0.0;
 }
 
-/* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta), and
+/* Alg. 2 with the prior of choice: prior 0 = IWP(q), 1 = IOUP(q, theta),
+ * 2 = Matern(q + 1/2, length scale theta), and
  * the paper's stopping criteria (Sec. 3.2.2): stop_rule bit 0 -- the
  * trajectory change delta_k < tol; bit 1 -- the change of the objective value
  * (eq. objective-value) |V_k - V_{k-1}| <= obj_atol + obj_rtol |V_k|, with V_0

@@ -13,6 +13,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 import scipy.linalg
+import scipy.special
 
 import oracle
 
@@ -664,6 +665,66 @@ def test_ioup_with_zero_rate_is_the_integrated_wiener_process(q):
     assert (np.abs(Q - Q0) / sc).max() < 1e-10
 
 
+def matern_cov_blocks(q, lam, h):
+    """P = Cov(X^(i), X^(j)) = (-1)^j k^(i+j)(0) and C(h) = Cov(X^(i)(t+h),
+    X^(j)(t)) = (-1)^j k^(i+j)(h), and P - C P^-1 C^T, all in 40-digit
+    arithmetic, for the autocovariance k of the stationary process with
+    spectral density (lam^2 + w^2)^-(q+1) (unit-diffusion Matern,
+    nu = q + 1/2), from its textbook closed form
+    k(tau) = e^{-lam tau} / ((p-1)! (2 lam)^{2p-1})
+             sum_{j<p} (p-1+j)! / (j! (p-1-j)!) (2 lam tau)^{p-1-j},  p = q+1."""
+    import mpmath
+
+    p, S = q + 1, q + 1
+    with mpmath.workdps(40):
+        lam = mpmath.mpf(lam)
+
+        def k(t):
+            s = sum(mpmath.factorial(p - 1 + j) / (mpmath.factorial(j) * mpmath.factorial(p - 1 - j))
+                    * (2 * lam * t) ** (p - 1 - j) for j in range(p))
+            return mpmath.exp(-lam * t) * s / (mpmath.factorial(p - 1) * (2 * lam) ** (2 * p - 1))
+
+        d0 = [mpmath.diff(k, mpmath.mpf(0), n) for n in range(2 * S - 1)]
+        dh = [mpmath.diff(k, mpmath.mpf(h), n) for n in range(2 * S - 1)]
+        P = mpmath.matrix(S, S)
+        C = mpmath.matrix(S, S)
+        for i in range(S):
+            for j in range(S):
+                P[i, j] = (-1) ** j * d0[i + j]
+                C[i, j] = (-1) ** j * dh[i + j]
+        Qm = P - C * mpmath.inverse(P) * C.T
+        f = lambda M: np.array([[float(M[i, j]) for j in range(S)] for i in range(S)])
+        return f(P), f(C), f(Qm)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+@pytest.mark.parametrize("ell,h", [(1.0, 0.1), (0.5, 0.4), (3.0, 0.05)])
+def test_matern_prior_reproduces_the_matern_covariance(q, ell, h):
+    """Matern(q + 1/2, ell) blocks against the Matern autocovariance k: a
+    transition that reproduces the stationary process has Phi P = C(h) and
+    Q = P - Phi P Phi^T = P - C P^-1 C^T (P, C as in matern_cov_blocks)."""
+    Phi, Q = oracle.matern(q, ell, h)
+    P, C, Qr = matern_cov_blocks(q, np.sqrt(2 * q + 1) / ell, h)
+    sc = np.sqrt(np.outer(np.diag(P), np.diag(P)))
+    assert (np.abs(Phi @ P - C) / sc).max() < 1e-11
+    scq = np.sqrt(np.outer(np.diag(Qr), np.diag(Qr)))
+    assert (np.abs(Q - Qr) / scq).max() < 1e-10
+
+
+@pytest.mark.parametrize("q", [1, 3])
+def test_matern_with_long_length_scale_approaches_the_integrated_wiener_process(q):
+    """As ell grows the drift's coefficients lam^(q+1-k) binom(q+1, k) vanish
+    and the Matern blocks tend to the IWP(q) blocks."""
+    h = 0.05
+    Phi, Q = oracle.matern(q, 1e7, h)
+    P0, Q0 = oracle.iwp(q, h)
+    assert np.abs(Phi - P0).max() < 1e-6
+    sc = np.sqrt(np.outer(np.diag(Q0), np.diag(Q0)))
+    assert (np.abs(Q - Q0) / sc).max() < 1e-6
+    Phi2, _ = oracle.matern(q, 2.0, h)
+    assert np.abs(Phi2 - P0).max() > 1e-4
+
+
 # ---------------------------------------------------------------------------
 # Stopping quantity (Sec. 3.2.2): delta_k from the returned iterates
 # ---------------------------------------------------------------------------
@@ -888,7 +949,7 @@ def test_sigma_hat_of_an_affine_solve_is_the_quasi_mle_of_its_linear_model():
     assert abs(r["sigma2"] - qf / (N * d)) <= 1e-9 * qf / (N * d)
 
 
-@pytest.mark.parametrize("q,prior,theta", [(1, "iwp", 0.0), (2, "iwp", 0.0), (3, "ioup", 0.7)])
+@pytest.mark.parametrize("q,prior,theta", [(1, "iwp", 0.0), (2, "iwp", 0.0), (3, "ioup", 0.7), (2, "matern", 1.5)])
 def test_objective_is_the_negative_log_density_under_the_prior(q, prior, theta):
     """V = sum_n -log N(eta_n; Phi eta_{n-1}, Q) minus the normalising
     constants, with Phi, Q from the Van Loan exponential of the prior's SDE and
@@ -898,7 +959,11 @@ def test_objective_is_the_negative_log_density_under_the_prior(q, prior, theta):
 
     S, d, N, h = q + 1, 2, 6, 0.3
     F = np.diag(np.ones(q), 1)
-    F[q, q] = -theta
+    if prior == "matern":
+        lam = np.sqrt(2 * q + 1) / theta
+        F[q] = [-scipy.special.comb(q + 1, k) * lam ** (q + 1 - k) for k in range(S)]
+    else:
+        F[q, q] = -theta
     M = np.zeros((2 * S, 2 * S))
     M[:S, :S] = F
     M[q, S + q] = 1.0
