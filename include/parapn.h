@@ -41,6 +41,7 @@ extern "C" {
 /* priors */
 #define PARAPN_PRIOR_IWP 0
 #define PARAPN_PRIOR_IOUP 1
+#define PARAPN_PRIOR_MATERN 2
 
 /* starting trajectory (parapn_problem.init_mode; a given init_traj overrides it) */
 #define PARAPN_INIT_CONSTANT 0 /* eta_n = mu0 for every n (Alg. 2)                         */
@@ -135,12 +136,18 @@ typedef struct {
                               * conditioned at unstable iterates.  Factors
                               * (sqrtcov_out) then come from one more, undamped pass
                               * at the final iterate.  0: plain Alg. 2.             */
-    int32_t prior;           /* PARAPN_PRIOR_IWP (0, Sec. 2.1) or PARAPN_PRIOR_IOUP: the
-                              * q-th derivative an Ornstein-Uhlenbeck process
-                              * dX_q = -prior_theta X_q dt + dW (one of the alternative
-                              * Gauss-Markov priors of Sec. 2.1), discretised in FP64
-                              * on the host.  Served requests must use the IWP prior. */
-    double prior_theta;      /* IOUP rate, finite and >= 0 (0 gives the IWP)         */
+    int32_t prior;           /* PARAPN_PRIOR_IWP (0, Sec. 2.1), or one of the
+                              * alternative Gauss-Markov priors of Sec. 2.1:
+                              * PARAPN_PRIOR_IOUP, the q-th derivative an Ornstein-
+                              * Uhlenbeck process dX_q = -prior_theta X_q dt + dW;
+                              * PARAPN_PRIOR_MATERN, the Matern process of
+                              * smoothness q + 1/2 and length scale prior_theta
+                              * (drift polynomial (s + lambda)^(q+1), lambda =
+                              * sqrt(2q+1) / prior_theta, unit diffusion).  Both are
+                              * discretised in FP64 on the host (Van Loan).  Served
+                              * requests must use the IWP prior.                   */
+    double prior_theta;      /* IOUP: rate, finite and >= 0 (0 gives the IWP);
+                              * Matern: length scale, finite and > 0              */
     int32_t init_mode;       /* PARAPN_INIT_CONSTANT or PARAPN_INIT_COARSE; used only
                               * when init_traj is NULL.  COARSE: a sequential EK1
                               * filter (linearised at each predicted mean) and RTS

@@ -30,7 +30,7 @@ FIELDS = {
 }
 FIELD_DIM = {"logistic": 1, "fhn": 2, "lorenz": 3, "lotka_volterra": 2, "rigid_body": 3, "van_der_pol": 2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_SQRT, "fp32_sqrt": FP32_SQRT}
-PRIORS = {"iwp": 0, "ioup": 1}
+PRIORS = {"iwp": 0, "ioup": 1, "matern": 2}
 INITS = {"constant": 0, "coarse": 1}
 STARTS = {0: "constant", 1: "coarse", 2: "given", 3: "coarse_failed"}
 STOP_RULES = {"trajectory": 1, "objective": 2, "either": 3}

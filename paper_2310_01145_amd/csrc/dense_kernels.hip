@@ -532,7 +532,7 @@ __global__ __launch_bounds__(nt_of<T>()) void k_elements(DenseModel md, DenseWor
         for (int rho = threadIdx.x; rho < D; rho += NT) {
             const int i = rho / S, a = rho - i * S;
             double s = -eta[rho];
-            for (int c = a; c < S; ++c) s += md.phib[a * 5 + c] * etap[i * S + c];
+            for (int c = 0; c < S; ++c) s += md.phib[a * 5 + c] * etap[i * S + c];
             u[rho] = (T)s;
         }
         __syncthreads();
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(nt_of<T>()) void k_selements(DenseModel md, DenseWo
             if (row < D) {
                 const int i = row / S, a = row - i * S;
                 if (col < D) {
-                    for (int c = a; c < S; ++c) x += (T)md.phib[a * 5 + c] * Pf[(size_t)(i * S + c) * D + col];
+                    for (int c = 0; c < S; ++c) x += (T)md.phib[a * 5 + c] * Pf[(size_t)(i * S + c) * D + col];
                 } else {
                     const int cc = col - D, j = cc / S, c = cc - j * S;
                     x = i == j ? (T)md.sqb[a * 5 + c] : T(0);
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(nt_of<T>()) void k_selements(DenseModel md, DenseWo
             const int i = rho / S, a = rho - i * S;
             double uu = -e1[rho];
             T pm = T(0);
-            for (int c = a; c < S; ++c) {
+            for (int c = 0; c < S; ++c) {
                 uu += md.phib[a * 5 + c] * e0[i * S + c];
                 pm += (T)md.phib[a * 5 + c] * mf[i * S + c];
             }

@@ -233,14 +233,15 @@ void expm_small(int n, const std::vector<double> &A, std::vector<double> &E)
     }
 }
 
-// Preconditioned IOUP(q, theta) prior (the q-th derivative an Ornstein-
-// Uhlenbeck process, dX_q = -theta X_q dt + dW).  With T as above the drift
-// becomes h T^{-1} F T = Fb, Fb[i][i+1] = q - i, Fb[q][q] = -theta h, and the
-// noise enters as e_q e_q^T over unit time, so Van Loan's block exponential
+// Preconditioned blocks of a prior whose q-th derivative has the drift
+// dX_q = sum_k c_k X_k dt + dW (the alternative Gauss-Markov priors of
+// Sec. 2.1; c = 0 is the integrated Wiener process).  With T as above the
+// drift becomes h T^{-1} F T = Fb, Fb[i][i+1] = q - i and last row
+// cb[k] = Fb[q][k] = c_k h^{q+1-k} / (q-k)!, and the noise enters as
+// e_q e_q^T over unit time, so Van Loan's block exponential
 // exp([[-Fb, e_q e_q^T], [0, Fb^T]]) = [[., E12], [0, E22]] gives
-// Phibar = E22^T and Qbar = Phibar E12 without cancellation.  theta = 0
-// reproduces the binomial / Hilbert blocks of the integrated Wiener process.
-void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double> &Phi, std::vector<double> &sQ)
+// Phibar = E22^T and Qbar = Phibar E12 without cancellation.
+void prior_blocks_lti(int d, int q, const double *cb, std::vector<double> &Phi, std::vector<double> &sQ)
 {
     const int S = q + 1, D = d * S, M = 2 * S;
     std::vector<double> C(M * M, 0.0), E;
@@ -248,8 +249,10 @@ void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double>
         C[i * M + i + 1] = -(double)(q - i);
         C[(S + i + 1) * M + S + i] = (double)(q - i);
     }
-    C[q * M + q] = theta * h;
-    C[(S + q) * M + S + q] = -theta * h;
+    for (int k = 0; k <= q; ++k) {
+        C[q * M + k] -= cb[k];
+        C[(S + k) * M + S + q] += cb[k];
+    }
     C[q * M + S + q] = 1.0;
     expm_small(M, C, E);
     std::vector<double> Pb(S * S), Qb(S * S, 0.0), Lb(S * S, 0.0);
@@ -281,6 +284,26 @@ void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double>
                 Phi[(b * S + i) * D + b * S + j] = Pb[i * S + j];
                 sQ[(b * S + i) * D + b * S + j] = Lb[i * S + j];
             }
+}
+
+// IOUP(q, theta): dX_q = -theta X_q dt + dW
+void prior_blocks_ioup(int d, int q, double h, double theta, std::vector<double> &Phi, std::vector<double> &sQ)
+{
+    double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    cb[q] = -theta * h;
+    prior_blocks_lti(d, q, cb, Phi, sQ);
+}
+
+// Matern(nu = q + 1/2, length scale ell): drift polynomial (s + lambda)^(q+1),
+// lambda = sqrt(2 nu) / ell, so c_k = -binom(q+1, k) lambda^(q+1-k); unit
+// diffusion.  In preconditioned form cb[k] = c_k h^{q+1-k} / (q-k)! =
+// -binom(q+1, k) (lambda h)^{q+1-k} / (q-k)!.
+void prior_blocks_matern(int d, int q, double h, double ell, std::vector<double> &Phi, std::vector<double> &sQ)
+{
+    const double lh = std::sqrt(2.0 * q + 1.0) / ell * h;
+    double cb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k <= q; ++k) cb[k] = -binom(q + 1, k) * std::pow(lh, q + 1 - k) / fact(q - k);
+    prior_blocks_lti(d, q, cb, Phi, sQ);
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -462,8 +485,8 @@ struct Solve {
     int64_t N;
     double t0, t1, h, tol;
     double lm_sigma, lm_s;  // damping (0: none) and its preconditioned per-step std
-    int prior;              // PARAPN_PRIOR_IWP or PARAPN_PRIOR_IOUP
-    double theta;           // IOUP rate
+    int prior;              // PARAPN_PRIOR_*
+    double theta;           // IOUP rate or Matern length scale
     int max_iter, fixed_iters;
     int init_mode;          // PARAPN_INIT_*
     int64_t coarse_target;  // coarse-grid size target (init_mode COARSE)
@@ -529,6 +552,8 @@ void prior_blocks_of(const Solve &sv, int d, std::vector<double> &Phi, std::vect
 {
     if (sv.prior == PARAPN_PRIOR_IOUP)
         prior_blocks_ioup(d, sv.q, sv.h, sv.theta, Phi, sQ);
+    else if (sv.prior == PARAPN_PRIOR_MATERN)
+        prior_blocks_matern(d, sv.q, sv.h, sv.theta, Phi, sQ);
     else
         prior_blocks(d, sv.q, Phi, sQ);
 }
@@ -771,7 +796,8 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
         return fail(PARAPN_EINVAL, "unknown precision");
     if (p->init_on_device != 0 && p->init_on_device != 1) return fail(PARAPN_EINVAL, "init_on_device must be 0 or 1");
     if (!(p->lm_sigma >= 0.0) || !std::isfinite(p->lm_sigma)) return fail(PARAPN_EINVAL, "lm_sigma must be finite and >= 0");
-    if (p->prior != PARAPN_PRIOR_IWP && p->prior != PARAPN_PRIOR_IOUP) return fail(PARAPN_EINVAL, "unknown prior");
+    if (p->prior != PARAPN_PRIOR_IWP && p->prior != PARAPN_PRIOR_IOUP && p->prior != PARAPN_PRIOR_MATERN)
+        return fail(PARAPN_EINVAL, "unknown prior");
     if (p->init_mode != PARAPN_INIT_CONSTANT && p->init_mode != PARAPN_INIT_COARSE)
         return fail(PARAPN_EINVAL, "unknown init_mode");
     if (p->coarse_points < 0) return fail(PARAPN_EINVAL, "coarse_points must be >= 0");
@@ -786,6 +812,8 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
         return fail(PARAPN_EINVAL, "the coarse-grid start is available for the fixed-size fields");
     if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
         return fail(PARAPN_EINVAL, "prior_theta must be finite and >= 0");
+    if (p->prior == PARAPN_PRIOR_MATERN && !(std::isfinite(p->prior_theta) && p->prior_theta > 0.0))
+        return fail(PARAPN_EINVAL, "the Matern length scale (prior_theta) must be finite and > 0");
     for (int i = 0; i < p->d; ++i)
         if (!std::isfinite(p->y0[i])) return fail(PARAPN_EINVAL, "y0 is not finite");
     *q_out = p->q;

@@ -1,9 +1,10 @@
-"""IOUP prior (the q-th derivative an Ornstein-Uhlenbeck process, one of the
-Gauss-Markov priors of Sec. 2.1): the GPU solves, whose host discretises the
-preconditioned prior by Van Loan's block exponential, against the oracle,
-which integrates the process noise by quadrature in original coordinates.
-Gates as for the IWP prior: FP64 E0 means and covariances 1e-9, FP32 E0 means
-1e-4.  A zero rate must reproduce the IWP solve."""
+"""The alternative Gauss-Markov priors of Sec. 2.1 -- IOUP (the q-th
+derivative an Ornstein-Uhlenbeck process) and Matern (smoothness q + 1/2):
+the GPU solves, whose host discretises the preconditioned prior by Van Loan's
+block exponential, against the oracle, which integrates the process noise by
+quadrature in original coordinates.  Gates as for the IWP prior: FP64 E0 means
+and covariances 1e-9, FP32 E0 means 1e-4.  A zero IOUP rate must reproduce
+the IWP solve."""
 from __future__ import annotations
 
 import numpy as np
@@ -101,3 +102,54 @@ def test_server_refuses_other_priors(pp):
         srv.submit(0, "logistic", [], [0.01], 0.0, 1.0, 2, 10, precision="fp32", prior="ioup", theta=1.0)
     assert e.value.code == pp.EINVAL
     srv.close()
+
+
+MATERN = [
+    ("logistic", [], [0.01], 10.0, 2, 300, 3.0),
+    ("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 5.0, 3, 250, 2.0),
+    ("rigid_body", [], [1.0, 0.0, 0.9], 20.0, 4, 200, 5.0),
+]
+
+
+@pytest.mark.parametrize("field,params,y0,t1,q,N,ell", MATERN, ids=[c[0] for c in MATERN])
+def test_matern_solve_matches_oracle(pp, field, params, y0, t1, q, N, ell):
+    k = 4
+    ref = oracle.ieks(field, params, y0, 0.0, t1, q, N, fixed_iters=k, want_cov=True, prior="matern", theta=ell,
+                      init="coarse")
+    S = q + 1
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        print("case matern", field, prec, flush=True)
+        r = pp.solve(field, params, y0, 0.0, t1, q, N, precision=prec, fixed_iters=k, want_cov=True, prior="matern",
+                     theta=ell, init="coarse")
+        assert r["status"] == pp.OK
+        assert rel(np_(r["mean"])[:, ::S], ref["mean"][:, ::S]) < tol, prec
+        if prec == "fp64":
+            assert rel(sigma(np_(r["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+
+
+def test_matern_converges_like_the_oracle(pp):
+    kw = dict(tol=1e-10, max_iter=20, prior="matern", theta=2.0, stop_rule="either")
+    ref = oracle.ieks("logistic", [], [0.01], 0.0, 10.0, 2, 1000, **{**kw, "stop_rule": 3})
+    r = pp.solve("logistic", [], [0.01], 0.0, 10.0, 2, 1000, precision="fp64", calibrate=True, want_cov=True, **kw)
+    assert ref["status"] == 0 and r["status"] == pp.OK and r["iterations"] == ref["iterations"]
+    assert rel(np_(r["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-9
+    assert abs(r["sigma_hat"] ** 2 - ref["sigma2"]) <= 1e-9 * ref["sigma2"]
+
+
+@pytest.mark.parametrize("lin", ["ek1", "diag_ek1"])
+def test_matern_on_the_method_of_lines_engines(pp, lin):
+    """The dense engine (EK1) and the decoupled chains (DiagonalEK1)."""
+    y0 = 0.5 + 0.1 * np.sin(2 * np.pi * np.arange(8) / 8)
+    ref = oracle.ieks("mol_heat_reaction", [0.01], y0, 0.0, 0.25, 2, 40, fixed_iters=3, want_cov=True,
+                      prior="matern", theta=1.0, linearization=lin)
+    r = pp.solve("mol_heat_reaction", [0.01], y0, 0.0, 0.25, 2, 40, precision="fp64", fixed_iters=3, want_cov=True,
+                 prior="matern", theta=1.0, linearization=lin)
+    assert r["status"] == pp.OK
+    assert rel(np_(r["mean"])[:, ::3], ref["mean"][:, ::3]) < 1e-9
+    assert rel(sigma(np_(r["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+
+
+def test_matern_length_scale_must_be_positive(pp):
+    with pytest.raises(pp.ParapnError) as e:
+        pp.solve("logistic", [], [0.01], 0.0, 1.0, 2, 10, prior="matern", theta=0.0)
+    assert e.value.code == pp.EINVAL
