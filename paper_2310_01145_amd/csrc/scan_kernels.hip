@@ -1598,14 +1598,22 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
 // G_n = P_n Phi^T (P-_{n+1})^-1 and nu_{n+1} = (P-_{n+1})^-1 (m^s_{n+1} -
 // m-_{n+1}).  Per coarse node the records hold m^f_n, P_n, and for n >= 1
 // Hbar_n, K_n and z_n; the smoothed means go to the node array.
+// Sequential EK1 filter (covariance form, FP64) on the coarse grid, one
+// wavefront per request, then the RTS means.  The coarse prior is the IWP:
+// Phi = I_d (x) Phi1 and Q = I_d (x) Q1 with (q+1)-blocks, so a product with
+// Phi or Q touches q+1 terms, and Hbar = E1 - (H/q) F_y E0 has d+1 nonzeros
+// per row.  With U = P- Hbar^T, S = Hbar U and K = U S^-1 the update is the
+// Joseph form (I - K Hbar) P- (I - K Hbar)^T (noiseless data), whose factor
+// differs from I in 2d columns only: both products cost O(D^2 d).  (The
+// algebraically equal P- - K U^T - U K^T + K S K^T loses definiteness within
+// a few dozen steps on FitzHugh-Nagumo: its terms are large and cancel.)
 template <int d, int q>
 __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const CoarseDev *cds, const double *Phi,
                                                    const double *Q)
 {
     constexpr int S = q + 1, D = d * S, DD = D * D, EPL = (DD + 63) / 64;
     constexpr int REC = D + DD + 2 * d * D + d;
-    __shared__ double sPhi[DD], sQ[DD], sP[DD], sA[DD], sB[DD], sPp[DD], sm[D], smp[D], sH[d * D], sU[D * d],
-        sK[D * d], st[D], snu[D], su[d];
+    __shared__ double sP[DD], sA[DD], sPp[DD], sm[D], smp[D], sU[D * d], sK[D * d], st[D], snu[D], su[d];
     const int lane = threadIdx.x;
     const ReqDev &rq = reqs[blockIdx.x];
     const CoarseDev cd = cds[blockIdx.x];
@@ -1615,12 +1623,17 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
     double prm[kMaxParams];
 #pragma unroll
     for (int i = 0; i < kMaxParams; ++i) prm[i] = rq.p[i];
+    // one (q+1)-block of Phi and Q (uniform: every lane holds it)
+    double p1[S][S], q1[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            p1[i][j] = Phi[i * D + j];
+            q1[i][j] = Q[i * D + j];
+        }
     double *rec = (double *)cd.gain;
-    for (int e = lane; e < DD; e += 64) {
-        sPhi[e] = Phi[e];
-        sQ[e] = Q[e];
-        sP[e] = 0.0;
-    }
+    for (int e = lane; e < DD; e += 64) sP[e] = 0.0;
     if (lane < D) sm[lane] = cd.mu0c[lane];
     wave_sync();
     bool bad = false;
@@ -1633,29 +1646,33 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         for (int k = 0; k < EPL; ++k) {
             const int e = lane + 64 * k;
             if (e < DD) {
-                const int i = e / D, j = e % D;
+                const int i = e / D, j = e % D, bi = i / S, ri = i % S;
                 double acc = 0.0;
 #pragma unroll
-                for (int l = 0; l < D; ++l) acc += sPhi[i * D + l] * sP[l * D + j];
+                for (int l = 0; l < S; ++l) acc += p1[ri][l] * sP[(bi * S + l) * D + j];
                 sA[e] = acc;
             }
         }
         if (lane < D) {
+            const int bi = lane / S, ri = lane % S;
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc += sPhi[lane * D + l] * sm[l];
+            for (int l = 0; l < S; ++l) acc += p1[ri][l] * sm[bi * S + l];
             smp[lane] = acc;
         }
         wave_sync();
-        // P- = A Phi^T + Q
+        // P- = A Phi^T + Q (kept in registers for the update, and in LDS)
+        double pp[EPL];
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const int e = lane + 64 * k;
+            pp[k] = 0.0;
             if (e < DD) {
-                const int i = e / D, j = e % D;
-                double acc = sQ[e];
+                const int i = e / D, j = e % D, bi = i / S, ri = i % S, bj = j / S, rj = j % S;
+                double acc = bi == bj ? q1[ri][rj] : 0.0;
 #pragma unroll
-                for (int l = 0; l < D; ++l) acc += sA[i * D + l] * sPhi[j * D + l];
+                for (int l = 0; l < S; ++l) acc += sA[i * D + bj * S + l] * p1[rj][l];
+                pp[k] = acc;
                 sPp[e] = acc;
             }
         }
@@ -1668,36 +1685,38 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             for (int j = 0; j < d; ++j) yd[i].g[j] = (i == j) ? 1.0 : 0.0;
         }
         field_eval<d>(field, prm, yd, fd);
-        double r[d];
+        double r[d], hj[d][d];  // hj = -(H/q) F_y
 #pragma unroll
-        for (int a = 0; a < d; ++a) r[a] = (fd[a].v - cd.T1 * smp[a * S + 1]) * cd.invT1;
-        for (int e = lane; e < d * D; e += 64) {
-            const int a = e / D, c = e % D;
-            double h = (c == a * S + 1) ? 1.0 : 0.0;
-            if (c % S == 0) h -= cd.hq * fd[a].g[c / S];
-            sH[e] = h;
+        for (int a = 0; a < d; ++a) {
+            r[a] = (fd[a].v - cd.T1 * smp[a * S + 1]) * cd.invT1;
+#pragma unroll
+            for (int b = 0; b < d; ++b) hj[a][b] = -cd.hq * fd[a].g[b];
         }
         wave_sync();
-        // U = P- Hbar^T (D x d)
+        // U = P- Hbar^T (D x d): U[i][a] = P-[i][a S + 1] + sum_b hj[a][b] P-[i][b S]
         for (int e = lane; e < D * d; e += 64) {
             const int i = e / d, a = e % d;
-            double acc = 0.0;
+            double acc = sPp[i * D + a * S + 1];
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc += sPp[i * D + l] * sH[a * D + l];
+            for (int b = 0; b < d; ++b) acc += hj[a][b] * sPp[i * D + b * S];
             sU[e] = acc;
         }
         wave_sync();
-        // S = Hbar U and its Cholesky factor (d <= 3: every lane)
-        double L[d][d];
+        // S = Hbar U (every lane) and its Cholesky factor
+        double Sm[d][d], L[d][d];
 #pragma unroll
         for (int a = 0; a < d; ++a)
 #pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                double acc = 0.0;
+            for (int b = 0; b < d; ++b) {
+                double acc = sU[(a * S + 1) * d + b];
 #pragma unroll
-                for (int l = 0; l < D; ++l) acc += sH[a * D + l] * sU[l * d + b];
-                L[a][b] = acc;
+                for (int c = 0; c < d; ++c) acc += hj[a][c] * sU[(c * S) * d + b];
+                Sm[a][b] = acc;
             }
+#pragma unroll
+        for (int a = 0; a < d; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) L[a][b] = 0.5 * (Sm[a][b] + Sm[b][a]);
         // (one FP64 division per diagonal entry; the substitutions multiply
         // by the reciprocals)
         double inv[d];
@@ -1761,43 +1780,69 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             sm[lane] = mn;
             bad |= !__builtin_isfinite(mn);
         }
-        for (int e = lane; e < d * D; e += 64) rn[D + DD + e] = sH[e];
+        // Hbar rows: 1 at (a, a S + 1), hj[a][b] at (a, b S)
+        for (int e = lane; e < d * D; e += 64) {
+            const int a = e / D, c = e % D;
+            double h = (c == a * S + 1) ? 1.0 : 0.0;
+            if (c % S == 0) h += hj[a][c / S];
+            rn[D + DD + e] = h;
+        }
         if (lane < d) rn[D + DD + 2 * d * D + lane] = z[lane];
         wave_sync();
-        // P = A P- A^T with A = I - K Hbar (into sA; the old A is consumed)
+        // Joseph form P = A P- A^T, A = I - K Hbar.  A differs from I only in
+        // the 2d columns c with c mod S <= 1 (where Hbar has its nonzeros):
+        // A[i][b S] = [i == b S] - sum_a K[i][a] hj[a][b],
+        // A[i][a S + 1] = [i == a S + 1] - K[i][a].  B = A P- first.
+        {
+            double bb[EPL];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) {
-            const int e = lane + 64 * k;
-            if (e < DD) {
-                const int i = e / D, j = e % D;
-                double acc = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < EPL; ++k) {
+                const int e = lane + 64 * k;
+                bb[k] = 0.0;
+                if (e < DD) {
+                    const int i = e / D, j = e % D;
+                    double ki[d];
 #pragma unroll
-                for (int a = 0; a < d; ++a) acc -= sK[i * d + a] * sH[a * D + j];
-                sA[e] = acc;
+                    for (int a = 0; a < d; ++a) ki[a] = sK[i * d + a];
+                    double acc = (i % S > 1) ? pp[k] : 0.0;
+#pragma unroll
+                    for (int b = 0; b < d; ++b) {
+                        double a0 = (i == b * S) ? 1.0 : 0.0;
+#pragma unroll
+                        for (int a = 0; a < d; ++a) a0 -= ki[a] * hj[a][b];
+                        const double a1 = ((i == b * S + 1) ? 1.0 : 0.0) - ki[b];
+                        acc += a0 * sPp[(b * S) * D + j] + a1 * sPp[(b * S + 1) * D + j];
+                    }
+                    bb[k] = acc;
+                }
             }
-        }
-        wave_sync();
+            // sA is free here (its last reader was the P- stage)
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) {
-            const int e = lane + 64 * k;
-            if (e < DD) {
-                const int i = e / D, j = e % D;
-                double acc = 0.0;
-#pragma unroll
-                for (int l = 0; l < D; ++l) acc += sA[i * D + l] * sPp[l * D + j];
-                sB[e] = acc;
+            for (int k = 0; k < EPL; ++k) {
+                const int e = lane + 64 * k;
+                if (e < DD) sA[e] = bb[k];
             }
-        }
-        wave_sync();
+            wave_sync();
+            // P = B A^T
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) {
-            const int e = lane + 64 * k;
-            if (e < DD) {
-                const int i = e / D, j = e % D;
-                double acc = 0.0;
+            for (int k = 0; k < EPL; ++k) {
+                const int e = lane + 64 * k;
+                if (e < DD) {
+                    const int i = e / D, j = e % D;
+                    double kj[d];
 #pragma unroll
-                for (int l = 0; l < D; ++l) acc += sB[i * D + l] * sA[j * D + l];
-                sP[e] = acc;
+                    for (int a = 0; a < d; ++a) kj[a] = sK[j * d + a];
+                    double acc = (j % S > 1) ? bb[k] : 0.0;
+#pragma unroll
+                    for (int b = 0; b < d; ++b) {
+                        double a0 = (j == b * S) ? 1.0 : 0.0;
+#pragma unroll
+                        for (int a = 0; a < d; ++a) a0 -= kj[a] * hj[a][b];
+                        const double a1 = ((j == b * S + 1) ? 1.0 : 0.0) - kj[b];
+                        acc += sA[i * D + b * S] * a0 + sA[i * D + b * S + 1] * a1;
+                    }
+                    sP[e] = acc;
+                }
             }
         }
         wave_sync();
@@ -1834,11 +1879,12 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
     wave_sync();
     for (int64_t n = cd.M; n >= 0; --n) {
         if (n >= 1) load_share(n - 1, nxt);
-        // t = Phi^T nu_{n+1}
+        // t = Phi^T nu_{n+1} (block diagonal: q+1 terms)
         if (lane < D) {
+            const int bl = lane / S, rl = lane % S;
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc += sPhi[l * D + lane] * snu[l];
+            for (int l = 0; l < S; ++l) acc += p1[l][rl] * snu[bl * S + l];
             st[lane] = acc;
         }
         wave_sync();
@@ -2112,11 +2158,13 @@ __global__ void k_blocks_out(int d, int S, int64_t N, const double *Td, const do
 template <int D>
 __global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, const double *sQ, int slot)
 {
-    __shared__ double sPhi[D * D], sL[D * D];
+    __shared__ double sPhi[D * D], sL[D * D], sInv[D], wsum[4];
+    __shared__ int wreq[4];
     for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
         sPhi[i] = Phi[i];
         sL[i] = sQ[i];
     }
+    if (threadIdx.x < D) sInv[threadIdx.x] = 1.0 / sQ[threadIdx.x * (D + 1)];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v = 0.0;
@@ -2143,16 +2191,36 @@ __global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, c
                 for (int k = 0; k < D; ++k) u -= sPhi[i * D + k] * a[k];
 #pragma unroll
                 for (int j = 0; j < i; ++j) u -= sL[i * D + j] * w[j];
-                w[i] = u / sL[i * D + i];
+                w[i] = u * sInv[i];
                 v += w[i] * w[i];
             }
             v *= 0.5;
         }
     }
-    const int r0 = __shfl(ri, 0);
-    if (__all(ri == r0)) {
+    // one atomic per block when all its rows belong to one request, else one
+    // per wavefront of one request, else one per row
+    const int wv = threadIdx.x >> 6, r0 = __shfl(ri, 0);
+    const bool uni = __all(ri == r0);
+    if (uni) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[wv] = v;
+        wreq[wv] = uni ? r0 : -2;
+    }
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    bool block_uni = true;
+    for (int k = 1; k < nw; ++k) block_uni = block_uni && wreq[k] == wreq[0];
+    block_uni = block_uni && wreq[0] >= 0;
+    if (block_uni) {
+        if (threadIdx.x == 0 && pk.reqs[wreq[0]].dbits) {
+            double t = 0.0;
+            for (int k = 0; k < nw; ++k) t += wsum[k];
+            atomicAdd((double *)pk.reqs[wreq[0]].dbits + slot, t);
+        }
+    } else if (uni) {
         if ((threadIdx.x & 63) == 0 && r0 >= 0 && pk.reqs[r0].dbits)
             atomicAdd((double *)pk.reqs[r0].dbits + slot, v);
     } else if (ri >= 0 && pk.reqs[ri].dbits) {
