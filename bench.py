@@ -104,6 +104,18 @@ def n_sweep(pp, torch, iters, steps=3):
     return out
 
 
+def beyond_cache(pp, torch, e=20):
+    """The step-level scan kernels at N = 2^e (FP32, 3 fixed iterations from
+    the coarse start): there the smoothing elements that k_fwd_down1 writes
+    and the reverse-scan kernels read (about 100 B per step) no longer fit the
+    256 MB Infinity Cache, so the algorithmic GB/s are HBM figures."""
+    wl = workload(1 << e, 3)
+    r = run_gpu(pp, torch, wl, "fp32", 2, 1, True)
+    out = {"N": wl["N"], "iterations": 3, "status": r["status"][0], "ms_per_solve": r["ms_per_step"],
+           "kernels": scan_kernel_table(r["profile_untimed"], wl, "fp32")}
+    return out
+
+
 def constant_start(pp, wl, prec):
     """Outcome of the same solve from the constant initial trajectory."""
     r = pp.solve(wl["field"], wl["params"], wl["y0"], wl["t0"], wl["t1"], wl["q"], wl["N"], precision=prec,
@@ -185,6 +197,17 @@ def roofline(prof, wl, prec, prof_all=None):
     ref = prof_all if prof_all else prof
     out = {"kernel": name, "avg_launch_us": avg_s * 1e6, "launches": launches,
            "share_of_kernel_time": ref[name][0] / sum(v[0] for v in ref.values())}
+    if name == "coarse_eks":
+        # one wavefront runs the sequential coarse filter and smoother in FP64:
+        # a recursion bound by instruction latency, priced against the FP64 peak
+        M = costmodel.coarse_points(N)
+        fl = costmodel.coarse_step_flops(d, q) * M
+        out.update({"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                    "frac": fl / avg_s / PEAK["f64"], "traffic": stored_traffic(name, "fhn_n%d_%s" % (N, prec)),
+                    "coarse_steps": M, "us_per_coarse_step": avg_s * 1e6 / M,
+                    "note": "sequential recursion on one wavefront (one SIMD of 1024); its FP64 work per step is "
+                            "%d flop" % costmodel.coarse_step_flops(d, q)})
+        return out
     if steps_per_launch is None:
         out.update({"bound": "alu", "achieved": None, "peak": PEAK["f32" if esize == 4 else "f64"] / 1e12,
                     "unit": "TFLOP/s", "frac": None, "traffic": None})
@@ -198,7 +221,7 @@ def roofline(prof, wl, prec, prof_all=None):
         "peak": peak / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": stored_traffic(name, "fhn_n262144_%s" % prec),
+        "traffic": stored_traffic(name, "fhn_n%d_%s" % (N, prec)),
         "forward_chunk": b1,
         "algorithmic_flops_per_launch": flops * steps_per_launch,
         "algorithmic_bytes_per_launch": byts * steps_per_launch,
@@ -349,6 +372,51 @@ def mol_decoupled_run(pp, torch, prec, lin="diag_ek1", B=16, max_iter=400):
     }
 
 
+def _fhn_oracle_sample(N):
+    """One whole oracle solve of the FitzHugh-Nagumo workload (worker of the
+    per-core measurement); returns (time-steps x iterations, seconds)."""
+    import oracle
+
+    wl = workload(N, 0)
+    t = time.perf_counter()
+    r = oracle.ieks(wl["field"], wl["params"], wl["y0"], wl["t0"], wl["t1"], wl["q"], N, max_iter=20, tol=1e-10,
+                    want_cov=False, init="coarse")
+    return N * r["iterations"], time.perf_counter() - t
+
+
+def _mol_oracle_sample(steps):
+    """The method-of-lines oracle sample (worker of the per-core measurement)."""
+    import oracle
+
+    from paper_2310_01145_amd import workloads
+
+    sp = workloads.mol(N=4096)
+    t = time.perf_counter()
+    r = oracle.ieks(sp["field"], sp["params"], sp["y0"], sp["t0"], sp["t1"] * steps / sp["N"], sp["q"], steps,
+                    fixed_iters=2, want_cov=False)
+    return steps * r["iterations"], time.perf_counter() - t
+
+
+def per_core_instances(fn, arg, label):
+    """One oracle instance per host core (at most 16, this host's share of a
+    one-GPU node), all started together in fresh interpreters: the aggregate
+    rate is the total work over the wall time until the last one ends."""
+    import multiprocessing as mp
+
+    ncpu, model = host_cpu()
+    P = max(1, min(16, ncpu or 1))
+    ctx = mp.get_context("spawn")
+    t = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        res = pool.map(fn, [arg] * P)
+    wall = time.perf_counter() - t
+    work = sum(w for w, _ in res)
+    return {"value": work / wall, "unit": UNIT, "cores": P, "kind": "oracle", "instances": P,
+            "host_logical_cpus": ncpu, "host_cpu_model": model,
+            "sample": "%d concurrent oracle instances (one per core), each %s; wall %.1f s (slowest instance "
+                      "%.1f s, interpreter start included)" % (P, label, wall, max(e for _, e in res))}
+
+
 def mol_cpu_baseline(steps=96):
     """The oracle on a bounded sample of the method-of-lines workload: one
     instance, its first `steps` steps (same h), two iterations."""
@@ -468,6 +536,9 @@ def main():
     if r32["profile"]:
         # the dominant kernel, timed by events inside the timed region
         line["roofline"] = roofline(r32["profile"], wl, "fp32", r32["profile_untimed"])
+        # the dominant kernel of the iterations (the scans' step-level kernels)
+        it = {k: v for k, v in r32["profile_untimed"].items() if not k.startswith("coarse")}
+        line["roofline_iteration"] = roofline(it, wl, "fp32", r32["profile_untimed"])
         # every kernel, from the untimed profiled solve before it
         line["scan_kernels"] = scan_kernel_table(r32["profile_untimed"], wl, "fp32")
         line["kernel_ms_per_solve"] = {k: v[0] for k, v in sorted(r32["profile_untimed"].items(),
@@ -495,6 +566,7 @@ def main():
     if not args.no_extras:
         line["logistic_c0"] = logistic_latency(pp, torch)
         line["fhn_n_sweep"] = n_sweep(pp, torch, args.iters)
+        line["fhn_n1048576_scan_kernels"] = beyond_cache(pp, torch)
         print("bench: extras done", file=sys.stderr, flush=True)
     if not args.no_mol:
         m32r, m32 = mol_batch_run(pp, torch, "fp32")
@@ -532,6 +604,8 @@ def main():
         del m32r, g32r, g64r, a, b, c
         if not args.no_cpu_baseline:
             line["mol_batch"]["cpu_baseline"] = mol_cpu_baseline()
+            line["mol_batch"]["cpu_baseline_per_core"] = per_core_instances(
+                _mol_oracle_sample, 96, "the method-of-lines sample above (96 steps, 2 iterations)")
     if not args.no_stream:
         from paper_2310_01145_amd import serve
 
@@ -540,6 +614,8 @@ def main():
         line["served_stream"] = st
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
+        line["cpu_baseline_per_core"] = per_core_instances(
+            _fhn_oracle_sample, wl["N"], "the whole FitzHugh-Nagumo solve above")
     print(json.dumps(line))
 
 

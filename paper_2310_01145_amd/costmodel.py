@@ -101,6 +101,33 @@ def per_step(d, q, esize, b1=32, bs1=8):
     }
 
 
+def coarse_points(N):
+    """Coarse grid of the library's default start: target max(1024,
+    64 ceil(log2 N)) capped at N, s = ceil(N / target) fine steps per coarse
+    step, M = ceil(N / s) coarse steps."""
+    import math
+
+    target = min(N, max(1024, 64 * max(1, math.ceil(math.log2(max(N, 2))))))
+    s = -(-N // target)
+    return -(-N // s)
+
+
+def coarse_step_flops(d, q):
+    """FP64 flops of one step of the coarse extended Kalman filter and its RTS
+    means (block-structured prior products, column-sparse Joseph update)."""
+    S = q + 1
+    D = d * S
+    DD = D * D
+    fwd = (2 * DD * S * 2 + DD            # Phi P, (Phi P) Phi^T + Q
+           + 2 * D * S                    # m- = Phi m
+           + 2 * D * d * (1 + d)          # U = P- Hbar^T
+           + 2 * d * d * (1 + d) + d ** 3  # S and its factor
+           + 2 * D * d * d + 2 * D * d    # gain rows, mean update
+           + 2 * DD * (2 * d + d * d) * 2)  # B = A P-, P = B A^T
+    bwd = 2 * D * S + 2 * D * D + 2 * d * D + 2 * D * d
+    return fwd + bwd
+
+
 def iteration_flops(d, q, b1=32):
     return sum(v[0] for v in per_step(d, q, 4, b1).values())
 
