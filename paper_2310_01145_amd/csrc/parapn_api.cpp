@@ -1168,7 +1168,10 @@ static int decoupled_layout(const parapn_problem *p, int B, bool want_cov, Decou
     DL.stage = DL.mu + align_up((size_t)B * D * 8);
     DL.pack = DL.stage + (p->init_traj && !p->init_on_device ? align_up((size_t)(N + 1) * D * 8) : 0);
     std::vector<parapn::ReqDev> r((size_t)B * d, parapn::ReqDev{});
-    for (auto &x : r) x.N = N;
+    for (auto &x : r) {
+        x.N = N;
+        x.b1 = parapn::forward_chunk(N * d);
+    }
     PackPlan pl;
     int rc = plan_pack(fp64, 1, p->q, r, want_cov, 0, pl);
     if (rc) return rc;
@@ -1225,6 +1228,10 @@ static int decoupled_solve(parapn_ctx *ctx, const parapn_problem *p, int B, cons
                 parapn::ReqDev &r = reqs[a * d + i];
                 fill_reqdev(sv[act[a]], trajs ? trajs + ((size_t)act[a] * d + i) * ts : nullptr, nullptr, r);
                 r.field = parapn::F_MOL_COMPONENT;
+                // the chunk length of a solve with the chain's total steps: each
+                // chain alone is short, and short chunks would leave most of
+                // the work to the upper scan levels
+                r.b1 = parapn::forward_chunk(N * d);
                 std::memset(r.p, 0, sizeof(r.p));
                 r.p[0] = k;
                 r.p[1] = (double)((((i + d - 1) % d) - i) * ts);

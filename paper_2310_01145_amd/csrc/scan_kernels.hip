@@ -1217,52 +1217,78 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
     load_consts<C>(cphi, csq, a.Phi, a.sQ);
     constexpr int D = C::D;
     const int64_t chunk = (int64_t)blockIdx.x * C::GPB + grp;
-    if (chunk >= a.pk.nf) return;
-    const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
-    const ReqView q = view_of(a.pk.reqs[ri]);
-    const int b1 = a.pk.reqs[ri].b1;
-    const int64_t lc = chunk - a.pk.reqs[ri].fchunk;
-    const int64_t s = 1 + lc * b1;
-    const int64_t e = s + b1 <= q.N + 1 ? s + b1 : q.N + 1;
-    SRow<C> st = s == 1 ? init_state<C>(a.init, lane)
-                        : load_state<C>(pref + (a.pk.ftab[ri].base + lc) * C::FS, lane);
-    if (s == 1 && mf && lane < D) {
-        mf[q.row * D + lane] = st.m;
-        store_packed<C>(sPf + q.row * C::DP, lane, st.P);
-    }
+    const bool valid = chunk < a.pk.nf;
     double qsum = 0.0;  // lane 0: the chunk's innovation quadratic forms
-    for (int64_t n = s; n < e; ++n) {
-        obs_setup<C>(a.pk, q, n, lane, sh, cphi);
-        ERow<C> eo;
-        T mfp, qf;
-        st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp, qf);
-        qsum += (double)qf;
-        const int64_t row = q.row + n - 1;
-        if (lane >= D && lane < C::D2) {
-            const int r = lane - D;
+    unsigned long long *qdst = nullptr;
+    if (valid) {
+        const int ri = find_req<true>(a.pk.reqs, a.pk.nreq, chunk);
+        const ReqView q = view_of(a.pk.reqs[ri]);
+        qdst = q.dbits;
+        const int b1 = a.pk.reqs[ri].b1;
+        const int64_t lc = chunk - a.pk.reqs[ri].fchunk;
+        const int64_t s = 1 + lc * b1;
+        const int64_t e = s + b1 <= q.N + 1 ? s + b1 : q.N + 1;
+        SRow<C> st = s == 1 ? init_state<C>(a.init, lane)
+                            : load_state<C>(pref + (a.pk.ftab[ri].base + lc) * C::FS, lane);
+        if (s == 1 && mf && lane < D) {
+            mf[q.row * D + lane] = st.m;
+            store_packed<C>(sPf + q.row * C::DP, lane, st.P);
+        }
+        for (int64_t n = s; n < e; ++n) {
+            obs_setup<C>(a.pk, q, n, lane, sh, cphi);
+            ERow<C> eo;
+            T mfp, qf;
+            st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp, qf);
+            qsum += (double)qf;
+            const int64_t row = q.row + n - 1;
+            if (lane >= D && lane < C::D2) {
+                const int r = lane - D;
+                T *rec = se + row * C::SEF;
+#pragma unroll
+                for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
+                rec[D * D + r] = eo.g;
+                rec[D * D + D + r] = mfp;
+                if (r == 0) rec[C::SE] = 0;
+                store_packed<C>(sL + row * C::DP, r, eo.L);
+            }
+            if (mf && lane < D) {
+                mf[(row + 1) * D + lane] = st.m;
+                store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
+            }
+        }
+        if (e == q.N + 1 && lane < D) {
+            const int64_t row = q.row + q.N;
             T *rec = se + row * C::SEF;
 #pragma unroll
-            for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
-            rec[D * D + r] = eo.g;
-            rec[D * D + D + r] = mfp;
-            if (r == 0) rec[C::SE] = 0;
-            store_packed<C>(sL + row * C::DP, r, eo.L);
-        }
-        if (mf && lane < D) {
-            mf[(row + 1) * D + lane] = st.m;
-            store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
+            for (int c = 0; c < D; ++c) rec[lane * D + c] = 0;
+            rec[D * D + lane] = 0;
+            rec[D * D + D + lane] = st.m;
+            if (lane == 0) rec[C::SE] = 1;
+            store_packed<C>(sL + row * C::DP, lane, st.P);
         }
     }
-    if (lane == 0 && q.dbits) atomicAdd((double *)q.dbits + 2, qsum);
-    if (e == q.N + 1 && lane < D) {
-        const int64_t row = q.row + q.N;
-        T *rec = se + row * C::SEF;
-#pragma unroll
-        for (int c = 0; c < D; ++c) rec[lane * D + c] = 0;
-        rec[D * D + lane] = 0;
-        rec[D * D + D + lane] = st.m;
-        if (lane == 0) rec[C::SE] = 1;
-        store_packed<C>(sL + row * C::DP, lane, st.P);
+    // Block-level sums, then one atomic per counter slot present in the block
+    // (a block's chunks are consecutive, so requests -- and requests sharing
+    // a slot -- form runs).
+    __shared__ double qred[C::GPB];
+    __shared__ unsigned long long *qptr[C::GPB];
+    if (lane == 0) {
+        qred[grp] = qsum;
+        qptr[grp] = qdst;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *cur = nullptr;
+        double x = 0.0;
+        for (int g = 0; g <= C::GPB; ++g) {
+            unsigned long long *r = g < C::GPB ? qptr[g] : nullptr;
+            if (r != cur) {
+                if (cur) atomicAdd((double *)cur + 2, x);
+                cur = r;
+                x = 0.0;
+            }
+            if (r) x += qred[g];
+        }
     }
 }
 
@@ -2166,18 +2192,28 @@ __global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, c
     }
     if (threadIdx.x < D) sInv[threadIdx.x] = 1.0 / sQ[threadIdx.x * (D + 1)];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
-    int ri = -1;
-    if (r < pk.rows) {
+    // the request of the block's first row by bisection (one thread), then
+    // each row walks forward from it (rows are ordered by request)
+    __shared__ int rbase;
+    const int64_t r0b = (int64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0) {
         int lo = 0, hi = pk.nreq - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (pk.reqs[mid].row <= r)
+            if (pk.reqs[mid].row <= r0b)
                 lo = mid;
             else
                 hi = mid - 1;
         }
+        rbase = lo;
+    }
+    __syncthreads();
+    const int64_t r = r0b + threadIdx.x;
+    double v = 0.0;
+    int ri = -1;
+    if (r < pk.rows) {
+        int lo = rbase;
+        while (lo + 1 < pk.nreq && pk.reqs[lo + 1].row <= r) ++lo;
         ri = lo;
         const ReqDev &q = pk.reqs[ri];
         const int64_t n = r - q.row;
@@ -2537,7 +2573,9 @@ int pack_layout(int fp64, int d, int q, ReqDev *reqs, ScanTab *ftab, ScanTab *st
     for (int i = 0; i < nreq; ++i) {
         ReqDev &rq = reqs[i];
         if (rq.N < 1) return -1;
-        rq.b1 = forward_chunk(rq.N);
+        // a caller may preset the chunk length (a function of its own
+        // problem only, so results stay independent of the pack)
+        if (rq.b1 < 1 || rq.b1 > 32) rq.b1 = forward_chunk(rq.N);
         rq.fchunk = f;
         rq.schunk = sm;
         rq.row = r;
