@@ -266,9 +266,15 @@ PARAPN_DEV void store_packed(typename C::T *p, int r, const typename C::T (&v)[C
 // The request fields the step kernels use, held in registers: the kernels
 // store through pointers the compiler cannot separate from the request table,
 // and fields read through it would be reloaded after every such store.
+// Device memory reached through pointers read from tables is "flat" to the
+// compiler, and a flat access also counts against the LDS wait counter: every
+// LDS wait after a flat store then waits for that store to reach memory.
+// Pointers known to address global memory are cast to this type.
+typedef __attribute__((address_space(1))) double gdouble;
+
 struct ReqView {
     const double *p;
-    double *traj;
+    gdouble *traj;
     unsigned long long *dbits;
     double T0, T1, invT1, hq, lm_s;
     int64_t N, row;
@@ -279,7 +285,7 @@ PARAPN_DEV ReqView view_of(const ReqDev &q)
 {
     ReqView v;
     v.p = q.p;
-    v.traj = q.traj;
+    v.traj = (gdouble *)q.traj;
     v.dbits = q.dbits;
     v.T0 = q.T0;
     v.T1 = q.T1;
@@ -304,8 +310,8 @@ PARAPN_DEV void obs_setup(const Pack &pk, const ReqView &o, int64_t n, int lane,
     for (int c = 0; c < D; ++c) hrow[c] = 0;
     T rval = 0, uval = 0;
     if (pk.mode == 0) {
-        const double *tn = o.traj + n * D;
-        const double *tp = tn - D;
+        const gdouble *tn = o.traj + n * D;
+        const gdouble *tp = tn - D;
         bool component = false;
         if constexpr (d == 1) {
             if (o.field == F_MOL_COMPONENT) {
@@ -1649,22 +1655,43 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
     double prm[kMaxParams];
 #pragma unroll
     for (int i = 0; i < kMaxParams; ++i) prm[i] = rq.p[i];
-    // one (q+1)-block of Phi and Q (uniform: every lane holds it)
-    double p1[S][S], q1[S][S];
+    // one (q+1)-block of Phi (uniform: every lane holds it, indexed only by
+    // compile-time constants), and each lane's own rows of Phi and entries of Q
+    // for the P- entries it forms (loaded once: an array indexed by lane-
+    // dependent values would live in scratch memory, and waiting for a scratch
+    // load inside the loop waits for every global store before it)
+    double p1[S][S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            p1[i][j] = Phi[i * D + j];
-            q1[i][j] = Q[i * D + j];
+        for (int j = 0; j < S; ++j) p1[i][j] = Phi[i * D + j];
+    double prow[EPL][S], pcol[EPL][S], qv[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int e = lane + 64 * k, ee = e < DD ? e : 0;
+        const int i = ee / D, j = ee % D, ri = i % S, rj = j % S;
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            prow[k][l] = Phi[ri * D + l];
+            pcol[k][l] = Phi[rj * D + l];
         }
-    double *rec = (double *)cd.gain;
+        qv[k] = (i / S == j / S) ? Q[(i % S) * D + (j % S)] : 0.0;
+    }
+    // the lane's row of Phi1 for m- = Phi m, and its column for t = Phi^T nu
+    // in the smoother (lane < D holds component lane)
+    double prl[S], pcb[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        prl[l] = Phi[(lane % S) * D + l];
+        pcb[l] = Phi[l * D + (lane % S)];
+    }
+    gdouble *rec = (gdouble *)cd.gain, *node = (gdouble *)cd.node;
     for (int e = lane; e < DD; e += 64) sP[e] = 0.0;
     if (lane < D) sm[lane] = cd.mu0c[lane];
     wave_sync();
     bool bad = false;
     for (int64_t n = 1; n <= cd.M; ++n) {
-        double *rp = rec + (n - 1) * REC;  // node n-1: m^f, P
+        gdouble *rp = rec + (n - 1) * REC;  // node n-1: m^f, P
         if (lane < D) rp[lane] = sm[lane];
         for (int e = lane; e < DD; e += 64) rp[D + e] = sP[e];
         // A = Phi P, m- = Phi m
@@ -1672,18 +1699,18 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         for (int k = 0; k < EPL; ++k) {
             const int e = lane + 64 * k;
             if (e < DD) {
-                const int i = e / D, j = e % D, bi = i / S, ri = i % S;
+                const int i = e / D, j = e % D, bi = i / S;
                 double acc = 0.0;
 #pragma unroll
-                for (int l = 0; l < S; ++l) acc += p1[ri][l] * sP[(bi * S + l) * D + j];
+                for (int l = 0; l < S; ++l) acc += prow[k][l] * sP[(bi * S + l) * D + j];
                 sA[e] = acc;
             }
         }
         if (lane < D) {
-            const int bi = lane / S, ri = lane % S;
+            const int bi = lane / S;
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < S; ++l) acc += p1[ri][l] * sm[bi * S + l];
+            for (int l = 0; l < S; ++l) acc += prl[l] * sm[bi * S + l];
             smp[lane] = acc;
         }
         wave_sync();
@@ -1694,10 +1721,10 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             const int e = lane + 64 * k;
             pp[k] = 0.0;
             if (e < DD) {
-                const int i = e / D, j = e % D, bi = i / S, ri = i % S, bj = j / S, rj = j % S;
-                double acc = bi == bj ? q1[ri][rj] : 0.0;
+                const int i = e / D, j = e % D, bj = j / S;
+                double acc = qv[k];
 #pragma unroll
-                for (int l = 0; l < S; ++l) acc += sA[i * D + bj * S + l] * p1[rj][l];
+                for (int l = 0; l < S; ++l) acc += sA[i * D + bj * S + l] * pcol[k][l];
                 pp[k] = acc;
                 sPp[e] = acc;
             }
@@ -1718,13 +1745,23 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
 #pragma unroll
             for (int b = 0; b < d; ++b) hj[a][b] = -cd.hq * fd[a].g[b];
         }
+        // hj[a][b] for lane-dependent a, b, selected among the compile-time
+        // entries (dynamic indexing would put the array in scratch memory)
+        auto hj_at = [&](int a, int b) {
+            double v = 0.0;
+#pragma unroll
+            for (int x = 0; x < d; ++x)
+#pragma unroll
+                for (int y = 0; y < d; ++y) v = (x == a && y == b) ? hj[x][y] : v;
+            return v;
+        };
         wave_sync();
         // U = P- Hbar^T (D x d): U[i][a] = P-[i][a S + 1] + sum_b hj[a][b] P-[i][b S]
         for (int e = lane; e < D * d; e += 64) {
             const int i = e / d, a = e % d;
             double acc = sPp[i * D + a * S + 1];
 #pragma unroll
-            for (int b = 0; b < d; ++b) acc += hj[a][b] * sPp[i * D + b * S];
+            for (int b = 0; b < d; ++b) acc += hj_at(a, b) * sPp[i * D + b * S];
             sU[e] = acc;
         }
         wave_sync();
@@ -1779,7 +1816,7 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             z[a] = v * inv[a];
         }
         // K = U S^-1 (row i: W_i L_S^T = U_i, then K_i L_S = W_i)
-        double *rn = rec + n * REC;  // step n: Hbar, K, z after node n's m^f, P
+        gdouble *rn = rec + n * REC;  // step n: Hbar, K, z after node n's m^f, P
         if (lane < D) {
             double w[d], kk[d];
 #pragma unroll
@@ -1810,7 +1847,7 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         for (int e = lane; e < d * D; e += 64) {
             const int a = e / D, c = e % D;
             double h = (c == a * S + 1) ? 1.0 : 0.0;
-            if (c % S == 0) h += hj[a][c / S];
+            if (c % S == 0) h += hj_at(a, c / S);
             rn[D + DD + e] = h;
         }
         if (lane < d) rn[D + DD + 2 * d * D + lane] = z[lane];
@@ -1874,7 +1911,7 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         wave_sync();
     }
     {
-        double *rp = rec + cd.M * REC;
+        gdouble *rp = rec + cd.M * REC;
         if (lane < D) rp[lane] = sm[lane];
         for (int e = lane; e < DD; e += 64) rp[D + e] = sP[e];
     }
@@ -1887,7 +1924,7 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         double mf, P[D], H[d], K[D], z;
     };
     auto load_share = [&](int64_t n, Share &sh) {
-        const double *rp = rec + n * REC;
+        const gdouble *rp = rec + n * REC;
         const int r = lane < D ? lane : 0, a = lane < d ? lane : 0;
         sh.mf = rp[r];
 #pragma unroll
@@ -1900,17 +1937,14 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             sh.z = rp[D + DD + 2 * d * D + a];
         }
     };
-    Share cur, nxt;
-    load_share(cd.M, cur);
-    wave_sync();
-    for (int64_t n = cd.M; n >= 0; --n) {
-        if (n >= 1) load_share(n - 1, nxt);
+    // one smoother step on the share of record n
+    auto step = [&](int64_t n, const Share &cur) {
         // t = Phi^T nu_{n+1} (block diagonal: q+1 terms)
         if (lane < D) {
-            const int bl = lane / S, rl = lane % S;
+            const int bl = lane / S;
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < S; ++l) acc += p1[l][rl] * snu[bl * S + l];
+            for (int l = 0; l < S; ++l) acc += pcb[l] * snu[bl * S + l];
             st[lane] = acc;
         }
         wave_sync();
@@ -1918,7 +1952,7 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             double acc = cur.mf;
 #pragma unroll
             for (int l = 0; l < D; ++l) acc += cur.P[l] * st[l];
-            cd.node[n * D + lane] = acc;
+            node[n * D + lane] = acc;
             bad |= !__builtin_isfinite(acc);
         }
         if (n >= 1 && lane < d) {
@@ -1935,7 +1969,18 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             snu[lane] = acc;
         }
         wave_sync();
-        cur = nxt;
+    };
+    // two buffers taken in turn (the loop body holds two steps, so no share
+    // is copied: a copy of a share still being loaded would wait for it)
+    Share A, B;
+    load_share(cd.M, A);
+    wave_sync();
+    for (int64_t n = cd.M; n >= 0; n -= 2) {
+        if (n >= 1) load_share(n - 1, B);
+        step(n, A);
+        if (n == 0) break;
+        if (n >= 2) load_share(n - 2, A);
+        step(n - 1, B);
     }
     const unsigned long long ballot = __ballot(bad ? 1 : 0);
     if (lane == 0) *cd.status = ballot ? 1 : 0;
