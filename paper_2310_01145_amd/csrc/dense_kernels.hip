@@ -104,13 +104,25 @@ __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 // assumes its inputs are complete and ends with a workgroup barrier.
 // ---------------------------------------------------------------------------
 
+// The primitives are not inlined, so a plain pointer parameter is "flat" to
+// the compiler, and a flat access counts against the LDS wait counter too:
+// every LDS wait would then also wait for the global loads and stores in
+// flight.  Operands in global memory are therefore accessed through G<T>
+// pointers and the LDS scratch through S<T> pointers.
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+template <typename T>
+using S = __attribute__((address_space(3))) T;
+
 // C (m x n) = alpha op(A) op(B) + beta C.  op(A) is m x k: A[i lda + p], or
 // A[p lda + i] when ta; op(B) is k x n: B[p ldb + j], or B[j ldb + p] when tb.
 // beta == 0: C is not read.  C must not overlap A or B.
 template <typename T>
-__device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool ta, const T *B, int ldb, bool tb,
-                        T beta, T *C, int ldc)
+__device__ void wg_gemm(int m, int n, int k, T alpha, const T *A_, int lda, bool ta, const T *B_, int ldb, bool tb,
+                        T beta, T *C_, int ldc)
 {
+    const G<T> *A = (const G<T> *)A_, *B = (const G<T> *)B_;
+    G<T> *C = (G<T> *)C_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
@@ -158,8 +170,10 @@ __device__ void wg_gemm(int m, int n, int k, T alpha, const T *A, int lda, bool 
 // y (m) = alpha op(A) x + beta y, op(A) m x k (A[i lda + j], or A[j lda + i]
 // when ta).  beta == 0: y is not read.  y must not overlap A or x.
 template <typename T>
-__device__ void wg_gemv(int m, int k, T alpha, const T *A, int lda, bool ta, const T *x, T beta, T *y)
+__device__ void wg_gemv(int m, int k, T alpha, const T *A_, int lda, bool ta, const T *x_, T beta, T *y_)
 {
+    const G<T> *A = (const G<T> *)A_, *x = (const G<T> *)x_;
+    G<T> *y = (G<T> *)y_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     for (int i = threadIdx.x; i < m; i += NT) {
@@ -175,8 +189,10 @@ __device__ void wg_gemv(int m, int k, T alpha, const T *A, int lda, bool ta, con
 
 // dst (m x n) = src, or zero where src is null
 template <typename T>
-__device__ void wg_copy(T *dst, int ldd, const T *src, int ldsrc, int m, int n)
+__device__ void wg_copy(T *dst_, int ldd, const T *src_, int ldsrc, int m, int n)
 {
+    G<T> *dst = (G<T> *)dst_;
+    const G<T> *src = (const G<T> *)src_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     for (int e = threadIdx.x; e < m * n; e += NT) {
@@ -187,8 +203,10 @@ __device__ void wg_copy(T *dst, int ldd, const T *src, int ldsrc, int m, int n)
 }
 
 template <typename T>
-__device__ void wg_vcopy(T *dst, const T *src, int n)
+__device__ void wg_vcopy(T *dst_, const T *src_, int n)
 {
+    G<T> *dst = (G<T> *)dst_;
+    const G<T> *src = (const G<T> *)src_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     for (int i = threadIdx.x; i < n; i += NT) dst[i] = src ? src[i] : T(0);
@@ -202,11 +220,12 @@ __device__ void wg_vcopy(T *dst, const T *src, int n)
 // factor Tm (NB x NB, upper triangular, zero outside nb x nb) with
 // H_0 H_1 ... H_{nb-1} = I - Y Tm Y^T, Y = [v_0 .. v_{nb-1}].
 template <typename T>
-__device__ void panel_factor(T *P, int nb, int w, T *Tm, T *Z, T *tau)
+__device__ void panel_factor(T *P_, int nb, int w, T *Tm_, T *Z_, T *tau_)
 {
+    S<T> *P = (S<T> *)P_, *Tm = (S<T> *)Tm_, *Z = (S<T> *)Z_, *tau = (S<T> *)tau_;
     const int lane = threadIdx.x & 63;
     for (int j = 0; j < nb; ++j) {
-        T *pj = P + j * w;
+        S<T> *pj = P + j * w;
         T s = T(0);
         for (int c = j + 1 + lane; c < w; c += 64) s += pj[c] * pj[c];
         s = wave_sum(s);
@@ -226,7 +245,7 @@ __device__ void panel_factor(T *P, int nb, int w, T *Tm, T *Z, T *tau)
         }
         wave_sync();
         for (int r = j + 1; r < nb; ++r) {
-            T *pr = P + r * w;
+            S<T> *pr = P + r * w;
             T dt = T(0);
             for (int c = j + 1 + lane; c < w; c += 64) dt += pr[c] * pj[c];
             dt = wave_sum(dt) + pr[j];
@@ -242,7 +261,7 @@ __device__ void panel_factor(T *P, int nb, int w, T *Tm, T *Z, T *tau)
         const int i = e / NB, j = e - i * NB;
         T z = T(0);
         if (i < j && j < nb) {
-            const T *pi = P + i * w, *pj = P + j * w;
+            const S<T> *pi = P + i * w, *pj = P + j * w;
             z = pi[j];
             for (int c = j + 1; c < w; ++c) z += pi[c] * pj[c];
         }
@@ -272,15 +291,16 @@ __host__ __device__ constexpr int smem_elems(int nmax) { return NB * nmax + 2 * 
 // trapezoidal L (columns >= min(m, n) zero) with L L^T = M M^T, M = L Q.
 // sm: smem_elems(n) elements of LDS.
 template <typename T>
-__device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
+__device__ void wg_tria(T *M_, int m, int n, int ld, T *sm)
 {
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
-    T *P = sm;
-    T *Tm = P + NB * n;
-    T *Z = Tm + NB * NB;
-    T *tau = Z + NB * NB;
-    T *Wb = tau + NB;
+    G<T> *M = (G<T> *)M_;
+    S<T> *P = (S<T> *)sm;
+    S<T> *Tm = P + NB * n;
+    S<T> *Z = Tm + NB * NB;
+    S<T> *tau = Z + NB * NB;
+    S<T> *Wb = tau + NB;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
     const int kmax = m < n ? m : n;
     for (int k0 = 0; k0 < kmax; k0 += NB) {
@@ -290,15 +310,15 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
             P[e] = M[(size_t)(k0 + j) * ld + k0 + c];
         }
         __syncthreads();
-        if (wv == 0) panel_factor(P, nb, w, Tm, Z, tau);
+        if (wv == 0) panel_factor((T *)P, nb, w, (T *)Tm, (T *)Z, (T *)tau);
         __syncthreads();
         // trailing rows: M_t <- M_t - ((M_t Y) Tm) Y^T over columns k0..n-1
         const int r0s = k0 + nb, nst = (m - r0s + 15) >> 4;
-        T *Wl = Wb + wv * 256;
+        S<T> *Wl = Wb + wv * 256;
         for (int st = wv; st < nst; st += NW) {
             const int r0 = r0s + (st << 4);
             const int ra = r0 + li;
-            const T *mrow = M + (size_t)ra * ld + k0;
+            const G<T> *mrow = M + (size_t)ra * ld + k0;
             typename MF<T>::v4 acc = {T(0), T(0), T(0), T(0)};
             const bool rok = ra < m;
             constexpr int U = kstep_of<T>();
@@ -375,8 +395,10 @@ __device__ void wg_tria(T *M, int m, int n, int ld, T *sm)
 // TRANS: X <- X L^{-T} (solves X L^T = B, column blocks left to right);
 // else   X <- X L^{-1} (solves X L = B, column blocks right to left).
 template <typename T, bool TRANS>
-__device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
+__device__ void wg_trsm(T *X_, int m, int k, int ldx, const T *L_, int ldl)
 {
+    G<T> *X = (G<T> *)X_;
+    const G<T> *L = (const G<T> *)L_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     const int nblk = (k + 15) >> 4;
@@ -384,16 +406,17 @@ __device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
         const int jb = TRANS ? bi : nblk - 1 - bi;
         const int j0 = jb << 4, nbk = min(16, k - j0), j1 = j0 + nbk;
         if (TRANS) {
-            if (j0 > 0) wg_gemm<T>(m, nbk, j0, T(-1), X, ldx, false, L + (size_t)j0 * ldl, ldl, true, T(1), X + j0, ldx);
+            if (j0 > 0)
+                wg_gemm<T>(m, nbk, j0, T(-1), X_, ldx, false, L_ + (size_t)j0 * ldl, ldl, true, T(1), X_ + j0, ldx);
         } else {
             if (j1 < k)
-                wg_gemm<T>(m, nbk, k - j1, T(-1), X + j1, ldx, false, L + (size_t)j1 * ldl + j0, ldl, false, T(1),
-                           X + j0, ldx);
+                wg_gemm<T>(m, nbk, k - j1, T(-1), X_ + j1, ldx, false, L_ + (size_t)j1 * ldl + j0, ldl, false, T(1),
+                           X_ + j0, ldx);
         }
         // the diagonal block, one row per thread (the row stays in L1)
-        const T *Lb = L + (size_t)j0 * ldl + j0;
+        const G<T> *Lb = L + (size_t)j0 * ldl + j0;
         for (int r = threadIdx.x; r < m; r += NT) {
-            T *xr = X + (size_t)r * ldx + j0;
+            G<T> *xr = X + (size_t)r * ldx + j0;
             if (sizeof(T) == 4 && TRANS && nbk == 16) {
                 // a full block of the forward solve in registers (FP32 only:
                 // in FP64 the block would push the combine kernel into spills)
@@ -432,8 +455,11 @@ __device__ void wg_trsm(T *X, int m, int k, int ldx, const T *L, int ldl)
 // z = L^{-1} v for lower k x k L (k <= NW * 256), one wavefront, column-
 // oriented forward substitution through LDS; z may alias v.
 template <typename T>
-__device__ void wg_lower_solve_vec(const T *L, int ldl, int k, const T *v, T *z, T *sm)
+__device__ void wg_lower_solve_vec(const T *L_, int ldl, int k, const T *v_, T *z_, T *sm_)
 {
+    const G<T> *L = (const G<T> *)L_, *v = (const G<T> *)v_;
+    G<T> *z = (G<T> *)z_;
+    S<T> *sm = (S<T> *)sm_;
     constexpr int NT = nt_of<T>(), NW = NT / 64;
     (void)NW;
     for (int i = threadIdx.x; i < k; i += NT) sm[i] = v[i];
