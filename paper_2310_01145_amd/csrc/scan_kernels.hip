@@ -2227,20 +2227,20 @@ __global__ void k_blocks_out(int d, int S, int64_t N, const double *Td, const do
 // (FP64).  One thread per pack row; a wavefront whose rows all belong to one
 // request adds its sum with one atomic.
 template <int D>
-__global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, const double *sQ, int slot)
+__global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, const double *sQ, int slot, int rpb)
 {
     __shared__ double sPhi[D * D], sL[D * D], sInv[D], wsum[4];
-    __shared__ int wreq[4];
+    __shared__ unsigned long long *wdst[4];
+    __shared__ int rbase;
     for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
         sPhi[i] = Phi[i];
         sL[i] = sQ[i];
     }
     if (threadIdx.x < D) sInv[threadIdx.x] = 1.0 / sQ[threadIdx.x * (D + 1)];
-    __syncthreads();
-    // the request of the block's first row by bisection (one thread), then
-    // each row walks forward from it (rows are ordered by request)
-    __shared__ int rbase;
-    const int64_t r0b = (int64_t)blockIdx.x * blockDim.x;
+    // the block takes rows [r0b, r0b + rpb); the request of its first row by
+    // bisection (one thread), then each row walks forward from the previous
+    // one (rows are ordered by request)
+    const int64_t r0b = (int64_t)blockIdx.x * rpb;
     if (threadIdx.x == 0) {
         int lo = 0, hi = pk.nreq - 1;
         while (lo < hi) {
@@ -2253,59 +2253,69 @@ __global__ __launch_bounds__(256) void k_objective(Pack pk, const double *Phi, c
         rbase = lo;
     }
     __syncthreads();
-    const int64_t r = r0b + threadIdx.x;
-    double v = 0.0;
-    int ri = -1;
-    if (r < pk.rows) {
-        int lo = rbase;
-        while (lo + 1 < pk.nreq && pk.reqs[lo + 1].row <= r) ++lo;
-        ri = lo;
-        const ReqDev &q = pk.reqs[ri];
-        const int64_t n = r - q.row;
-        if (n >= 1 && q.traj) {
-            const double *a = q.traj + (n - 1) * D, *b = q.traj + n * D;
-            double w[D];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int ri = rbase;
+    // per wavefront: a running sum for one counter slot, added to memory when
+    // the slot changes (requests sharing a slot accumulate together)
+    double acc = 0.0;
+    unsigned long long *accdst = nullptr;
+    for (int64_t base = r0b; base < r0b + rpb; base += blockDim.x) {
+        const int64_t r = base + threadIdx.x;
+        double v = 0.0;
+        unsigned long long *dst = nullptr;
+        if (r < pk.rows) {
+            while (ri + 1 < pk.nreq && pk.reqs[ri + 1].row <= r) ++ri;
+            const ReqDev &q = pk.reqs[ri];
+            dst = q.dbits;
+            const int64_t n = r - q.row;
+            if (n >= 1 && q.traj) {
+                const double *a = q.traj + (n - 1) * D, *b = q.traj + n * D;
+                double w[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double u = b[i];
+                for (int i = 0; i < D; ++i) {
+                    double u = b[i];
 #pragma unroll
-                for (int k = 0; k < D; ++k) u -= sPhi[i * D + k] * a[k];
+                    for (int k = 0; k < D; ++k) u -= sPhi[i * D + k] * a[k];
 #pragma unroll
-                for (int j = 0; j < i; ++j) u -= sL[i * D + j] * w[j];
-                w[i] = u * sInv[i];
-                v += w[i] * w[i];
+                    for (int j = 0; j < i; ++j) u -= sL[i * D + j] * w[j];
+                    w[i] = u * sInv[i];
+                    v += w[i] * w[i];
+                }
+                v *= 0.5;
             }
-            v *= 0.5;
+        }
+        const unsigned long long *d0 = (const unsigned long long *)__shfl((long long)(uintptr_t)dst, 0);
+        if (__all(dst == d0)) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+            if (dst != accdst) {
+                if (lane == 0 && accdst) atomicAdd((double *)accdst + slot, acc);
+                acc = 0.0;
+                accdst = dst;
+            }
+            acc += v;
+        } else if (dst) {
+            atomicAdd((double *)dst + slot, v);  // a wavefront across a slot boundary
         }
     }
-    // one atomic per block when all its rows belong to one request, else one
-    // per wavefront of one request, else one per row
-    const int wv = threadIdx.x >> 6, r0 = __shfl(ri, 0);
-    const bool uni = __all(ri == r0);
-    if (uni) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        wsum[wv] = v;
-        wreq[wv] = uni ? r0 : -2;
+    if (lane == 0) {
+        wsum[wv] = acc;
+        wdst[wv] = accdst;
     }
     __syncthreads();
-    const int nw = blockDim.x >> 6;
-    bool block_uni = true;
-    for (int k = 1; k < nw; ++k) block_uni = block_uni && wreq[k] == wreq[0];
-    block_uni = block_uni && wreq[0] >= 0;
-    if (block_uni) {
-        if (threadIdx.x == 0 && pk.reqs[wreq[0]].dbits) {
-            double t = 0.0;
-            for (int k = 0; k < nw; ++k) t += wsum[k];
-            atomicAdd((double *)pk.reqs[wreq[0]].dbits + slot, t);
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        unsigned long long *cur = nullptr;
+        double t = 0.0;
+        for (int k = 0; k <= nw; ++k) {
+            unsigned long long *dk = k < nw ? wdst[k] : nullptr;
+            if (dk != cur) {
+                if (cur) atomicAdd((double *)cur + slot, t);
+                cur = dk;
+                t = 0.0;
+            }
+            if (dk) t += wsum[k];
         }
-    } else if (uni) {
-        if ((threadIdx.x & 63) == 0 && r0 >= 0 && pk.reqs[r0].dbits)
-            atomicAdd((double *)pk.reqs[r0].dbits + slot, v);
-    } else if (ri >= 0 && pk.reqs[ri].dbits) {
-        atomicAdd((double *)pk.reqs[ri].dbits + slot, v);
     }
 }
 
@@ -2697,8 +2707,10 @@ hipError_t launch_objective(int d, int q, const Pack &pk, const double *Phi, con
     if (pk.rows < 1) return hipSuccess;
     return dispatch_t<double>(d, q, [&](auto cfg) {
         using C = decltype(cfg);
-        PARAPN_LAUNCH("objective", s, k_objective<C::D>, dim3((unsigned)cdiv(pk.rows, 256)), dim3(256), 0, s, pk, Phi,
-                      sQ, slot);
+        // about 2048 blocks, each a whole number of 256-row passes
+        const int64_t rpb = 256 * cdiv(cdiv(pk.rows, 2048), 256);
+        PARAPN_LAUNCH("objective", s, k_objective<C::D>, dim3((unsigned)cdiv(pk.rows, rpb)), dim3(256), 0, s, pk, Phi,
+                      sQ, slot, (int)rpb);
         return hipGetLastError();
     });
 }
