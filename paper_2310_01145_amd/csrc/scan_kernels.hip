@@ -1765,8 +1765,10 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             sU[e] = acc;
         }
         wave_sync();
-        // S = Hbar U (every lane) and its Cholesky factor
-        double Sm[d][d], L[d][d];
+        // S = Hbar U (every lane, symmetrised) and its inverse from the
+        // adjugate: one FP64 division per step instead of a factorisation's
+        // chain of square roots and divisions (d <= 3)
+        double Sm[d][d], Si[d][d];
 #pragma unroll
         for (int a = 0; a < d; ++a)
 #pragma unroll
@@ -1779,59 +1781,46 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
 #pragma unroll
         for (int a = 0; a < d; ++a)
 #pragma unroll
-            for (int b = 0; b <= a; ++b) L[a][b] = 0.5 * (Sm[a][b] + Sm[b][a]);
-        // (one FP64 division per diagonal entry; the substitutions multiply
-        // by the reciprocals)
-        double inv[d];
-#pragma unroll
-        for (int b = 0; b < d; ++b) {
-            double dg = L[b][b];
-#pragma unroll
-            for (int c = 0; c < b; ++c) dg -= L[b][c] * L[b][c];
-            dg = __builtin_sqrt(dg);
-            L[b][b] = dg;
-            inv[b] = 1.0 / dg;
-#pragma unroll
-            for (int a = b + 1; a < d; ++a) {
-                double v = L[a][b];
-#pragma unroll
-                for (int c = 0; c < b; ++c) v -= L[a][c] * L[b][c];
-                L[a][b] = v * inv[b];
-            }
+            for (int b = 0; b < a; ++b) Sm[a][b] = Sm[b][a] = 0.5 * (Sm[a][b] + Sm[b][a]);
+        if constexpr (d == 1) {
+            Si[0][0] = 1.0 / Sm[0][0];
+        } else if constexpr (d == 2) {
+            const double id = 1.0 / (Sm[0][0] * Sm[1][1] - Sm[0][1] * Sm[0][1]);
+            Si[0][0] = Sm[1][1] * id;
+            Si[1][1] = Sm[0][0] * id;
+            Si[0][1] = Si[1][0] = -Sm[0][1] * id;
+        } else {
+            const double c00 = Sm[1][1] * Sm[2][2] - Sm[1][2] * Sm[1][2];
+            const double c01 = Sm[1][2] * Sm[0][2] - Sm[0][1] * Sm[2][2];
+            const double c02 = Sm[0][1] * Sm[1][2] - Sm[1][1] * Sm[0][2];
+            const double id = 1.0 / (Sm[0][0] * c00 + Sm[0][1] * c01 + Sm[0][2] * c02);
+            Si[0][0] = c00 * id;
+            Si[0][1] = Si[1][0] = c01 * id;
+            Si[0][2] = Si[2][0] = c02 * id;
+            Si[1][1] = (Sm[0][0] * Sm[2][2] - Sm[0][2] * Sm[0][2]) * id;
+            Si[1][2] = Si[2][1] = (Sm[0][2] * Sm[0][1] - Sm[0][0] * Sm[1][2]) * id;
+            Si[2][2] = (Sm[0][0] * Sm[1][1] - Sm[0][1] * Sm[0][1]) * id;
         }
-        // z = S^-1 r (forward then backward substitution)
+        // z = S^-1 r, K = U S^-1
         double z[d];
 #pragma unroll
         for (int a = 0; a < d; ++a) {
-            double v = r[a];
+            double v = 0.0;
 #pragma unroll
-            for (int c = 0; c < a; ++c) v -= L[a][c] * z[c];
-            z[a] = v * inv[a];
+            for (int c = 0; c < d; ++c) v += Si[a][c] * r[c];
+            z[a] = v;
         }
-#pragma unroll
-        for (int a = d - 1; a >= 0; --a) {
-            double v = z[a];
-#pragma unroll
-            for (int c = a + 1; c < d; ++c) v -= L[c][a] * z[c];
-            z[a] = v * inv[a];
-        }
-        // K = U S^-1 (row i: W_i L_S^T = U_i, then K_i L_S = W_i)
         gdouble *rn = rec + n * REC;  // step n: Hbar, K, z after node n's m^f, P
         if (lane < D) {
-            double w[d], kk[d];
+            double uu[d], kk[d];
+#pragma unroll
+            for (int a = 0; a < d; ++a) uu[a] = sU[lane * d + a];
 #pragma unroll
             for (int a = 0; a < d; ++a) {
-                double v = sU[lane * d + a];
+                double v = 0.0;
 #pragma unroll
-                for (int c = 0; c < a; ++c) v -= w[c] * L[a][c];
-                w[a] = v * inv[a];
-            }
-#pragma unroll
-            for (int a = d - 1; a >= 0; --a) {
-                double v = w[a];
-#pragma unroll
-                for (int c = a + 1; c < d; ++c) v -= kk[c] * L[c][a];
-                kk[a] = v * inv[a];
+                for (int c = 0; c < d; ++c) v += uu[c] * Si[c][a];
+                kk[a] = v;
             }
             double mn = smp[lane];
 #pragma unroll
