@@ -47,6 +47,16 @@ def test_workspace_size_and_validation_on_host():
     pbc = pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0, 1.0], 0.0, 100.0, 3, 1 << 12, precision="fp32",
                           init="coarse")
     assert pp.workspace_size(pbc) > n32
+    # the method-of-lines chain under DiagonalEK1 runs as d decoupled problems
+    # of state size q+1: its workspace grows linearly in d (the dense EK1
+    # engine's with d^2), and the objective rule is accepted there
+    mk = lambda d, lin: pp.make_problem("mol_heat_reaction", [0.01], [0.5] * d, 0.0, 1.0, 2, 1024,
+                                        precision="fp32", linearization=lin)
+    w16, w32 = pp.workspace_size(mk(16, "diag_ek1")), pp.workspace_size(mk(32, "diag_ek1"))
+    assert 1.8 * w16 < w32 < 2.2 * w16
+    assert pp.workspace_size(mk(32, "ek1")) > 10 * w32
+    pp.workspace_size(pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10,
+                                      linearization="ek0", stop_rule="objective"))
     bad = [
         pp.make_problem("fhn", [0.2, 0.2], [-1.0, 1.0], 0.0, 1.0, 3, 100),         # too few params
         pp.make_problem("fhn", [0.2, 0.2, 3.0], [-1.0], 0.0, 1.0, 3, 100),          # d mismatch
@@ -58,6 +68,12 @@ def test_workspace_size_and_validation_on_host():
         pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, init=7),            # unknown start
         pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, init="coarse", coarse_points=-1),
         pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, init="coarse"),
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, linearization=3),  # unknown linearisation
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior="matern", theta=0.0),  # length scale 0
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior="matern", theta=float("inf")),
+        pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior=3),          # unknown prior
+        # the objective rule on the dense EK1 engine
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, stop_rule="objective"),
     ]
     for b in bad:
         with pytest.raises(pp.ParapnError) as e:

@@ -222,3 +222,26 @@ def test_decoupled_chain_full_size(pp):
     f = k * (np.roll(E0, 1, -1) - 2 * E0 + np.roll(E0, -1, -1)) + E0 * (1 - E0)
     assert np.abs(E1 - f).max() < 1e-7 * max(np.abs(f).max(), 1.0)
     assert rel(out["fp32"][:, :, 0::3], m[:, :, 0::3]) < 1e-4
+
+
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_decoupled_chain_from_a_given_trajectory(pp, where):
+    """A caller's starting trajectory (original coordinates, host or device
+    memory) is split over the chains: three DiagonalEK1 iterations from the
+    EK1 fixed point equal the oracle's from the same start."""
+    import torch
+
+    d, q, N = 8, 2, 48
+    y0 = mol_y0(d)
+    start = oracle.ieks("mol_heat_reaction", [0.01], y0, 0.0, 1.0, q, N, max_iter=20, tol=1e-12,
+                        want_cov=False)["mean"]
+    start = start + 1e-3 * np.sin(np.arange(start.size)).reshape(start.shape)  # off the fixed point
+    kw = dict(fixed_iters=3, linearization="diag_ek1")
+    ref = oracle.ieks("mol_heat_reaction", [0.01], y0, 0.0, 1.0, q, N, want_cov=True, init_traj=start, **kw)
+    init = torch.tensor(start, dtype=torch.float64, device="cuda") if where == "device" else start
+    r = pp.solve("mol_heat_reaction", [0.01], y0, 0.0, 1.0, q, N, precision="fp64", want_cov=True, init_traj=init,
+                 **kw)
+    assert r["start"] == "given"
+    assert rel(np_(r["mean"]), ref["mean"]) < 1e-9
+    assert rel(sigma(np_(r["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
+    assert np.allclose(r["deltas"], ref["deltas"], rtol=1e-6, atol=0)
