@@ -84,6 +84,8 @@ def lib():
         L.orc_ieks_prior.argtypes = [i, P, i, i, P, dl, dl, i, l, i, dl, i, P, dl, i, dl, P, P, P,
                                      ctypes.POINTER(ctypes.c_int)]
         L.orc_ieks_prior.restype = i
+        L.orc_kf_rts_tv.argtypes = [i, i, l, P, P, P, P, P, P, P, P, P, P]
+        L.orc_kf_rts_tv.restype = i
         L.orc_ioup.argtypes = [i, dl, dl, P, P]
         L.orc_ioup.restype = None
         L.orc_matern.argtypes = [i, dl, dl, P, P]
@@ -185,6 +187,7 @@ def precond_model(d, q, h):
 
 def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None, return_qf=False):
     """Sequential square-root KF + RTS.  H is [N, dobs, D], dv [N, dobs];
+    Phi, sqrtQ are [D, D] (constant) or [N, D, D] (step n uses entry n-1);
     rstd (dobs) optional per-row observation noise standard deviations.
     Returns (mf, sPf, ms, sPs), stacks over n = 0..N; with return_qf (noiseless
     rows only) also the sum of the innovations' quadratic forms."""
@@ -192,6 +195,13 @@ def kf_rts(mu0, S0, Phi, sqrtQ, H, dv, rstd=None, return_qf=False):
     N, dobs, D = H.shape
     mf, ms = np.zeros((N + 1, D)), np.zeros((N + 1, D))
     sPf, sPs = np.zeros((N + 1, D, D)), np.zeros((N + 1, D, D))
+    if Phi.ndim == 3:
+        assert Phi.shape == (N, D, D) and sqrtQ.shape == (N, D, D) and rstd is None and not return_qf
+        rc = lib().orc_kf_rts_tv(D, dobs, N, _p(mu0), _p(S0), _p(Phi), _p(sqrtQ), _p(H), _p(dv), _p(mf), _p(sPf),
+                                 _p(ms), _p(sPs))
+        if rc != 0:
+            raise FloatingPointError("non-finite values in the sequential smoother")
+        return mf, sPf, ms, sPs
     if return_qf:
         assert rstd is None
         qf = ctypes.c_double(0.0)

@@ -586,9 +586,12 @@ static void precond_model(int d, int q, double h, double *PhiB, double *sQB, dou
  * prediction-error decomposition of the data's log-likelihood, whose
  * maximiser over the diffusion sigma^2 is qf / (N dobs) (the quasi-maximum-
  * likelihood calibration of Sec. 2.4; every covariance scales with sigma^2). */
-static int kf_rts_core(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
-                       const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
-                       double *sPf, double *ms, double *sPs, double *qf)
+/* Step n (1..N) takes its transition and process-noise factor from
+ * Phi + (n-1) pstride and sqrtQ + (n-1) pstride: pstride 0 is a constant model,
+ * D*D a time-varying one (eq. affine-estimation with Phi_n, Q_n). */
+static int kf_rts_core(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi0,
+                       const double *sqrtQ0, long pstride, const double *H, const double *dv, const double *rstd,
+                       double *mf, double *sPf, double *ms, double *sPs, double *qf)
 {
     int n2 = dobs + D;
     double *mp = dalloc(D), *sPp = dalloc(D * D), *M = dalloc((long)n2 * n2), *Psi = dalloc((long)n2 * n2);
@@ -601,6 +604,7 @@ static int kf_rts_core(int D, int dobs, long N, const double *mu0, const double 
     for (long n = 1; n <= N; ++n) {
         const double *m = mf + (n - 1) * D, *sP = sPf + (n - 1) * D * D;
         const double *Hn = H + (n - 1) * dobs * D, *dn = dv + (n - 1) * dobs;
+        const double *Phi = Phi0 + (n - 1) * pstride, *sqrtQ = sqrtQ0 + (n - 1) * pstride;
         /* predict: m- = Phi m, sqrtP- = tria([Phi sqrtP, sqrtQ]) */
         mv(D, D, Phi, 0, m, mp);
         mm(D, D, D, Phi, 0, sP, 0, tmp);
@@ -646,6 +650,7 @@ static int kf_rts_core(int D, int dobs, long N, const double *mu0, const double 
     memcpy(sPs + N * D * D, sPf + N * D * D, sizeof(double) * D * D);
     for (long n = N - 1; n >= 0; --n) {
         const double *m = mf + n * D, *sP = sPf + n * D * D;
+        const double *Phi = Phi0 + n * pstride, *sqrtQ = sqrtQ0 + n * pstride; /* step n+1 */
         /* Pi = tria([[Phi sqrtPf, sqrtQ], [sqrtPf, 0]]) */
         memset(W, 0, sizeof(double) * 4 * D * D);
         mm(D, D, D, Phi, 0, sP, 0, tmp);
@@ -691,14 +696,23 @@ int orc_kf_rts_noise(int D, int dobs, long N, const double *mu0, const double *S
                      const double *sqrtQ, const double *H, const double *dv, const double *rstd, double *mf,
                      double *sPf, double *ms, double *sPs)
 {
-    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, rstd, mf, sPf, ms, sPs, NULL);
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, 0, H, dv, rstd, mf, sPf, ms, sPs, NULL);
 }
 
 int orc_kf_rts(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
                const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf,
                double *ms, double *sPs)
 {
-    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs, NULL);
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, 0, H, dv, NULL, mf, sPf, ms, sPs, NULL);
+}
+
+/* the sequential filter/smoother of a time-varying model: Phi, sqrtQ are
+ * [N][D][D], step n using entry n-1 */
+int orc_kf_rts_tv(int D, int dobs, long N, const double *mu0, const double *S0, const double *Phi,
+                  const double *sqrtQ, const double *H, const double *dv, double *mf, double *sPf, double *ms,
+                  double *sPs)
+{
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, (long)D * D, H, dv, NULL, mf, sPf, ms, sPs, NULL);
 }
 
 /* the noiseless filter/smoother and the innovations' quadratic-form sum */
@@ -707,7 +721,7 @@ int orc_kf_rts_qf(int D, int dobs, long N, const double *mu0, const double *S0, 
                   double *sPs, double *qf)
 {
     *qf = 0.0;
-    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, H, dv, NULL, mf, sPf, ms, sPs, qf);
+    return kf_rts_core(D, dobs, N, mu0, S0, Phi, sqrtQ, 0, H, dv, NULL, mf, sPf, ms, sPs, qf);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -845,7 +859,7 @@ int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const 
             }
         }
         qf = 0.0;
-        int rc = kf_rts_core(D, dobs, N, mu0b, S0, PhiB, sQB, H, dv, rstd, mf, sPf, ms, sPs, lm ? NULL : &qf);
+        int rc = kf_rts_core(D, dobs, N, mu0b, S0, PhiB, sQB, 0, H, dv, rstd, mf, sPf, ms, sPs, lm ? NULL : &qf);
         if (!lm) s2 = qf / ((double)N * d);
         double delta = 0.0;
         for (long n = 0; n <= N; ++n)
@@ -889,7 +903,7 @@ int orc_ieks_ext(int field, const double *params, int nparams, int d_req, const 
             }
         }
         qf = 0.0;
-        kf_rts_core(D, d, N, mu0b, S0, PhiB, sQB, H, dv, NULL, mf, sPf, ms, sPs, &qf);
+        kf_rts_core(D, d, N, mu0b, S0, PhiB, sQB, 0, H, dv, NULL, mf, sPf, ms, sPs, &qf);
         s2 = qf / ((double)N * d);
         memcpy(ms, msk, sizeof(double) * (N + 1) * D);
         free(msk);

@@ -239,9 +239,11 @@ def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None, rstd=None):
     G[:D, :D] = S0
     m[:D] = mu0
     for n in range(1, N + 1):
-        G[n * D:(n + 1) * D] = Phi @ G[(n - 1) * D:n * D]
-        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += sQ
-        m[n * D:(n + 1) * D] = Phi @ m[(n - 1) * D:n * D]
+        Pn = Phi[n - 1] if np.ndim(Phi) == 3 else Phi  # per-step transition (or constant)
+        Qn = sQ[n - 1] if np.ndim(sQ) == 3 else sQ
+        G[n * D:(n + 1) * D] = Pn @ G[(n - 1) * D:n * D]
+        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += Qn
+        m[n * D:(n + 1) * D] = Pn @ m[(n - 1) * D:n * D]
     Sig = G @ G.T
     C = np.zeros((upto * dobs, (N + 1) * D))
     for n in range(1, upto + 1):
@@ -254,6 +256,26 @@ def dense_conditioning(mu0, S0, Phi, sQ, H, dv, upto=None, rstd=None):
     mp = m + K @ (dd - C @ m)
     Sp = Sig - K @ C @ Sig
     return mp.reshape(N + 1, D), Sp
+
+
+@pytest.mark.parametrize("D,dobs,N", [(3, 1, 5), (8, 2, 6)])
+def test_time_varying_kf_rts_equals_dense_conditioning(D, dobs, N):
+    """A model whose transition and process noise change every step (e.g. a
+    non-uniform grid): the sequential smoother equals dense conditioning with
+    the same per-step matrices, and differs from the constant model built from
+    the first step's (so the per-step matrices are really used)."""
+    rng = np.random.default_rng(7 * D + N)
+    mu0, S0, Phi, sQ, H, dv = random_linear_model(D, dobs, N, rng)
+    Phis = np.stack([Phi + 0.1 * rng.normal(size=(D, D)) for _ in range(N)])
+    sQs = np.stack([np.tril(sQ + 0.1 * rng.normal(size=(D, D))) for _ in range(N)])
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phis, sQs, H, dv)
+    m_all, S_all = dense_conditioning(mu0, S0, Phis, sQs, H, dv)
+    for n in range(N + 1):
+        assert rel(ms[n], m_all[n]) < 1e-10
+        Pn = S_all[n * D:(n + 1) * D, n * D:(n + 1) * D]
+        assert np.abs(sPs[n] @ sPs[n].T - Pn).max() < 1e-10 * max(1.0, np.abs(Pn).max())
+    m_c = oracle.kf_rts(mu0, S0, Phis[0], sQs[0], H, dv)[2]
+    assert rel(m_c, m_all) > 1e-3
 
 
 @pytest.mark.parametrize("D,dobs,N", [(3, 1, 5), (4, 2, 6), (8, 2, 7)])
@@ -898,9 +920,11 @@ def dense_quadratic_form(mu0, S0, Phi, sQ, H, dv):
     G[:D, :D] = S0
     m[:D] = mu0
     for n in range(1, N + 1):
-        G[n * D:(n + 1) * D] = Phi @ G[(n - 1) * D:n * D]
-        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += sQ
-        m[n * D:(n + 1) * D] = Phi @ m[(n - 1) * D:n * D]
+        Pn = Phi[n - 1] if np.ndim(Phi) == 3 else Phi  # per-step transition (or constant)
+        Qn = sQ[n - 1] if np.ndim(sQ) == 3 else sQ
+        G[n * D:(n + 1) * D] = Pn @ G[(n - 1) * D:n * D]
+        G[n * D:(n + 1) * D, n * D:(n + 1) * D] += Qn
+        m[n * D:(n + 1) * D] = Pn @ m[(n - 1) * D:n * D]
     C = np.zeros((N * dobs, (N + 1) * D))
     for n in range(1, N + 1):
         C[(n - 1) * dobs:n * dobs, n * D:(n + 1) * D] = H[n - 1]
