@@ -266,6 +266,18 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
                    const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
                    void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream);
 
+/* ParaRTS (Alg. 1) on a time-varying linear model (eq. affine-estimation with
+ * Phi_n, Q_n, e.g. a non-uniform time grid):  Y_n = Phi_n Y_{n-1} + w_n,
+ * w_n ~ N(0, sqrtQ_n sqrtQ_n^T).  Phi and sqrtQ are device [N][D][D], step n
+ * using entry n-1; every other argument, the outputs and the status as for
+ * parapn_pararts.  The per-step matrices are copied once into the context's
+ * workspace (in the kernels' padded row layout) and read by the forward
+ * step kernels at every step. */
+int parapn_pararts_tv(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                      const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
+                      void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out,
+                      void *stream);
+
 /* ParaRTS as parapn_pararts, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no context, and no hipMalloc, hipFree or other allocating call.

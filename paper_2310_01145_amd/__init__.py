@@ -37,7 +37,7 @@ STOP_RULES = {"trajectory": 1, "objective": 2, "either": 3}
 LINEARIZATIONS = {"ek1": 0, "ek0": 1, "diag_ek1": 2}
 EXPORTED = ["parapn_create", "parapn_destroy", "parapn_workspace_size", "parapn_solve", "parapn_solve_batch",
             "parapn_start_trajectory", "parapn_pararts_noalloc",
-            "parapn_pararts",
+            "parapn_pararts", "parapn_pararts_tv",
             "parapn_filter_combine", "parapn_profile_enable", "parapn_profile_only", "parapn_profile_read",
             "parapn_server_create", "parapn_server_destroy", "parapn_server_clock", "parapn_server_submit", "parapn_server_step",
             "parapn_server_poll", "parapn_server_footprint", "parapn_server_stats", "parapn_last_error"]
@@ -137,6 +137,8 @@ def load_library(path: str = LIB_PATH):
     L.parapn_solve_batch.restype = ctypes.c_int
     L.parapn_pararts.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.parapn_pararts.restype = ctypes.c_int
+    L.parapn_pararts_tv.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.parapn_pararts_tv.restype = ctypes.c_int
     L.parapn_filter_combine.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp]
     L.parapn_filter_combine.restype = ctypes.c_int
     L.parapn_profile_enable.argtypes = [ctypes.c_int]
@@ -375,7 +377,9 @@ def pararts(mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, *, precision="fp64", want_cov
             device=0, stream=None):
     """ParaRTS (Alg. 1) on a linear model with noiseless observations
     H_n Y_n = dvec_n.  Inputs are torch tensors on the device with the dtype
-    of the precision; H is [N, dobs, D], dvec [N, dobs]."""
+    of the precision; H is [N, dobs, D], dvec [N, dobs]; Phi and sqrtQ are
+    [D, D] (constant) or [N, D, D] (step n uses entry n-1:
+    parapn_pararts_tv)."""
     torch = _torch()
     L = load_library()
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -387,8 +391,12 @@ def pararts(mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, *, precision="fp64", want_cov
     sPs = torch.empty((N + 1, D, D), dtype=dt, device=dev) if want_cov else None
     mf = torch.empty((N + 1, D), dtype=dt, device=dev) if want_filter else None
     sPf = torch.empty((N + 1, D, D), dtype=dt, device=dev) if want_filter else None
-    _check(L.parapn_pararts(context(device), D, dobs, N, prec, *[_dptr(x) for x in ins], _dptr(ms), _dptr(sPs),
-                            _dptr(mf), _dptr(sPf), _stream_handle(stream)))
+    tv = ins[2].dim() == 3
+    if tv and (tuple(ins[2].shape) != (N, D, D) or tuple(ins[3].shape) != (N, D, D)):
+        raise ValueError("per-step Phi and sqrtQ must be [N, D, D]")
+    fn = L.parapn_pararts_tv if tv else L.parapn_pararts
+    _check(fn(context(device), D, dobs, N, prec, *[_dptr(x) for x in ins], _dptr(ms), _dptr(sPs), _dptr(mf),
+              _dptr(sPf), _stream_handle(stream)))
     return {"mean": ms, "sqrtcov": sPs, "filt_mean": mf, "filt_sqrtcov": sPf}
 
 

@@ -1723,9 +1723,12 @@ int pararts_check(int32_t D, int32_t dobs, int64_t N, int32_t precision, const v
 
 // ParaRTS on a planned pack whose scratch starts at ws (device memory of at
 // least pl.L.total bytes).  Allocates nothing; waits for the stream.
+// phin, sqn: a time-varying model's per-step Phi_n, sqrtQ_n in the kernels'
+// padded layout [N][D][D+1] (device), or null for the constant Phi, sqrtQ.
 int pararts_run(char *ws, PackPlan &pl, int32_t D, int32_t dobs, int q, int64_t N, bool fp64, const void *mu0,
                 const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
-                void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, hipStream_t s)
+                void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, hipStream_t s,
+                const void *phin = nullptr, const void *sqn = nullptr)
 {
     const int d = dobs, esz = fp64 ? 8 : 4;
     const PackLayout &L = pl.L;
@@ -1748,6 +1751,8 @@ int pararts_run(char *ws, PackPlan &pl, int32_t D, int32_t dobs, int q, int64_t 
     pk.mode = 1;
     pk.H = H;
     pk.dv = dvec;
+    pk.phin = phin;
+    pk.sqn = sqn;
     PARAPN_HIP(parapn::launch_forward(fp64, d, q, pk, m, w, s), "forward scan");
     if (filt_mean_out || filt_sqrtcov_out)
         PARAPN_HIP(parapn::launch_unscale(fp64, D, N, nullptr, w.mf, w.sPf, filt_mean_out, filt_sqrtcov_out, s),
@@ -1814,6 +1819,34 @@ int parapn_pararts(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t 
     ctx->reqs_at = nullptr;
     return pararts_run((char *)ctx->ws, pl, D, dobs, q, N, fp64, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out,
                        sqrtcov_out, filt_mean_out, filt_sqrtcov_out, s);
+}
+
+int parapn_pararts_tv(parapn_ctx *ctx, int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,
+                      const void *sqrt_sigma0, const void *Phi, const void *sqrtQ, const void *H, const void *dvec,
+                      void *mean_out, void *sqrtcov_out, void *filt_mean_out, void *filt_sqrtcov_out, void *stream)
+{
+    if (!ctx) return fail(PARAPN_EINVAL, "ctx is NULL");
+    int q;
+    int rc = pararts_check(D, dobs, N, precision, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out, &q);
+    if (rc) return rc;
+    const bool fp64 = precision == PARAPN_FP64;
+    const size_t esz = fp64 ? 8 : 4, padded = align_up((size_t)N * D * (D + 1) * esz);
+    hipStream_t s = (hipStream_t)stream;
+    PARAPN_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    PackPlan pl;
+    std::vector<parapn::ReqDev> r(1, parapn::ReqDev{});
+    r[0].N = N;
+    rc = plan_pack(fp64, dobs, q, r, true, 2 * padded, pl);
+    if (rc) return rc;
+    rc = ensure_ws(ctx, pl.L.total);
+    if (rc) return rc;
+    ctx->consts_at = nullptr;  // every region is overwritten
+    ctx->reqs_at = nullptr;
+    char *ws = (char *)ctx->ws, *phin = ws + pl.L.extra, *sqn = phin + padded;
+    PARAPN_HIP(parapn::launch_pad_rows(fp64, D, N, Phi, phin, s), "per-step transitions");
+    PARAPN_HIP(parapn::launch_pad_rows(fp64, D, N, sqrtQ, sqn, s), "per-step noise factors");
+    return pararts_run(ws, pl, D, dobs, q, N, fp64, mu0, sqrt_sigma0, Phi, sqrtQ, H, dvec, mean_out, sqrtcov_out,
+                       filt_mean_out, filt_sqrtcov_out, s, phin, sqn);
 }
 
 int parapn_pararts_noalloc(int32_t D, int32_t dobs, int64_t N, int32_t precision, const void *mu0,

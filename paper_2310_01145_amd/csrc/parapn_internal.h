@@ -84,6 +84,8 @@ struct Pack {
     int lm;              // 1: every request is damped (Levenberg-Marquardt rows, mode 0 only)
     const void *H;       // mode 1: [N][dobs][D]
     const void *dv;      // mode 1: [N][dobs]
+    const void *phin;    // mode 1, time-varying model: Phi_n, sqrtQ_n of step n at entry n-1 of [N][D][D+1]
+    const void *sqn;     // (rows padded to the LDS constants' stride); null: the constant Phi, sqrtQ
 };
 
 // forward chunk length of a request of N steps
@@ -183,6 +185,8 @@ inline hipError_t launch_coarse(int fp64, int d, int q, const ReqDev *reqs, cons
 hipError_t launch_objective(int d, int q, const Pack &pk, const double *Phi, const double *sQ, int slot, hipStream_t s);
 // p[0..n) = 0 by a kernel (graph-capturable, unlike a memset node)
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
+// [N][D][D] -> [N][D][D+1] (the row stride of the kernels' constants), path precision
+hipError_t launch_pad_rows(int fp64, int D, int64_t N, const void *src, void *dst, hipStream_t s);
 // traj [N+1][D] = preconditioned starting trajectory (k_init_traj)
 hipError_t launch_init_traj(int D, int64_t N, const double *init, const double *Td, double *traj, hipStream_t s);
 

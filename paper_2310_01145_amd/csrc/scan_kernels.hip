@@ -1089,25 +1089,36 @@ __global__ __launch_bounds__(C::NT) void k_fwd_reduce1(KArgs<C> a, typename C::T
     const int64_t e = s + b1 <= q.N + 1 ? s + b1 : q.N + 1;
     FRow<C> acc;
     zero(acc);
-    for (int64_t n = s; n < e; ++n) {
-        obs_setup<C>(a.pk, q, n, lane, sh, cphi);
-        FRow<C> el = filter_element<C>(lane, sh, cphi, csq);
-        if (n == 1) {
-            SRow<C> st = state_apply<C>(lane, sh, init_state<C>(a.init, lane), el);
-            zero(el);
-            el.b = st.m;
+    // the transition and noise factor of step n: the block's constants, or a
+    // time-varying model's Phi_n, sqrtQ_n (padded rows) read from memory.  The
+    // two cases are separate inlined copies of the loop, so no pointer in it
+    // may address either memory.
+    auto fold = [&](const T *phi0, const T *sq0, int64_t stride) __attribute__((always_inline)) {
+        for (int64_t n = s; n < e; ++n) {
+            const T *pn = phi0 + (n - 1) * stride, *qn = sq0 + (n - 1) * stride;
+            obs_setup<C>(a.pk, q, n, lane, sh, pn);
+            FRow<C> el = filter_element<C>(lane, sh, pn, qn);
+            if (n == 1) {
+                SRow<C> st = state_apply<C>(lane, sh, init_state<C>(a.init, lane), el);
+                zero(el);
+                el.b = st.m;
 #pragma unroll
-            for (int c = 0; c < C::D; ++c) {
-                el.sC[c] = st.P[c];
-                el.A[c] = (c == lane) ? T(-1) : T(0);  // A = 0
+                for (int c = 0; c < C::D; ++c) {
+                    el.sC[c] = st.P[c];
+                    el.A[c] = (c == lane) ? T(-1) : T(0);  // A = 0
+                }
+                el.flag = 1;
             }
-            el.flag = 1;
+            if (n == s)
+                acc = el;
+            else
+                acc = filter_combine<C, C::DO, C::D - C::d>(lane, sh, acc, el);
         }
-        if (n == s)
-            acc = el;
-        else
-            acc = filter_combine<C, C::DO, C::D - C::d>(lane, sh, acc, el);
-    }
+    };
+    if (a.pk.phin)
+        fold((const T *)a.pk.phin, (const T *)a.pk.sqn, C::D * C::LDM);
+    else
+        fold(cphi, csq, 0);
     store_frow<C>(agg + (fbase + lc) * C::FEF, lane, acc);
 }
 
@@ -1240,28 +1251,37 @@ __global__ __launch_bounds__(C::NT) void k_fwd_down1(KArgs<C> a, const typename 
             mf[q.row * D + lane] = st.m;
             store_packed<C>(sPf + q.row * C::DP, lane, st.P);
         }
-        for (int64_t n = s; n < e; ++n) {
-            obs_setup<C>(a.pk, q, n, lane, sh, cphi);
-            ERow<C> eo;
-            T mfp, qf;
-            st = kf_step_se<C>(lane, sh, st, cphi, csq, eo, mfp, qf);
-            qsum += (double)qf;
-            const int64_t row = q.row + n - 1;
-            if (lane >= D && lane < C::D2) {
-                const int r = lane - D;
-                T *rec = se + row * C::SEF;
+        // as in k_fwd_reduce1: the constant or the time-varying model, each
+        // in its own inlined copy of the loop
+        auto walk = [&](const T *phi0, const T *sq0, int64_t stride) __attribute__((always_inline)) {
+            for (int64_t n = s; n < e; ++n) {
+                const T *pn = phi0 + (n - 1) * stride, *qn = sq0 + (n - 1) * stride;
+                obs_setup<C>(a.pk, q, n, lane, sh, pn);
+                ERow<C> eo;
+                T mfp, qf;
+                st = kf_step_se<C>(lane, sh, st, pn, qn, eo, mfp, qf);
+                qsum += (double)qf;
+                const int64_t row = q.row + n - 1;
+                if (lane >= D && lane < C::D2) {
+                    const int r = lane - D;
+                    T *rec = se + row * C::SEF;
 #pragma unroll
-                for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
-                rec[D * D + r] = eo.g;
-                rec[D * D + D + r] = mfp;
-                if (r == 0) rec[C::SE] = 0;
-                store_packed<C>(sL + row * C::DP, r, eo.L);
+                    for (int c = 0; c < D; ++c) rec[r * D + c] = eo.E[c];
+                    rec[D * D + r] = eo.g;
+                    rec[D * D + D + r] = mfp;
+                    if (r == 0) rec[C::SE] = 0;
+                    store_packed<C>(sL + row * C::DP, r, eo.L);
+                }
+                if (mf && lane < D) {
+                    mf[(row + 1) * D + lane] = st.m;
+                    store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
+                }
             }
-            if (mf && lane < D) {
-                mf[(row + 1) * D + lane] = st.m;
-                store_packed<C>(sPf + (row + 1) * C::DP, lane, st.P);
-            }
-        }
+        };
+        if (a.pk.phin)
+            walk((const T *)a.pk.phin, (const T *)a.pk.sqn, D * C::LDM);
+        else
+            walk(cphi, csq, 0);
         if (e == q.N + 1 && lane < D) {
             const int64_t row = q.row + q.N;
             T *rec = se + row * C::SEF;
@@ -2170,6 +2190,19 @@ __global__ void k_init_traj(int D, int64_t N, const T *init, const T *Td, T *tra
     traj[i] = (i < D || !init) ? Td[D + k] : init[i] / Td[k];
 }
 
+// [N][D][D] -> [N][D][D+1]: one thread per destination entry (the padding
+// column is written as zero)
+template <typename T>
+__global__ void k_pad_rows(int D, int64_t N, const T *src, T *dst)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = N * D * (D + 1);
+    if (e >= total) return;
+    const int64_t row = e / (D + 1);
+    const int c = (int)(e - row * (D + 1));
+    dst[e] = c < D ? src[row * D + c] : T(0);
+}
+
 // starting trajectories of decoupled chains: one thread per element of
 // [B][d][N+1][S]
 static __global__ void k_blocks_in(int B, int d, int S, int64_t N, const double *init, const double *Td, const double *mu0b,
@@ -2708,6 +2741,17 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s)
 {
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_rows(int fp64, int D, int64_t N, const void *src, void *dst, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)cdiv(N * D * (D + 1), 256);
+    if (fp64)
+        hipLaunchKernelGGL(k_pad_rows<double>, dim3(blocks), dim3(256), 0, s, D, N, (const double *)src,
+                           (double *)dst);
+    else
+        hipLaunchKernelGGL(k_pad_rows<float>, dim3(blocks), dim3(256), 0, s, D, N, (const float *)src, (float *)dst);
     return hipGetLastError();
 }
 

@@ -146,6 +146,73 @@ def test_pararts_fp32(pp, d, q):
     assert relerr(np_(r["filt_mean"]), mf) < 1e-4
 
 
+def time_varying_model(d, q, N, seed, h0=0.01):
+    """A linear model on a non-uniform grid: step n has its own h_n in
+    [0.5, 1.5] h0, and Phi(h_n), Q(h_n) of the IWP(q) prior written in the
+    coordinates T(h0) of the mean step (so the blocks stay well scaled)."""
+    import math
+
+    rng = np.random.default_rng(seed)
+    S, D = q + 1, d * (q + 1)
+    T = np.array([math.sqrt(h0) * h0 ** (q - i) / math.factorial(q - i) for i in range(S)])
+    Phis, sQs = np.zeros((N, D, D)), np.zeros((N, D, D))
+    for n in range(N):
+        Ph, Qh = oracle.iwp(q, h0 * (0.5 + rng.random()))
+        Pb = Ph * T[None, :] / T[:, None]
+        Qb = Qh / np.outer(T, T)
+        Phis[n] = np.kron(np.eye(d), Pb)
+        sQs[n] = np.kron(np.eye(d), np.linalg.cholesky(Qb))
+    mu0, S0, _, _, H, dv = linear_model(d, q, N, seed + 1, h=h0)
+    return mu0, S0, Phis, sQs, H, dv
+
+
+@pytest.mark.parametrize("N", [1, 7, 129, 1000])
+@pytest.mark.parametrize("d,q", [(2, 3), (1, 2)])
+def test_time_varying_pararts_fp64_equals_sequential_smoother(pp, N, d, q):
+    """ParaRTS with a per-step transition and process noise
+    (parapn_pararts_tv) against the sequential smoother of the same model."""
+    import torch
+
+    mu0, S0, Phis, sQs, H, dv = time_varying_model(d, q, N, seed=3 * N + d)
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phis, sQs, H, dv)
+    t = [torch.tensor(x, device="cuda") for x in (mu0, S0, Phis, sQs, H, dv)]
+    r = pp.pararts(*t, precision="fp64")
+    assert relerr(np_(r["filt_mean"]), mf) < 1e-9
+    assert cov_relerr(np_(r["filt_sqrtcov"]), sPf) < 1e-9
+    assert relerr(np_(r["mean"]), ms) < 1e-9
+    assert cov_relerr(np_(r["sqrtcov"]), sPs) < 1e-9
+
+
+def test_time_varying_pararts_fp32(pp):
+    import torch
+
+    mu0, S0, Phis, sQs, H, dv = time_varying_model(2, 3, 3000, seed=11)
+    S0[:] = 0.0
+    mf, sPf, ms, sPs = oracle.kf_rts(mu0, S0, Phis, sQs, H, dv)
+    t = [torch.tensor(x, device="cuda") for x in (mu0, S0, Phis, sQs, H, dv)]
+    r = pp.pararts(*t, precision="fp32")
+    assert relerr(np_(r["mean"]), ms) < 1e-4
+    assert relerr(np_(r["filt_mean"]), mf) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_time_varying_pararts_with_constant_steps_is_pararts(pp, prec):
+    """The same matrix at every step gives bitwise the constant-model result."""
+    import torch
+
+    N = 300
+    mu0, S0, Phi, sQ, H, dv = linear_model(2, 3, N, seed=2)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t = [torch.tensor(x, device="cuda", dtype=dt) for x in (mu0, S0, Phi, sQ, H, dv)]
+    a = pp.pararts(*t, precision=prec)
+    tv = list(t)
+    tv[2] = t[2].expand(N, -1, -1).contiguous()
+    tv[3] = t[3].expand(N, -1, -1).contiguous()
+    b = pp.pararts(*tv, precision=prec)
+    for k in ("mean", "sqrtcov", "filt_mean", "filt_sqrtcov"):
+        assert torch.equal(a[k], b[k]), k
+
+
 # ---------------------------------------------------------------------------
 # ParaIEKS (Alg. 2)
 # ---------------------------------------------------------------------------
