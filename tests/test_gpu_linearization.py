@@ -116,7 +116,7 @@ def mol_y0(d, seed=0):
 
 
 MOL = [(8, 2, 40, "diag_ek1", 4), (16, 2, 256, "diag_ek1", 4), (16, 3, 101, "ek0", 2), (5, 1, 7, "diag_ek1", 3),
-       (64, 2, 40, "diag_ek1", 3)]
+       (64, 2, 40, "diag_ek1", 3), (3, 4, 1, "diag_ek1", 2), (4, 2, 2, "ek0", 2), (6, 1, 4097, "diag_ek1", 2)]
 
 
 @pytest.mark.parametrize("d,q,N,lin,its", MOL)
