@@ -5,14 +5,19 @@ iteration: linearisation, filtering elements, forward scan, smoothing
 elements, reverse scan, convergence test; finally the output in original
 coordinates) of the FitzHugh-Nagumo workload: d = 2, IWP(3) (D = 8),
 N = 2^18 steps on t in [0, 100], started from the library's coarse-grid
-trajectory (a sequential extended Kalman smoother on 1152 coarse steps,
+trajectory (a sequential extended Kalman smoother on 1150 coarse steps,
 bridged to the fine grid; computed inside the timed solve) and iterated to
 Delta < 1e-10 (the FP32 path's threshold is max(1e-10, 2^-20 max|E0 mu|)), at
 most 20 iterations.  From Alg. 2's constant start the Gauss-Newton iteration
 diverges on this problem (in the sequential smoother too), which is reported
 beside the figure.  value = N * iterations / seconds (time-steps x iterations
-per second), whole job, FP32 square-root path; the FP64 path, a solve of 20
-fixed iterations, and Lorenz-63 at D = 15 are reported beside it.
+per second), whole job, FP32 square-root path.  Reported beside it: the FP64
+path, a solve of 20 fixed iterations, the roofline of the dominant kernel of
+the solve and of its iterations, the scan kernels at N = 2^18 and 2^20 (beyond
+the Infinity Cache), an N sweep, the logistic latency, Lorenz-63 at D = 15,
+the method-of-lines batch (EK1 on the dense engine; DiagonalEK1 as decoupled
+chains), the served stream, and the oracle on the host (one thread, and one
+instance per core).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -497,6 +502,9 @@ def main():
     # the same solve with 20 fixed iterations (the per-iteration rate with the start amortised)
     f20 = run_gpu(pp, torch, workload(args.N, 20), "fp32", max(2, args.steps // 2), 1, False)
     print("bench: fp32 20 iterations done %.3f ms/solve" % f20["ms_per_step"], file=sys.stderr, flush=True)
+    from paper_2310_01145_amd import costmodel
+
+    coarse_m = costmodel.coarse_points(wl["N"])
     line = {
         "metric": METRIC,
         "value": r32["value"],
@@ -511,11 +519,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "FitzHugh-Nagumo a=b=0.2 c=3, y0=(-1,1), t in [0,100], IWP(3) D=8, N=%d, one whole "
-                               "solve: coarse-grid start (1152 coarse steps) then IEKS iterations to Delta < 1e-10 "
-                               "(at most 20)" % wl["N"],
+                               "solve: coarse-grid start then IEKS iterations to Delta < 1e-10 (at most 20)" % wl["N"],
                    "N": wl["N"], "q": wl["q"], "d": 2, "precision": "fp32_sqrt",
-                   "initial_trajectory": "the library's coarse-grid start (sequential EKS on ceil(N/228) = 1150 "
-                                         "steps, bridged by the prior), computed inside every timed solve"},
+                   "initial_trajectory": "the library's coarse-grid start (sequential EKS on %d coarse steps of %d "
+                                         "fine steps, bridged by the prior), computed inside every timed solve"
+                                         % (coarse_m, -(-wl["N"] // coarse_m))},
         "latency_ms_p50": r32["latency_ms_p50"],
         "latency_ms_p99": r32["latency_ms_p99"],
         "iterations_per_solve": r32["iterations_per_solve"][0],
