@@ -181,9 +181,10 @@ typedef struct {
                               * the linearised model is block diagonal over the d
                               * grid points and the solve runs as d independent
                               * problems of state size q+1 (cost linear in d); its
-                              * factors (sqrtcov_out) are block diagonal, and the
-                              * objective stopping rule and sigma-hat are available
-                              * there as for the fixed-size fields.                */
+                              * factors (sqrtcov_out) are block diagonal, and
+                              * sigma-hat is available there as for the fixed-size
+                              * fields (under EK1 the method-of-lines field reports
+                              * V but not sigma-hat).                             */
 } parapn_problem;
 
 typedef struct {
@@ -202,10 +203,10 @@ typedef struct {
                              * triggers, else NaN).  FP32 path: from one FP64 filter pass
                              * at the final iterate that calibrate with sqrtcov_out
                              * triggers, else NaN (the FP32 innovations cancel at a
-                             * converged iterate).  NaN for the method-of-lines field. */
+                             * converged iterate).  NaN for the method-of-lines field
+                             * under EK1 (its dense engine forms no innovations).     */
     double objective;       /* V (eq. objective-value) of the returned trajectory, FP64 (in
-                             * the FP32 path V of a trajectory carrying FP32 increments);
-                             * NaN for the method-of-lines field                      */
+                             * the FP32 path V of a trajectory carrying FP32 increments) */
     double *objective_history; /* host, max_iter entries (V after each iteration), may be NULL */
 } parapn_info;
 

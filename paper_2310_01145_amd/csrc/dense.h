@@ -50,5 +50,8 @@ hipError_t dense_iteration(int fp64, const DenseModel &m, const DenseWork &w, hi
 // reverse scan with factors and writes cov_out [B][N+1][D][D] (original
 // coordinates, row 0 zero)
 hipError_t dense_covariance(int fp64, const DenseModel &m, const DenseWork &w, void *cov_out, hipStream_t s);
+// objective value V (eq. objective-value, FP64) of each active instance's
+// trajectory, added to obj[2b + slot] (slot 0 or 1; the caller zeroes obj)
+hipError_t dense_objective(const DenseModel &m, const DenseWork &w, double *obj, int slot, hipStream_t s);
 
 }  // namespace parapn

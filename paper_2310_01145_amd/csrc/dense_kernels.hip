@@ -917,6 +917,55 @@ __global__ void k_cov_out(DenseModel md, DenseWork w, T *cov)
     }
 }
 
+// Objective value (eq. objective-value) of every active instance's resident
+// trajectory, in the preconditioned coordinates it is kept in.  The prior is
+// d independent copies of one (q+1)-state process, so the weighted norm splits
+// over the grid components i:
+//   |eta_n - Phi eta_{n-1}|^2_{Q^-1} = sum_i |sqrtQb^-1 (eta_n[i] - Phib eta_{n-1}[i])|^2
+// with the (q+1) x (q+1) blocks (FP64).  Halved and summed over n = 1..N into
+// obj[2b + slot]: one thread per (step, component) pair, one FP64 atomic per
+// workgroup.
+__global__ __launch_bounds__(256) void k_objective(DenseModel md, const double *traj, int64_t ts, const int *active,
+                                                   double *obj, int slot)
+{
+    __shared__ double wsum[4];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const int S = md.q + 1, D = md.D, d = md.d;
+    const double *tb = traj + (size_t)b * ts;
+    const int64_t units = md.N * d;
+    double v = 0.0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = u / d + 1;
+        const int i = (int)(u % d);
+        const double *a = tb + (n - 1) * D + i * S, *x = a + D;
+        double w[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            if (r >= S) break;
+            double t = x[r];
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                if (c < S) t -= md.phib[r * 5 + c] * a[c];
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                if (c < r) t -= md.sqb[r * 5 + c] * w[c];
+            w[r] = t / md.sqb[r * 5 + r];
+            v += w[r] * w[r];
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wsum[k];
+        atomicAdd(obj + 2 * b + slot, 0.5 * t);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
@@ -1034,6 +1083,16 @@ hipError_t dense_iteration(int fp64, const DenseModel &m, const DenseWork &w, hi
 hipError_t dense_covariance(int fp64, const DenseModel &m, const DenseWork &w, void *cov_out, hipStream_t s)
 {
     return fp64 ? dense::covariance_t<double>(m, w, cov_out, s) : dense::covariance_t<float>(m, w, cov_out, s);
+}
+
+hipError_t dense_objective(const DenseModel &m, const DenseWork &w, double *obj, int slot, hipStream_t s)
+{
+    if (m.q + 1 > 5 || slot < 0 || slot > 1) return hipErrorInvalidValue;
+    const int64_t units = m.N * m.d;
+    const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((units + 255) / 256, 1024));
+    PARAPN_LAUNCH("dense_objective", s, dense::k_objective, dim3(bx, m.B), dim3(256), 0, s, m, w.traj, w.traj_stride,
+                  w.active, obj, slot);
+    return hipGetLastError();
 }
 
 }  // namespace parapn

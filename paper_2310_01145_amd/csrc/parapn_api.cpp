@@ -805,9 +805,10 @@ static int check_problem(const parapn_problem *p, int *q_out, int *D_out)
     if (!(p->obj_atol >= 0.0) || !(p->obj_rtol >= 0.0)) return fail(PARAPN_EINVAL, "objective tolerances must be >= 0");
     if (p->linearization < PARAPN_LIN_EK1 || p->linearization > PARAPN_LIN_DIAG_EK1)
         return fail(PARAPN_EINVAL, "unknown linearization");
-    if (p->field == parapn::F_MOL && p->linearization == PARAPN_LIN_EK1 && (p->stop_rule & 2))
-        return fail(PARAPN_EINVAL, "the objective stopping rule is available for the fixed-size fields and for the "
-                                   "method-of-lines field under an approximate Jacobian");
+    if (p->calibrate != 0 && p->calibrate != 1) return fail(PARAPN_EINVAL, "calibrate must be 0 or 1");
+    if (p->field == parapn::F_MOL && p->linearization == PARAPN_LIN_EK1 && p->calibrate)
+        return fail(PARAPN_EINVAL, "sigma-hat (calibrate) is formed for the method-of-lines field under EK0 or "
+                                   "DiagonalEK1 only");
     if (p->field == parapn::F_MOL && p->init_mode == PARAPN_INIT_COARSE && !p->init_traj)
         return fail(PARAPN_EINVAL, "the coarse-grid start is available for the fixed-size fields");
     if (p->prior == PARAPN_PRIOR_IOUP && !(std::isfinite(p->prior_theta) && p->prior_theta >= 0.0))
@@ -886,8 +887,6 @@ static int pack_enqueue(parapn_ctx *ctx, std::vector<Solve *> &sv, std::vector<d
     return PARAPN_OK;
 }
 
-// Advance each solve's state from its iteration's counters (bits: 2 per
-// request, delta and max |E0 trajectory|, as doubles).
 // Advance each solve's state from its iteration's counters (stride words per
 // request: delta and max |E0 trajectory| as bit patterns; with the row
 // engine's kCounters also the innovations' quadratic-form sum, the objective
@@ -1004,7 +1003,7 @@ static DenseLayout dense_layout(bool fp64, int D, int64_t N, int B, bool cov)
         return o;
     };
     L.traj = take((size_t)B * dense_traj_stride(D, N) * 8);
-    L.dbits = take((size_t)2 * B * 8);
+    L.dbits = take((size_t)4 * B * 8);  // delta and max |E0 mu| per instance, then V after and before the pass
     L.active = take((size_t)B * 4);
     L.A = take(el * DD * esz);
     L.C = take(el * DD * esz);
@@ -1042,7 +1041,7 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     const DenseLayout L = dense_layout(fp64, D, N, B, cov_out != nullptr);
     int rc = ensure_ws(ctx, L.total);
     if (rc) return rc;
-    rc = ensure_host_bits(ctx, 2 * (size_t)B);
+    rc = ensure_host_bits(ctx, 4 * (size_t)B);
     if (rc) return rc;
     char *ws = (char *)ctx->ws;
     // the dense layout overwrites what the row-per-lane packs cached there
@@ -1094,16 +1093,35 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
     std::vector<Solve *> ptr(B);
     for (int b = 0; b < B; ++b) ptr[b] = &sv[b];
     std::vector<int> active(B, 1);
+    double *obj = (double *)(w.dbits + 2 * B);
+    // counters in pack_finish's layout: delta, max |E0 mu|, no quadratic-form
+    // sum (sigma-hat is not formed here), V after and before the pass
+    std::vector<unsigned long long> counters((size_t)parapn::kCounters * B);
+    const double nan = NAN;
+    unsigned long long nan_bits;
+    std::memcpy(&nan_bits, &nan, 8);
     while (true) {
+        bool obj_start = false;
+        for (int b = 0; b < B; ++b) obj_start |= !sv[b].done && sv[b].iter == 0 && (sv[b].stop_rule & 2);
         PARAPN_HIP(hipMemcpyAsync(active_dev, active.data(), (size_t)B * sizeof(int), hipMemcpyHostToDevice, s),
                    "copy flags");
-        PARAPN_HIP(parapn::launch_zero_u64(w.dbits, 2 * (int64_t)B, s), "reset delta slots");
+        PARAPN_HIP(parapn::launch_zero_u64(w.dbits, 4 * (int64_t)B, s), "reset counters");
+        if (obj_start) PARAPN_HIP(parapn::dense_objective(md, w, obj, 1, s), "objective of the start");
         PARAPN_HIP(parapn::dense_iteration(fp64, md, w, s), "dense iteration");
-        PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, w.dbits, (size_t)2 * B * sizeof(unsigned long long),
+        PARAPN_HIP(parapn::dense_objective(md, w, obj, 0, s), "objective");
+        PARAPN_HIP(hipMemcpyAsync(ctx->host_bits, w.dbits, (size_t)4 * B * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, s),
-                   "read delta");
+                   "read counters");
         PARAPN_HIP(hipStreamSynchronize(s), "sync");
-        pack_finish(ptr, ctx->host_bits, 2);
+        for (int b = 0; b < B; ++b) {
+            unsigned long long *c = counters.data() + (size_t)parapn::kCounters * b;
+            c[0] = ctx->host_bits[2 * b];
+            c[1] = ctx->host_bits[2 * b + 1];
+            c[2] = nan_bits;
+            c[3] = ctx->host_bits[2 * B + 2 * b];
+            c[4] = obj_start ? ctx->host_bits[2 * B + 2 * b + 1] : nan_bits;
+        }
+        pack_finish(ptr, counters.data(), parapn::kCounters);
         bool all = true;
         for (int b = 0; b < B; ++b) {
             active[b] = sv[b].done ? 0 : 1;
@@ -1135,11 +1153,12 @@ static int dense_solve(parapn_ctx *ctx, const parapn_problem *p, int B, const do
             f.tol_used = v.tol_used;
             f.start = p->init_traj ? PARAPN_START_GIVEN : PARAPN_START_CONSTANT;
             f.sigma_hat = NAN;  // not computed by the dense engine
-            f.objective = NAN;
-            if (f.delta_history) {
-                const int cap = std::max(v.max_iter, v.fixed_iters);
+            f.objective = v.objective;
+            const int cap = std::max(v.max_iter, v.fixed_iters);
+            if (f.delta_history)
                 for (int k = 0; k < (int)v.deltas.size() && k < cap; ++k) f.delta_history[k] = v.deltas[k];
-            }
+            if (f.objective_history)
+                for (int k = 0; k < (int)v.objectives.size() && k < cap; ++k) f.objective_history[k] = v.objectives[k];
         }
         if (v.status == PARAPN_ENONFINITE)
             status = PARAPN_ENONFINITE;

@@ -72,8 +72,8 @@ def test_workspace_size_and_validation_on_host():
         pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior="matern", theta=0.0),  # length scale 0
         pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior="matern", theta=float("inf")),
         pp.make_problem("logistic", [], [0.1], 0.0, 1.0, 2, 10, prior=3),          # unknown prior
-        # the objective rule on the dense EK1 engine
-        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, stop_rule="objective"),
+        # sigma-hat on the dense EK1 engine
+        pp.make_problem("mol_heat_reaction", [0.01], [0.5] * 8, 0.0, 1.0, 2, 10, calibrate=True),
     ]
     for b in bad:
         with pytest.raises(pp.ParapnError) as e:

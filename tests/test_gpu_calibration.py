@@ -4,7 +4,8 @@ objective value (eq. objective-value) and the stopping rule built on it
 
 sigma-hat^2 is accumulated inside the Kalman-step kernel of the forward scan
 (each step's innovation quadratic form over the d ODE rows) and the objective
-by a kernel over the updated FP64 trajectory; the oracle sums the sequential
+by a kernel over the updated FP64 trajectory (the dense engine of the
+method-of-lines field has a kernel of its own for it); the oracle sums the sequential
 filter's innovation quadratic forms and evaluates V in original coordinates.
 FP64 gates 1e-9 relative; the FP32 path computes the innovations in FP32 and
 V of a trajectory carrying FP32 increments (gates stated per test)."""
@@ -80,6 +81,34 @@ def test_sigma_hat_and_objective_match_the_oracle(pp, spec, coarse):
     assert es < 1e-9
     assert np.all(eo <= np.maximum(64 * np.array(bounds), 1e-9))
     assert np.isfinite(r["objective"]) and r["objective"] == r["objectives"][-1]
+
+
+def test_dense_engine_objective_and_stopping_rule(pp):
+    """The method-of-lines field under EK1 (the dense engine; d = 8, q = 2,
+    D = 24): V after every iteration within 64 times its rounding bound (at
+    least 1e-9) of the oracle's, and the objective rule stops where the oracle
+    stops, at the same iterate.  The dense engine forms no innovations, so
+    sigma-hat is NaN there."""
+    spec = wl.mol(d=8, N=200, q=2, seed=3)
+    a = args_of(spec)
+    h = (spec["t1"] - spec["t0"]) / spec["N"]
+    print("dense objective: mol d=8 q=2 N=200", flush=True)
+    ref = oracle.ieks(*a, fixed_iters=3, want_cov=False)
+    r = pp.solve(*a, precision="fp64", fixed_iters=3)
+    bounds = [objective_rounding_bound(oracle.ieks(*a, fixed_iters=k, want_cov=False)["mean"], spec["q"], h)
+              for k in range(1, 4)]
+    eo = np.abs(r["objectives"] - ref["objectives"]) / np.abs(ref["objectives"])
+    print("objective rel err %s, rounding bounds %s" % (eo, bounds), flush=True)
+    assert np.all(eo <= np.maximum(64 * np.array(bounds), 1e-9))
+    assert r["objective"] == r["objectives"][-1] and np.isnan(r["sigma_hat"])
+    kw = dict(max_iter=20, tol=1e-10, obj_atol=1e-9, obj_rtol=1e-6)
+    for rule, code in (("objective", 2), ("either", 3)):
+        ref = oracle.ieks(*a, want_cov=False, stop_rule=code, **kw)
+        r = pp.solve(*a, precision="fp64", stop_rule=rule, **kw)
+        assert r["status"] == ref["status"] == 0
+        assert r["iterations"] == ref["iterations"], rule
+        m = r["mean"].double().cpu().numpy()[:, ::3]
+        assert np.abs(m - ref["mean"][:, ::3]).max() / np.abs(ref["mean"][:, ::3]).max() < 1e-9
 
 
 @pytest.mark.parametrize("spec,coarse", CASES, ids=[c[0]["field"] for c in CASES])
