@@ -114,7 +114,9 @@ def test_dense_d64_matches_oracle(pp, prec, tol):
         assert rel(sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9
     else:
         S, R = sigma(np_(out["sqrtcov"]))[:, ::3, ::3], sigma(ref["sqrtcov"])[:, ::3, ::3]
-        assert rel(S, R) < 1e-2
+        # the E0 block of the covariances (measured 4.8e-6)
+        print("  E0 covariance rel err %.2e" % rel(S, R), flush=True)
+        assert rel(S, R) < 1e-4
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -230,6 +232,8 @@ def test_dense_workgroup_stride_loop_matches_oracle(pp, prec, tol):
     e = rel(np_(out["mean"])[:, ::3], ref["mean"][:, ::3])
     print("  E0 mean rel err %.2e" % e)
     assert e < tol
+    # FP32 delta_2: a difference of two iterates with ~1e-4-relative FP32
+    # error each, gated relative to itself at 1e-2 (the means carry 1e-4)
     np.testing.assert_allclose(out["deltas"], ref["deltas"], rtol=(1e-6 if prec == "fp64" else 1e-2))
     if prec == "fp64":
         assert rel(sigma(np_(out["sqrtcov"])), sigma(ref["sqrtcov"])) < 1e-9

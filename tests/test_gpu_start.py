@@ -110,4 +110,7 @@ def test_fixed_iterations_from_the_coarse_start(pp, prec, tol):
         ref = oracle.ieks(*args, fixed_iters=3, want_cov=False, init="coarse")
         r = pp.solve(*args, precision=prec, fixed_iters=3, init="coarse")
         assert relerr(e0(r["mean"].double().cpu().numpy(), spec["q"]), e0(ref["mean"], spec["q"])) < tol
+        # an FP32 delta_k (k > 1) is a difference of two iterates that each
+        # carry ~1e-4-relative FP32 error, so it is gated relative to itself
+        # at 1e-2 (the means above carry the 1e-4 gate)
         assert np.allclose(r["deltas"], ref["deltas"], rtol=(1e-6 if prec == "fp64" else 1e-2))
