@@ -1926,26 +1926,30 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
     }
     // smoother.  Each lane's share of a record (its row of P and m^f, its
     // column of Hbar; lanes < d their column of K and entry of z) is loaded
-    // one step ahead, so the global-memory latency overlaps the previous
-    // step's arithmetic.
+    // ahead of its step, so the global-memory latency overlaps the arithmetic
+    // of the steps before it.
     if (lane < D) snu[lane] = 0.0;
     struct Share {
         double mf, P[D], H[d], K[D], z;
     };
+    // Every call issues the same loads, whatever n (0 <= n <= M; record 0's
+    // Hbar, K, z slots are read and left unused): a load taken on one path
+    // and skipped on another leaves the compiler no static count of the loads
+    // issued after a share, and it then waits for all of them -- the prefetch
+    // would not hide anything.
     auto load_share = [&](int64_t n, Share &sh) {
         const gdouble *rp = rec + n * REC;
         const int r = lane < D ? lane : 0, a = lane < d ? lane : 0;
         sh.mf = rp[r];
 #pragma unroll
         for (int l = 0; l < D; ++l) sh.P[l] = rp[D + r * D + l];
-        if (n >= 1) {
 #pragma unroll
-            for (int b = 0; b < d; ++b) sh.H[b] = rp[D + DD + b * D + r];
+        for (int b = 0; b < d; ++b) sh.H[b] = rp[D + DD + b * D + r];
 #pragma unroll
-            for (int l = 0; l < D; ++l) sh.K[l] = rp[D + DD + d * D + l * d + a];
-            sh.z = rp[D + DD + 2 * d * D + a];
-        }
+        for (int l = 0; l < D; ++l) sh.K[l] = rp[D + DD + d * D + l * d + a];
+        sh.z = rp[D + DD + 2 * d * D + a];
     };
+    auto at_least0 = [](int64_t k) { return k > 0 ? k : (int64_t)0; };
     // one smoother step on the share of record n
     auto step = [&](int64_t n, const Share &cur) {
         // t = Phi^T nu_{n+1} (block diagonal: q+1 terms)
@@ -1979,17 +1983,28 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         }
         wave_sync();
     };
-    // two buffers taken in turn (the loop body holds two steps, so no share
-    // is copied: a copy of a share still being loaded would wait for it)
-    Share A, B;
-    load_share(cd.M, A);
+    // four buffers taken in turn, loaded three steps ahead: a record comes
+    // from L2 in about as long as three steps take.  The loop body holds four
+    // steps, so no share is copied (a copy of a share still being loaded
+    // would wait for it).
+    Share A, B, C, E;
+    const int64_t M = cd.M;
+    load_share(M, A);
+    load_share(at_least0(M - 1), B);
+    load_share(at_least0(M - 2), C);
     wave_sync();
-    for (int64_t n = cd.M; n >= 0; n -= 2) {
-        if (n >= 1) load_share(n - 1, B);
+    for (int64_t n = M; n >= 0; n -= 4) {
+        load_share(at_least0(n - 3), E);
         step(n, A);
         if (n == 0) break;
-        if (n >= 2) load_share(n - 2, A);
+        load_share(at_least0(n - 4), A);
         step(n - 1, B);
+        if (n == 1) break;
+        load_share(at_least0(n - 5), B);
+        step(n - 2, C);
+        if (n == 2) break;
+        load_share(at_least0(n - 6), C);
+        step(n - 3, E);
     }
     const unsigned long long ballot = __ballot(bad ? 1 : 0);
     if (lane == 0) *cd.status = ballot ? 1 : 0;
