@@ -649,7 +649,7 @@ CoarseLayout coarse_layout(const Solve &sv)
     };
     const size_t d = sv.d;
     c.node = take((size_t)(c.M + 1) * D * 8);
-    c.gain = take((size_t)(c.M + 1) * (D + D * D + 2 * d * D + d) * 8);
+    c.gain = take((size_t)(c.M + 1) * parapn::coarse_record_doubles((int)d, sv.q) * 8);
     c.W = take((size_t)c.s * S * 2 * S * 8);
     c.mu0c = take(D * 8);
     c.status = take(sizeof(int));
@@ -2273,8 +2273,7 @@ int admit_enqueue(parapn_server *srv, std::vector<ServedReq *> &adm, hipStream_t
     for (auto &kv : groups)
         for (Item &it : kv.second) {
             it.node_off = take((size_t)(it.cl.M + 1) * it.r->sv.D * 8);
-            const size_t D = it.r->sv.D, d = it.r->sv.d;
-            it.gain_off = take((size_t)(it.cl.M + 1) * (D + D * D + 2 * d * D + d) * 8);
+            it.gain_off = take((size_t)(it.cl.M + 1) * parapn::coarse_record_doubles(it.r->sv.d, it.r->sv.q) * 8);
         }
     int rc = srv->stage.ensure(upload);
     if (rc) return rc;

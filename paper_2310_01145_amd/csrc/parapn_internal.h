@@ -12,6 +12,14 @@ constexpr int kMaxParams = 16;
 constexpr int kMaxLevels = 24;  // scan levels per request (tree width >= 2, <= 2^24 chunks)
 constexpr int kCounters = 5;    // per-request counter words (ReqDev::dbits)
 
+// Doubles per node record of the coarse-grid smoother (k_coarse_eks), with
+// D = d (q+1): m^f (D), P (D x D), the 2d columns of A = I - K Hbar that
+// differ from I (D each) and c = Hbar^T z (D).
+constexpr __host__ __device__ int coarse_record_doubles(int d, int q)
+{
+    return d * (q + 1) * (2 + d * (q + 1) + 2 * d);
+}
+
 // One request of a pack (device-side table, filled by the host).
 struct ReqDev {
     int field;

@@ -1645,11 +1645,14 @@ __global__ __launch_bounds__(C::NT) void k_filter_combine_batch(const typename C
 // rank-deficient noiseless-data covariance to cancellation).
 // Smoother (the RTS means, written without inverting P-): with
 // nu_{M+1} = 0 and t_n = Phi^T nu_{n+1},
-//   m^s_n = m^f_n + P_n t_n,   nu_n = Hbar_n^T (z_n - K_n^T t_n) + t_n,
-// which is m^s_n = m^f_n + G_n (m^s_{n+1} - m-_{n+1}) with the RTS gain
+//   m^s_n = m^f_n + P_n t_n,   nu_n = Hbar_n^T (z_n - K_n^T t_n) + t_n
+//                                   = A_n^T t_n + c_n,
+// A_n = I - K_n Hbar_n (the Joseph factor), c_n = Hbar_n^T z_n; this is
+// m^s_n = m^f_n + G_n (m^s_{n+1} - m-_{n+1}) with the RTS gain
 // G_n = P_n Phi^T (P-_{n+1})^-1 and nu_{n+1} = (P-_{n+1})^-1 (m^s_{n+1} -
 // m-_{n+1}).  Per coarse node the records hold m^f_n, P_n, and for n >= 1
-// Hbar_n, K_n and z_n; the smoothed means go to the node array.
+// the 2d columns of A_n that differ from I and c_n; the smoothed means go to
+// the node array.
 // Sequential EK1 filter (covariance form, FP64) on the coarse grid, one
 // wavefront per request, then the RTS means.  The coarse prior is the IWP:
 // Phi = I_d (x) Phi1 and Q = I_d (x) Q1 with (q+1)-blocks, so a product with
@@ -1664,8 +1667,8 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
                                                    const double *Q)
 {
     constexpr int S = q + 1, D = d * S, DD = D * D, EPL = (DD + 63) / 64;
-    constexpr int REC = D + DD + 2 * d * D + d;
-    __shared__ double sP[DD], sA[DD], sPp[DD], sm[D], smp[D], sU[D * d], sK[D * d], st[D], snu[D], su[d];
+    constexpr int REC = coarse_record_doubles(d, q);
+    __shared__ double sP[DD], sA[DD], sPp[DD], sm[D], smp[D], sU[D * d], sK[D * d], snu[D];
     const int lane = threadIdx.x;
     const ReqDev &rq = reqs[blockIdx.x];
     const CoarseDev cd = cds[blockIdx.x];
@@ -1697,14 +1700,10 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         }
         qv[k] = (i / S == j / S) ? Q[(i % S) * D + (j % S)] : 0.0;
     }
-    // the lane's row of Phi1 for m- = Phi m, and its column for t = Phi^T nu
-    // in the smoother (lane < D holds component lane)
-    double prl[S], pcb[S];
+    // the lane's row of Phi1 for m- = Phi m (lane < D holds component lane)
+    double prl[S];
 #pragma unroll
-    for (int l = 0; l < S; ++l) {
-        prl[l] = Phi[(lane % S) * D + l];
-        pcb[l] = Phi[l * D + (lane % S)];
-    }
+    for (int l = 0; l < S; ++l) prl[l] = Phi[(lane % S) * D + l];
     gdouble *rec = (gdouble *)cd.gain, *node = (gdouble *)cd.node;
     for (int e = lane; e < DD; e += 64) sP[e] = 0.0;
     if (lane < D) sm[lane] = cd.mu0c[lane];
@@ -1830,7 +1829,8 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
             for (int c = 0; c < d; ++c) v += Si[a][c] * r[c];
             z[a] = v;
         }
-        gdouble *rn = rec + n * REC;  // step n: Hbar, K, z after node n's m^f, P
+        // step n: A's columns b S, b S + 1 (rows 0..D-1), then c, after node
+        // n's m^f, P
         if (lane < D) {
             double uu[d], kk[d];
 #pragma unroll
@@ -1846,20 +1846,23 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
 #pragma unroll
             for (int a = 0; a < d; ++a) {
                 sK[lane * d + a] = kk[a];
-                rn[D + DD + d * D + lane * d + a] = kk[a];
                 mn += kk[a] * r[a];
             }
             sm[lane] = mn;
             bad |= !__builtin_isfinite(mn);
         }
-        // Hbar rows: 1 at (a, a S + 1), hj[a][b] at (a, b S)
-        for (int e = lane; e < d * D; e += 64) {
-            const int a = e / D, c = e % D;
-            double h = (c == a * S + 1) ? 1.0 : 0.0;
-            if (c % S == 0) h += hj_at(a, c / S);
-            rn[D + DD + e] = h;
+        gdouble *rn = rec + n * REC;
+        // c = Hbar^T z: Hbar has 1 at (a, a S + 1) and hj[a][b] at (a, b S)
+        if (lane < D) {
+            const int b = lane / S, k = lane % S;
+            double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+            for (int a = 0; a < d; ++a) {
+                c0 += hj_at(a, b) * z[a];
+                c1 = (a == b) ? z[a] : c1;
+            }
+            rn[D + DD + 2 * d * D + lane] = k == 0 ? c0 : (k == 1 ? c1 : 0.0);
         }
-        if (lane < d) rn[D + DD + 2 * d * D + lane] = z[lane];
         wave_sync();
         // Joseph form P = A P- A^T, A = I - K Hbar.  A differs from I only in
         // the 2d columns c with c mod S <= 1 (where Hbar has its nonzeros):
@@ -1884,6 +1887,10 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
                         for (int a = 0; a < d; ++a) a0 -= ki[a] * hj[a][b];
                         const double a1 = ((i == b * S + 1) ? 1.0 : 0.0) - ki[b];
                         acc += a0 * sPp[(b * S) * D + j] + a1 * sPp[(b * S + 1) * D + j];
+                        if (j == 0) {  // the smoother's record: A[i][b S], A[i][b S + 1]
+                            rn[D + DD + (2 * b) * D + i] = a0;
+                            rn[D + DD + (2 * b + 1) * D + i] = a1;
+                        }
                     }
                     bb[k] = acc;
                 }
@@ -1924,62 +1931,61 @@ __global__ __launch_bounds__(64) void k_coarse_eks(const ReqDev *reqs, const Coa
         if (lane < D) rp[lane] = sm[lane];
         for (int e = lane; e < DD; e += 64) rp[D + e] = sP[e];
     }
-    // smoother.  Each lane's share of a record (its row of P and m^f, its
-    // column of Hbar; lanes < d their column of K and entry of z) is loaded
-    // ahead of its step, so the global-memory latency overlaps the arithmetic
-    // of the steps before it.
+    // smoother.  Each lane's share of a record (its row of P and m^f; for its
+    // index i its column of A and c_i) is loaded ahead of its step, so the
+    // global-memory latency overlaps the arithmetic of the steps before it.
+    // Every lane forms all of t = Phi^T nu from nu in LDS (D (q+1) products:
+    // cheaper than a second exchange), so a step is one LDS round trip.
     if (lane < D) snu[lane] = 0.0;
     struct Share {
-        double mf, P[D], H[d], K[D], z;
+        double mf, P[D], acol[D], c;
     };
     // Every call issues the same loads, whatever n (0 <= n <= M; record 0's
-    // Hbar, K, z slots are read and left unused): a load taken on one path
-    // and skipped on another leaves the compiler no static count of the loads
+    // A and c slots are read and left unused): a load taken on one path and
+    // skipped on another leaves the compiler no static count of the loads
     // issued after a share, and it then waits for all of them -- the prefetch
-    // would not hide anything.
+    // would not hide anything.  Lanes whose index is not a column of A that
+    // differs from I (i mod S > 1) read column 0 and do not use it.
+    const int r_own = lane < D ? lane : 0;
+    const bool a_col = lane < D && lane % S <= 1;
+    const int a_blk = a_col ? 2 * (lane / S) + lane % S : 0;
     auto load_share = [&](int64_t n, Share &sh) {
         const gdouble *rp = rec + n * REC;
-        const int r = lane < D ? lane : 0, a = lane < d ? lane : 0;
-        sh.mf = rp[r];
+        sh.mf = rp[r_own];
 #pragma unroll
-        for (int l = 0; l < D; ++l) sh.P[l] = rp[D + r * D + l];
+        for (int l = 0; l < D; ++l) sh.P[l] = rp[D + r_own * D + l];
 #pragma unroll
-        for (int b = 0; b < d; ++b) sh.H[b] = rp[D + DD + b * D + r];
-#pragma unroll
-        for (int l = 0; l < D; ++l) sh.K[l] = rp[D + DD + d * D + l * d + a];
-        sh.z = rp[D + DD + 2 * d * D + a];
+        for (int l = 0; l < D; ++l) sh.acol[l] = rp[D + DD + a_blk * D + l];
+        sh.c = rp[D + DD + 2 * d * D + r_own];
     };
     auto at_least0 = [](int64_t k) { return k > 0 ? k : (int64_t)0; };
     // one smoother step on the share of record n
     auto step = [&](int64_t n, const Share &cur) {
-        // t = Phi^T nu_{n+1} (block diagonal: q+1 terms)
-        if (lane < D) {
-            const int bl = lane / S;
+        double nu[D], t[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) nu[j] = snu[j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < S; ++l) acc += pcb[l] * snu[bl * S + l];
-            st[lane] = acc;
+            for (int l = 0; l < S; ++l) acc += p1[l][j % S] * nu[(j / S) * S + l];
+            t[j] = acc;
         }
-        wave_sync();
         if (lane < D) {
             double acc = cur.mf;
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc += cur.P[l] * st[l];
+            for (int l = 0; l < D; ++l) acc += cur.P[l] * t[l];
             node[n * D + lane] = acc;
             bad |= !__builtin_isfinite(acc);
         }
-        if (n >= 1 && lane < d) {
-            double acc = 0.0;
+        if (n >= 1) {
+            double v = cur.c, tl = 0.0;
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc += cur.K[l] * st[l];
-            su[lane] = cur.z - acc;
-        }
-        wave_sync();
-        if (n >= 1 && lane < D) {
-            double acc = st[lane];
-#pragma unroll
-            for (int a = 0; a < d; ++a) acc += cur.H[a] * su[a];
-            snu[lane] = acc;
+            for (int l = 0; l < D; ++l) {
+                v += cur.acol[l] * t[l];
+                tl = (l == lane) ? t[l] : tl;
+            }
+            if (lane < D) snu[lane] = a_col ? v : tl;
         }
         wave_sync();
     };
