@@ -489,3 +489,35 @@ def test_lorenz_full_size_first_iteration(pp):
     r32 = pp.solve(*args, precision="fp32", fixed_iters=1, init_traj=start)
     assert r32["status"] == 0
     assert relerr(e0(np_(r32["mean"]), 4)[: n8 + 1], ref0[: n8 + 1]) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# the caller's stream
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_on_a_stream_of_its_own_is_bitwise_the_default_stream_solve(pp, prec):
+    """A solve enqueued on a stream of the caller's (not the legacy default
+    stream) returns bitwise what the same solve on the default stream returns:
+    iteration count, deltas, means and factors (constant and coarse-grid
+    starts)."""
+    import torch
+
+    fhn = wl.fhn(N=4096)
+    cases = [(("logistic", [], [0.01], 0.0, 10.0, 2, 1000), {}),
+             ((fhn["field"], fhn["params"], fhn["y0"], fhn["t0"], fhn["t1"], fhn["q"], fhn["N"]),
+              {"init": "coarse"})]
+    st = torch.cuda.Stream()
+    for args, kw in cases:
+        print("own stream %s %s" % (args[0], prec), flush=True)
+        a = pp.solve(*args, precision=prec, tol=1e-10, max_iter=20, want_cov=True, **kw)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            b = pp.solve(*args, precision=prec, tol=1e-10, max_iter=20, want_cov=True, **kw)
+        torch.cuda.synchronize()
+        assert a["status"] == b["status"] == 0
+        assert a["iterations"] == b["iterations"] and a["iterations"] >= 3
+        assert np.array_equal(np.asarray(a["deltas"]), np.asarray(b["deltas"]))
+        iv = {4: torch.int32, 8: torch.int64}
+        for key in ("mean", "sqrtcov"):
+            x, y = a[key], b[key]
+            assert torch.equal(x.view(iv[x.element_size()]), y.view(iv[y.element_size()])), key
