@@ -49,6 +49,11 @@ CASES = [
     ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 0.0, 2.0, 2, 2048, 100),
     ("van_der_pol", [1.0], [2.0, 0.0], 0.0, 6.3, 1, 333, 7),
     ("logistic", [], [0.3], 0.0, 1.0, 4, 1, 0),
+    # the largest state sizes (d = 3: D = 12 and 15) and d = 1 at q = 1
+    ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 0.0, 2.0, 4, 2048, 200),
+    ("lorenz", [10.0, 28.0, 8.0 / 3.0], [1.0, 1.0, 1.0], 0.0, 2.0, 3, 2048, 300),
+    ("rigid_body", [], [1.0, 0.0, 0.9], 0.0, 20.0, 3, 1500, 300),
+    ("logistic", [], [0.01], 0.0, 10.0, 1, 500, 64),
 ]
 
 
